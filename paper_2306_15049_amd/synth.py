@@ -1,0 +1,140 @@
+"""Seeded synthetic inputs for the shifted deblurring systems.
+
+This module draws the raw ingredients of a deblurring problem and nothing
+else: a piecewise-constant phantom, a sampled Gaussian point-spread function,
+a standard-normal noise direction and a log-spaced shift grid.  It performs
+none of the method's arithmetic (no blur, no differences, no weights, no
+solves): the data ``d = K x_true + e`` and the right-hand side ``b = K^T d``
+are formed by whichever side consumes these inputs, with its own operators.
+
+The paper's experiments (Section 7, Examples 1 and 2) use a third-party
+128x128 test image and an 82x82 CT phantom that are not available here; the
+rectangle phantoms below stand in for them.  They share the structure class
+that drives the edge-preserving weights: flat regions with sharp edges and
+values in [0, 1].
+
+Readings fixed here (each is stated in the design notes as well):
+  * PSF: point-sampled exp(-(a^2 + c^2) / (2 sigma^2)) on the integer s x s
+    grid centred at (s//2, s//2), normalised to sum 1 after truncation, which
+    matches the normalisation ||C||_2 ~ 1 assumed in Section 2.2.
+  * Support "6 sigma + 1" for non-integer sigma is read as s = 2 ceil(3 sigma) + 1.
+  * Phantom: background 0; each rectangle takes two sorted row indices and two
+    sorted column indices uniformly from the image and a value from U[0, 1];
+    later rectangles overwrite earlier ones.
+  * Noise: g ~ N(0, I); the consumer scales it to e = level * ||K x|| g / ||g||.
+  * Shifts: numpy.logspace(lo, hi, M), inclusive and ascending (Section 4.2
+    orders the shifts ascending).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+def gaussian_psf(sigma: float, size: int) -> np.ndarray:
+    """Sampled, truncated, sum-normalised Gaussian PSF of odd ``size``."""
+    if size < 1 or size % 2 == 0:
+        raise ValueError("PSF size must be a positive odd integer")
+    c = size // 2
+    a = np.arange(size, dtype=np.float64) - c
+    g1 = np.exp(-(a * a) / (2.0 * sigma * sigma))
+    h = np.outer(g1, g1)
+    return h / h.sum()
+
+
+def psf_support(sigma: float) -> int:
+    """Odd support 2*ceil(3 sigma) + 1 (reading of "6 sigma + 1")."""
+    return 2 * int(math.ceil(3.0 * sigma)) + 1
+
+
+def phantom(rng: np.random.Generator, ny: int, nx: int, n_rect: int) -> np.ndarray:
+    """Piecewise-constant image of ``n_rect`` random rectangles, values in U[0,1]."""
+    x = np.zeros((ny, nx), dtype=np.float64)
+    for _ in range(n_rect):
+        i0, i1 = np.sort(rng.integers(0, ny, size=2))
+        j0, j1 = np.sort(rng.integers(0, nx, size=2))
+        x[i0:i1 + 1, j0:j1 + 1] = rng.uniform(0.0, 1.0)
+    return x
+
+
+def shift_grid(lo_exp: float, hi_exp: float, m: int) -> np.ndarray:
+    """Ascending log-spaced shifts 10**lo_exp .. 10**hi_exp (inclusive)."""
+    return np.logspace(lo_exp, hi_exp, m)
+
+
+@dataclass
+class Problem:
+    """Raw inputs of one deblurring instance (no derived quantities)."""
+    ny: int
+    nx: int
+    psf: np.ndarray          # (s, s), sums to 1
+    sigma: float
+    x_true: np.ndarray       # (ny, nx)
+    noise_dir: np.ndarray    # (ny, nx), standard normal
+    noise_level: float       # relative noise level, e.g. 0.01
+
+    @property
+    def n(self) -> int:
+        return self.ny * self.nx
+
+
+def make_problem(seed: int, ny: int, nx: int, sigma: float, size: int,
+                 n_rect: int, noise_level: float = 0.01) -> Problem:
+    """Draw one instance; draw order is rectangles, then noise."""
+    rng = np.random.default_rng(seed)
+    x = phantom(rng, ny, nx, n_rect)
+    g = rng.standard_normal((ny, nx))
+    return Problem(ny, nx, gaussian_psf(sigma, size), sigma, x, g, noise_level)
+
+
+@dataclass
+class Config:
+    """One workload: instances, shift grid and recycling sizes."""
+    name: str
+    problems: List[Problem]
+    gammas: np.ndarray
+    outer_steps: int
+    p: int                   # principal recycle dimension cap
+    q: int = 5               # local space width (Ritz + previous corrections)
+    mode: str = "sequential"  # or "batched"
+    tol: float = 1e-8
+    extra: dict = field(default_factory=dict)
+
+
+def config(name: str, small: Optional[int] = None) -> Config:
+    """The five workloads C1..C5.  ``small`` replaces the image side (tests)."""
+    if name == "C1":
+        n = small or 32
+        pr = make_problem(1, n, n, 1.5, 7, 6)
+        return Config("C1", [pr], shift_grid(-4, 0, 8), 3, 10, 5, "sequential")
+    if name == "C2":
+        n = small or 256
+        pr = make_problem(2, n, n, 3.0, 15, 20)
+        return Config("C2", [pr], shift_grid(-5, 1, 20), 5, 40, 5, "sequential")
+    if name == "C3":
+        n = small or 1024
+        pr = make_problem(3, n, n, 4.0, 21, 20)
+        return Config("C3", [pr], shift_grid(-5, 1, 32), 6, 64, 5, "batched")
+    if name == "C4":
+        rng = np.random.default_rng(4)
+        sides = rng.choice(np.array([128, 192, 256, 384, 512]), size=64)
+        sigmas = rng.uniform(1.0, 4.0, size=64)
+        probs = []
+        for i in range(64):
+            n = small or int(sides[i])
+            s = psf_support(float(sigmas[i]))
+            probs.append(make_problem(4000 + i, n, n, float(sigmas[i]), s, 20))
+        return Config("C4", probs, shift_grid(-5, 1, 8), 3, 20, 5, "batched")
+    if name == "C5":
+        n = small or 512
+        pr = make_problem(5, n, n, 3.0, 15, 20)
+        return Config("C5", [pr], shift_grid(-5, 1, 16), 1, 40, 5, "batched",
+                      extra={"fd_h": 1e-6})
+    if name == "C5_small":
+        pr = make_problem(6, 24, 24, 3.0, 15, 20)
+        return Config("C5_small", [pr], shift_grid(-5, 1, 16), 1, 40, 5, "batched",
+                      extra={"fd_h": 1e-6})
+    raise KeyError(name)
