@@ -1,0 +1,201 @@
+/*
+ * rsr.h -- recycled shifted solver for MI355X (gfx950), C ABI.
+ *
+ * Solves the sequences of shifted SPD systems
+ *     (A + gamma_l E_k) x^(k,l) = b,   l = 1..M,  k = 0..K          (eq. seqsys / eq. shift)
+ * of Kilmer & de Sturler, "Subspace Recycling for Sequences of Shifted Systems
+ * with Applications in Image Recovery", with
+ *     A   = K^T K, K a zero-boundary 2-D convolution by a PSF       (Sec. 2.1, eq. blkeqn: A = C^T C)
+ *     E_k = D^T W_k D, D forward differences, W_k diagonal weights  (Sec. 2.1, eq. blkeqn: L^T D_k^2 L)
+ * by conjugate gradients recycled across shifts and outer steps: initial
+ * guesses from a principal recycle space U_k (Sec. 4.1, eq. orthupdate) and
+ * deflation by small shift-specific spaces (Sec. 4.2, Algorithms 2-4).
+ *
+ * Conventions
+ *  - All numeric data are IEEE FP64.  Images are row-major [ny][nx]; a batch
+ *    of vectors is column-major: column j starts at base + j*ld (ld >= ny*nx).
+ *  - "device" pointers are HIP device allocations on the context's device;
+ *    "host" pointers are ordinary host memory.  The caller owns every buffer
+ *    it passes; the library only borrows it for the duration of the call.
+ *  - The library owns its persistent state (PSF factors, weights, recycle
+ *    spaces, small Gram blocks, workspaces).  It allocates device memory only
+ *    in rsr_set_operators, rsr_set_recycle_space and when a solve needs a
+ *    larger workspace than any earlier call.
+ *  - stream is a hipStream_t (NULL = the default stream).  Work is enqueued on
+ *    it; calls that return host results (stats, p_kept, gradients, norms)
+ *    synchronise that stream before returning.
+ *  - Every call returns an rsr_status.  No C++ exception crosses the ABI.  On
+ *    a negative status rsr_last_error gives a message.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef RSR_H
+#define RSR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsr_ctx rsr_ctx;
+
+typedef enum {
+    RSR_OK = 0,
+    RSR_NOT_CONVERGED = 1,   /* result usable; some shifts missed tol, see stats */
+    RSR_E_ARG = -1,          /* invalid argument (null, size, range)             */
+    RSR_E_STATE = -2,        /* call out of order (e.g. solve before operators)  */
+    RSR_E_NONFINITE = -3,    /* NaN/Inf met in inputs or iterates                */
+    RSR_E_NOT_SPD = -4,      /* p^T B p <= 0: the shifted matrix is not SPD      */
+    RSR_E_RANK = -5,         /* recycle space empty after stabilisation          */
+    RSR_E_NOMEM = -6,        /* device allocation failed                         */
+    RSR_E_HIP = -7,          /* HIP runtime error (message has the HIP text)     */
+    RSR_E_TIMEOUT = -8       /* a device-wide barrier did not complete in time   */
+} rsr_status;
+
+/* One deblurring instance: image ny x nx and a PSF of odd size sy x sx
+ * (host, row-major, centre at (sy/2, sx/2)); the PSF is copied.  A rank-1 PSF
+ * is detected and applied separably (row pass then column pass); any other
+ * PSF uses the direct 2-D stencil.                                           */
+typedef struct {
+    int ny, nx;
+    int sy, sx;
+    const double *psf_host;
+} rsr_instance;
+
+/* Operator selector for rsr_apply. */
+enum { RSR_OP_B = 0,   /* y = (A + gamma E) v */
+       RSR_OP_A = 1,   /* y = K^T K v         */
+       RSR_OP_E = 2,   /* y = D^T W D v       */
+       RSR_OP_K = 3,   /* y = K v             */
+       RSR_OP_KT = 4   /* y = K^T v           */ };
+
+/* Initial guess (Sec. 4.1). */
+enum { RSR_INIT_ZERO = 0,      /* x0 = 0                                        */
+       RSR_INIT_GIVEN = 1,     /* x0 = contents of X on entry                   */
+       RSR_INIT_MR = 2,        /* x0 = U q, q minimises ||b - (AU + gamma EU) q|| (eq. orthupdate) */
+       RSR_INIT_GALERKIN = 3   /* x0 = U (U^T B U)^{-1} U^T b                   */ };
+
+/* Solve modes. */
+enum { RSR_BATCHED = 0,        /* all systems advance together in one persistent launch */
+       RSR_SEQUENTIAL = 1      /* systems one at a time in list order (Algorithm 5 loops)  */ };
+
+/* A set of shifted systems.  System i is instance inst[i] with shift
+ * gammas[i] and slot[i] (the shift index l, used to keep g^(k-1,l) between
+ * outer steps).  Right-hand sides: b + i*ld_b; solutions: X + i*ld_x.       */
+typedef struct {
+    int n_sys;
+    const int *inst;          /* host [n_sys]                                 */
+    const double *gammas;     /* host [n_sys], >= 0                           */
+    const int *slot;          /* host [n_sys] or NULL (slot = i)              */
+    double tol;               /* relative residual ||b - Bx|| / ||b||          */
+    int maxit;                /* CG iterations per system (<= 0: 10 * n)       */
+    int mode;                 /* RSR_BATCHED | RSR_SEQUENTIAL                  */
+    int init;                 /* RSR_INIT_*                                    */
+    int n_ritz;               /* Ritz vectors per group in the local space (Alg. 2); 0 = none */
+    int use_prev_k;           /* add g^(k-1,l) to the local space (Alg. 3)     */
+    int use_prev_shift;       /* add g^(k,l-1) (sequential mode only, Alg. 3)  */
+    int split_I;              /* left group = slots < split_I (Sec. 5.4)       */
+    double gamma_JL;          /* shift defining the left group's Ritz block    */
+    double gamma_JR;          /* shift defining the right group's Ritz block   */
+    long ld_b;                /* column stride of b (0: all systems share b)   */
+    long ld_x;                /* column stride of X                            */
+} rsr_solve_desc;
+
+typedef struct {
+    int iters;                /* CG iterations                                 */
+    int matvec_A;             /* applications of A (K^T K) for this system      */
+    int matvec_E;             /* applications of E                              */
+    int converged;            /* 1 if the true relative residual <= tol         */
+    int restarts;             /* true-residual restarts                         */
+    int local_dim;            /* columns of the local (deflation) space used    */
+    double relres_init;       /* ||b - B x0|| / ||b|| after the initial guess    */
+    double relres_true;       /* final ||b - B x|| / ||b|| (recomputed)          */
+} rsr_shift_stats;
+
+/* Context lifetime. */
+rsr_status  rsr_create(rsr_ctx **out, int hip_device);
+void        rsr_destroy(rsr_ctx *ctx);
+const char *rsr_last_error(const rsr_ctx *ctx);  /* valid until the next call on ctx */
+const char *rsr_version(void);
+
+/* Set the instances (replaces any earlier set; weights reset to W = I, i.e.
+ * E_0 = D^T D, and recycle spaces cleared).                                  */
+rsr_status rsr_set_operators(rsr_ctx *ctx, int n_inst, const rsr_instance *inst, void *stream);
+
+/* Replace W_k of one instance: device w_h, w_v [ny*nx]; w_h[i,j] weights
+ * x[i,j+1]-x[i,j] (ignored in the last column), w_v[i,j] weights
+ * x[i+1,j]-x[i,j] (ignored in the last row).  Invalidates the instance's
+ * cached A U / E U products (recomputed by the next rsr_set_recycle_space). */
+rsr_status rsr_update_weights(rsr_ctx *ctx, int inst, const double *w_h, const double *w_v,
+                              void *stream);
+
+/* W from an image x (device [ny*nx]): w = ((D x)^2 + beta)^(-1/2) per
+ * difference (the edge-preserving reweighting of the outer iteration).       */
+rsr_status rsr_weights_from_image(rsr_ctx *ctx, int inst, const double *x, double beta,
+                                  void *stream);
+
+/* Copy the instance's current weights to device buffers w_h, w_v [ny*nx].  */
+rsr_status rsr_get_weights(rsr_ctx *ctx, int inst, double *w_h, double *w_v, void *stream);
+
+/* y = op(v) for n_vec vectors (device, column-major with stride ld).        */
+rsr_status rsr_apply(rsr_ctx *ctx, int inst, int op, double gamma, const double *v, double *y,
+                     int n_vec, long ld, void *stream);
+
+/* Principal recycle space (Algorithm 1 and Sec. 5.2).  U_raw: device
+ * [ncols][ld] candidate columns (e.g. the previous outer step's solutions).
+ * If n_retain > 0 the n_retain Ritz vectors of (A_hat + gamma_retain E_hat)
+ * with the smallest Ritz values from the current space are appended first
+ * (the retained invariant-subspace approximation of Sec. 5.2).  The columns
+ * are orthonormalised, those with sigma_1/sigma_i >= cond_max are dropped,
+ * at most p_max are kept; then A U, E U and the Gram blocks U^T A U, U^T E U,
+ * (AU)^T(AU), (AU)^T(EU), (EU)^T(EU) are formed.  ncols = 0 and n_retain = 0
+ * clears the space.  *p_kept (host) receives the dimension.                  */
+rsr_status rsr_set_recycle_space(rsr_ctx *ctx, int inst, const double *U_raw, long ld, int ncols,
+                                 int n_retain, double gamma_retain, int p_max, double cond_max,
+                                 int *p_kept, void *stream);
+
+/* Solve a shift set.  b, X: device.  stats_host: host [n_sys] (may be NULL).
+ * Returns RSR_OK, RSR_NOT_CONVERGED, or an error.                           */
+rsr_status rsr_solve_shift_set(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *b,
+                               double *X, rsr_shift_stats *stats_host, void *stream);
+
+/* Adjoint for L(x_1..x_M): given the solutions X of a shift set on one
+ * instance and Gbar = dL/dX (device, same layout), solves B_l lambda_l =
+ * Gbar_l with the same recycled solver (B_l is symmetric) and returns
+ *   dgamma_host[l] = -lambda_l^T E x_l                       (host [n_sys])
+ *   dw_h, dw_v     = -sum_l gamma_l (D lambda_l) .* (D x_l)  (device [ny*nx], each plane)
+ * Lambda (device, layout of X) receives the adjoint solutions.             */
+rsr_status rsr_adjoint(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *X,
+                       const double *Gbar, double *Lambda, double *dgamma_host, double *dw_h,
+                       double *dw_v, rsr_shift_stats *stats_host, void *stream);
+
+/* Time the candidate tile shapes of one instance's stencil for a batch of
+ * n_vec vectors and keep the fastest (optionally cached in a text file).    */
+rsr_status rsr_autotune(rsr_ctx *ctx, int inst, int n_vec, const char *cache_path);
+
+/* Current tile shape of an instance (host outputs). */
+rsr_status rsr_get_tile(const rsr_ctx *ctx, int inst, int *tile_y, int *tile_x);
+rsr_status rsr_set_tile(rsr_ctx *ctx, int inst, int tile_y, int tile_x);
+
+/* Dimension of the instance's principal space and host copies of its small
+ * blocks (row-major p x p each; any pointer may be NULL).                   */
+rsr_status rsr_get_recycle_info(const rsr_ctx *ctx, int inst, int *p, double *Ahat, double *Ehat);
+
+/* Copy the instance's orthonormal principal basis U (p columns) into the
+ * caller's device buffer U_out (column j at U_out + j*ld, ld >= ny*nx).      */
+rsr_status rsr_get_recycle_basis(rsr_ctx *ctx, int inst, double *U_out, long ld, void *stream);
+
+/* Cumulative applications of A and of E made by the context (all calls,
+ * including A U, E U and true-residual checks).                              */
+rsr_status rsr_get_counters(const rsr_ctx *ctx, long *matvec_A, long *matvec_E);
+
+/* Timing of the most recent solve: milliseconds spent in the persistent CG
+ * kernel(s), measured with HIP events on the solve stream, and the number of
+ * CG launches.                                                               */
+rsr_status rsr_last_solve_timing(const rsr_ctx *ctx, double *cg_kernel_ms, int *launches,
+                                 long *tile_items);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSR_H */

@@ -1,0 +1,1343 @@
+// Host engine and C ABI of the recycled shifted solver.
+//
+// Per outer step k the caller sets W_k (rsr_update_weights /
+// rsr_weights_from_image), the principal recycle space U_k
+// (rsr_set_recycle_space: Algorithm 1 plus the products A U, E U and their
+// small Gram blocks, Sections 4.1 and 5.3), and solves the shift set
+// (rsr_solve_shift_set).  A solve
+//   1. takes an initial guess from U_k: x0 = U q with q minimising
+//      ||b - (AU + gamma EU) q|| (Section 4.1, eq. orthupdate), all from the
+//      cached Gram blocks -- no operator application per shift;
+//   2. builds each system's local space W = [Ritz block, g^(k-1,l), g^(k,l-1)]
+//      (Algorithms 2-4), Z = B W from the cached A U, E U plus one A and one E
+//      application per correction column, and applies the Galerkin correction
+//      x0 += W G^{-1} W^T r0 (G = W^T Z);
+//   3. runs deflated CG for every system in one persistent launch;
+//   4. accepts on the recomputed true residual, restarting if needed, and keeps
+//      the correction g = x - x0 for the next shift / outer step.
+#include "internal.hpp"
+#include "smalldense.hpp"
+#include "../../include/rsr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using namespace rsr;
+
+namespace {
+
+struct Err {
+    rsr_status st;
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            throw Err{e_ == hipErrorOutOfMemory ? RSR_E_NOMEM : RSR_E_HIP,                         \
+                      std::string(#expr) + ": " + hipGetErrorString(e_)};                         \
+    } while (0)
+
+void fail(rsr_status st, const std::string &m) { throw Err{st, m}; }
+
+// Grow-only device buffer.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t b)
+    {
+        if (b <= bytes) return;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t nb = std::max(b, (size_t)256);
+        HIPCHK(hipMalloc(&p, nb));
+        bytes = nb;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+struct Instance {
+    int ny = 0, nx = 0, sy = 1, sx = 1;
+    long n = 0;
+    std::vector<double> psf;
+    int sep = 0;
+    std::vector<double> fy, fx;
+    DBuf d_fy, d_fx, d_psf, d_wh, d_wv;
+    int ty = 16, tx = 16;
+    // principal recycle space
+    int p = 0;
+    DBuf d_U, d_AE;   // U: p columns; AE: [AU | EU], 2p columns; stride n
+    std::vector<double> Ahat, Ehat, Gaa, Gae, Gee;   // p x p row-major
+    bool ae_valid = false;
+    // latest correction g = x - x0 per shift slot
+    std::map<int, std::unique_ptr<DBuf>> gstore;
+};
+
+}  // namespace
+
+struct rsr_ctx {
+    int dev = 0;
+    int n_cu = 256;
+    double wall_khz = 100000.0;
+    std::string err;
+    std::vector<std::unique_ptr<Instance>> inst;
+    DBuf d_inst;                       // InstDev[n_inst]
+    std::vector<InstDev> h_inst;
+    // scratch
+    DBuf d_jobs, d_gram_scratch, d_small, d_sys, d_partA, d_partB, d_ctl, d_out;
+    DBuf d_ws;                         // per-system vectors of a solve
+    DBuf d_tmp;                        // misc n-vectors
+    // counters and timing
+    long mv_A = 0, mv_E = 0;
+    double last_cg_ms = 0.0;
+    int last_launches = 0;
+    long last_items = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+void set_device(rsr_ctx *c) { HIPCHK(hipSetDevice(c->dev)); }
+
+Instance &get_inst(rsr_ctx *c, int i)
+{
+    if (c->inst.empty()) fail(RSR_E_STATE, "operators not set");
+    if (i < 0 || i >= (int)c->inst.size()) fail(RSR_E_ARG, "instance index out of range");
+    return *c->inst[i];
+}
+
+void upload_inst(rsr_ctx *c)
+{
+    c->h_inst.resize(c->inst.size());
+    for (size_t i = 0; i < c->inst.size(); ++i) {
+        Instance &I = *c->inst[i];
+        InstDev &d = c->h_inst[i];
+        d.ny = I.ny;
+        d.nx = I.nx;
+        d.ty = I.ty;
+        d.tx = I.tx;
+        d.nty = (I.ny + I.ty - 1) / I.ty;
+        d.ntx = (I.nx + I.tx - 1) / I.tx;
+        d.sep = I.sep;
+        d.sy = I.sy;
+        d.sx = I.sx;
+        d.fy = I.d_fy.as<double>();
+        d.fx = I.d_fx.as<double>();
+        d.psf = I.d_psf.as<double>();
+        d.wh = I.d_wh.as<double>();
+        d.wv = I.d_wv.as<double>();
+    }
+    c->d_inst.ensure(sizeof(InstDev) * std::max<size_t>(1, c->h_inst.size()));
+    HIPCHK(hipMemcpy(c->d_inst.p, c->h_inst.data(), sizeof(InstDev) * c->h_inst.size(), hipMemcpyHostToDevice));
+}
+
+// Upload a host array through the job buffer region starting at byte offset.
+template <class T> T *upload(rsr_ctx *c, DBuf &buf, const std::vector<T> &v, hipStream_t s)
+{
+    buf.ensure(sizeof(T) * std::max<size_t>(1, v.size()));
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(buf.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return buf.as<T>();
+}
+
+int max_tile_lds(rsr_ctx *c)
+{
+    int m = 2048;
+    for (auto &p : c->inst) m = std::max(m, tile_lds_doubles(p->ty, p->tx, p->sy, p->sx));
+    return m;
+}
+
+// ----------------------------------------------------------- operators --
+// y_j = cA A v_j + cE E v_j for nvec vectors of one instance.
+void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ldv, double *y, long ldy,
+              int nvec, hipStream_t s, DBuf *jobbuf = nullptr)
+{
+    if (nvec <= 0) return;
+    Instance &I = get_inst(c, ii);
+    std::vector<ApplyJob> jobs(nvec);
+    for (int j = 0; j < nvec; ++j) jobs[j] = ApplyJob{ii, 0, cA, cE, v + j * ldv, y + j * ldy};
+    DBuf &jb = jobbuf ? *jobbuf : c->d_jobs;
+    ApplyJob *dj = upload(c, jb, jobs, s);
+    const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, I.sy, I.sx);
+    HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, nvec, lds, s));
+    if (cA != 0.0) c->mv_A += nvec;
+    if (cE != 0.0) c->mv_E += nvec;
+    if (jobbuf == nullptr) HIPCHK(hipStreamSynchronize(s));   // job buffer reuse
+}
+
+void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
+{
+    // group by instance (one launch per instance)
+    std::map<int, std::vector<ApplyJob>> by;
+    for (auto &j : jobs) by[j.inst].push_back(j);
+    for (auto &kv : by) {
+        Instance &I = get_inst(c, kv.first);
+        ApplyJob *dj = upload(c, c->d_jobs, kv.second, s);
+        const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, I.sy, I.sx);
+        HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[kv.first], dj, (int)kv.second.size(), lds, s));
+        for (auto &j : kv.second) {
+            if (j.cA != 0.0) c->mv_A++;
+            if (j.cE != 0.0) c->mv_E++;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+    }
+}
+
+// C_j = X_j^T Y_j for a list of jobs; results copied to host (row-major a x c each).
+std::vector<std::vector<double>> gram(rsr_ctx *c, std::vector<GramJob> jobs, hipStream_t s)
+{
+    std::vector<std::vector<double>> out(jobs.size());
+    if (jobs.empty()) return out;
+    size_t coff = 0;
+    for (auto &j : jobs) coff += (size_t)j.a * j.c;
+    c->d_small.ensure(sizeof(double) * std::max<size_t>(1, coff));
+    size_t o = 0, sc = 0;
+    for (auto &j : jobs) {
+        j.C = c->d_small.as<double>() + o;
+        o += (size_t)j.a * j.c;
+        j.sc_off = (long)sc;
+        sc += gram_scratch_doubles(&j, 1);
+    }
+    c->d_gram_scratch.ensure(sizeof(double) * std::max<size_t>(1, sc));
+    GramJob *dj = upload(c, c->d_jobs, jobs, s);
+    HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), c->d_gram_scratch.as<double>(), sc, s));
+    std::vector<double> h(coff);
+    HIPCHK(hipMemcpyAsync(h.data(), c->d_small.p, sizeof(double) * coff, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    o = 0;
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        out[k].assign(h.begin() + o, h.begin() + o + (size_t)jobs[k].a * jobs[k].c);
+        o += (size_t)jobs[k].a * jobs[k].c;
+    }
+    return out;
+}
+
+// Y_j = beta Y_j + X_j Q_j (Q from host, column-major a x c with ldq = a).
+void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector<double>> &Qs, hipStream_t s)
+{
+    if (jobs.empty()) return;
+    size_t tot = 0;
+    for (auto &q : Qs) tot += q.size();
+    std::vector<double> all;
+    all.reserve(tot);
+    std::vector<size_t> off;
+    for (auto &q : Qs) {
+        off.push_back(all.size());
+        all.insert(all.end(), q.begin(), q.end());
+    }
+    double *dq = upload(c, c->d_small, all, s);
+    for (size_t k = 0; k < jobs.size(); ++k) jobs[k].Q = dq + off[k];
+    ComboJob *dj = upload(c, c->d_jobs, jobs, s);
+    HIPCHK(launch_combo(dj, jobs.data(), (int)jobs.size(), s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+std::vector<double> norms(rsr_ctx *c, const std::vector<const double *> &v, const std::vector<long> &n,
+                          hipStream_t s)
+{
+    std::vector<GramJob> jobs;
+    for (size_t i = 0; i < v.size(); ++i) jobs.push_back(GramJob{v[i], n[i], 1, v[i], n[i], 1, n[i], nullptr, 0});
+    auto r = gram(c, jobs, s);
+    std::vector<double> out(v.size());
+    for (size_t i = 0; i < v.size(); ++i) out[i] = std::sqrt(std::max(0.0, r[i][0]));
+    return out;
+}
+
+// ---------------------------------------------------------- PSF factors --
+void factor_psf(Instance &I)
+{
+    // rank-1 test: h = fy fx^T iff h equals the outer product built from its
+    // largest entry's row and column.
+    const int sy = I.sy, sx = I.sx;
+    int am = 0, cm = 0;
+    double best = -1.0, nrm = 0.0;
+    for (int a = 0; a < sy; ++a)
+        for (int c2 = 0; c2 < sx; ++c2) {
+            const double v = std::fabs(I.psf[a * sx + c2]);
+            nrm += v * v;
+            if (v > best) { best = v; am = a; cm = c2; }
+        }
+    I.sep = 0;
+    if (best <= 0.0 || sx > MAXS || sy > MAXS) return;
+    const double piv = I.psf[am * sx + cm];
+    std::vector<double> fy(sy), fx(sx);
+    const double sc = std::sqrt(std::fabs(piv));
+    for (int a = 0; a < sy; ++a) fy[a] = I.psf[a * sx + cm] / sc;
+    for (int c2 = 0; c2 < sx; ++c2) fx[c2] = I.psf[am * sx + c2] / sc * (piv < 0 ? -1.0 : 1.0);
+    double err = 0.0;
+    for (int a = 0; a < sy; ++a)
+        for (int c2 = 0; c2 < sx; ++c2) {
+            const double d = I.psf[a * sx + c2] - fy[a] * fx[c2];
+            err += d * d;
+        }
+    if (err <= 1e-28 * nrm) {
+        I.sep = 1;
+        I.fy = fy;
+        I.fx = fx;
+    }
+}
+
+void default_tile(Instance &I)
+{
+    const long n = I.n;
+    if (n <= 512L * 512L) { I.ty = 16; I.tx = 16; }
+    else { I.ty = 32; I.tx = 32; }
+}
+
+// ------------------------------------------------------ persistent CG --
+struct SysHost {
+    int inst;
+    int slot;
+    double gamma;
+    long n;
+    const double *b;
+    double *x;
+    double *r, *p0, *p1, *w, *xinit, *rt;   // workspace vectors
+    double *W, *Z;                            // QMAX columns each
+    int q = 0;
+    std::vector<double> Ginv;                 // q x q
+    double bnorm = 0.0;
+    int iters = 0, restarts = 0, mvA = 0, mvE = 0, status = 0;
+    double relres_init = 0.0, relres_true = 0.0;
+    bool done = false;
+};
+
+struct Opts {
+    double tol;
+    int maxit;
+    int init;
+    int n_ritz;
+    int use_prev_k;
+    int use_prev_shift;
+    int split_I;
+    double gJL, gJR;
+};
+
+// Runs deflated CG from the current (x, r) of each listed system to the
+// recursive-residual tolerance.  Returns per-system kernel status.
+void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s)
+{
+    const int m = (int)sy.size();
+    if (m == 0) return;
+    if (m > MAXSYS) fail(RSR_E_ARG, "too many systems in one launch");
+    std::vector<SysDev> hd(m);
+    long tiles = 0;
+    for (int i = 0; i < m; ++i) {
+        SysHost &Y = *sy[i];
+        const InstDev &I = c->h_inst[Y.inst];
+        SysDev &d = hd[i];
+        memset(&d, 0, sizeof(d));
+        d.inst = Y.inst;
+        d.q = Y.q;
+        d.ntiles = I.nty * I.ntx;
+        d.tile_base = (int)tiles;
+        tiles += d.ntiles;
+        d.gamma = Y.gamma;
+        d.tolabs = o.tol * Y.bnorm;
+        d.x = Y.x;
+        d.r = Y.r;
+        d.p0 = Y.p0;
+        d.p1 = Y.p1;
+        d.w = Y.w;
+        d.W = Y.W;
+        d.Z = Y.Z;
+        d.ldw = Y.n;
+        for (int a = 0; a < Y.q; ++a)
+            for (int b2 = 0; b2 < Y.q; ++b2) d.Ginv[a * QMAX + b2] = Y.Ginv[a * Y.q + b2];
+    }
+    SysDev *dsys = upload(c, c->d_sys, hd, s);
+    c->d_partA.ensure(sizeof(double) * tiles);
+    c->d_partB.ensure(sizeof(double) * tiles * NVB);
+    c->d_ctl.ensure(64);
+    c->d_out.ensure((sizeof(int) * 2 + sizeof(double)) * m + 64);
+    HIPCHK(launch_fill(c->d_ctl.as<double>(), 0.0, 8, s));
+    int *out_iters = (int *)c->d_out.p;
+    int *out_status = out_iters + m;
+    double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
+    HIPCHK(hipMemsetAsync(c->d_out.p, 0, sizeof(int) * 2 * m, s));
+
+    const int tl = max_tile_lds(c);
+    const size_t lds = cg_lds_bytes(tl);
+    int bpc = cg_max_blocks_per_cu(lds);
+    if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
+    int G = std::min<long>((long)bpc * c->n_cu, 1024);
+    G = (int)std::min<long>(G, std::max<long>(8, tiles));
+    if (G >= 8) G -= G % 8;
+
+    CGArgs a;
+    a.nsys = m;
+    a.sys = dsys;
+    a.inst = c->d_inst.as<InstDev>();
+    a.partA = c->d_partA.as<double>();
+    a.partB = c->d_partB.as<double>();
+    a.bar = (unsigned long long *)c->d_ctl.p;
+    a.abort_flag = (int *)((char *)c->d_ctl.p + 16);
+    a.out_iters = out_iters;
+    a.out_status = out_status;
+    a.out_rho = out_rho;
+    a.maxit = o.maxit;
+    a.G = G;
+    a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * 30.0);   // 30 s
+    a.tile_lds = tl;
+    HIPCHK(hipEventRecord(c->ev0, s));
+    HIPCHK(launch_cg(a, G, lds, s, true));
+    HIPCHK(hipEventRecord(c->ev1, s));
+    std::vector<int> hi(2 * m + 8);
+    std::vector<double> hr(m);
+    int abort_h = 0;
+    HIPCHK(hipMemcpyAsync(hi.data(), out_iters, sizeof(int) * 2 * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hr.data(), out_rho, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&abort_h, a.abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_cg_ms += ms;
+    c->last_launches += 1;
+    if (abort_h) fail(RSR_E_TIMEOUT, "persistent CG barrier timed out");
+    for (int i = 0; i < m; ++i) {
+        SysHost &Y = *sy[i];
+        Y.iters += hi[i];
+        Y.mvA += hi[i];
+        Y.mvE += hi[i];
+        c->mv_A += hi[i];
+        c->mv_E += hi[i];
+        Y.status = hi[m + i];
+        c->last_items += (long)hi[i] * hd[i].ntiles;
+    }
+}
+
+// Galerkin correction with the local space: x += W y, r -= Z y, y = G^+ W^T r.
+void local_correction(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
+{
+    std::vector<GramJob> gj;
+    std::vector<SysHost *> act;
+    for (auto *Y : sy)
+        if (Y->q > 0) {
+            gj.push_back(GramJob{Y->W, Y->n, Y->q, Y->r, Y->n, 1, Y->n, nullptr, 0});
+            act.push_back(Y);
+        }
+    if (act.empty()) return;
+    auto cs = gram(c, gj, s);
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
+    for (size_t k = 0; k < act.size(); ++k) {
+        SysHost &Y = *act[k];
+        std::vector<double> y(Y.q), ny(Y.q);
+        matvec(Y.q, Y.q, Y.Ginv.data(), cs[k].data(), y.data());
+        for (int i = 0; i < Y.q; ++i) ny[i] = -y[i];
+        cj.push_back(ComboJob{Y.W, Y.n, Y.q, nullptr, Y.q, Y.x, Y.n, 1, 1.0, nullptr, 0, Y.n});
+        qs.push_back(y);
+        cj.push_back(ComboJob{Y.Z, Y.n, Y.q, nullptr, Y.q, Y.r, Y.n, 1, 1.0, nullptr, 0, Y.n});
+        qs.push_back(ny);
+    }
+    combo(c, cj, qs, s);
+}
+
+// Builds W, Z, G^+ for each system (Algorithms 2-4 in CG form).
+void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const double *g_prev_shift,
+                 hipStream_t s)
+{
+    // Ritz blocks per (instance, group)
+    struct Grp {
+        int inst;
+        double gJ;
+        int nr;
+        double *R;   // [nr][n], AR, ER follow
+    };
+    std::map<std::pair<int, int>, Grp> groups;
+    for (auto *Y : sy) {
+        Instance &I = *c->inst[Y->inst];
+        if (o.n_ritz <= 0 || I.p == 0 || !I.ae_valid) continue;
+        const int side = Y->slot < o.split_I ? 0 : 1;
+        auto key = std::make_pair(Y->inst, side);
+        if (groups.count(key)) continue;
+        groups[key] = Grp{Y->inst, side == 0 ? o.gJL : o.gJR, std::min(o.n_ritz, I.p), nullptr};
+    }
+    // workspace for Ritz blocks: 3 * nr columns per group
+    size_t need = 0;
+    for (auto &kv : groups) need += (size_t)3 * kv.second.nr * c->inst[kv.second.inst]->n;
+    c->d_tmp.ensure(sizeof(double) * std::max<size_t>(1, need));
+    size_t off = 0;
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
+    for (auto &kv : groups) {
+        Grp &g = kv.second;
+        Instance &I = *c->inst[g.inst];
+        const int p = I.p;
+        g.R = c->d_tmp.as<double>() + off;
+        off += (size_t)3 * g.nr * I.n;
+        std::vector<double> H((size_t)p * p), w, V;
+        for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + g.gJ * I.Ehat[k];
+        sym_eig(p, H.data(), w, V);
+        std::vector<double> Wt((size_t)p * g.nr);   // column-major p x nr
+        for (int j = 0; j < g.nr; ++j)
+            for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
+        cj.push_back(ComboJob{I.d_U.as<double>(), I.n, p, nullptr, p, g.R, I.n, g.nr, 0.0, nullptr, 0, I.n});
+        qs.push_back(Wt);
+        cj.push_back(ComboJob{I.d_AE.as<double>(), I.n, p, nullptr, p, g.R + (size_t)g.nr * I.n, I.n, g.nr, 0.0,
+                              nullptr, 0, I.n});
+        qs.push_back(Wt);
+        cj.push_back(ComboJob{I.d_AE.as<double>() + (size_t)p * I.n, I.n, p, nullptr, p,
+                              g.R + (size_t)2 * g.nr * I.n, I.n, g.nr, 0.0, nullptr, 0, I.n});
+        qs.push_back(Wt);
+    }
+    combo(c, cj, qs, s);
+    // assemble W, Z per system
+    std::vector<ApplyJob> aj;
+    cj.clear();
+    qs.clear();
+    for (auto *Yp : sy) {
+        SysHost &Y = *Yp;
+        Instance &I = *c->inst[Y.inst];
+        int q = 0;
+        const int side = Y.slot < o.split_I ? 0 : 1;
+        auto it = groups.find(std::make_pair(Y.inst, side));
+        if (it != groups.end()) {
+            Grp &g = it->second;
+            const int nr = std::min(g.nr, QMAX);
+            // W[:, 0:nr] = R ; Z[:, 0:nr] = AR + gamma ER
+            std::vector<double> id((size_t)nr * nr, 0.0), gid((size_t)2 * nr * nr, 0.0);
+            for (int j = 0; j < nr; ++j) id[(size_t)j * nr + j] = 1.0;
+            cj.push_back(ComboJob{g.R, I.n, nr, nullptr, nr, Y.W, Y.n, nr, 0.0, nullptr, 0, Y.n});
+            qs.push_back(id);
+            // [AR ER] (2nr columns, contiguous) times [I; gamma I]
+            for (int j = 0; j < nr; ++j) {
+                gid[(size_t)j * 2 * nr + j] = 1.0;
+                gid[(size_t)j * 2 * nr + nr + j] = Y.gamma;
+            }
+            cj.push_back(ComboJob{g.R + (size_t)g.nr * I.n, I.n, 2 * nr, nullptr, 2 * nr, Y.Z, Y.n, nr, 0.0, nullptr,
+                                  0, Y.n});
+            qs.push_back(gid);
+            q = nr;
+        }
+        // previous corrections
+        std::vector<const double *> gcols;
+        if (o.use_prev_k) {
+            auto gi = I.gstore.find(Y.slot);
+            if (gi != I.gstore.end() && gi->second && gi->second->p) gcols.push_back(gi->second->as<double>());
+        }
+        if (o.use_prev_shift && g_prev_shift) gcols.push_back(g_prev_shift);
+        for (const double *gv : gcols) {
+            if (q >= QMAX) break;
+            HIPCHK(hipMemcpyAsync(Y.W + (size_t)q * Y.n, gv, sizeof(double) * Y.n, hipMemcpyDeviceToDevice, s));
+            aj.push_back(ApplyJob{Y.inst, 0, 1.0, Y.gamma, Y.W + (size_t)q * Y.n, Y.Z + (size_t)q * Y.n});
+            Y.mvA += 1;
+            Y.mvE += 1;
+            ++q;
+        }
+        Y.q = q;
+    }
+    combo(c, cj, qs, s);
+    apply_jobs(c, aj, s);
+    // angle check between the two correction columns and G = W^T Z
+    std::vector<GramJob> gj;
+    std::vector<SysHost *> act;
+    for (auto *Y : sy)
+        if (Y->q > 0) {
+            gj.push_back(GramJob{Y->W, Y->n, Y->q, Y->Z, Y->n, Y->q, Y->n, nullptr, 0});
+            gj.push_back(GramJob{Y->W, Y->n, Y->q, Y->W, Y->n, Y->q, Y->n, nullptr, 0});
+            act.push_back(Y);
+        }
+    auto G = gram(c, gj, s);
+    for (size_t k = 0; k < act.size(); ++k) {
+        SysHost &Y = *act[k];
+        std::vector<double> Gm = G[2 * k], WW = G[2 * k + 1];
+        const int q = Y.q;
+        // symmetrise W^T Z (B symmetric)
+        for (int i = 0; i < q; ++i)
+            for (int j = i + 1; j < q; ++j) {
+                const double v = 0.5 * (Gm[i * q + j] + Gm[j * q + i]);
+                Gm[i * q + j] = Gm[j * q + i] = v;
+            }
+        // drop the later of two nearly parallel columns (|cos| > 0.99), footnote of Sec. 5.3
+        std::vector<int> keep(q, 1);
+        for (int i = 0; i < q; ++i)
+            for (int j = i + 1; j < q; ++j) {
+                const double den = std::sqrt(WW[i * q + i] * WW[j * q + j]);
+                if (keep[i] && keep[j] && den > 0 && std::fabs(WW[i * q + j]) > 0.99 * den) keep[j] = 0;
+            }
+        for (int i = 0; i < q; ++i)
+            if (!keep[i])
+                for (int j = 0; j < q; ++j) Gm[i * q + j] = Gm[j * q + i] = 0.0;
+        spd_pinv(q, Gm.data(), 1e-12, Y.Ginv);
+    }
+}
+
+// ------------------------------------------------------------- solving --
+void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const double *g_prev_shift,
+                 hipStream_t s)
+{
+    // b norms
+    {
+        std::vector<const double *> v;
+        std::vector<long> n;
+        for (auto *Y : sy) { v.push_back(Y->b); n.push_back(Y->n); }
+        auto bn = norms(c, v, n, s);
+        for (size_t i = 0; i < sy.size(); ++i) sy[i]->bnorm = bn[i];
+    }
+    // initial guess
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
+    std::vector<ApplyJob> aj;
+    std::vector<SysHost *> need_r;   // r = b - B x
+    for (auto *Yp : sy) {
+        SysHost &Y = *Yp;
+        Instance &I = *c->inst[Y.inst];
+        int init = o.init;
+        if ((init == RSR_INIT_MR || init == RSR_INIT_GALERKIN) && (I.p == 0 || !I.ae_valid)) init = RSR_INIT_ZERO;
+        if (init == RSR_INIT_ZERO) {
+            HIPCHK(launch_fill(Y.x, 0.0, Y.n, s));
+            HIPCHK(hipMemcpyAsync(Y.r, Y.b, sizeof(double) * Y.n, hipMemcpyDeviceToDevice, s));
+        } else if (init == RSR_INIT_GIVEN) {
+            aj.push_back(ApplyJob{Y.inst, 0, 1.0, Y.gamma, Y.x, Y.r});
+            Y.mvA++;
+            Y.mvE++;
+            need_r.push_back(&Y);
+        }
+    }
+    apply_jobs(c, aj, s);
+    for (auto *Y : need_r) {
+        std::vector<double> one{-1.0};
+        cj.push_back(ComboJob{Y->r, Y->n, 1, nullptr, 1, Y->r, Y->n, 1, 0.0, Y->b, Y->n, Y->n});
+        qs.push_back(one);
+    }
+    combo(c, cj, qs, s);
+    cj.clear();
+    qs.clear();
+    // principal-space guesses (one small solve per shift, Section 4.1)
+    std::vector<GramJob> gj;
+    std::vector<SysHost *> prin;
+    for (auto *Yp : sy) {
+        SysHost &Y = *Yp;
+        Instance &I = *c->inst[Y.inst];
+        if (!((o.init == RSR_INIT_MR || o.init == RSR_INIT_GALERKIN) && I.p > 0 && I.ae_valid)) continue;
+        prin.push_back(&Y);
+        if (o.init == RSR_INIT_MR)
+            gj.push_back(GramJob{I.d_AE.as<double>(), I.n, 2 * I.p, Y.b, Y.n, 1, Y.n, nullptr, 0});
+        else
+            gj.push_back(GramJob{I.d_U.as<double>(), I.n, I.p, Y.b, Y.n, 1, Y.n, nullptr, 0});
+    }
+    if (!prin.empty()) {
+        auto rhs = gram(c, gj, s);
+        for (size_t k = 0; k < prin.size(); ++k) {
+            SysHost &Y = *prin[k];
+            Instance &I = *c->inst[Y.inst];
+            const int p = I.p;
+            const double g = Y.gamma;
+            std::vector<double> H((size_t)p * p), f(p), q(p), P;
+            if (o.init == RSR_INIT_MR) {
+                // (AU + g EU)^T (AU + g EU) q = (AU + g EU)^T b
+                for (int i = 0; i < p; ++i)
+                    for (int j = 0; j < p; ++j)
+                        H[(size_t)i * p + j] = I.Gaa[(size_t)i * p + j] + g * (I.Gae[(size_t)i * p + j] + I.Gae[(size_t)j * p + i]) +
+                                               g * g * I.Gee[(size_t)i * p + j];
+                for (int i = 0; i < p; ++i) f[i] = rhs[k][i] + g * rhs[k][p + i];
+                spd_pinv(p, H.data(), 1e-15, P);
+            } else {
+                for (size_t t = 0; t < H.size(); ++t) H[t] = I.Ahat[t] + g * I.Ehat[t];
+                for (int i = 0; i < p; ++i) f[i] = rhs[k][i];
+                spd_pinv(p, H.data(), 1e-15, P);
+            }
+            matvec(p, p, P.data(), f.data(), q.data());
+            // x = U q ; r = b - [AU EU] [q; g q]
+            cj.push_back(ComboJob{I.d_U.as<double>(), I.n, p, nullptr, p, Y.x, Y.n, 1, 0.0, nullptr, 0, Y.n});
+            qs.push_back(q);
+            std::vector<double> q2(2 * p);
+            for (int i = 0; i < p; ++i) { q2[i] = -q[i]; q2[p + i] = -g * q[i]; }
+            cj.push_back(ComboJob{I.d_AE.as<double>(), I.n, 2 * p, nullptr, 2 * p, Y.r, Y.n, 1, 0.0, Y.b, Y.n, Y.n});
+            qs.push_back(q2);
+        }
+        combo(c, cj, qs, s);
+    }
+    // keep x_init for the correction g = x - x_init
+    for (auto *Y : sy) HIPCHK(hipMemcpyAsync(Y->xinit, Y->x, sizeof(double) * Y->n, hipMemcpyDeviceToDevice, s));
+    {
+        std::vector<const double *> v;
+        std::vector<long> n;
+        for (auto *Y : sy) { v.push_back(Y->r); n.push_back(Y->n); }
+        auto rn = norms(c, v, n, s);
+        for (size_t i = 0; i < sy.size(); ++i)
+            sy[i]->relres_init = sy[i]->bnorm > 0 ? rn[i] / sy[i]->bnorm : 0.0;
+    }
+    // local spaces and Galerkin correction
+    build_local(c, sy, o, g_prev_shift, s);
+    local_correction(c, sy, s);
+
+    // CG with true-residual acceptance
+    std::vector<SysHost *> todo;
+    for (auto *Y : sy) {
+        if (Y->bnorm == 0.0) {
+            HIPCHK(launch_fill(Y->x, 0.0, Y->n, s));
+            Y->done = true;
+            Y->status = 1;
+            Y->relres_true = 0.0;
+        } else {
+            todo.push_back(Y);
+        }
+    }
+    for (int attempt = 0; attempt <= 3 && !todo.empty(); ++attempt) {
+        Opts oo = o;
+        run_cg(c, todo, oo, s);
+        // true residual rt = b - B x
+        std::vector<ApplyJob> tj;
+        for (auto *Y : todo) {
+            tj.push_back(ApplyJob{Y->inst, 0, 1.0, Y->gamma, Y->x, Y->rt});
+            Y->mvA++;
+            Y->mvE++;
+        }
+        apply_jobs(c, tj, s);
+        std::vector<ComboJob> rj;
+        std::vector<std::vector<double>> rq;
+        for (auto *Y : todo) {
+            rj.push_back(ComboJob{Y->rt, Y->n, 1, nullptr, 1, Y->rt, Y->n, 1, 0.0, Y->b, Y->n, Y->n});
+            rq.push_back(std::vector<double>{-1.0});
+        }
+        combo(c, rj, rq, s);
+        std::vector<const double *> v;
+        std::vector<long> n;
+        for (auto *Y : todo) { v.push_back(Y->rt); n.push_back(Y->n); }
+        auto rn = norms(c, v, n, s);
+        std::vector<SysHost *> again;
+        for (size_t i = 0; i < todo.size(); ++i) {
+            SysHost &Y = *todo[i];
+            Y.relres_true = rn[i] / Y.bnorm;
+            if (Y.status < 0) fail((rsr_status)Y.status, Y.status == -4 ? "shifted matrix not SPD (p^T B p <= 0)"
+                                                                         : "non-finite value in CG");
+            if (Y.relres_true <= o.tol || Y.status == 2 || attempt == 3 || !std::isfinite(Y.relres_true)) {
+                Y.done = true;
+                if (!std::isfinite(Y.relres_true)) fail(RSR_E_NONFINITE, "non-finite residual");
+            } else {
+                // restart from the true residual
+                HIPCHK(hipMemcpyAsync(Y.r, Y.rt, sizeof(double) * Y.n, hipMemcpyDeviceToDevice, s));
+                Y.restarts++;
+                again.push_back(&Y);
+            }
+        }
+        if (!again.empty()) local_correction(c, again, s);
+        todo.swap(again);
+    }
+}
+
+void store_corrections(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
+{
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
+    for (auto *Y : sy) {
+        Instance &I = *c->inst[Y->inst];
+        auto &slot = I.gstore[Y->slot];
+        if (!slot) slot.reset(new DBuf());
+        slot->ensure(sizeof(double) * Y->n);
+        // g = x - xinit
+        cj.push_back(ComboJob{Y->xinit, Y->n, 1, nullptr, 1, slot->as<double>(), Y->n, 1, 0.0, Y->x, Y->n, Y->n});
+        qs.push_back(std::vector<double>{-1.0});
+    }
+    combo(c, cj, qs, s);
+}
+
+void alloc_ws(rsr_ctx *c, std::vector<SysHost> &sys)
+{
+    // per system: r p0 p1 w xinit rt + W, Z (QMAX each)
+    size_t tot = 0;
+    for (auto &Y : sys) tot += (size_t)Y.n * (6 + 2 * QMAX) + 32;
+    c->d_ws.ensure(sizeof(double) * tot);
+    double *p = c->d_ws.as<double>();
+    for (auto &Y : sys) {
+        const long n = Y.n;
+        Y.r = p; p += n;
+        Y.p0 = p; p += n;
+        Y.p1 = p; p += n;
+        Y.w = p; p += n;
+        Y.xinit = p; p += n;
+        Y.rt = p; p += n;
+        Y.W = p; p += n * QMAX;
+        Y.Z = p; p += n * QMAX;
+        p += 32 - ((uintptr_t)p / 8) % 32;   // keep 256-byte alignment
+    }
+}
+
+}  // namespace
+
+// ================================================================ C ABI ==
+namespace {
+rsr_status guard(rsr_ctx *c, const std::function<void()> &f)
+{
+    if (!c) return RSR_E_ARG;
+    try {
+        c->err.clear();
+        f();
+        return RSR_OK;
+    } catch (const Err &e) {
+        c->err = e.msg;
+        return e.st;
+    } catch (const std::exception &e) {
+        c->err = e.what();
+        return RSR_E_ARG;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+const char *rsr_version(void) { return "rsr 0.1 gfx950 fp64"; }
+
+rsr_status rsr_create(rsr_ctx **out, int dev)
+{
+    if (!out) return RSR_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return RSR_E_HIP;
+    if (dev < 0 || dev >= ndev) return RSR_E_ARG;
+    rsr_ctx *c = new rsr_ctx();
+    c->dev = dev;
+    rsr_status st = guard(c, [&] {
+        set_device(c);
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        c->n_cu = prop.multiProcessorCount;
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            c->wall_khz = khz;
+        HIPCHK(hipEventCreate(&c->ev0));
+        HIPCHK(hipEventCreate(&c->ev1));
+    });
+    if (st != RSR_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return RSR_OK;
+}
+
+void rsr_destroy(rsr_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->dev);
+    (void)hipDeviceSynchronize();
+    for (auto &p : c->inst) {
+        Instance &I = *p;
+        I.d_fy.release(); I.d_fx.release(); I.d_psf.release(); I.d_wh.release(); I.d_wv.release();
+        I.d_U.release(); I.d_AE.release();
+        for (auto &g : I.gstore) if (g.second) g.second->release();
+    }
+    for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
+                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp})
+        b->release();
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+const char *rsr_last_error(const rsr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, void *stream)
+{
+    return guard(c, [&] {
+        if (n_inst <= 0 || !in) fail(RSR_E_ARG, "n_inst must be positive");
+        for (int i = 0; i < n_inst; ++i) {
+            const rsr_instance &r = in[i];
+            if (r.ny <= 0 || r.nx <= 0 || r.sy <= 0 || r.sx <= 0 || !(r.sy & 1) || !(r.sx & 1) || !r.psf_host)
+                fail(RSR_E_ARG, "instance " + std::to_string(i) + ": sizes must be positive and the PSF odd");
+            if (r.sy > 63 || r.sx > 63) fail(RSR_E_ARG, "PSF larger than 63 x 63");
+            for (int k = 0; k < r.sy * r.sx; ++k)
+                if (!std::isfinite(r.psf_host[k])) fail(RSR_E_NONFINITE, "non-finite PSF entry");
+        }
+        set_device(c);
+        hipStream_t s = S(stream);
+        HIPCHK(hipStreamSynchronize(s));
+        for (auto &p : c->inst) {
+            p->d_fy.release(); p->d_fx.release(); p->d_psf.release(); p->d_wh.release(); p->d_wv.release();
+            p->d_U.release(); p->d_AE.release();
+        }
+        c->inst.clear();
+        for (int i = 0; i < n_inst; ++i) {
+            std::unique_ptr<Instance> I(new Instance());
+            const rsr_instance &r = in[i];
+            I->ny = r.ny; I->nx = r.nx; I->sy = r.sy; I->sx = r.sx;
+            I->n = (long)r.ny * r.nx;
+            I->psf.assign(r.psf_host, r.psf_host + r.sy * r.sx);
+            factor_psf(*I);
+            default_tile(*I);
+            I->d_psf.ensure(sizeof(double) * I->psf.size());
+            HIPCHK(hipMemcpy(I->d_psf.p, I->psf.data(), sizeof(double) * I->psf.size(), hipMemcpyHostToDevice));
+            if (I->sep) {
+                I->d_fy.ensure(sizeof(double) * I->sy);
+                I->d_fx.ensure(sizeof(double) * I->sx);
+                HIPCHK(hipMemcpy(I->d_fy.p, I->fy.data(), sizeof(double) * I->sy, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(I->d_fx.p, I->fx.data(), sizeof(double) * I->sx, hipMemcpyHostToDevice));
+            }
+            I->d_wh.ensure(sizeof(double) * I->n);
+            I->d_wv.ensure(sizeof(double) * I->n);
+            HIPCHK(launch_copy_weights(nullptr, nullptr, I->d_wh.as<double>(), I->d_wv.as<double>(), I->ny, I->nx, s));
+            c->inst.push_back(std::move(I));
+        }
+        upload_inst(c);
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
+
+rsr_status rsr_update_weights(rsr_ctx *c, int ii, const double *wh, const double *wv, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (!wh || !wv) fail(RSR_E_ARG, "null weights");
+        set_device(c);
+        HIPCHK(launch_copy_weights(wh, wv, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny, I.nx, S(stream)));
+        I.ae_valid = false;
+    });
+}
+
+rsr_status rsr_weights_from_image(rsr_ctx *c, int ii, const double *x, double beta, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (!x) fail(RSR_E_ARG, "null image");
+        if (!(beta > 0.0) || !std::isfinite(beta)) fail(RSR_E_ARG, "beta must be positive");
+        set_device(c);
+        HIPCHK(launch_weights(x, beta, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny, I.nx, S(stream)));
+        I.ae_valid = false;
+    });
+}
+
+rsr_status rsr_get_weights(rsr_ctx *c, int ii, double *wh, double *wv, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        set_device(c);
+        if (wh) HIPCHK(hipMemcpyAsync(wh, I.d_wh.p, sizeof(double) * I.n, hipMemcpyDeviceToDevice, S(stream)));
+        if (wv) HIPCHK(hipMemcpyAsync(wv, I.d_wv.p, sizeof(double) * I.n, hipMemcpyDeviceToDevice, S(stream)));
+    });
+}
+
+rsr_status rsr_apply(rsr_ctx *c, int ii, int op, double gamma, const double *v, double *y, int n_vec, long ld,
+                     void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (!v || !y || n_vec <= 0) fail(RSR_E_ARG, "null vectors or n_vec <= 0");
+        if (n_vec > 1 && ld < I.n) fail(RSR_E_ARG, "ld smaller than ny*nx");
+        if (!std::isfinite(gamma)) fail(RSR_E_ARG, "gamma not finite");
+        if (ld <= 0) ld = I.n;
+        set_device(c);
+        hipStream_t s = S(stream);
+        if (op == RSR_OP_K || op == RSR_OP_KT) {
+            std::vector<ApplyJob> jobs(n_vec);
+            for (int j = 0; j < n_vec; ++j) jobs[j] = ApplyJob{ii, op, 0.0, 0.0, v + j * ld, y + j * ld};
+            ApplyJob *dj = upload(c, c->d_jobs, jobs, s);
+            HIPCHK(launch_blur(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, n_vec, s));
+            HIPCHK(hipStreamSynchronize(s));
+            return;
+        }
+        double cA = 0.0, cE = 0.0;
+        if (op == RSR_OP_B) { cA = 1.0; cE = gamma; }
+        else if (op == RSR_OP_A) cA = 1.0;
+        else if (op == RSR_OP_E) cE = 1.0;
+        else fail(RSR_E_ARG, "unknown operator");
+        apply_op(c, ii, cA, cE, v, ld, y, ld, n_vec, s);
+    });
+}
+
+rsr_status rsr_set_recycle_space(rsr_ctx *c, int ii, const double *U_raw, long ld, int ncols, int n_retain,
+                                 double gamma_retain, int p_max, double cond_max, int *p_kept, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (ncols < 0 || n_retain < 0 || p_max < 0) fail(RSR_E_ARG, "negative sizes");
+        if (ncols > 0 && (!U_raw || ld < I.n)) fail(RSR_E_ARG, "U_raw null or ld < ny*nx");
+        if (!(cond_max > 1.0)) fail(RSR_E_ARG, "cond_max must exceed 1");
+        set_device(c);
+        hipStream_t s = S(stream);
+        const long n = I.n;
+        const int nr = std::min(n_retain, I.p);
+        const int m = nr + ncols;
+        if (p_kept) *p_kept = 0;
+        if (m == 0 || p_max == 0) {
+            I.p = 0;
+            I.ae_valid = false;
+            return;
+        }
+        // candidate block C = [U W~(:, 1:nr), U_raw]
+        DBuf Cb;
+        Cb.ensure(sizeof(double) * (size_t)m * n);
+        double *C = Cb.as<double>();
+        if (nr > 0) {
+            const int p = I.p;
+            std::vector<double> H((size_t)p * p), w, V;
+            for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + gamma_retain * I.Ehat[k];
+            sym_eig(p, H.data(), w, V);
+            std::vector<double> Wt((size_t)p * nr);
+            for (int j = 0; j < nr; ++j)
+                for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
+            combo(c, {ComboJob{I.d_U.as<double>(), n, p, nullptr, p, C, n, nr, 0.0, nullptr, 0, n}}, {Wt}, s);
+        }
+        for (int j = 0; j < ncols; ++j)
+            HIPCHK(hipMemcpyAsync(C + (size_t)(nr + j) * n, U_raw + (size_t)j * ld, sizeof(double) * n,
+                                  hipMemcpyDeviceToDevice, s));
+        // Algorithm 1 through the Gram matrix: C^T C = V diag(sigma^2) V^T,
+        // keep sigma_1 / sigma_i < cond_max (and above the FP64 resolution of
+        // the Gram route), Q = C V_k diag(1/sigma_k); a second pass restores
+        // orthonormality to rounding level.
+        DBuf Qb;
+        Qb.ensure(sizeof(double) * (size_t)m * n);
+        double *Q = Qb.as<double>();
+        int keep = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            const double *X = pass == 0 ? C : Q;
+            const int mm = pass == 0 ? m : keep;
+            auto Gm = gram(c, {GramJob{X, n, mm, X, n, mm, n, nullptr, 0}}, s)[0];
+            std::vector<double> w, V;
+            sym_eig(mm, Gm.data(), w, V);
+            const double lmax = w.empty() ? 0.0 : w.back();
+            if (!(lmax > 0.0) || !std::isfinite(lmax)) fail(RSR_E_RANK, "recycle candidates are zero or non-finite");
+            std::vector<int> idx;
+            for (int k = mm - 1; k >= 0; --k) {
+                const double lam = w[k];
+                const bool ok = pass == 0 ? (lam > lmax / (cond_max * cond_max) && lam > lmax * 1e-14) : lam > 0.0;
+                if (ok) idx.push_back(k);
+            }
+            if (pass == 0 && (int)idx.size() > p_max) idx.resize(p_max);
+            keep = (int)idx.size();
+            if (keep == 0) fail(RSR_E_RANK, "recycle space empty after stabilisation");
+            std::vector<double> T((size_t)mm * keep);   // column-major mm x keep
+            for (int j = 0; j < keep; ++j) {
+                const double sc = 1.0 / std::sqrt(w[idx[j]]);
+                for (int i = 0; i < mm; ++i) T[(size_t)j * mm + i] = V[(size_t)i * mm + idx[j]] * sc;
+            }
+            if (pass == 0) {
+                combo(c, {ComboJob{C, n, mm, nullptr, mm, Q, n, keep, 0.0, nullptr, 0, n}}, {T}, s);
+            } else {
+                I.d_U.ensure(sizeof(double) * (size_t)keep * n);
+                combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {T}, s);
+            }
+        }
+        const int p = keep;
+        I.p = p;
+        // A U and E U (p applications each), then the small blocks
+        I.d_AE.ensure(sizeof(double) * (size_t)2 * p * n);
+        double *AU = I.d_AE.as<double>(), *EU = AU + (size_t)p * n;
+        apply_op(c, ii, 1.0, 0.0, I.d_U.as<double>(), n, AU, n, p, s);
+        apply_op(c, ii, 0.0, 1.0, I.d_U.as<double>(), n, EU, n, p, s);
+        auto blocks = gram(c,
+                           {GramJob{I.d_U.as<double>(), n, p, AU, n, p, n, nullptr, 0},
+                            GramJob{I.d_U.as<double>(), n, p, EU, n, p, n, nullptr, 0},
+                            GramJob{AU, n, p, AU, n, p, n, nullptr, 0}, GramJob{AU, n, p, EU, n, p, n, nullptr, 0},
+                            GramJob{EU, n, p, EU, n, p, n, nullptr, 0}},
+                           s);
+        auto sym = [p](std::vector<double> M) {
+            for (int i = 0; i < p; ++i)
+                for (int j = i + 1; j < p; ++j) {
+                    const double v = 0.5 * (M[(size_t)i * p + j] + M[(size_t)j * p + i]);
+                    M[(size_t)i * p + j] = M[(size_t)j * p + i] = v;
+                }
+            return M;
+        };
+        I.Ahat = sym(blocks[0]);
+        I.Ehat = sym(blocks[1]);
+        I.Gaa = sym(blocks[2]);
+        I.Gae = blocks[3];
+        I.Gee = sym(blocks[4]);
+        I.ae_valid = true;
+        if (p_kept) *p_kept = p;
+        Cb.release();
+        Qb.release();
+    });
+}
+
+rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X,
+                               rsr_shift_stats *stats, void *stream)
+{
+    return guard(c, [&] {
+        if (!d || !b || !X) fail(RSR_E_ARG, "null descriptor, b or X");
+        if (c->inst.empty()) fail(RSR_E_STATE, "operators not set");
+        const int m = d->n_sys;
+        if (m <= 0 || !d->inst || !d->gammas) fail(RSR_E_ARG, "n_sys must be positive with inst and gammas");
+        if (!(d->tol > 0.0)) fail(RSR_E_ARG, "tol must be positive");
+        if (d->init < 0 || d->init > 3) fail(RSR_E_ARG, "unknown init");
+        if (d->n_ritz < 0 || d->n_ritz > QMAX) fail(RSR_E_ARG, "n_ritz out of range");
+        if (d->mode != RSR_BATCHED && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "unknown mode");
+        std::vector<SysHost> sys(m);
+        for (int i = 0; i < m; ++i) {
+            Instance &I = get_inst(c, d->inst[i]);
+            if (!(d->gammas[i] >= 0.0) || !std::isfinite(d->gammas[i])) fail(RSR_E_ARG, "gamma must be >= 0");
+            if (m > 1 && d->ld_x < I.n) fail(RSR_E_ARG, "ld_x smaller than ny*nx");
+            if (d->ld_b != 0 && d->ld_b < I.n) fail(RSR_E_ARG, "ld_b smaller than ny*nx");
+            SysHost &Y = sys[i];
+            Y.inst = d->inst[i];
+            Y.slot = d->slot ? d->slot[i] : i;
+            Y.gamma = d->gammas[i];
+            Y.n = I.n;
+            Y.b = b + (size_t)i * d->ld_b;
+            Y.x = X + (size_t)i * d->ld_x;
+        }
+        set_device(c);
+        hipStream_t s = S(stream);
+        alloc_ws(c, sys);
+        Opts o{d->tol, d->maxit, d->init, d->n_ritz, d->use_prev_k, d->use_prev_shift, d->split_I, d->gamma_JL,
+               d->gamma_JR};
+        c->last_cg_ms = 0.0;
+        c->last_launches = 0;
+        c->last_items = 0;
+        long maxn = 0;
+        for (auto &Y : sys) maxn = std::max(maxn, Y.n);
+        if (o.maxit <= 0) o.maxit = (int)std::min<long>(10 * maxn, 1 << 30);
+        if (d->mode == RSR_BATCHED) {
+            for (int i0 = 0; i0 < m; i0 += MAXSYS) {
+                std::vector<SysHost *> grp;
+                for (int i = i0; i < std::min(m, i0 + MAXSYS); ++i) grp.push_back(&sys[i]);
+                solve_group(c, grp, o, nullptr, s);
+                store_corrections(c, grp, s);
+            }
+        } else {
+            DBuf gprev;
+            const double *gp = nullptr;
+            for (int i = 0; i < m; ++i) {
+                std::vector<SysHost *> one{&sys[i]};
+                if (i > 0 && sys[i].inst != sys[i - 1].inst) gp = nullptr;
+                solve_group(c, one, o, o.use_prev_shift ? gp : nullptr, s);
+                store_corrections(c, one, s);
+                if (o.use_prev_shift) {
+                    Instance &I = *c->inst[sys[i].inst];
+                    gprev.ensure(sizeof(double) * I.n);
+                    HIPCHK(hipMemcpyAsync(gprev.p, I.gstore[sys[i].slot]->p, sizeof(double) * I.n,
+                                          hipMemcpyDeviceToDevice, s));
+                    gp = gprev.as<double>();
+                }
+            }
+            HIPCHK(hipStreamSynchronize(s));
+            gprev.release();
+        }
+        bool all = true;
+        for (int i = 0; i < m; ++i) {
+            SysHost &Y = sys[i];
+            const bool conv = Y.relres_true <= d->tol;
+            all = all && conv;
+            if (stats) {
+                rsr_shift_stats &t = stats[i];
+                t.iters = Y.iters;
+                t.matvec_A = Y.mvA;
+                t.matvec_E = Y.mvE;
+                t.converged = conv ? 1 : 0;
+                t.restarts = Y.restarts;
+                t.local_dim = Y.q;
+                t.relres_init = Y.relres_init;
+                t.relres_true = Y.relres_true;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        if (!all) throw Err{RSR_NOT_CONVERGED, "some systems did not reach tol"};
+    });
+}
+
+rsr_status rsr_adjoint(rsr_ctx *c, const rsr_solve_desc *d, const double *X, const double *Gbar, double *Lambda,
+                       double *dgamma_host, double *dw_h, double *dw_v, rsr_shift_stats *stats, void *stream)
+{
+    if (!c) return RSR_E_ARG;
+    if (!d || !X || !Gbar || !Lambda) {
+        c->err = "null argument";
+        return RSR_E_ARG;
+    }
+    // B_l lambda_l = Gbar_l with the same recycled solver (B_l symmetric); the
+    // adjoint slots are offset so the forward corrections are kept.
+    rsr_solve_desc ad = *d;
+    std::vector<int> slots(d->n_sys);
+    for (int i = 0; i < d->n_sys; ++i) slots[i] = (d->slot ? d->slot[i] : i) + (1 << 20);
+    ad.slot = slots.data();
+    ad.ld_b = d->ld_x;
+    if (ad.init == RSR_INIT_GIVEN) ad.init = RSR_INIT_ZERO;
+    rsr_status st = rsr_solve_shift_set(c, &ad, Gbar, Lambda, stats, stream);
+    if (st < 0) return st;
+    rsr_status st2 = guard(c, [&] {
+        const int m = d->n_sys;
+        const int ii = d->inst[0];
+        for (int i = 1; i < m; ++i)
+            if (d->inst[i] != ii) fail(RSR_E_ARG, "adjoint expects one instance");
+        Instance &I = get_inst(c, ii);
+        hipStream_t s = S(stream);
+        set_device(c);
+        const int nch = 512;
+        DBuf dg, gam;
+        dg.ensure(sizeof(double) * (size_t)nch * m);
+        gam.ensure(sizeof(double) * m);
+        HIPCHK(hipMemcpyAsync(gam.p, d->gammas, sizeof(double) * m, hipMemcpyHostToDevice, s));
+        DBuf tmpw;
+        double *wh = dw_h, *wv = dw_v;
+        if (!wh || !wv) {
+            tmpw.ensure(sizeof(double) * 2 * I.n);
+            wh = tmpw.as<double>();
+            wv = wh + I.n;
+        }
+        HIPCHK(launch_grad(X, Lambda, d->ld_x, gam.as<double>(), m, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny,
+                           I.nx, wh, wv, dg.as<double>(), nch, s));
+        std::vector<double> h((size_t)nch * m);
+        HIPCHK(hipMemcpyAsync(h.data(), dg.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (dgamma_host)
+            for (int l = 0; l < m; ++l) {
+                double sm = 0.0;
+                for (int k = 0; k < nch; ++k) sm += h[(size_t)k * m + l];
+                dgamma_host[l] = sm;
+            }
+        dg.release();
+        gam.release();
+        tmpw.release();
+    });
+    if (st2 != RSR_OK) return st2;
+    return st;
+}
+
+rsr_status rsr_get_tile(const rsr_ctx *c, int ii, int *ty, int *tx)
+{
+    if (!c || ii < 0 || ii >= (int)c->inst.size()) return RSR_E_ARG;
+    if (ty) *ty = c->inst[ii]->ty;
+    if (tx) *tx = c->inst[ii]->tx;
+    return RSR_OK;
+}
+
+rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (ty < 4 || tx < 4 || ty > 128 || tx > 128) fail(RSR_E_ARG, "tile sides must be in [4, 128]");
+        const int tl = tile_lds_doubles(ty, tx, I.sy, I.sx);
+        if (cg_lds_bytes(tl) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
+        set_device(c);
+        I.ty = ty;
+        I.tx = tx;
+        upload_inst(c);
+    });
+}
+
+rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (n_vec <= 0) n_vec = 1;
+        set_device(c);
+        std::ostringstream key;
+        key << "gfx950 " << I.ny << " " << I.nx << " " << I.sy << " " << I.sx << " " << n_vec;
+        if (cache_path) {
+            std::ifstream f(cache_path);
+            std::string line;
+            while (std::getline(f, line)) {
+                if (line.rfind(key.str() + " ->", 0) == 0) {
+                    int ty = 0, tx = 0;
+                    if (sscanf(line.c_str() + key.str().size() + 3, "%d %d", &ty, &tx) == 2) {
+                        I.ty = ty;
+                        I.tx = tx;
+                        upload_inst(c);
+                        return;
+                    }
+                }
+            }
+        }
+        const long n = I.n;
+        DBuf v, y;
+        v.ensure(sizeof(double) * n * n_vec);
+        y.ensure(sizeof(double) * n * n_vec);
+        hipStream_t s = nullptr;
+        HIPCHK(launch_fill(v.as<double>(), 1.0, n * n_vec, s));
+        const int cand[][2] = {{8, 32}, {16, 16}, {16, 32}, {32, 16}, {32, 32}, {16, 64}, {32, 64}, {64, 32}, {64, 64}};
+        double best = 1e30;
+        int bty = I.ty, btx = I.tx;
+        const long mvA = c->mv_A, mvE = c->mv_E;
+        for (auto &cd : cand) {
+            const int tl = tile_lds_doubles(cd[0], cd[1], I.sy, I.sx);
+            if (cg_lds_bytes(tl) > 160 * 1024) continue;
+            I.ty = cd[0];
+            I.tx = cd[1];
+            upload_inst(c);
+            std::vector<ApplyJob> jobs(n_vec);
+            for (int j = 0; j < n_vec; ++j) jobs[j] = ApplyJob{ii, 0, 1.0, 0.5, v.as<double>() + j * n, y.as<double>() + j * n};
+            ApplyJob *dj = upload(c, c->d_jobs, jobs, s);
+            const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, I.sy, I.sx);
+            HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, n_vec, lds, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const int reps = 5;
+            HIPCHK(hipEventRecord(c->ev0, s));
+            for (int r = 0; r < reps; ++r)
+                HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, n_vec, lds, s));
+            HIPCHK(hipEventRecord(c->ev1, s));
+            HIPCHK(hipEventSynchronize(c->ev1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            if (ms < best) {
+                best = ms;
+                bty = cd[0];
+                btx = cd[1];
+            }
+        }
+        c->mv_A = mvA;
+        c->mv_E = mvE;
+        I.ty = bty;
+        I.tx = btx;
+        upload_inst(c);
+        v.release();
+        y.release();
+        if (cache_path) {
+            std::ofstream f(cache_path, std::ios::app);
+            f << key.str() << " -> " << bty << " " << btx << "\n";
+        }
+    });
+}
+
+rsr_status rsr_get_recycle_info(const rsr_ctx *c, int ii, int *p, double *Ahat, double *Ehat)
+{
+    if (!c || ii < 0 || ii >= (int)c->inst.size()) return RSR_E_ARG;
+    const Instance &I = *c->inst[ii];
+    if (p) *p = I.p;
+    if (Ahat && !I.Ahat.empty()) memcpy(Ahat, I.Ahat.data(), sizeof(double) * I.p * I.p);
+    if (Ehat && !I.Ehat.empty()) memcpy(Ehat, I.Ehat.data(), sizeof(double) * I.p * I.p);
+    return RSR_OK;
+}
+
+rsr_status rsr_get_recycle_basis(rsr_ctx *c, int ii, double *U_out, long ld, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (I.p > 0 && (!U_out || ld < I.n)) fail(RSR_E_ARG, "null output or ld < ny*nx");
+        set_device(c);
+        for (int j = 0; j < I.p; ++j)
+            HIPCHK(hipMemcpyAsync(U_out + (size_t)j * ld, I.d_U.as<double>() + (size_t)j * I.n, sizeof(double) * I.n,
+                                  hipMemcpyDeviceToDevice, S(stream)));
+        HIPCHK(hipStreamSynchronize(S(stream)));
+    });
+}
+
+rsr_status rsr_last_solve_timing(const rsr_ctx *c, double *ms, int *launches, long *items)
+{
+    if (!c) return RSR_E_ARG;
+    if (ms) *ms = c->last_cg_ms;
+    if (launches) *launches = c->last_launches;
+    if (items) *items = c->last_items;
+    return RSR_OK;
+}
+
+rsr_status rsr_get_counters(const rsr_ctx *c, long *matvec_A, long *matvec_E)
+{
+    if (!c) return RSR_E_ARG;
+    if (matvec_A) *matvec_A = c->mv_A;
+    if (matvec_E) *matvec_E = c->mv_E;
+    return RSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Internal declarations shared by the device kernels and the host engine.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rsr {
+
+constexpr int NT = 256;        // threads per workgroup (4 wave64)
+constexpr int QMAX = 8;        // widest local (deflation) space per system
+constexpr int NVB = 1 + QMAX;  // values per partial in the update phase: r.r, Z^T r
+constexpr int MAXSYS = 512;    // systems per persistent launch
+constexpr int RB = 8;          // register-blocked outputs per thread in the stencil passes
+constexpr int MAXS = 31;       // largest separable PSF extent with a compiled path
+
+// Device view of one instance (image geometry, PSF, weights, tiling).
+struct InstDev {
+    int ny, nx;
+    int ty, tx;        // tile (outputs per workgroup item)
+    int nty, ntx;      // tiles per dimension
+    int sep;           // 1: rank-1 separable PSF, 0: direct 2-D stencil
+    int sy, sx;        // PSF extent (odd)
+    const double *fy;  // [sy] column factor (sep)
+    const double *fx;  // [sx] row factor (sep)
+    const double *psf; // [sy*sx] (direct)
+    const double *wh;  // [ny*nx] weights of x[i,j+1]-x[i,j]; 0 in the last column
+    const double *wv;  // [ny*nx] weights of x[i+1,j]-x[i,j]; 0 in the last row
+};
+
+// Device view of one shifted system inside a persistent CG launch.
+struct SysDev {
+    int inst;
+    int q;             // local space width (0..QMAX)
+    int ntiles;
+    int tile_base;     // offset of this system's partial slots
+    double gamma;
+    double tolabs;     // tol * ||b||
+    double *x, *r, *p0, *p1, *w;
+    const double *W;   // [q][ldw] local basis (deflation), column-major
+    const double *Z;   // [q][ldw] B W
+    long ldw;
+    double Ginv[QMAX * QMAX];   // pseudo-inverse of W^T Z (row-major q x q)
+};
+
+struct CGArgs {
+    int nsys;
+    const SysDev *sys;
+    const InstDev *inst;
+    double *partA;                 // [total tiles] p.w partials
+    double *partB;                 // [total tiles][NVB] r.r and Z^T r partials
+    unsigned long long *bar;       // grid-barrier arrival counter, 0 at launch
+    int *abort_flag;               // set on barrier timeout
+    int *out_iters;                // [nsys]
+    int *out_status;               // [nsys] 1 converged, 2 maxit, -3 nonfinite, -4 not SPD
+    double *out_rho;               // [nsys] final recursive r.r
+    int maxit;
+    int G;                         // workgroups in the grid
+    long long timeout_ticks;       // barrier wait limit in s_memrealtime ticks (100 MHz)
+    int tile_lds;                  // doubles of dynamic LDS used by the stencil buffers
+};
+
+// Launch plumbing implemented in kernels.hip.
+int tile_lds_doubles(int ty, int tx, int sy, int sx);
+size_t cg_lds_bytes(int tile_lds);
+hipError_t launch_cg(const CGArgs &a, int G, size_t lds, hipStream_t s, bool cooperative);
+int cg_max_blocks_per_cu(size_t lds);
+
+struct ApplyJob {              // y = cA K^T K v + cE E v   (or K / K^T alone)
+    int inst;
+    int op;                    // 0: cA*A + cE*E ; 3: K ; 4: K^T
+    double cA, cE;
+    const double *v;
+    double *y;
+};
+hipError_t launch_apply(const InstDev *inst_dev, const InstDev &inst_host, const ApplyJob *jobs_dev,
+                        int njobs, size_t lds, hipStream_t s);
+
+hipError_t launch_blur(const InstDev *inst_dev, const InstDev &inst_host, const ApplyJob *jobs_dev,
+                       int njobs, hipStream_t s);
+
+hipError_t launch_weights(const double *x, double beta, double *wh, double *wv, int ny, int nx,
+                          hipStream_t s);
+hipError_t launch_copy_weights(const double *wh_in, const double *wv_in, double *wh, double *wv,
+                               int ny, int nx, hipStream_t s);
+hipError_t launch_fill(double *p, double v, long n, hipStream_t s);
+
+// Tall-skinny products over n rows:
+//   C[i][j] = sum_r X[r + i*ldx] * Y[r + j*ldy],  i < a, j < c      (gram)
+//   Y[r + j*ldy] = beta*Y + sum_k X[r + k*ldx] * Q[k + j*ldq]       (combo)
+struct GramJob {
+    const double *X; long ldx; int a;
+    const double *Y; long ldy; int c;
+    long n;
+    double *C;                 // device [a][c] row-major (result)
+    long sc_off;               // offset of this job's chunk partials in the scratch buffer
+};
+hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jobs_host, int njobs, double *scratch,
+                       size_t scratch_doubles, hipStream_t s);
+size_t gram_scratch_doubles(const GramJob *jobs_host, int njobs);
+
+struct ComboJob {
+    const double *X; long ldx; int a;
+    const double *Q; int ldq;  // device [c][ldq] column-major coefficients (k fast)
+    double *Y; long ldy; int c;
+    double beta;               // Y = beta*Y + X Q   (beta = 0: Y is not read)
+    const double *Y0;          // optional: Y = Y0 + X Q when non-null (beta ignored)
+    long ldy0;
+    long n;
+};
+hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jobs_host, int njobs, hipStream_t s);
+
+hipError_t launch_grad(const double *X, const double *Lam, long ld, const double *gammas_dev, int m,
+                       const double *wh, const double *wv, int ny, int nx, double *dw_h, double *dw_v,
+                       double *dg_partial, int nchunks, hipStream_t s);
+
+}  // namespace rsr

@@ -1,0 +1,292 @@
+"""ctypes binding of the C ABI in include/rsr.h (argument marshalling only).
+
+Device memory comes from torch (contiguous float64 CUDA tensors); every
+numeric step runs in the HIP library.  Loading fails loudly when the built
+library is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "librsr.so")
+
+OP_B, OP_A, OP_E, OP_K, OP_KT = 0, 1, 2, 3, 4
+INIT_ZERO, INIT_GIVEN, INIT_MR, INIT_GALERKIN = 0, 1, 2, 3
+BATCHED, SEQUENTIAL = 0, 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_STATE", -3: "E_NONFINITE", -4: "E_NOT_SPD",
+          -5: "E_RANK", -6: "E_NOMEM", -7: "E_HIP", -8: "E_TIMEOUT"}
+
+EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_set_operators",
+           "rsr_update_weights", "rsr_weights_from_image", "rsr_get_weights", "rsr_apply",
+           "rsr_set_recycle_space", "rsr_solve_shift_set", "rsr_adjoint", "rsr_autotune", "rsr_get_tile",
+           "rsr_set_tile", "rsr_get_recycle_info", "rsr_get_recycle_basis", "rsr_get_counters",
+           "rsr_last_solve_timing"]
+
+
+class RsrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int), ("nx", ctypes.c_int), ("sy", ctypes.c_int), ("sx", ctypes.c_int),
+                ("psf_host", ctypes.POINTER(ctypes.c_double))]
+
+
+class SolveDesc(ctypes.Structure):
+    _fields_ = [("n_sys", ctypes.c_int), ("inst", ctypes.POINTER(ctypes.c_int)),
+                ("gammas", ctypes.POINTER(ctypes.c_double)), ("slot", ctypes.POINTER(ctypes.c_int)),
+                ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("mode", ctypes.c_int),
+                ("init", ctypes.c_int), ("n_ritz", ctypes.c_int), ("use_prev_k", ctypes.c_int),
+                ("use_prev_shift", ctypes.c_int), ("split_I", ctypes.c_int), ("gamma_JL", ctypes.c_double),
+                ("gamma_JR", ctypes.c_double), ("ld_b", ctypes.c_long), ("ld_x", ctypes.c_long)]
+
+
+class ShiftStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("matvec_A", ctypes.c_int), ("matvec_E", ctypes.c_int),
+                ("converged", ctypes.c_int), ("restarts", ctypes.c_int), ("local_dim", ctypes.c_int),
+                ("relres_init", ctypes.c_double), ("relres_true", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load librsr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO):
+        raise RuntimeError(f"{SO} is missing: build it with paper_2306_15049_amd.build.build()")
+    try:
+        import torch  # noqa: F401  -- load torch's HIP runtime first so both share one
+    except ImportError:
+        pass
+    L = ctypes.CDLL(SO)
+    P, I, D, L_ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_long
+    pD = ctypes.POINTER(ctypes.c_double)
+    pI = ctypes.POINTER(ctypes.c_int)
+    L.rsr_create.argtypes = [ctypes.POINTER(P), I]
+    L.rsr_destroy.argtypes = [P]
+    L.rsr_destroy.restype = None
+    L.rsr_last_error.argtypes = [P]
+    L.rsr_last_error.restype = ctypes.c_char_p
+    L.rsr_version.restype = ctypes.c_char_p
+    L.rsr_set_operators.argtypes = [P, I, ctypes.POINTER(Instance), P]
+    L.rsr_update_weights.argtypes = [P, I, P, P, P]
+    L.rsr_weights_from_image.argtypes = [P, I, P, D, P]
+    L.rsr_get_weights.argtypes = [P, I, P, P, P]
+    L.rsr_apply.argtypes = [P, I, I, D, P, P, I, L_, P]
+    L.rsr_set_recycle_space.argtypes = [P, I, P, L_, I, I, D, I, D, pI, P]
+    L.rsr_solve_shift_set.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(ShiftStats), P]
+    L.rsr_adjoint.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, P, pD, P, P, ctypes.POINTER(ShiftStats), P]
+    L.rsr_autotune.argtypes = [P, I, I, ctypes.c_char_p]
+    L.rsr_get_tile.argtypes = [P, I, pI, pI]
+    L.rsr_set_tile.argtypes = [P, I, I, I]
+    L.rsr_get_recycle_info.argtypes = [P, I, pI, pD, pD]
+    L.rsr_get_recycle_basis.argtypes = [P, I, P, L_, P]
+    L.rsr_get_counters.argtypes = [P, ctypes.POINTER(L_), ctypes.POINTER(L_)]
+    L.rsr_last_solve_timing.argtypes = [P, pD, pI, ctypes.POINTER(L_)]
+    for name in EXPORTS:
+        if name not in ("rsr_destroy", "rsr_last_error", "rsr_version"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t) -> int:
+    """Device pointer of a contiguous float64 CUDA tensor."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class SolveOptions:
+    tol: float = 1e-8
+    maxit: int = 0
+    mode: int = BATCHED
+    init: int = INIT_ZERO
+    n_ritz: int = 0
+    use_prev_k: bool = False
+    use_prev_shift: bool = False
+    split_I: int = 1 << 30
+    gamma_JL: float = 0.0
+    gamma_JR: float = 0.0
+
+
+class Context:
+    """One library context on one device (wraps rsr_ctx)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        self._check(self.lib.rsr_create(ctypes.byref(h), int(device)), None)
+        self.h = h
+        self.shapes: List[tuple] = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rsr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, h=None, allow_not_converged=False):
+        if st == 0 or (st == 1 and allow_not_converged):
+            return st
+        msg = self.lib.rsr_last_error(h if h is not None else getattr(self, "h", None))
+        raise RsrError(st, msg.decode() if msg else "")
+
+    # ------------------------------------------------------------ setup --
+    def set_operators(self, shapes: Sequence[tuple], psfs: Sequence[np.ndarray]):
+        n = len(shapes)
+        arr = (Instance * n)()
+        keep = []
+        for i, ((ny, nx), h) in enumerate(zip(shapes, psfs)):
+            h = np.ascontiguousarray(h, dtype=np.float64)
+            keep.append(h)
+            arr[i] = Instance(int(ny), int(nx), h.shape[0], h.shape[1],
+                              h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._check(self.lib.rsr_set_operators(self.h, n, arr, _stream()))
+        self.shapes = [tuple(s) for s in shapes]
+
+    def update_weights(self, inst: int, wh, wv):
+        self._check(self.lib.rsr_update_weights(self.h, inst, _ptr(wh), _ptr(wv), _stream()))
+
+    def weights_from_image(self, inst: int, x, beta: float = 1e-4):
+        self._check(self.lib.rsr_weights_from_image(self.h, inst, _ptr(x), float(beta), _stream()))
+
+    def get_weights(self, inst: int):
+        import torch
+        ny, nx = self.shapes[inst]
+        wh = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
+        wv = torch.empty_like(wh)
+        self._check(self.lib.rsr_get_weights(self.h, inst, _ptr(wh), _ptr(wv), _stream()))
+        return wh, wv
+
+    def apply(self, inst: int, op: int, v, gamma: float = 0.0, out=None):
+        """op(v) for v of shape [ny, nx] or [k, ny, nx]."""
+        import torch
+        y = torch.empty_like(v) if out is None else out
+        nvec = 1 if v.dim() == 2 else v.shape[0]
+        ld = v.shape[-1] * v.shape[-2]
+        self._check(self.lib.rsr_apply(self.h, inst, op, float(gamma), _ptr(v), _ptr(y), nvec, ld, _stream()))
+        return y
+
+    def set_recycle_space(self, inst: int, U_raw=None, n_retain: int = 0, gamma_retain: float = 0.0,
+                          p_max: int = 64, cond_max: float = 1e10) -> int:
+        p = ctypes.c_int(0)
+        if U_raw is None:
+            ptr, ld, nc = None, 0, 0
+        else:
+            nc = U_raw.shape[0]
+            ld = U_raw[0].numel()
+            ptr = _ptr(U_raw)
+        self._check(self.lib.rsr_set_recycle_space(self.h, inst, ptr, ld, nc, int(n_retain), float(gamma_retain),
+                                                   int(p_max), float(cond_max), ctypes.byref(p), _stream()))
+        return p.value
+
+    def recycle_info(self, inst: int):
+        p = ctypes.c_int(0)
+        self._check(self.lib.rsr_get_recycle_info(self.h, inst, ctypes.byref(p), None, None))
+        A = np.zeros((p.value, p.value))
+        E = np.zeros((p.value, p.value))
+        pd = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.rsr_get_recycle_info(self.h, inst, ctypes.byref(p), A.ctypes.data_as(pd),
+                                                  E.ctypes.data_as(pd)))
+        return p.value, A, E
+
+    def recycle_basis(self, inst: int):
+        """Copy of the orthonormal principal basis, shape [p, ny, nx]."""
+        import torch
+        p, _, _ = self.recycle_info(inst)
+        ny, nx = self.shapes[inst]
+        out = torch.empty((max(p, 1), ny, nx), dtype=torch.float64, device="cuda")
+        self._check(self.lib.rsr_get_recycle_basis(self.h, inst, _ptr(out), ny * nx, _stream()))
+        return out[:p]
+
+    # ------------------------------------------------------------ solve --
+    def _desc(self, inst: Sequence[int], gammas: Sequence[float], slots, o: SolveOptions, ld_b: int, ld_x: int):
+        m = len(gammas)
+        ia = (ctypes.c_int * m)(*[int(i) for i in inst])
+        ga = (ctypes.c_double * m)(*[float(g) for g in gammas])
+        sa = (ctypes.c_int * m)(*[int(s) for s in (slots if slots is not None else range(m))])
+        d = SolveDesc(m, ia, ga, sa, float(o.tol), int(o.maxit), int(o.mode), int(o.init), int(o.n_ritz),
+                      int(bool(o.use_prev_k)), int(bool(o.use_prev_shift)), int(o.split_I), float(o.gamma_JL),
+                      float(o.gamma_JR), int(ld_b), int(ld_x))
+        return d, (ia, ga, sa)
+
+    def solve(self, gammas: Sequence[float], b, X, inst: Optional[Sequence[int]] = None, slots=None,
+              opts: Optional[SolveOptions] = None, shared_b: bool = True):
+        """Solve (A + gamma_i E) x_i = b_i; X is [m, ny, nx] (in/out).  Returns (status, stats)."""
+        o = opts or SolveOptions()
+        m = len(gammas)
+        inst = list(inst) if inst is not None else [0] * m
+        ld_x = X[0].numel()
+        ld_b = 0 if shared_b else b[0].numel()
+        d, keep = self._desc(inst, gammas, slots, o, ld_b, ld_x)
+        st = (ShiftStats * m)()
+        rc = self.lib.rsr_solve_shift_set(self.h, ctypes.byref(d), _ptr(b), _ptr(X), st, _stream())
+        self._check(rc, allow_not_converged=True)
+        return rc, [s.as_dict() for s in st]
+
+    def adjoint(self, gammas, X, Gbar, Lam, inst: int = 0, slots=None, opts: Optional[SolveOptions] = None):
+        """Adjoint solves and gradients; returns (status, dgamma[np], dwh, dwv, stats)."""
+        import torch
+        o = opts or SolveOptions()
+        m = len(gammas)
+        d, keep = self._desc([inst] * m, gammas, slots, o, X[0].numel(), X[0].numel())
+        ny, nx = self.shapes[inst]
+        dg = np.zeros(m)
+        dwh = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
+        dwv = torch.empty_like(dwh)
+        st = (ShiftStats * m)()
+        rc = self.lib.rsr_adjoint(self.h, ctypes.byref(d), _ptr(X), _ptr(Gbar), _ptr(Lam),
+                                  dg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(dwh), _ptr(dwv), st,
+                                  _stream())
+        self._check(rc, allow_not_converged=True)
+        return rc, dg, dwh, dwv, [s.as_dict() for s in st]
+
+    # ------------------------------------------------------------ misc --
+    def autotune(self, inst: int, n_vec: int = 1, cache_path: Optional[str] = None):
+        self._check(self.lib.rsr_autotune(self.h, inst, int(n_vec), cache_path.encode() if cache_path else None))
+        return self.tile(inst)
+
+    def tile(self, inst: int):
+        ty, tx = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.rsr_get_tile(self.h, inst, ctypes.byref(ty), ctypes.byref(tx)))
+        return ty.value, tx.value
+
+    def set_tile(self, inst: int, ty: int, tx: int):
+        self._check(self.lib.rsr_set_tile(self.h, inst, int(ty), int(tx)))
+
+    def counters(self):
+        a, e = ctypes.c_long(), ctypes.c_long()
+        self._check(self.lib.rsr_get_counters(self.h, ctypes.byref(a), ctypes.byref(e)))
+        return a.value, e.value
+
+    def last_timing(self):
+        ms, n, it = ctypes.c_double(), ctypes.c_int(), ctypes.c_long()
+        self._check(self.lib.rsr_last_solve_timing(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(it)))
+        return ms.value, n.value, it.value

@@ -1,0 +1,111 @@
+"""GPU solver parity against the oracle.
+
+Gates (two, because a relative residual of 1e-8 does not bound the solution
+error of an ill-conditioned shift to 1e-6):
+  * residual gate: at tol 1e-8 every GPU solution has ||b - Bx|| / ||b|| <= tol
+    recomputed by the oracle's loop operator on the CPU;
+  * solution gate: at tol 1e-12 the GPU solution is within 1e-6 (relative) of
+    the dense Cholesky solution (images up to 32 x 32) or of the oracle CG
+    solution at the same tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_2306_15049_amd import rsr, synth
+from conftest import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n, seed, sigma, s, rects=6):
+    pr = synth.make_problem(seed, n, n, sigma, s, rects)
+    _, b = oracle.rhs(pr)
+    return pr, b
+
+
+def _relres(h, wh, wv, g, b, x):
+    return oracle.true_relres(h, wh, wv, g, b, x)
+
+
+@pytest.mark.parametrize("mode", [rsr.BATCHED, rsr.SEQUENTIAL])
+def test_plain_cg_matches_cholesky_16(ctx, mode):
+    pr, b = _case(16, 21, 1.5, 7)
+    wh, wv = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    gammas = synth.shift_grid(-4, 0, 6)
+    print(f"plain CG 16x16 mode={mode}", flush=True)
+    ctx.set_operators([(16, 16)], [pr.psf])
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    bd = to_dev(b)
+    X = to_dev(np.zeros((6, 16, 16)))
+    rc, st = ctx.solve(gammas, bd, X, opts=rsr.SolveOptions(tol=1e-12, mode=mode))
+    assert rc == 0
+    Xh = to_host(X)
+    Am, Em = dense.dense_A(pr.psf, 16, 16), dense.dense_E(wh, wv)
+    for l, g in enumerate(gammas):
+        ref = dense.cholesky_solve(Am + g * Em, b)
+        assert np.linalg.norm(Xh[l] - ref) <= 1e-6 * np.linalg.norm(ref)
+        assert _relres(pr.psf, wh, wv, g, b, Xh[l]) <= 1e-12 * 1.5
+        assert st[l]["converged"] == 1
+
+
+def test_plain_cg_c1_residual_gate_and_counts(ctx):
+    cfg = synth.config("C1")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    wh, wv = oracle.unit_weights(32, 32)
+    print("plain CG C1 32x32, 8 shifts", flush=True)
+    ctx.set_operators([(32, 32)], [pr.psf])
+    X = to_dev(np.zeros((8, 32, 32)))
+    rc, st = ctx.solve(cfg.gammas, to_dev(b), X, opts=rsr.SolveOptions(tol=1e-8))
+    assert rc == 0
+    Xh = to_host(X)
+    Xo, so = oracle.cg_shifts(pr.psf, wh, wv, cfg.gammas, b, tol=1e-8)
+    for l, g in enumerate(cfg.gammas):
+        assert _relres(pr.psf, wh, wv, g, b, Xh[l]) <= 1e-8
+        # same method, same arithmetic class: iteration counts agree closely
+        assert abs(st[l]["iters"] - so[l]["iters"]) <= max(3, 0.05 * so[l]["iters"])
+
+
+def test_plain_cg_c1_solution_gate(ctx):
+    cfg = synth.config("C1")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    wh, wv = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    ctx.set_operators([(32, 32)], [pr.psf])
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    X = to_dev(np.zeros((8, 32, 32)))
+    rc, st = ctx.solve(cfg.gammas, to_dev(b), X, opts=rsr.SolveOptions(tol=1e-12))
+    Xh = to_host(X)
+    Am, Em = dense.dense_A(pr.psf, 32, 32), dense.dense_E(wh, wv)
+    for l, g in enumerate(cfg.gammas):
+        ref = dense.cholesky_solve(Am + g * Em, b)
+        assert np.linalg.norm(Xh[l] - ref) <= 1e-6 * np.linalg.norm(ref), l
+
+
+def test_ragged_multi_tile_and_zero_rhs(ctx):
+    pr, b = _case(45, 22, 2.0, 9)
+    h = pr.psf
+    ctx.set_operators([(45, 45)], [h])
+    ctx.set_tile(0, 16, 16)
+    wh, wv = oracle.unit_weights(45, 45)
+    gam = [1e-3, 0.1, 5.0]
+    B = np.stack([b, np.zeros_like(b), b])
+    X = to_dev(np.zeros((3, 45, 45)))
+    rc, st = ctx.solve(gam, to_dev(B), X, opts=rsr.SolveOptions(tol=1e-10), shared_b=False)
+    Xh = to_host(X)
+    assert not Xh[1].any() and st[1]["iters"] == 0
+    for l in (0, 2):
+        assert _relres(h, wh, wv, gam[l], b, Xh[l]) <= 1e-10
+        xo, so = oracle.cg(h, wh, wv, gam[l], b, tol=1e-12)
+        assert np.linalg.norm(Xh[l] - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_maxit_reports_not_converged(ctx):
+    pr, b = _case(32, 23, 1.5, 7)
+    ctx.set_operators([(32, 32)], [pr.psf])
+    X = to_dev(np.zeros((2, 32, 32)))
+    rc, st = ctx.solve([1e-4, 1e-3], to_dev(b), X, opts=rsr.SolveOptions(tol=1e-10, maxit=5))
+    assert rc == 1
+    assert all(s["iters"] == 5 and s["converged"] == 0 for s in st)
