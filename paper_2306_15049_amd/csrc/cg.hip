@@ -1,0 +1,567 @@
+// Persistent multi-system deflated CG (gfx950, FP64).
+//
+// Every system (A + gamma E) x = b of a shift set advances in one cooperative
+// launch.  Deflated CG with local space W (Z = B W, G = W^T Z) takes
+//   p_{j+1} = r_{j+1} + beta_j p_j - W mu_{j+1},   mu = G^{-1} Z^T r.
+// To keep W off the stencil halo the kernel recurs the undeflated part
+//   ph_{j+1} = r_{j+1} + beta_j ph_j,   c_{j+1} = beta_j c_j + mu_{j+1},
+// so that p = ph - W c and B p = B ph - Z c: the stencil runs on ph (two
+// loads per halo pixel) and W, Z are read on the tile interior only.
+//
+// One iteration is two grid-wide phases separated by grid barriers:
+//   phase 1: ph = r + beta ph (halo recomputed, ping-pong buffers),
+//            w = B ph - Z c, p = ph - W c, partial p.w;
+//   phase 2: alpha = rho / p.w, x += alpha p, r -= alpha w, partial r.r, Z^T r.
+// The active systems' tiles are concatenated and split into G contiguous
+// chunks (one per workgroup, XCD-aware), each chunk's partials land in their
+// own slots, and every workgroup reduces the slots it needs in a fixed order,
+// so all workgroups take identical decisions and results are deterministic.
+// A system leaves the launch once sqrt(r.r) <= tol ||b|| (or on maxit /
+// breakdown) and the remaining tiles are re-split over the whole grid.
+#include "internal.hpp"
+#include "stencil.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace rsr {
+
+__device__ __forceinline__ unsigned long long realtime() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Grid barrier: a monotone arrival counter.  Barrier k completes when the
+// counter reaches (k+1)*G.  Thread 0 of each workgroup publishes the
+// workgroup's stores with one agent-scope release (the arrival), spins on
+// relaxed loads (an acquire inside the loop would invalidate the XCD's L2 on
+// every poll, evicting what the still-working workgroups are reading), and
+// performs a single agent-scope acquire once the count is reached.  The wait
+// is bounded: past the time limit the waiting workgroup raises the abort flag
+// and every workgroup leaves the kernel at its next barrier, so the grid
+// always drains.
+__device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned long long target, int *abort_flag,
+                                             long long timeout, int *s_flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t0 = realtime();
+        int ok = 1;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+            if ((long long)(realtime() - t0) > timeout) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_flag = ok;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
+// Exclusive scan of n <= 2*NT ints in LDS (in place); returns the total.
+__device__ int block_excl_scan(int *v, int n, int *tmp)
+{
+    const int t = threadIdx.x;
+    const int i0 = 2 * t, i1 = 2 * t + 1;
+    const int a0 = i0 < n ? v[i0] : 0, a1 = i1 < n ? v[i1] : 0;
+    const int s = a0 + a1;
+    const int lane = t & 63, wid = t >> 6;
+    int incl = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) tmp[wid] = incl;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < wid) base += tmp[w];
+        total += tmp[w];
+    }
+    const int excl = base + incl - s;
+    if (i0 < n) v[i0] = excl;
+    if (i1 < n) v[i1] = excl + a0;
+    __syncthreads();
+    return total;
+}
+
+// Work assignment of one phase: the active systems (ascending ids), their
+// tiles concatenated, split into G chunks of ipb items.
+struct Assign {
+    int *act;    // [MAXSYS] system ids, ascending
+    int *pre;    // [MAXSYS+1] tile prefix
+    int *foff;   // [MAXSYS+1] prefix of chunk counts (flat partial offsets)
+};
+
+__device__ __forceinline__ int chunk_of_block(int b, int G)
+{
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // run of chunks so that neighbouring tiles (shared halos) share an L2.
+    if (G % 8 == 0) return (b % 8) * (G / 8) + b / 8;
+    return b;
+}
+
+__device__ __forceinline__ int nch_of(int pre_a, int nt, int ipb)
+{
+    return (pre_a + nt - 1) / ipb - pre_a / ipb + 1;
+}
+
+__device__ __forceinline__ int find_pos(const int *v, int n, int key)   // last i with v[i] <= key
+{
+    int l = 0, h = n - 1;
+    while (l < h) {
+        const int md = (l + h + 1) >> 1;
+        if (v[md] <= key) l = md;
+        else h = md - 1;
+    }
+    return l;
+}
+
+__device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m, int *s_ipb, int *tmp)
+{
+    for (int k = threadIdx.x; k < m; k += NT) S.pre[k] = A.sys[S.act[k]].ntiles;
+    __syncthreads();
+    const int T = block_excl_scan(S.pre, m, tmp);
+    if (threadIdx.x == 0) {
+        S.pre[m] = T;
+        *s_m = m;
+        *s_ipb = T > 0 ? (T + G - 1) / G : 1;
+    }
+    __syncthreads();
+    const int ipb = *s_ipb;
+    for (int k = threadIdx.x; k < m; k += NT) S.foff[k] = nch_of(S.pre[k], A.sys[S.act[k]].ntiles, ipb);
+    __syncthreads();
+    const int F = block_excl_scan(S.foff, m, tmp);
+    if (threadIdx.x == 0) S.foff[m] = F;
+    __syncthreads();
+}
+
+// Deterministic block-wide sum of cnt consecutive partial values of one
+// system: part[(base + k) * nv + v0 + j] over k < nch.  Result in out[0..cnt).
+__device__ void block_reduce_partials(const double *part, int base, int nch, int nv, int v0, int cnt, double *out,
+                                      double *red)
+{
+    double acc[NVB];
+#pragma unroll
+    for (int j = 0; j < NVB; ++j) acc[j] = 0.0;
+    for (int k = threadIdx.x; k < nch; k += NT) {
+        const double *p = part + (long)(base + k) * nv + v0;
+#pragma unroll
+        for (int j = 0; j < NVB; ++j)
+            if (j < cnt) acc[j] += p[j];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NVB; ++j)
+        if (j < cnt) {
+            const double s = wave_sum(acc[j]);
+            if (lane == 0) red[wid * NVB + j] = s;
+        }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w * NVB + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Block-reduce `cnt` per-thread accumulators (fixed order) and write them to
+// part[slot * nv + j].
+__device__ __forceinline__ void flush_partials(const double (&acc)[NVB], int cnt, double *part, long slot, int nv,
+                                               double *red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NVB; ++j)
+        if (j < cnt) {
+            const double sm = wave_sum(acc[j]);
+            if (lane == 0) red[wid * NVB + j] = sm;
+        }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+        double sm = 0.0;
+        for (int w = 0; w < NT / 64; ++w) sm += red[w * NVB + threadIdx.x];
+        part[slot * nv + threadIdx.x] = sm;
+    }
+    __syncthreads();
+}
+
+constexpr int NB = 4;    // pixels per thread whose loads are issued together (tile interior)
+constexpr int NBW = 16;  // window pixels per thread loaded together in phase 1
+
+__global__ __launch_bounds__(NT) void k_cg(CGArgs A)
+{
+    extern __shared__ double smem[];
+    double *tile = smem;                          // stencil buffers / reduction scratch
+    double *s_rho = smem + A.tile_lds;            // [MAXSYS] current r.r
+    double *s_rho_old = s_rho + MAXSYS;           // [MAXSYS] previous r.r
+    int *ib = (int *)(s_rho_old + MAXSYS);
+    Assign S0, S1;   // two named assignments (a runtime-indexed array would live in scratch)
+    S0.act = ib; ib += MAXSYS;
+    S0.pre = ib; ib += MAXSYS + 1;
+    S0.foff = ib; ib += MAXSYS + 1;
+    S1.act = ib; ib += MAXSYS;
+    S1.pre = ib; ib += MAXSYS + 1;
+    S1.foff = ib; ib += MAXSYS + 1;
+    __shared__ int s_m[2], s_ipb[2], s_tmp[NT / 64], s_flag;
+    __shared__ double s_red[(NT / 64) * NVB];
+    __shared__ double s_vals[NVB + 2];
+    __shared__ double s_c[QMAX];                  // c_{j+1} of the current system
+    __shared__ double s_alpha;
+
+    const int G = A.G;
+    const int chunk = chunk_of_block(blockIdx.x, G);
+    int cur = 0;
+
+    for (int k = threadIdx.x; k < A.nsys; k += NT) S0.act[k] = k;
+    __syncthreads();
+    build_assign(A, S0, A.nsys, G, &s_m[0], &s_ipb[0], s_tmp);
+
+    // ---- phase 2 (and the initial reduction pass with update = false)
+    auto run_phase2 = [&](const Assign &As, int m, int ipb, bool update, int it) {
+        const int T = As.pre[m];
+        const int lo = chunk * ipb;
+        const int hi = lo + ipb < T ? lo + ipb : T;
+        if (lo >= hi) return;
+        int a = find_pos(As.pre, m, lo);
+        int cur_sys = -1;
+        double racc[NVB];
+        double alpha = 0.0;
+        int q = 0;
+        for (int item = lo; item < hi; ++item) {
+            while (item >= As.pre[a + 1]) ++a;
+            const int s = uni(As.act[a]);
+            if (s != cur_sys) {
+                if (cur_sys >= 0)
+                    flush_partials(racc, 1 + q, A.partB,
+                                   A.sys[cur_sys].tile_base + (chunk - As.pre[find_pos(As.act, m, cur_sys)] / ipb),
+                                   NVB, s_red);
+                cur_sys = s;
+                q = A.sys[s].q;
+#pragma unroll
+                for (int j = 0; j < NVB; ++j) racc[j] = 0.0;
+                if (update) {
+                    block_reduce_partials(A.partA, A.sys[s].tile_base, As.foff[a + 1] - As.foff[a], 1, 0, 1,
+                                          s_vals, s_red);
+                    const double pw = s_vals[0];
+                    alpha = (pw > 0.0 && isfinite(pw)) ? s_rho[s] / pw : -1.0;   // -1: breakdown
+                }
+            }
+            // copies of the system's pointers and the instance geometry: read through a
+            // reference, every global store below would force them to be reloaded
+            const SysDev &Yg = A.sys[s];
+            const InstDev I = A.inst[Yg.inst];
+            double *__restrict__ Yx = Yg.x;
+            double *__restrict__ Yr = Yg.r;
+            const double *__restrict__ Ypa = Yg.pa;
+            const double *__restrict__ Yw = Yg.w;
+            const double *__restrict__ YZ = Yg.Z;
+            const long ldw = Yg.ldw;
+            const int t = uni(item - As.pre[a]);
+            const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
+            const int ne = I.ty * I.tx;
+            for (int base = 0; base < ne; base += NT * NB) {
+                long gi[NB];
+                bool ok[NB];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int k = base + u * NT + threadIdx.x;
+                    const int gy = y0 + k / I.tx, gx = x0 + k % I.tx;
+                    ok[u] = k < ne && gy < I.ny && gx < I.nx;
+                    gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
+                }
+                double rv[NB], xv[NB], pv[NB], wv[NB], zv[NB][QMAX];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    rv[u] = ok[u] ? Yr[gi[u]] : 0.0;
+                    if (update && alpha >= 0.0) {
+                        xv[u] = ok[u] ? Yx[gi[u]] : 0.0;
+                        pv[u] = ok[u] ? Ypa[gi[u]] : 0.0;
+                        wv[u] = ok[u] ? Yw[gi[u]] : 0.0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < QMAX; ++j) zv[u][j] = (j < q && ok[u]) ? YZ[j * ldw + gi[u]] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    double rn = rv[u];
+                    if (update && alpha >= 0.0 && ok[u]) {
+                        Yx[gi[u]] = fma(alpha, pv[u], xv[u]);
+                        rn = fma(-alpha, wv[u], rn);
+                        Yr[gi[u]] = rn;
+                    }
+                    racc[0] = fma(rn, rn, racc[0]);
+#pragma unroll
+                    for (int j = 0; j < QMAX; ++j) racc[1 + j] = fma(zv[u][j], rn, racc[1 + j]);
+                }
+            }
+            if (update && alpha < 0.0) racc[0] = -1e300 / (double)NT;   // propagate breakdown
+        }
+        if (cur_sys >= 0)
+            flush_partials(racc, 1 + q, A.partB,
+                           A.sys[cur_sys].tile_base + (chunk - As.pre[find_pos(As.act, m, cur_sys)] / ipb), NVB,
+                           s_red);
+    };
+
+    run_phase2(S0, s_m[0], s_ipb[0], false, -1);
+    int nbar = 0;
+    if (!grid_barrier(A.bar, (unsigned long long)(++nbar) * G, A.abort_flag, A.timeout_ticks, &s_flag)) return;
+
+    auto stamp = [&](int it, int k) {
+        if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) A.stamps[it * 8 + k] = realtime();
+    };
+    for (int it = 0;; ++it) {
+        stamp(it, 0);
+        // ---- r.r of every active system (partials of assignment O) and decisions
+        Assign O = cur ? S1 : S0;
+        const int mo = s_m[cur];
+        const int F = O.foff[mo];
+        double *flat = tile;
+        for (int f = threadIdx.x; f < F; f += NT) {
+            const int l = find_pos(O.foff, mo, f);
+            flat[f] = A.partB[(long)(A.sys[O.act[l]].tile_base + (f - O.foff[l])) * NVB];
+        }
+        __syncthreads();
+        Assign N = cur ? S0 : S1;
+        int *keep = N.pre;       // scratch, rebuilt by build_assign
+        int *newpos = N.foff;    // scratch
+        if (mo <= 16) {
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+            for (int a = wid; a < mo; a += NT / 64) {
+                double v = 0.0;
+                for (int k = O.foff[a] + lane; k < O.foff[a + 1]; k += 64) v += flat[k];
+                v = wave_sum(v);
+                if (lane == 0) flat[F + a] = v;
+            }
+        } else {
+            for (int a = threadIdx.x; a < mo; a += NT) {
+                double v = 0.0;
+                for (int k = O.foff[a]; k < O.foff[a + 1]; ++k) v += flat[k];
+                flat[F + a] = v;
+            }
+        }
+        __syncthreads();
+        for (int a = threadIdx.x; a < mo; a += NT) {
+            const int s = O.act[a];
+            const double rho = flat[F + a];
+            int st = 0;
+            if (!isfinite(rho)) st = -3;
+            else if (rho < 0.0) st = -4;
+            else if (sqrt(rho) <= A.sys[s].tolabs) st = 1;
+            else if (it >= A.maxit) st = 2;
+            s_rho_old[s] = s_rho[s];
+            s_rho[s] = rho;
+            keep[a] = (st == 0);
+            newpos[a] = (st == 0);
+            if (st != 0 && blockIdx.x == 0) {
+                A.out_status[s] = st;
+                A.out_iters[s] = it;
+                A.out_rho[s] = rho;
+            }
+        }
+        __syncthreads();
+        // compact the active list (keep ascending order)
+        {
+            int kk[2];
+            for (int u = 0; u < 2; ++u) kk[u] = (2 * threadIdx.x + u < mo) ? keep[2 * threadIdx.x + u] : 0;
+            __syncthreads();
+            const int mn_ = block_excl_scan(newpos, mo, s_tmp);
+            for (int u = 0; u < 2; ++u) {
+                const int a = 2 * threadIdx.x + u;
+                if (a < mo && kk[u]) N.act[newpos[a]] = O.act[a];
+            }
+            if (threadIdx.x == 0) s_m[cur ^ 1] = mn_;
+            __syncthreads();
+        }
+        const int mn = s_m[cur ^ 1];
+        if (mn == 0) break;
+        build_assign(A, N, mn, G, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp);
+        const int ipbn = s_ipb[cur ^ 1];
+        stamp(it, 1);
+
+        // ---- phase 1 under N
+        {
+            const int T = N.pre[mn];
+            const int lo = chunk * ipbn;
+            const int hi = lo + ipbn < T ? lo + ipbn : T;
+            int a = lo < hi ? find_pos(N.pre, mn, lo) : 0;
+            int cur_sys = -1;
+            double pacc[NVB];
+            pacc[0] = 0.0;
+            int q = 0;
+            double beta = 0.0;
+            for (int item = lo; item < hi; ++item) {
+                while (item >= N.pre[a + 1]) ++a;
+                const int s = uni(N.act[a]);
+                const SysDev &Y = A.sys[s];
+                if (s != cur_sys) {
+                    if (cur_sys >= 0)
+                        flush_partials(pacc, 1, A.partA,
+                                       A.sys[cur_sys].tile_base + (chunk - N.pre[find_pos(N.act, mn, cur_sys)] / ipbn),
+                                       1, s_red);
+                    cur_sys = s;
+                    pacc[0] = 0.0;
+                    q = Y.q;
+                    beta = it > 0 ? s_rho[s] / s_rho_old[s] : 0.0;
+                    if (q > 0) {
+                        // mu = Ginv (Z^T r) from the previous assignment's partials; c_{j+1} = beta c_j + mu
+                        const int po = find_pos(O.act, mo, s);
+                        block_reduce_partials(A.partB, Y.tile_base, O.foff[po + 1] - O.foff[po], NVB, 1, q, s_vals,
+                                              s_red);
+                        if (threadIdx.x < q) {
+                            double m = 0.0;
+                            for (int j = 0; j < q; ++j) m += Y.Ginv[threadIdx.x * QMAX + j] * s_vals[j];
+                            const double cold = it > 0 ? Y.cbuf[(it & 1) * QMAX + threadIdx.x] : 0.0;
+                            const double cn = fma(beta, cold, m);
+                            s_c[threadIdx.x] = cn;
+                            // the workgroup holding the system's first chunk publishes c_{j+1}
+                            if (chunk == N.pre[a] / ipbn) Y.cbuf[((it + 1) & 1) * QMAX + threadIdx.x] = cn;
+                        }
+                        __syncthreads();
+                    }
+                }
+                const InstDev I = A.inst[Y.inst];
+                const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx);
+                const int t = uni(item - N.pre[a]);
+                const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
+                // local copies (see phase 2): no reloads after the global stores
+                const double *__restrict__ pold = (it & 1) ? Y.p1 : Y.p0;
+                double *__restrict__ pnew = (it & 1) ? Y.p0 : Y.p1;
+                const double *__restrict__ Yr = Y.r;
+                const double *__restrict__ YW = Y.W;
+                const double *__restrict__ YZ = Y.Z;
+                double *__restrict__ Ypa = Y.pa;
+                double *__restrict__ Yw = Y.w;
+                const long ldw = Y.ldw;
+                const double gam = Y.gamma;
+                double *pbuf = tile + g.offP;
+                // stage ph = r + beta ph_old on the window (all of a thread's loads
+                // issued together); keep the interior in pbuf
+                const int nw = g.H0 * g.W0;
+                for (int base = 0; base < nw; base += NT * NBW) {
+                    long gi[NBW];
+                    bool ok[NBW];
+#pragma unroll
+                    for (int u = 0; u < NBW; ++u) {
+                        const int k = base + u * NT + threadIdx.x;
+                        const int gy = y0 - g.hy + k / g.W0, gx = x0 - g.hx + k % g.W0;
+                        ok[u] = k < nw && gy >= 0 && gy < I.ny && gx >= 0 && gx < I.nx;
+                        gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
+                    }
+                    double rv[NBW], pv[NBW];
+#pragma unroll
+                    for (int u = 0; u < NBW; ++u) {
+                        rv[u] = ok[u] ? Yr[gi[u]] : 0.0;
+                        pv[u] = (ok[u] && it > 0) ? pold[gi[u]] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < NBW; ++u) {
+                        const int k = base + u * NT + threadIdx.x;
+                        if (k < nw) {
+                            const int li = k / g.W0, lj = k % g.W0;
+                            const double v = ok[u] ? fma(beta, pv[u], rv[u]) : 0.0;
+                            tile[li * g.P0 + lj] = v;
+                            const int ii = li - g.hy, jj = lj - g.hx;
+                            if (ok[u] && ii >= 0 && ii < I.ty && jj >= 0 && jj < I.tx) {
+                                pnew[gi[u]] = v;
+                                pbuf[ii * g.PE + jj] = v;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                if (item == lo) stamp(it, 6);
+                tile_E(I, g, tile, y0, x0, gam);
+                tile_A(I, g, tile, y0, x0, 1.0);
+                if (item == lo) stamp(it, 7);
+                // interior: p = ph - W c, w = B ph - Z c, partial p.w
+                const double *ebuf = tile + g.offE;
+                const int ne = I.ty * I.tx;
+                for (int base = 0; base < ne; base += NT * NB) {
+                    long gi[NB];
+                    bool ok[NB];
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int k = base + u * NT + threadIdx.x;
+                        const int gy = y0 + k / I.tx, gx = x0 + k % I.tx;
+                        ok[u] = k < ne && gy < I.ny && gx < I.nx;
+                        gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
+                    }
+                    double p[NB], w[NB];
+#pragma unroll
+                    for (int u = 0; u < NB; ++u) {
+                        const int k = base + u * NT + threadIdx.x;
+                        const int ii = ok[u] ? k / I.tx : 0, jj = ok[u] ? k % I.tx : 0;
+                        p[u] = pbuf[ii * g.PE + jj];
+                        w[u] = ebuf[ii * g.PE + jj];
+                    }
+                    for (int j = 0; j < q; ++j) {
+                        const double cj = s_c[j];
+                        const double *Wj = YW + j * ldw, *Zj = YZ + j * ldw;
+                        double wl[NB], zl[NB];
+#pragma unroll
+                        for (int u = 0; u < NB; ++u) {
+                            wl[u] = ok[u] ? Wj[gi[u]] : 0.0;
+                            zl[u] = ok[u] ? Zj[gi[u]] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < NB; ++u) {
+                            p[u] = fma(-cj, wl[u], p[u]);
+                            w[u] = fma(-cj, zl[u], w[u]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < NB; ++u)
+                        if (ok[u]) {
+                            Ypa[gi[u]] = p[u];
+                            Yw[gi[u]] = w[u];
+                            pacc[0] = fma(p[u], w[u], pacc[0]);
+                        }
+                }
+                __syncthreads();
+            }
+            if (cur_sys >= 0)
+                flush_partials(pacc, 1, A.partA,
+                               A.sys[cur_sys].tile_base + (chunk - N.pre[find_pos(N.act, mn, cur_sys)] / ipbn), 1,
+                               s_red);
+        }
+        stamp(it, 2);
+        if (!grid_barrier(A.bar, (unsigned long long)(++nbar) * G, A.abort_flag, A.timeout_ticks, &s_flag)) return;
+        stamp(it, 3);
+        run_phase2(N, mn, ipbn, true, it);
+        stamp(it, 4);
+        if (!grid_barrier(A.bar, (unsigned long long)(++nbar) * G, A.abort_flag, A.timeout_ticks, &s_flag)) return;
+        stamp(it, 5);
+        cur ^= 1;
+    }
+}
+
+size_t cg_lds_bytes(int tile_lds)
+{
+    const size_t d = (size_t)tile_lds + 2 * MAXSYS;                  // tile + rho arrays
+    const size_t ints = 2 * (size_t)(MAXSYS + 2 * (MAXSYS + 1));     // two assignments
+    return d * sizeof(double) + ints * sizeof(int);
+}
+
+int cg_max_blocks_per_cu(size_t lds)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cg, NT, lds) != hipSuccess) return 0;
+    return nb;
+}
+
+hipError_t launch_cg(const CGArgs &a, int G, size_t lds, hipStream_t s, bool cooperative)
+{
+    if (cooperative) {
+        void *args[] = {(void *)&a};
+        return hipLaunchCooperativeKernel((const void *)k_cg, dim3(G), dim3(NT), args, (unsigned)lds, s);
+    }
+    hipLaunchKernelGGL(k_cg, dim3(G), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace rsr

@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <functional>
@@ -81,6 +82,7 @@ struct Instance {
     long n = 0;
     std::vector<double> psf;
     int sep = 0;
+    int ssq = 0;                       // separable path: zero-padded square size
     std::vector<double> fy, fx;
     DBuf d_fy, d_fx, d_psf, d_wh, d_wv;
     int ty = 16, tx = 16;
@@ -92,6 +94,9 @@ struct Instance {
     // latest correction g = x - x0 per shift slot
     std::map<int, std::unique_ptr<DBuf>> gstore;
 };
+
+inline int eff_sy(const Instance &I) { return I.sep ? I.ssq : I.sy; }
+inline int eff_sx(const Instance &I) { return I.sep ? I.ssq : I.sx; }
 
 }  // namespace
 
@@ -106,6 +111,7 @@ struct rsr_ctx {
     // scratch
     DBuf d_jobs, d_gram_scratch, d_small, d_sys, d_partA, d_partB, d_ctl, d_out;
     DBuf d_ws;                         // per-system vectors of a solve
+    DBuf d_dbg;                        // optional phase timestamps
     DBuf d_tmp;                        // misc n-vectors
     // counters and timing
     long mv_A = 0, mv_E = 0;
@@ -141,8 +147,8 @@ void upload_inst(rsr_ctx *c)
         d.nty = (I.ny + I.ty - 1) / I.ty;
         d.ntx = (I.nx + I.tx - 1) / I.tx;
         d.sep = I.sep;
-        d.sy = I.sy;
-        d.sx = I.sx;
+        d.sy = eff_sy(I);
+        d.sx = eff_sx(I);
         d.fy = I.d_fy.as<double>();
         d.fx = I.d_fx.as<double>();
         d.psf = I.d_psf.as<double>();
@@ -164,7 +170,7 @@ template <class T> T *upload(rsr_ctx *c, DBuf &buf, const std::vector<T> &v, hip
 int max_tile_lds(rsr_ctx *c)
 {
     int m = 2048;
-    for (auto &p : c->inst) m = std::max(m, tile_lds_doubles(p->ty, p->tx, p->sy, p->sx));
+    for (auto &p : c->inst) m = std::max(m, tile_lds_doubles(p->ty, p->tx, eff_sy(*p), eff_sx(*p)));
     return m;
 }
 
@@ -179,7 +185,7 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
     for (int j = 0; j < nvec; ++j) jobs[j] = ApplyJob{ii, 0, cA, cE, v + j * ldv, y + j * ldy};
     DBuf &jb = jobbuf ? *jobbuf : c->d_jobs;
     ApplyJob *dj = upload(c, jb, jobs, s);
-    const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, I.sy, I.sx);
+    const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
     HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, nvec, lds, s));
     if (cA != 0.0) c->mv_A += nvec;
     if (cE != 0.0) c->mv_E += nvec;
@@ -194,7 +200,7 @@ void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
     for (auto &kv : by) {
         Instance &I = get_inst(c, kv.first);
         ApplyJob *dj = upload(c, c->d_jobs, kv.second, s);
-        const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, I.sy, I.sx);
+        const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
         HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[kv.first], dj, (int)kv.second.size(), lds, s));
         for (auto &j : kv.second) {
             if (j.cA != 0.0) c->mv_A++;
@@ -292,9 +298,16 @@ void factor_psf(Instance &I)
             err += d * d;
         }
     if (err <= 1e-28 * nrm) {
+        // zero-pad both factors symmetrically to one odd square size: zero taps add
+        // exact zeros, so the operator is unchanged and one compiled pass width serves
+        // both directions
+        const int S = std::max(sy, sx);
         I.sep = 1;
-        I.fy = fy;
-        I.fx = fx;
+        I.ssq = S;
+        I.fy.assign(S, 0.0);
+        I.fx.assign(S, 0.0);
+        for (int a = 0; a < sy; ++a) I.fy[(S - sy) / 2 + a] = fy[a];
+        for (int c2 = 0; c2 < sx; ++c2) I.fx[(S - sx) / 2 + c2] = fx[c2];
     }
 }
 
@@ -313,7 +326,8 @@ struct SysHost {
     long n;
     const double *b;
     double *x;
-    double *r, *p0, *p1, *w, *xinit, *rt;   // workspace vectors
+    double *r, *p0, *p1, *w, *xinit, *rt, *pa;   // workspace vectors
+    double *cbuf;                             // [2][QMAX]
     double *W, *Z;                            // QMAX columns each
     int q = 0;
     std::vector<double> Ginv;                 // q x q
@@ -360,6 +374,8 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         d.p0 = Y.p0;
         d.p1 = Y.p1;
         d.w = Y.w;
+        d.pa = Y.pa;
+        d.cbuf = Y.cbuf;
         d.W = Y.W;
         d.Z = Y.Z;
         d.ldw = Y.n;
@@ -382,6 +398,10 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     int bpc = cg_max_blocks_per_cu(lds);
     if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
     int G = std::min<long>((long)bpc * c->n_cu, 1024);
+    if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
+        const int v = atoi(cap);
+        if (v >= 8) G = std::min(G, v);
+    }
     G = (int)std::min<long>(G, std::max<long>(8, tiles));
     if (G >= 8) G -= G % 8;
 
@@ -400,6 +420,13 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.G = G;
     a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * 30.0);   // 30 s
     a.tile_lds = tl;
+    a.stamps = nullptr;
+    const bool dbg = getenv("RSR_CG_STAMPS") != nullptr;   // phase timing of workgroup 0 (diagnostics)
+    if (dbg) {
+        c->d_dbg.ensure(sizeof(unsigned long long) * DBG_ITERS * 8);
+        HIPCHK(launch_fill((double *)c->d_dbg.p, 0.0, DBG_ITERS * 8, s));
+        a.stamps = (unsigned long long *)c->d_dbg.p;
+    }
     HIPCHK(hipEventRecord(c->ev0, s));
     HIPCHK(launch_cg(a, G, lds, s, true));
     HIPCHK(hipEventRecord(c->ev1, s));
@@ -412,6 +439,25 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     HIPCHK(hipStreamSynchronize(s));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    if (dbg) {
+        std::vector<unsigned long long> st(DBG_ITERS * 8);
+        HIPCHK(hipMemcpy(st.data(), c->d_dbg.p, sizeof(unsigned long long) * st.size(), hipMemcpyDeviceToHost));
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        int n = 0;
+        for (int i = 1; i < DBG_ITERS && i + 1 < hi[0] && st[i * 8 + 5]; ++i, ++n) {
+            for (int k = 0; k < 5; ++k) acc[k] += (double)(st[i * 8 + k + 1] - st[i * 8 + k]);
+            if (st[i * 8 + 6] && st[i * 8 + 7]) {
+                acc[5] += (double)(st[i * 8 + 6] - st[i * 8 + 1]);
+                acc[6] += (double)(st[i * 8 + 7] - st[i * 8 + 6]);
+            }
+        }
+        const double tk = c->wall_khz / 1000.0;
+        if (n > 0)
+            fprintf(stderr, "[rsr cg stamps] G=%d iters=%d us: reduce+assign %.2f phase1 %.2f (first item: setup+load %.2f "
+                            "stencil %.2f) bar1 %.2f phase2 %.2f bar2 %.2f\n",
+                    G, n, acc[0] / n / tk, acc[1] / n / tk, acc[5] / n / tk, acc[6] / n / tk, acc[2] / n / tk,
+                    acc[3] / n / tk, acc[4] / n / tk);
+    }
     c->last_cg_ms += ms;
     c->last_launches += 1;
     if (abort_h) fail(RSR_E_TIMEOUT, "persistent CG barrier timed out");
@@ -759,7 +805,7 @@ void alloc_ws(rsr_ctx *c, std::vector<SysHost> &sys)
 {
     // per system: r p0 p1 w xinit rt + W, Z (QMAX each)
     size_t tot = 0;
-    for (auto &Y : sys) tot += (size_t)Y.n * (6 + 2 * QMAX) + 32;
+    for (auto &Y : sys) tot += (size_t)Y.n * (7 + 2 * QMAX) + 2 * QMAX + 64;
     c->d_ws.ensure(sizeof(double) * tot);
     double *p = c->d_ws.as<double>();
     for (auto &Y : sys) {
@@ -770,6 +816,8 @@ void alloc_ws(rsr_ctx *c, std::vector<SysHost> &sys)
         Y.w = p; p += n;
         Y.xinit = p; p += n;
         Y.rt = p; p += n;
+        Y.pa = p; p += n;
+        Y.cbuf = p; p += 2 * QMAX;
         Y.W = p; p += n * QMAX;
         Y.Z = p; p += n * QMAX;
         p += 32 - ((uintptr_t)p / 8) % 32;   // keep 256-byte alignment
@@ -841,7 +889,7 @@ void rsr_destroy(rsr_ctx *c)
         for (auto &g : I.gstore) if (g.second) g.second->release();
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
-                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp})
+                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg})
         b->release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -881,10 +929,10 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
             I->d_psf.ensure(sizeof(double) * I->psf.size());
             HIPCHK(hipMemcpy(I->d_psf.p, I->psf.data(), sizeof(double) * I->psf.size(), hipMemcpyHostToDevice));
             if (I->sep) {
-                I->d_fy.ensure(sizeof(double) * I->sy);
-                I->d_fx.ensure(sizeof(double) * I->sx);
-                HIPCHK(hipMemcpy(I->d_fy.p, I->fy.data(), sizeof(double) * I->sy, hipMemcpyHostToDevice));
-                HIPCHK(hipMemcpy(I->d_fx.p, I->fx.data(), sizeof(double) * I->sx, hipMemcpyHostToDevice));
+                I->d_fy.ensure(sizeof(double) * I->ssq);
+                I->d_fx.ensure(sizeof(double) * I->ssq);
+                HIPCHK(hipMemcpy(I->d_fy.p, I->fy.data(), sizeof(double) * I->ssq, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(I->d_fx.p, I->fx.data(), sizeof(double) * I->ssq, hipMemcpyHostToDevice));
             }
             I->d_wh.ensure(sizeof(double) * I->n);
             I->d_wv.ensure(sizeof(double) * I->n);
@@ -1218,7 +1266,7 @@ rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
     return guard(c, [&] {
         Instance &I = get_inst(c, ii);
         if (ty < 4 || tx < 4 || ty > 128 || tx > 128) fail(RSR_E_ARG, "tile sides must be in [4, 128]");
-        const int tl = tile_lds_doubles(ty, tx, I.sy, I.sx);
+        const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I));
         if (cg_lds_bytes(tl) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
         set_device(c);
         I.ty = ty;
@@ -1261,7 +1309,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         int bty = I.ty, btx = I.tx;
         const long mvA = c->mv_A, mvE = c->mv_E;
         for (auto &cd : cand) {
-            const int tl = tile_lds_doubles(cd[0], cd[1], I.sy, I.sx);
+            const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I));
             if (cg_lds_bytes(tl) > 160 * 1024) continue;
             I.ty = cd[0];
             I.tx = cd[1];
@@ -1269,7 +1317,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
             std::vector<ApplyJob> jobs(n_vec);
             for (int j = 0; j < n_vec; ++j) jobs[j] = ApplyJob{ii, 0, 1.0, 0.5, v.as<double>() + j * n, y.as<double>() + j * n};
             ApplyJob *dj = upload(c, c->d_jobs, jobs, s);
-            const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, I.sy, I.sx);
+            const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
             HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, n_vec, lds, s));
             HIPCHK(hipStreamSynchronize(s));
             const int reps = 5;

@@ -18,7 +18,7 @@ struct InstDev {
     int ty, tx;        // tile (outputs per workgroup item)
     int nty, ntx;      // tiles per dimension
     int sep;           // 1: rank-1 separable PSF, 0: direct 2-D stencil
-    int sy, sx;        // PSF extent (odd)
+    int sy, sx;        // PSF extent (odd); for sep both equal the zero-padded square size
     const double *fy;  // [sy] column factor (sep)
     const double *fx;  // [sx] row factor (sep)
     const double *psf; // [sy*sx] (direct)
@@ -35,6 +35,8 @@ struct SysDev {
     double gamma;
     double tolabs;     // tol * ||b||
     double *x, *r, *p0, *p1, *w;
+    double *pa;        // actual search direction p = ph - W c (ph ping-pongs in p0/p1)
+    double *cbuf;      // [2][QMAX] deflation coefficients c_j, double-buffered by iteration parity
     const double *W;   // [q][ldw] local basis (deflation), column-major
     const double *Z;   // [q][ldw] B W
     long ldw;
@@ -56,7 +58,9 @@ struct CGArgs {
     int G;                         // workgroups in the grid
     long long timeout_ticks;       // barrier wait limit in s_memrealtime ticks (100 MHz)
     int tile_lds;                  // doubles of dynamic LDS used by the stencil buffers
+    unsigned long long *stamps;    // optional [DBG_ITERS][8] phase timestamps of workgroup 0 (or null)
 };
+constexpr int DBG_ITERS = 64;
 
 // Launch plumbing implemented in kernels.hip.
 int tile_lds_doubles(int ty, int tx, int sy, int sx);

@@ -1,0 +1,191 @@
+"""Outer edge-preserving iteration driving the recycled shifted solver.
+
+One outer step k (Algorithm 5, per-k solve phase) on each instance:
+  1. k >= 1: new weights W_k from the previous step's selected solution
+     x^(k-1, l*)  (w = ((D x)^2 + beta)^(-1/2) per difference);
+  2. principal recycle space U_k from all previous solutions x^(k-1, 1..M)
+     plus Ritz vectors retained from U_{k-1} (Section 5.2), stabilised by
+     Algorithm 1;
+  3. all shifts solved: initial guess from U_k (eq. orthupdate), local spaces
+     of Ritz vectors and previous corrections (Algorithms 2-4), deflated CG.
+At k = 0 there is no principal space (the first-step spike of Section 7).
+
+The "plain" variant solves every shift from x0 = 0 with plain CG, one shift at
+a time -- the naive baseline of Section 7 with CG in place of MINRES.
+
+l* is fixed to the middle shift (ceil(M/2), 1-based) so that the plain and
+recycled runs see identical weight sequences.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import rsr, synth
+
+
+@dataclass
+class StepRecord:
+    k: int
+    wall_ms: float
+    matvec_A: int
+    matvec_E: int
+    iters: List[int]
+    relres: List[float]
+    relres_init: List[float]
+    p: int = 0
+    cg_kernel_ms: float = 0.0
+    cg_items: int = 0
+
+
+@dataclass
+class RecycleParams:
+    p: int
+    q: int = 5
+    n_ritz: int = 3
+    split_frac: float = 0.75
+    beta: float = 1e-4
+    cond_max: float = 1e10
+    init: int = rsr.INIT_MR
+
+
+def rhs_on_device(ctx: rsr.Context, inst: int, pr: synth.Problem):
+    """d = K x_true + e, b = K^T d, with K applied by the library."""
+    import torch
+    xt = torch.from_numpy(np.ascontiguousarray(pr.x_true)).cuda()
+    kx = ctx.apply(inst, rsr.OP_K, xt)
+    g = torch.from_numpy(np.ascontiguousarray(pr.noise_dir)).cuda()
+    e = g * (pr.noise_level * torch.linalg.vector_norm(kx) / torch.linalg.vector_norm(g))
+    d = (kx + e).contiguous()
+    b = ctx.apply(inst, rsr.OP_KT, d)
+    return d, b
+
+
+class OuterLoop:
+    """Runs outer steps of one config on one context (single instance or many)."""
+
+    def __init__(self, ctx: rsr.Context, cfg: synth.Config, method: str, rp: Optional[RecycleParams] = None,
+                 tol: Optional[float] = None, tiles: Optional[Dict[int, tuple]] = None,
+                 mode: Optional[int] = None):
+        import torch
+        self.ctx = ctx
+        self.cfg = cfg
+        self.method = method
+        self.rp = rp or RecycleParams(p=cfg.p, q=cfg.q)
+        self.tol = cfg.tol if tol is None else tol
+        self.M = len(cfg.gammas)
+        self.mode = mode if mode is not None else (rsr.SEQUENTIAL if cfg.mode == "sequential" else rsr.BATCHED)
+        shapes = [(p.ny, p.nx) for p in cfg.problems]
+        ctx.set_operators(shapes, [p.psf for p in cfg.problems])
+        if tiles:
+            for i, t in tiles.items():
+                ctx.set_tile(i, *t)
+        self.b = []
+        for i, pr in enumerate(cfg.problems):
+            _, b = rhs_on_device(ctx, i, pr)
+            self.b.append(b)
+        self.X = [torch.zeros((self.M, p.ny, p.nx), dtype=torch.float64, device="cuda") for p in cfg.problems]
+        self.k = 0
+        self.l_star = int(math.ceil(self.M / 2)) - 1
+
+    def reset(self):
+        for i in range(len(self.cfg.problems)):
+            self.X[i].zero_()
+        shapes = [(p.ny, p.nx) for p in self.cfg.problems]
+        tiles = [self.ctx.tile(i) for i in range(len(shapes))]
+        self.ctx.set_operators(shapes, [p.psf for p in self.cfg.problems])
+        for i, t in enumerate(tiles):
+            self.ctx.set_tile(i, *t)
+        self.k = 0
+
+    def _opts(self) -> rsr.SolveOptions:
+        M = self.M
+        g = self.cfg.gammas
+        if self.method == "plain":
+            return rsr.SolveOptions(tol=self.tol, mode=self.mode, init=rsr.INIT_ZERO)
+        split = int(math.ceil(self.rp.split_frac * M))
+        jl = max(1, min(split, M)) - 1            # J_L = split (1-based)
+        jr = max(split, M - 2)                    # J_R = M - 1 (1-based)
+        seq = self.mode == rsr.SEQUENTIAL
+        return rsr.SolveOptions(tol=self.tol, mode=self.mode, init=self.rp.init if self.k > 0 else rsr.INIT_ZERO,
+                                n_ritz=self.rp.n_ritz if self.k > 0 else 0, use_prev_k=self.k > 0,
+                                use_prev_shift=seq, split_I=split, gamma_JL=float(g[jl]),
+                                gamma_JR=float(g[min(jr, M - 1)]))
+
+    def step(self) -> StepRecord:
+        import torch
+        ctx = self.ctx
+        torch.cuda.synchronize()
+        a0, e0 = ctx.counters()
+        t0 = time.perf_counter()
+        n_inst = len(self.cfg.problems)
+        p_dim = 0
+        if self.k > 0:
+            for i in range(n_inst):
+                ctx.weights_from_image(i, self.X[i][self.l_star], self.rp.beta)
+                if self.method != "plain":
+                    n_retain = max(0, self.rp.p - self.M)
+                    p_dim = ctx.set_recycle_space(i, self.X[i], n_retain=n_retain,
+                                                  gamma_retain=float(self.cfg.gammas[0]), p_max=self.rp.p,
+                                                  cond_max=self.rp.cond_max)
+        o = self._opts()
+        iters, rel, rel0 = [], [], []
+        cg_ms, items = 0.0, 0
+        if n_inst == 1:
+            rc, st = ctx.solve(self.cfg.gammas, self.b[0], self.X[0], opts=o)
+            stats = [st]
+            t = ctx.last_timing()
+            cg_ms, items = t[0], t[2]
+        else:
+            stats = self._solve_instances(o)
+            t = ctx.last_timing()
+            cg_ms, items = t[0], t[2]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        a1, e1 = ctx.counters()
+        for st in stats:
+            iters += [s["iters"] for s in st]
+            rel += [s["relres_true"] for s in st]
+            rel0 += [s["relres_init"] for s in st]
+        rec = StepRecord(self.k, wall, a1 - a0, e1 - e0, iters, rel, rel0, p_dim, cg_ms, items)
+        self.k += 1
+        return rec
+
+    def _solve_instances(self, o: rsr.SolveOptions):
+        """All instances and shifts in one batched call (uneven sizes in one launch)."""
+        import torch
+        M = self.M
+        n_inst = len(self.cfg.problems)
+        inst = [i for i in range(n_inst) for _ in range(M)]
+        gam = [float(g) for _ in range(n_inst) for g in self.cfg.gammas]
+        slots = [l for _ in range(n_inst) for l in range(M)]
+        # pack right-hand sides and solutions with a common stride
+        nmax = max(p.ny * p.nx for p in self.cfg.problems)
+        if not hasattr(self, "_Bp"):
+            self._Bp = torch.zeros((n_inst * M, nmax), dtype=torch.float64, device="cuda")
+            self._Xp = torch.zeros((n_inst * M, nmax), dtype=torch.float64, device="cuda")
+            for i in range(n_inst):
+                for l in range(M):
+                    self._Bp[i * M + l, : self.b[i].numel()] = self.b[i].reshape(-1)
+        for i in range(n_inst):
+            n = self.X[i][0].numel()
+            self._Xp[i * M:(i + 1) * M, :n] = self.X[i].reshape(M, -1)
+        rc, st = self.ctx.solve(gam, self._Bp, self._Xp, inst=inst, slots=slots, opts=o, shared_b=False)
+        for i in range(n_inst):
+            n = self.X[i][0].numel()
+            self.X[i].copy_(self._Xp[i * M:(i + 1) * M, :n].reshape(self.X[i].shape))
+        return [st[i * M:(i + 1) * M] for i in range(n_inst)]
+
+    def run(self, steps: int, log=None) -> List[StepRecord]:
+        out = []
+        for _ in range(steps):
+            r = self.step()
+            if log is not None:
+                print(f"[{self.method}] k={r.k} wall={r.wall_ms:.2f} ms A={r.matvec_A} E={r.matvec_E} p={r.p} "
+                      f"iters={r.iters}", file=log, flush=True)
+            out.append(r)
+        return out
