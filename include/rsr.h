@@ -159,15 +159,18 @@ rsr_status rsr_set_recycle_space(rsr_ctx *ctx, int inst, const double *U_raw, lo
 rsr_status rsr_solve_shift_set(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *b,
                                double *X, rsr_shift_stats *stats_host, void *stream);
 
-/* Adjoint for L(x_1..x_M): given the solutions X of a shift set on one
+/* Adjoint for L(x_1..x_M) (gradient of the exact shifted solutions by
+ * implicit differentiation): given the solutions X of a shift set on one
  * instance and Gbar = dL/dX (device, same layout), solves B_l lambda_l =
  * Gbar_l with the same recycled solver (B_l is symmetric) and returns
  *   dgamma_host[l] = -lambda_l^T E x_l                       (host [n_sys])
- *   dw_h, dw_v     = -sum_l gamma_l (D lambda_l) .* (D x_l)  (device [ny*nx], each plane)
+ *   dw_h, dw_v     = -sum_l gamma_l (D lambda_l) .* (D x_l)  (device [ny*nx], each plane;
+ *                    zero where the difference does not exist)
+ *   db             = sum_l lambda_l                          (device [ny*nx], may be NULL)
  * Lambda (device, layout of X) receives the adjoint solutions.             */
 rsr_status rsr_adjoint(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *X,
                        const double *Gbar, double *Lambda, double *dgamma_host, double *dw_h,
-                       double *dw_v, rsr_shift_stats *stats_host, void *stream);
+                       double *dw_v, double *db, rsr_shift_stats *stats_host, void *stream);
 
 /* Time the candidate tile shapes of one instance's stencil for a batch of
  * n_vec vectors and keep the fastest (optionally cached in a text file).    */

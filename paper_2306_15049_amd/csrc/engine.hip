@@ -1197,7 +1197,8 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
 }
 
 rsr_status rsr_adjoint(rsr_ctx *c, const rsr_solve_desc *d, const double *X, const double *Gbar, double *Lambda,
-                       double *dgamma_host, double *dw_h, double *dw_v, rsr_shift_stats *stats, void *stream)
+                       double *dgamma_host, double *dw_h, double *dw_v, double *db, rsr_shift_stats *stats,
+                       void *stream)
 {
     if (!c) return RSR_E_ARG;
     if (!d || !X || !Gbar || !Lambda) {
@@ -1235,7 +1236,7 @@ rsr_status rsr_adjoint(rsr_ctx *c, const rsr_solve_desc *d, const double *X, con
             wv = wh + I.n;
         }
         HIPCHK(launch_grad(X, Lambda, d->ld_x, gam.as<double>(), m, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny,
-                           I.nx, wh, wv, dg.as<double>(), nch, s));
+                           I.nx, wh, wv, db, dg.as<double>(), nch, s));
         std::vector<double> h((size_t)nch * m);
         HIPCHK(hipMemcpyAsync(h.data(), dg.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

@@ -114,6 +114,6 @@ hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jobs_host, int
 
 hipError_t launch_grad(const double *X, const double *Lam, long ld, const double *gammas_dev, int m,
                        const double *wh, const double *wv, int ny, int nx, double *dw_h, double *dw_v,
-                       double *dg_partial, int nchunks, hipStream_t s);
+                       double *db, double *dg_partial, int nchunks, hipStream_t s);
 
 }  // namespace rsr

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(NT) void k_grad(const double *__restrict__ X, const
                                              const double *__restrict__ gam, int m,
                                              const double *__restrict__ wh, const double *__restrict__ wv,
                                              int ny, int nx, double *__restrict__ dwh, double *__restrict__ dwv,
-                                             double *__restrict__ dgp)
+                                             double *__restrict__ db, double *__restrict__ dgp)
 {
     __shared__ double red[NT / 64];
     const long n = (long)ny * nx;
@@ -335,23 +335,25 @@ __global__ __launch_bounds__(NT) void k_grad(const double *__restrict__ X, const
     }
     for (long gi = lo + threadIdx.x; gi < hi; gi += NT) {
         const int i = gi / nx, j = gi % nx;
-        double sh = 0.0, sv = 0.0;
+        double sh = 0.0, sv = 0.0, sb = 0.0;
         for (int l = 0; l < m; ++l) {
             const double *x = X + l * ld, *la = L + l * ld;
             if (j < nx - 1) sh += gam[l] * (la[gi + 1] - la[gi]) * (x[gi + 1] - x[gi]);
             if (i < ny - 1) sv += gam[l] * (la[gi + nx] - la[gi]) * (x[gi + nx] - x[gi]);
+            sb += la[gi];
         }
         dwh[gi] = -sh;
         dwv[gi] = -sv;
+        if (db) db[gi] = sb;
     }
 }
 
 hipError_t launch_grad(const double *X, const double *Lam, long ld, const double *gammas_dev, int m,
                        const double *wh, const double *wv, int ny, int nx, double *dw_h, double *dw_v,
-                       double *dg_partial, int nchunks, hipStream_t s)
+                       double *db, double *dg_partial, int nchunks, hipStream_t s)
 {
     hipLaunchKernelGGL(k_grad, dim3(nchunks), dim3(NT), 0, s, X, Lam, ld, gammas_dev, m, wh, wv, ny, nx, dw_h,
-                       dw_v, dg_partial);
+                       dw_v, db, dg_partial);
     return hipGetLastError();
 }
 

@@ -89,7 +89,7 @@ def load():
     L.rsr_apply.argtypes = [P, I, I, D, P, P, I, L_, P]
     L.rsr_set_recycle_space.argtypes = [P, I, P, L_, I, I, D, I, D, pI, P]
     L.rsr_solve_shift_set.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(ShiftStats), P]
-    L.rsr_adjoint.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, P, pD, P, P, ctypes.POINTER(ShiftStats), P]
+    L.rsr_adjoint.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, P, pD, P, P, P, ctypes.POINTER(ShiftStats), P]
     L.rsr_autotune.argtypes = [P, I, I, ctypes.c_char_p]
     L.rsr_get_tile.argtypes = [P, I, pI, pI]
     L.rsr_set_tile.argtypes = [P, I, I, I]
@@ -252,7 +252,7 @@ class Context:
         return rc, [s.as_dict() for s in st]
 
     def adjoint(self, gammas, X, Gbar, Lam, inst: int = 0, slots=None, opts: Optional[SolveOptions] = None):
-        """Adjoint solves and gradients; returns (status, dgamma[np], dwh, dwv, stats)."""
+        """Adjoint solves and gradients; returns (status, dgamma[np], dwh, dwv, db, stats)."""
         import torch
         o = opts or SolveOptions()
         m = len(gammas)
@@ -261,12 +261,13 @@ class Context:
         dg = np.zeros(m)
         dwh = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
         dwv = torch.empty_like(dwh)
+        db = torch.empty_like(dwh)
         st = (ShiftStats * m)()
         rc = self.lib.rsr_adjoint(self.h, ctypes.byref(d), _ptr(X), _ptr(Gbar), _ptr(Lam),
-                                  dg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(dwh), _ptr(dwv), st,
-                                  _stream())
+                                  dg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(dwh), _ptr(dwv), _ptr(db),
+                                  st, _stream())
         self._check(rc, allow_not_converged=True)
-        return rc, dg, dwh, dwv, [s.as_dict() for s in st]
+        return rc, dg, dwh, dwv, db, [s.as_dict() for s in st]
 
     # ------------------------------------------------------------ misc --
     def autotune(self, inst: int, n_vec: int = 1, cache_path: Optional[str] = None):
