@@ -13,7 +13,7 @@
  *   b = C^T d                                                      (Sec. 2.1)
  * The solve is plain Hestenes-Stiefel conjugate gradients from x0 = 0 (no
  * recycling), stopped on ||r|| <= tol ||b|| and accepted on the recomputed
- * true residual; this is the "naive" per-system solve of Section 7 with CG in
+ * true residual; this is the "naive" per-system solve of Section 8 with CG in
  * place of MINRES, which reaches the same unique solution of the SPD system
  * (Section 3 states A SPD and E SPSD).
  *

@@ -27,14 +27,29 @@ namespace rsr {
 
 __device__ __forceinline__ unsigned long long realtime() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Coherence across XCDs.  Each XCD has its own L2; an agent-scope acquire
+// invalidates it.  While the work assignment is unchanged a workgroup owns the
+// same tiles in every phase, so its own tile data, the weight planes and the
+// local bases stay valid in its L2 and L1.  Only data written by other
+// workgroups -- halo cells, reduction partials, deflation coefficients -- is
+// read with agent-scope coherent loads (sc1), which do not hit stale lines.
+// Writers publish with the release at the barrier arrival.  When the
+// assignment changes, one full agent-scope acquire is taken.
+__device__ __forceinline__ double cld(const double *p)
+{
+    const unsigned long long v =
+        __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)v);
+}
+
 // Grid barrier: a monotone arrival counter.  Barrier k completes when the
 // counter reaches (k+1)*G.  Thread 0 of each workgroup publishes the
 // workgroup's stores with one agent-scope release (the arrival), spins on
 // relaxed loads (an acquire inside the loop would invalidate the XCD's L2 on
-// every poll, evicting what the still-working workgroups are reading), and
-// performs a single agent-scope acquire once the count is reached.  The wait
-// is bounded: past the time limit the waiting workgroup raises the abort flag
-// and every workgroup leaves the kernel at its next barrier, so the grid
+// every poll), and then takes a workgroup-scope acquire (see the coherence
+// note above; a full agent acquire is issued separately when needed).  The
+// wait is bounded: past the time limit the waiting workgroup raises the abort
+// flag and every workgroup leaves the kernel at its next barrier, so the grid
 // always drains.
 __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned long long target, int *abort_flag,
                                              long long timeout, int *s_flag)
@@ -53,7 +68,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned l
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         *s_flag = ok;
     }
     __syncthreads();
@@ -151,7 +166,7 @@ __device__ void block_reduce_partials(const double *part, int base, int nch, int
         const double *p = part + (long)(base + k) * nv + v0;
 #pragma unroll
         for (int j = 0; j < NVB; ++j)
-            if (j < cnt) acc[j] += p[j];
+            if (j < cnt) acc[j] += cld(p + j);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -191,7 +206,7 @@ __device__ __forceinline__ void flush_partials(const double (&acc)[NVB], int cnt
 }
 
 constexpr int NB = 4;    // pixels per thread whose loads are issued together (tile interior)
-constexpr int NBW = 16;  // window pixels per thread loaded together in phase 1
+constexpr int NBW = 12;  // window rows per thread loaded together in phase 1
 
 __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
 {
@@ -270,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
 #pragma unroll
                 for (int u = 0; u < NB; ++u) {
                     const int k = base + u * NT + threadIdx.x;
-                    const int gy = y0 + k / I.tx, gx = x0 + k % I.tx;
+                    const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
                     ok[u] = k < ne && gy < I.ny && gx < I.nx;
                     gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
                 }
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
         double *flat = tile;
         for (int f = threadIdx.x; f < F; f += NT) {
             const int l = find_pos(O.foff, mo, f);
-            flat[f] = A.partB[(long)(A.sys[O.act[l]].tile_base + (f - O.foff[l])) * NVB];
+            flat[f] = cld(A.partB + (long)(A.sys[O.act[l]].tile_base + (f - O.foff[l])) * NVB);
         }
         __syncthreads();
         Assign N = cur ? S0 : S1;
@@ -379,6 +394,8 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
         }
         const int mn = s_m[cur ^ 1];
         if (mn == 0) break;
+        // tiles move between workgroups when the active set shrinks: drop cached copies
+        if (mn != mo) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         build_assign(A, N, mn, G, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp);
         const int ipbn = s_ipb[cur ^ 1];
         stamp(it, 1);
@@ -415,7 +432,7 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
                         if (threadIdx.x < q) {
                             double m = 0.0;
                             for (int j = 0; j < q; ++j) m += Y.Ginv[threadIdx.x * QMAX + j] * s_vals[j];
-                            const double cold = it > 0 ? Y.cbuf[(it & 1) * QMAX + threadIdx.x] : 0.0;
+                            const double cold = it > 0 ? cld(Y.cbuf + (it & 1) * QMAX + threadIdx.x) : 0.0;
                             const double cn = fma(beta, cold, m);
                             s_c[threadIdx.x] = cn;
                             // the workgroup holding the system's first chunk publishes c_{j+1}
@@ -441,34 +458,38 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
                 double *pbuf = tile + g.offP;
                 // stage ph = r + beta ph_old on the window (all of a thread's loads
                 // issued together); keep the interior in pbuf
-                const int nw = g.H0 * g.W0;
-                for (int base = 0; base < nw; base += NT * NBW) {
+                const WinMap wm = win_map(g.W0);
+                const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);     // window column of this thread
+                const int gx = x0 - g.hx + lj;
+                const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
+                const bool colown = lj >= g.hx && lj < g.hx + I.tx;
+                for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
                     long gi[NBW];
-                    bool ok[NBW];
+                    bool ok[NBW], own[NBW];
 #pragma unroll
                     for (int u = 0; u < NBW; ++u) {
-                        const int k = base + u * NT + threadIdx.x;
-                        const int gy = y0 - g.hy + k / g.W0, gx = x0 - g.hx + k % g.W0;
-                        ok[u] = k < nw && gy >= 0 && gy < I.ny && gx >= 0 && gx < I.nx;
+                        const int li = li0 + u * wm.rs;
+                        const int gy = y0 - g.hy + li;
+                        ok[u] = colok && li < g.H0 && gy >= 0 && gy < I.ny;
+                        own[u] = colown && li >= g.hy && li < g.hy + I.ty;
                         gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
                     }
                     double rv[NBW], pv[NBW];
 #pragma unroll
                     for (int u = 0; u < NBW; ++u) {
-                        rv[u] = ok[u] ? Yr[gi[u]] : 0.0;
-                        pv[u] = (ok[u] && it > 0) ? pold[gi[u]] : 0.0;
+                        // own interior: cached; halo cells belong to other tiles: coherent loads
+                        rv[u] = ok[u] ? (own[u] ? Yr[gi[u]] : cld(Yr + gi[u])) : 0.0;
+                        pv[u] = (ok[u] && it > 0) ? (own[u] ? pold[gi[u]] : cld(pold + gi[u])) : 0.0;
                     }
 #pragma unroll
                     for (int u = 0; u < NBW; ++u) {
-                        const int k = base + u * NT + threadIdx.x;
-                        if (k < nw) {
-                            const int li = k / g.W0, lj = k % g.W0;
+                        const int li = li0 + u * wm.rs;
+                        if (lj < g.W0 && li < g.H0) {
                             const double v = ok[u] ? fma(beta, pv[u], rv[u]) : 0.0;
                             tile[li * g.P0 + lj] = v;
-                            const int ii = li - g.hy, jj = lj - g.hx;
-                            if (ok[u] && ii >= 0 && ii < I.ty && jj >= 0 && jj < I.tx) {
+                            if (ok[u] && own[u]) {
                                 pnew[gi[u]] = v;
-                                pbuf[ii * g.PE + jj] = v;
+                                pbuf[(li - g.hy) * g.PE + (lj - g.hx)] = v;
                             }
                         }
                     }
@@ -487,7 +508,7 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
 #pragma unroll
                     for (int u = 0; u < NB; ++u) {
                         const int k = base + u * NT + threadIdx.x;
-                        const int gy = y0 + k / I.tx, gx = x0 + k % I.tx;
+                        const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
                         ok[u] = k < ne && gy < I.ny && gx < I.nx;
                         gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
                     }
@@ -495,7 +516,7 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
 #pragma unroll
                     for (int u = 0; u < NB; ++u) {
                         const int k = base + u * NT + threadIdx.x;
-                        const int ii = ok[u] ? k / I.tx : 0, jj = ok[u] ? k % I.tx : 0;
+                        const int ii = ok[u] ? (k >> I.ltx) : 0, jj = ok[u] ? (k & (I.tx - 1)) : 0;
                         p[u] = pbuf[ii * g.PE + jj];
                         w[u] = ebuf[ii * g.PE + jj];
                     }

@@ -144,6 +144,8 @@ void upload_inst(rsr_ctx *c)
         d.nx = I.nx;
         d.ty = I.ty;
         d.tx = I.tx;
+        d.lty = __builtin_ctz((unsigned)I.ty);
+        d.ltx = __builtin_ctz((unsigned)I.tx);
         d.nty = (I.ny + I.ty - 1) / I.ty;
         d.ntx = (I.nx + I.tx - 1) / I.tx;
         d.sep = I.sep;
@@ -1266,7 +1268,8 @@ rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
 {
     return guard(c, [&] {
         Instance &I = get_inst(c, ii);
-        if (ty < 4 || tx < 4 || ty > 128 || tx > 128) fail(RSR_E_ARG, "tile sides must be in [4, 128]");
+        if (ty < 4 || tx < 4 || ty > 64 || tx > 64 || (ty & (ty - 1)) || (tx & (tx - 1)))
+            fail(RSR_E_ARG, "tile sides must be powers of two in [4, 64]");
         const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I));
         if (cg_lds_bytes(tl) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
         set_device(c);
@@ -1305,7 +1308,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         y.ensure(sizeof(double) * n * n_vec);
         hipStream_t s = nullptr;
         HIPCHK(launch_fill(v.as<double>(), 1.0, n * n_vec, s));
-        const int cand[][2] = {{8, 32}, {16, 16}, {16, 32}, {32, 16}, {32, 32}, {16, 64}, {32, 64}, {64, 32}, {64, 64}};
+        const int cand[][2] = {{8, 32}, {16, 16}, {16, 32}, {32, 16}, {32, 32}, {8, 64}, {16, 64}, {32, 64}, {64, 32}};
         double best = 1e30;
         int bty = I.ty, btx = I.tx;
         const long mvA = c->mv_A, mvE = c->mv_E;

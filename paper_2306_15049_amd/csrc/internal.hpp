@@ -15,7 +15,8 @@ constexpr int MAXS = 31;       // largest separable PSF extent with a compiled p
 // Device view of one instance (image geometry, PSF, weights, tiling).
 struct InstDev {
     int ny, nx;
-    int ty, tx;        // tile (outputs per workgroup item)
+    int ty, tx;        // tile (outputs per workgroup item), powers of two
+    int lty, ltx;      // log2 of ty, tx
     int nty, ntx;      // tiles per dimension
     int sep;           // 1: rank-1 separable PSF, 0: direct 2-D stencil
     int sy, sx;        // PSF extent (odd); for sep both equal the zero-padded square size

@@ -40,22 +40,25 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
     if ((int)blockIdx.x >= ntile) return;
     const int y0 = (blockIdx.x / I.ntx) * I.ty, x0 = (blockIdx.x % I.ntx) * I.tx;
     const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx);
-    constexpr int NBW = 16;   // window pixels per thread whose loads are issued together
+    constexpr int NBW = 12;   // window rows per thread whose loads are issued together
     const double *__restrict__ vin = J.v;
-    const int nw = g.H0 * g.W0;
-    for (int base = 0; base < nw; base += NT * NBW) {
+    const WinMap wm = win_map(g.W0);
+    const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);
+    const int gx = x0 - g.hx + lj;
+    const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
+    for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
         double v[NBW];
 #pragma unroll
         for (int u = 0; u < NBW; ++u) {
-            const int k = base + u * NT + threadIdx.x;
-            const int gy = y0 - g.hy + k / g.W0, gx = x0 - g.hx + k % g.W0;
-            const bool ok = k < nw && gy >= 0 && gy < I.ny && gx >= 0 && gx < I.nx;
+            const int li = li0 + u * wm.rs;
+            const int gy = y0 - g.hy + li;
+            const bool ok = colok && li < g.H0 && gy >= 0 && gy < I.ny;
             v[u] = ok ? vin[(long)gy * I.nx + gx] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NBW; ++u) {
-            const int k = base + u * NT + threadIdx.x;
-            if (k < nw) lds[(k / g.W0) * g.P0 + (k % g.W0)] = v[u];
+            const int li = li0 + u * wm.rs;
+            if (lj < g.W0 && li < g.H0) lds[li * g.P0 + lj] = v[u];
         }
     }
     __syncthreads();
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
     if (J.cA != 0.0) tile_A(I, g, lds, y0, x0, J.cA);
     const double *ebuf = lds + g.offE;
     for (int k = threadIdx.x; k < I.ty * I.tx; k += NT) {
-        const int i = k / I.tx, j = k % I.tx;
+        const int i = k >> I.ltx, j = k & (I.tx - 1);
         const int gy = y0 + i, gx = x0 + j;
         if (gy < I.ny && gx < I.nx) J.y[(long)gy * I.nx + gx] = ebuf[i * g.PE + j];
     }

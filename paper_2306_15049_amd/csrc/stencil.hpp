@@ -26,6 +26,15 @@ __device__ __forceinline__ double wave_sum(double v)
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Staged-window traversal without integer division: a row of the window is
+// covered by LW consecutive threads (LW = 64 or 128 >= window width), the
+// NT / LW thread rows step down the window.
+struct WinMap {
+    int lw_log;   // log2(LW)
+    int rs;       // window rows per step (NT / LW)
+};
+__host__ __device__ inline WinMap win_map(int W0) { return W0 <= 64 ? WinMap{6, NT / 64} : WinMap{7, NT / 128}; }
+
 // Tile geometry shared by host (LDS sizing) and device.
 struct Geo {
     int ry, rx;        // PSF radii
@@ -223,8 +232,8 @@ __device__ inline void tile_E(const InstDev &I, const Geo &g, double *lds, int y
 #pragma unroll
         for (int u = 0; u < NE; ++u) {
             const int k = base + u * NT + threadIdx.x;
-            gy[u] = y0 + k / tx;
-            gx[u] = x0 + k % tx;
+            gy[u] = y0 + (k >> I.ltx);
+            gx[u] = x0 + (k & (tx - 1));
             ok[u] = cE != 0.0 && k < ne && gy[u] < ny && gx[u] < nx;
             gi[u] = ok[u] ? (long)gy[u] * nx + gx[u] : 0;
         }
@@ -240,7 +249,7 @@ __device__ inline void tile_E(const InstDev &I, const Geo &g, double *lds, int y
         for (int u = 0; u < NE; ++u) {
             const int k = base + u * NT + threadIdx.x;
             if (k < ne) {
-                const int i = k / tx, j = k % tx;
+                const int i = k >> I.ltx, j = k & (tx - 1);
                 double e = 0.0;
                 if (ok[u]) {
                     const double *c = buf0 + (g.hy + i) * g.P0 + (g.hx + j);

@@ -8,10 +8,10 @@ One outer step k (Algorithm 5, per-k solve phase) on each instance:
      Algorithm 1;
   3. all shifts solved: initial guess from U_k (eq. orthupdate), local spaces
      of Ritz vectors and previous corrections (Algorithms 2-4), deflated CG.
-At k = 0 there is no principal space (the first-step spike of Section 7).
+At k = 0 there is no principal space (the first-step spike of Section 8.2).
 
 The "plain" variant solves every shift from x0 = 0 with plain CG, one shift at
-a time -- the naive baseline of Section 7 with CG in place of MINRES.
+a time -- the naive baseline of Section 8 with CG in place of MINRES.
 
 l* is fixed to the middle shift (ceil(M/2), 1-based) so that the plain and
 recycled runs see identical weight sequences.

@@ -7,7 +7,7 @@ none of the method's arithmetic (no blur, no differences, no weights, no
 solves): the data ``d = K x_true + e`` and the right-hand side ``b = K^T d``
 are formed by whichever side consumes these inputs, with its own operators.
 
-The paper's experiments (Section 7, Examples 1 and 2) use a third-party
+The paper's experiments (Section 8, Examples 1 and 2) use a third-party
 128x128 test image and an 82x82 CT phantom that are not available here; the
 rectangle phantoms below stand in for them.  They share the structure class
 that drives the edge-preserving weights: flat regions with sharp edges and
@@ -22,7 +22,7 @@ Readings fixed here (each is stated in the design notes as well):
     sorted column indices uniformly from the image and a value from U[0, 1];
     later rectangles overwrite earlier ones.
   * Noise: g ~ N(0, I); the consumer scales it to e = level * ||K x|| g / ||g||.
-  * Shifts: numpy.logspace(lo, hi, M), inclusive and ascending (Section 4.2
+  * Shifts: numpy.logspace(lo, hi, M), inclusive and ascending (Section 4.1
     orders the shifts ascending).
 """
 from __future__ import annotations
