@@ -83,7 +83,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cap", type=int, default=40)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other recycled solve mode")
     ap.add_argument("--mode", choices=["sequential", "batched"], default=None,
                     help="solve mode of the recycled method (default: the workload's own)")
     ap.add_argument("--verbose", action="store_true")
@@ -102,36 +103,52 @@ def main():
     torch.cuda.set_device(0)
     cfg = synth.config(args.config)
     ctx = rsr.Context(0)
-    rmode = None if args.mode is None else (rsr.SEQUENTIAL if args.mode == "sequential" else rsr.BATCHED)
-    loop = irn.OuterLoop(ctx, cfg, "recycled", mode=rmode)
-    if args.autotune:
-        loop_tiles = {i: ctx.autotune(i, 1) for i in range(len(cfg.problems))}
-    # warm-up: an untimed loop of W steps from k = 0
-    if args.warmup > 0:
-        loop.run(args.warmup, log=sys.stderr if args.verbose else None)
-    loop.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    recs = loop.run(args.steps, log=sys.stderr if args.verbose else None)
-    torch.cuda.synchronize()
-    t_rec = (time.perf_counter() - t0) * 1e3 / args.steps
+    M = len(cfg.gammas)
+    seq_default = cfg.mode == "sequential"
+    head_mode = rsr.SEQUENTIAL if (args.mode or ("sequential" if seq_default else "batched")) == "sequential" \
+        else rsr.BATCHED
+    log = sys.stderr if args.verbose else None
+
+    def timed_loop(method, mode, label):
+        """W untimed steps, then a fresh loop from k = 0 timed for exactly K steps."""
+        loop = irn.OuterLoop(ctx, cfg, method, mode=mode)
+        if not args.no_autotune:
+            tiles = {i: ctx.autotune(i, 1 if mode == rsr.SEQUENTIAL else M) for i in range(len(cfg.problems))}
+            if log:
+                print(f"[{label}] autotuned tiles {tiles}", file=log, flush=True)
+            loop.reset()
+        if args.warmup > 0:
+            loop.run(args.warmup, log=log)
+        loop.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = loop.run(args.steps, log=log)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        return ms, recs
+
+    t_rec, recs = timed_loop("recycled", head_mode, "recycled")
+    other = None
+    if not args.no_variants:
+        alt_mode = rsr.BATCHED if head_mode == rsr.SEQUENTIAL else rsr.SEQUENTIAL
+        t_alt, arecs = timed_loop("recycled", alt_mode, "recycled-alt")
+        other = {"mode": "batched" if alt_mode == rsr.BATCHED else "sequential", "ms_per_step": t_alt,
+                 "matvecs_A_per_step": sum(r.matvec_A for r in arecs) / args.steps,
+                 "per_step_ms": [round(r.wall_ms, 3) for r in arecs],
+                 "per_step_matvecs_A": [r.matvec_A for r in arecs],
+                 "max_relres": max(max(r.relres) for r in arecs)}
 
     plain = None
     if not args.no_plain:
-        ploop = irn.OuterLoop(ctx, cfg, "plain", mode=rsr.SEQUENTIAL)
-        if args.warmup > 0:
-            ploop.run(1, log=sys.stderr if args.verbose else None)
-        ploop.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        precs = ploop.run(args.steps, log=sys.stderr if args.verbose else None)
-        torch.cuda.synchronize()
-        t_plain = (time.perf_counter() - t0) * 1e3 / args.steps
+        t_plain, precs = timed_loop("plain", rsr.SEQUENTIAL, "plain")
         plain = {"ms_per_step": t_plain,
                  "matvecs_A_per_step": sum(r.matvec_A for r in precs) / args.steps,
                  "matvecs_E_per_step": sum(r.matvec_E for r in precs) / args.steps,
                  "per_step_ms": [round(r.wall_ms, 3) for r in precs],
                  "per_step_matvecs_A": [r.matvec_A for r in precs]}
+        if other is not None:
+            other["speedup_vs_plain_per_shift"] = t_plain / other["ms_per_step"]
+            other["matvec_ratio_plain_over_this"] = plain["matvecs_A_per_step"] / other["matvecs_A_per_step"]
 
     # roofline of the dominant kernel (persistent CG) over the timed recycled steps
     pr0 = cfg.problems[0]
@@ -145,7 +162,7 @@ def main():
     for r in recs:
         its = sum(r.iters)
         tot_iters += its
-        m_share = 1 if cfg.mode == "sequential" else len(cfg.gammas)
+        m_share = 1 if head_mode == rsr.SEQUENTIAL else len(cfg.gammas)
         q = q_eff if r.k > 0 else 1
         tot_bytes += its * n_px * cg_alg_bytes_per_px_iter(q, m_share)
         tot_flops += its * n_px * cg_alg_flops_per_px_iter(s_taps, q)
@@ -157,6 +174,7 @@ def main():
             "alg_bytes_per_px_iter": cg_alg_bytes_per_px_iter(q_eff, 1),
             "fp64_tflops": tot_flops / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0,
             "cg_kernel_ms_per_step": tot_ms / args.steps,
+            "cg_avg_launch_ms": tot_ms / max(1, sum(r.cg_launches for r in recs)),
             "us_per_cg_iteration": tot_ms * 1e3 / max(1, tot_iters)}
 
     cpu = None
@@ -179,7 +197,8 @@ def main():
         "data": "synthetic (seeded rectangle phantom, Gaussian PSF, 1% noise)",
         "config": {"workload": f"{cfg.name}: {pr0.ny}x{pr0.nx} deblur, PSF {s_taps}x{s_taps} sigma={pr0.sigma}, "
                                f"{len(cfg.gammas)} shifts 1e-5..1e1, p={cfg.p}, q={cfg.q}, "
-                               f"{'one shift at a time' if cfg.mode == 'sequential' else 'batched'}, tol={cfg.tol}",
+                               f"{'one shift at a time' if head_mode == rsr.SEQUENTIAL else 'all shifts batched'}, "
+                               f"tol={cfg.tol}",
                    "outer_steps_timed": args.steps, "parallelism": "single GPU"},
         "recycled": {"ms_per_step": t_rec, "matvecs_A_per_step": mv_rec,
                      "matvecs_E_per_step": sum(r.matvec_E for r in recs) / args.steps,
@@ -188,6 +207,7 @@ def main():
                      "per_step_p": [r.p for r in recs],
                      "max_relres": max(max(r.relres) for r in recs)},
         "plain": plain,
+        "recycled_other_mode": other,
         "speedup_vs_plain_per_shift": (plain["ms_per_step"] / t_rec) if plain else None,
         "matvec_ratio_plain_over_recycled": (plain["matvecs_A_per_step"] / mv_rec) if plain else None,
         "roofline": roof,

@@ -172,8 +172,11 @@ rsr_status rsr_adjoint(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *X
                        const double *Gbar, double *Lambda, double *dgamma_host, double *dw_h,
                        double *dw_v, double *db, rsr_shift_stats *stats_host, void *stream);
 
-/* Time the candidate tile shapes of one instance's stencil for a batch of
- * n_vec vectors and keep the fastest (optionally cached in a text file).    */
+/* Autotune the persistent CG kernel for one instance: for every candidate
+ * tile shape and workgroup cap, time a bounded solve (40 iterations) of n_vec
+ * systems advancing together and keep the fastest per iteration.  The choice
+ * is cached in a text file when cache_path is given (lines
+ * "gfx950 ny nx sy sx n_vec -> ty tx cap").                                   */
 rsr_status rsr_autotune(rsr_ctx *ctx, int inst, int n_vec, const char *cache_path);
 
 /* Current tile shape of an instance (host outputs). */

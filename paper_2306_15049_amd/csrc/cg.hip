@@ -42,34 +42,73 @@ __device__ __forceinline__ double cld(const double *p)
     return __longlong_as_double((long long)v);
 }
 
-// Grid barrier: a monotone arrival counter.  Barrier k completes when the
-// counter reaches (k+1)*G.  Thread 0 of each workgroup publishes the
-// workgroup's stores with one agent-scope release (the arrival), spins on
-// relaxed loads (an acquire inside the loop would invalidate the XCD's L2 on
-// every poll), and then takes a workgroup-scope acquire (see the coherence
-// note above; a full agent acquire is issued separately when needed).  The
-// wait is bounded: past the time limit the waiting workgroup raises the abort
-// flag and every workgroup leaves the kernel at its next barrier, so the grid
-// always drains.
-__device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned long long target, int *abort_flag,
-                                             long long timeout, int *s_flag)
+// Grid barrier, two levels.  Workgroups are split into BAR_GROUPS groups
+// (workgroup b in group b % 8, i.e. one group per XCD under round-robin
+// dispatch).  Each workgroup publishes its stores with one agent-scope release
+// on its group's arrival counter; the last arriver of a group (the counter
+// reaching k * group size at barrier k) increments the global counter and,
+// once all groups have arrived, releases its group through the group's epoch
+// word.  One contended counter of G arrivals becomes G/8 arrivals per group
+// counter plus 8 on the global one, and every group polls its own word.
+// All spins use relaxed loads (an acquire inside the loop would invalidate
+// the XCD's L2 on every poll); the final acquire is workgroup-scope (see the
+// coherence note above).  Every wait is bounded: past the time limit the
+// waiting workgroup raises the abort flag and every workgroup leaves the
+// kernel at its next barrier, so the grid always drains.
+struct BarCtl {
+    unsigned long long *glob;   // global counter
+    unsigned long long *arr;    // group arrival counter of this workgroup
+    unsigned long long *rel;    // group release epoch of this workgroup
+    int *abort_flag;
+    unsigned long long gsize;   // workgroups in this group
+    unsigned long long ngrp;    // groups
+};
+
+__device__ __forceinline__ BarCtl bar_ctl(const CGArgs &A)
+{
+    BarCtl b;
+    const int ngrp = (A.G % BAR_GROUPS == 0) ? BAR_GROUPS : 1;
+    const int grp = blockIdx.x % ngrp;
+    char *base = (char *)A.bar;
+    b.glob = (unsigned long long *)base;
+    b.arr = (unsigned long long *)(base + 256 * (2 + grp));
+    b.rel = (unsigned long long *)(base + 256 * (2 + BAR_GROUPS + grp));
+    b.abort_flag = A.abort_flag;
+    b.gsize = (unsigned long long)(A.G / ngrp);
+    b.ngrp = (unsigned long long)ngrp;
+    return b;
+}
+
+__device__ __forceinline__ bool spin_until(unsigned long long *word, unsigned long long target, int *abort_flag,
+                                           unsigned long long t0, long long timeout)
+{
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if ((long long)(realtime() - t0) > timeout) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool grid_barrier(const BarCtl &b, unsigned long long k, long long timeout, int *s_flag)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long t0 = realtime();
-        int ok = 1;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-            if ((long long)(realtime() - t0) > timeout) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+        bool ok;
+        const unsigned long long old = __hip_atomic_fetch_add(b.arr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == k * b.gsize - 1) {
+            __hip_atomic_fetch_add(b.glob, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            ok = spin_until(b.glob, k * b.ngrp, b.abort_flag, t0, timeout);
+            if (ok) __hip_atomic_store(b.rel, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = spin_until(b.rel, k, b.abort_flag, t0, timeout);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        *s_flag = ok;
+        *s_flag = ok ? 1 : 0;
     }
     __syncthreads();
     return *s_flag != 0;
@@ -212,16 +251,18 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
 {
     extern __shared__ double smem[];
     double *tile = smem;                          // stencil buffers / reduction scratch
-    double *s_rho = smem + A.tile_lds;            // [MAXSYS] current r.r
-    double *s_rho_old = s_rho + MAXSYS;           // [MAXSYS] previous r.r
-    int *ib = (int *)(s_rho_old + MAXSYS);
+    const int ms = A.msys;                        // per-system arrays sized by the launch
+    double *s_rho = smem + A.tile_lds;            // [ms] current r.r
+    double *s_rho_old = s_rho + ms;               // [ms] previous r.r
+    int *ib = (int *)(s_rho_old + ms);
     Assign S0, S1;   // two named assignments (a runtime-indexed array would live in scratch)
-    S0.act = ib; ib += MAXSYS;
-    S0.pre = ib; ib += MAXSYS + 1;
-    S0.foff = ib; ib += MAXSYS + 1;
-    S1.act = ib; ib += MAXSYS;
-    S1.pre = ib; ib += MAXSYS + 1;
-    S1.foff = ib; ib += MAXSYS + 1;
+    S0.act = ib; ib += ms;
+    S0.pre = ib; ib += ms + 1;
+    S0.foff = ib; ib += ms + 1;
+    S1.act = ib; ib += ms;
+    S1.pre = ib; ib += ms + 1;
+    S1.foff = ib; ib += ms + 1;
+    const BarCtl bc = bar_ctl(A);
     __shared__ int s_m[2], s_ipb[2], s_tmp[NT / 64], s_flag;
     __shared__ double s_red[(NT / 64) * NVB];
     __shared__ double s_vals[NVB + 2];
@@ -324,7 +365,7 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
 
     run_phase2(S0, s_m[0], s_ipb[0], false, -1);
     int nbar = 0;
-    if (!grid_barrier(A.bar, (unsigned long long)(++nbar) * G, A.abort_flag, A.timeout_ticks, &s_flag)) return;
+    if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
 
     auto stamp = [&](int it, int k) {
         if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) A.stamps[it * 8 + k] = realtime();
@@ -551,20 +592,20 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
                                s_red);
         }
         stamp(it, 2);
-        if (!grid_barrier(A.bar, (unsigned long long)(++nbar) * G, A.abort_flag, A.timeout_ticks, &s_flag)) return;
+        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
         stamp(it, 3);
         run_phase2(N, mn, ipbn, true, it);
         stamp(it, 4);
-        if (!grid_barrier(A.bar, (unsigned long long)(++nbar) * G, A.abort_flag, A.timeout_ticks, &s_flag)) return;
+        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
         stamp(it, 5);
         cur ^= 1;
     }
 }
 
-size_t cg_lds_bytes(int tile_lds)
+size_t cg_lds_bytes(int tile_lds, int msys)
 {
-    const size_t d = (size_t)tile_lds + 2 * MAXSYS;                  // tile + rho arrays
-    const size_t ints = 2 * (size_t)(MAXSYS + 2 * (MAXSYS + 1));     // two assignments
+    const size_t d = (size_t)tile_lds + 2 * (size_t)msys;            // tile + rho arrays
+    const size_t ints = 2 * (size_t)(msys + 2 * (msys + 1)) + 2;     // two assignments
     return d * sizeof(double) + ints * sizeof(int);
 }
 

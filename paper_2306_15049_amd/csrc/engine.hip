@@ -93,6 +93,14 @@ struct Instance {
     bool ae_valid = false;
     // latest correction g = x - x0 per shift slot
     std::map<int, std::unique_ptr<DBuf>> gstore;
+    // Ritz blocks [R | AR | ER] per shift group, valid for the current U (version)
+    long u_version = 0;
+    struct RitzBlock {
+        long version = -1;
+        double gamma = 0.0;
+        int nr = 0;
+        DBuf buf;
+    } ritz[2];
 };
 
 inline int eff_sy(const Instance &I) { return I.sep ? I.ssq : I.sy; }
@@ -115,6 +123,7 @@ struct rsr_ctx {
     DBuf d_tmp;                        // misc n-vectors
     // counters and timing
     long mv_A = 0, mv_E = 0;
+    int cg_gmax = 1024;                // cap on persistent-kernel workgroups (autotuned)
     double last_cg_ms = 0.0;
     int last_launches = 0;
     long last_items = 0;
@@ -387,19 +396,20 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     SysDev *dsys = upload(c, c->d_sys, hd, s);
     c->d_partA.ensure(sizeof(double) * tiles);
     c->d_partB.ensure(sizeof(double) * tiles * NVB);
-    c->d_ctl.ensure(64);
+    c->d_ctl.ensure(BAR_BYTES);
     c->d_out.ensure((sizeof(int) * 2 + sizeof(double)) * m + 64);
-    HIPCHK(launch_fill(c->d_ctl.as<double>(), 0.0, 8, s));
+    HIPCHK(launch_fill(c->d_ctl.as<double>(), 0.0, BAR_BYTES / sizeof(double), s));
     int *out_iters = (int *)c->d_out.p;
     int *out_status = out_iters + m;
     double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
     HIPCHK(hipMemsetAsync(c->d_out.p, 0, sizeof(int) * 2 * m, s));
 
     const int tl = max_tile_lds(c);
-    const size_t lds = cg_lds_bytes(tl);
+    const int msys = (m + 7) & ~7;
+    const size_t lds = cg_lds_bytes(tl, msys);
     int bpc = cg_max_blocks_per_cu(lds);
     if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
-    int G = std::min<long>((long)bpc * c->n_cu, 1024);
+    int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
     if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
         const int v = atoi(cap);
         if (v >= 8) G = std::min(G, v);
@@ -414,7 +424,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.partA = c->d_partA.as<double>();
     a.partB = c->d_partB.as<double>();
     a.bar = (unsigned long long *)c->d_ctl.p;
-    a.abort_flag = (int *)((char *)c->d_ctl.p + 16);
+    a.abort_flag = (int *)((char *)c->d_ctl.p + 256);
     a.out_iters = out_iters;
     a.out_status = out_status;
     a.out_rho = out_rho;
@@ -422,6 +432,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.G = G;
     a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * 30.0);   // 30 s
     a.tile_lds = tl;
+    a.msys = msys;
     a.stamps = nullptr;
     const bool dbg = getenv("RSR_CG_STAMPS") != nullptr;   // phase timing of workgroup 0 (diagnostics)
     if (dbg) {
@@ -506,7 +517,8 @@ void local_correction(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
 void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const double *g_prev_shift,
                  hipStream_t s)
 {
-    // Ritz blocks per (instance, group)
+    // Ritz blocks per (instance, group): Algorithm 2 on A_hat + gamma_J E_hat, then
+    // R = U W~, AR = AU W~, ER = EU W~; cached until U or gamma_J changes
     struct Grp {
         int inst;
         double gJ;
@@ -514,41 +526,40 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         double *R;   // [nr][n], AR, ER follow
     };
     std::map<std::pair<int, int>, Grp> groups;
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
     for (auto *Y : sy) {
         Instance &I = *c->inst[Y->inst];
         if (o.n_ritz <= 0 || I.p == 0 || !I.ae_valid) continue;
         const int side = Y->slot < o.split_I ? 0 : 1;
         auto key = std::make_pair(Y->inst, side);
         if (groups.count(key)) continue;
-        groups[key] = Grp{Y->inst, side == 0 ? o.gJL : o.gJR, std::min(o.n_ritz, I.p), nullptr};
-    }
-    // workspace for Ritz blocks: 3 * nr columns per group
-    size_t need = 0;
-    for (auto &kv : groups) need += (size_t)3 * kv.second.nr * c->inst[kv.second.inst]->n;
-    c->d_tmp.ensure(sizeof(double) * std::max<size_t>(1, need));
-    size_t off = 0;
-    std::vector<ComboJob> cj;
-    std::vector<std::vector<double>> qs;
-    for (auto &kv : groups) {
-        Grp &g = kv.second;
-        Instance &I = *c->inst[g.inst];
-        const int p = I.p;
-        g.R = c->d_tmp.as<double>() + off;
-        off += (size_t)3 * g.nr * I.n;
-        std::vector<double> H((size_t)p * p), w, V;
-        for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + g.gJ * I.Ehat[k];
-        sym_eig(p, H.data(), w, V);
-        std::vector<double> Wt((size_t)p * g.nr);   // column-major p x nr
-        for (int j = 0; j < g.nr; ++j)
-            for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
-        cj.push_back(ComboJob{I.d_U.as<double>(), I.n, p, nullptr, p, g.R, I.n, g.nr, 0.0, nullptr, 0, I.n});
-        qs.push_back(Wt);
-        cj.push_back(ComboJob{I.d_AE.as<double>(), I.n, p, nullptr, p, g.R + (size_t)g.nr * I.n, I.n, g.nr, 0.0,
-                              nullptr, 0, I.n});
-        qs.push_back(Wt);
-        cj.push_back(ComboJob{I.d_AE.as<double>() + (size_t)p * I.n, I.n, p, nullptr, p,
-                              g.R + (size_t)2 * g.nr * I.n, I.n, g.nr, 0.0, nullptr, 0, I.n});
-        qs.push_back(Wt);
+        const double gJ = side == 0 ? o.gJL : o.gJR;
+        const int nr = std::min(o.n_ritz, I.p);
+        Instance::RitzBlock &rb = I.ritz[side];
+        if (rb.version != I.u_version || rb.gamma != gJ || rb.nr != nr) {
+            const int p = I.p;
+            rb.buf.ensure(sizeof(double) * (size_t)3 * nr * I.n);
+            std::vector<double> H((size_t)p * p), w, V;
+            for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + gJ * I.Ehat[k];
+            sym_eig(p, H.data(), w, V);
+            std::vector<double> Wt((size_t)p * nr);   // column-major p x nr
+            for (int j = 0; j < nr; ++j)
+                for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
+            double *R = rb.buf.as<double>();
+            cj.push_back(ComboJob{I.d_U.as<double>(), I.n, p, nullptr, p, R, I.n, nr, 0.0, nullptr, 0, I.n});
+            qs.push_back(Wt);
+            cj.push_back(ComboJob{I.d_AE.as<double>(), I.n, p, nullptr, p, R + (size_t)nr * I.n, I.n, nr, 0.0,
+                                  nullptr, 0, I.n});
+            qs.push_back(Wt);
+            cj.push_back(ComboJob{I.d_AE.as<double>() + (size_t)p * I.n, I.n, p, nullptr, p,
+                                  R + (size_t)2 * nr * I.n, I.n, nr, 0.0, nullptr, 0, I.n});
+            qs.push_back(Wt);
+            rb.version = I.u_version;
+            rb.gamma = gJ;
+            rb.nr = nr;
+        }
+        groups[key] = Grp{Y->inst, gJ, nr, rb.buf.as<double>()};
     }
     combo(c, cj, qs, s);
     // assemble W, Z per system
@@ -701,13 +712,16 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
                         H[(size_t)i * p + j] = I.Gaa[(size_t)i * p + j] + g * (I.Gae[(size_t)i * p + j] + I.Gae[(size_t)j * p + i]) +
                                                g * g * I.Gee[(size_t)i * p + j];
                 for (int i = 0; i < p; ++i) f[i] = rhs[k][i] + g * rhs[k][p + i];
-                spd_pinv(p, H.data(), 1e-15, P);
             } else {
                 for (size_t t = 0; t < H.size(); ++t) H[t] = I.Ahat[t] + g * I.Ehat[t];
                 for (int i = 0; i < p; ++i) f[i] = rhs[k][i];
-                spd_pinv(p, H.data(), 1e-15, P);
             }
-            matvec(p, p, P.data(), f.data(), q.data());
+            // Cholesky of the scaled p x p system; eigen pseudo-inverse when it is
+            // numerically singular (rank guard)
+            if (!spd_solve(p, H.data(), f.data(), q.data())) {
+                spd_pinv(p, H.data(), 1e-15, P);
+                matvec(p, p, P.data(), f.data(), q.data());
+            }
             // x = U q ; r = b - [AU EU] [q; g q]
             cj.push_back(ComboJob{I.d_U.as<double>(), I.n, p, nullptr, p, Y.x, Y.n, 1, 0.0, nullptr, 0, Y.n});
             qs.push_back(q);
@@ -888,6 +902,7 @@ void rsr_destroy(rsr_ctx *c)
         Instance &I = *p;
         I.d_fy.release(); I.d_fx.release(); I.d_psf.release(); I.d_wh.release(); I.d_wv.release();
         I.d_U.release(); I.d_AE.release();
+        I.ritz[0].buf.release(); I.ritz[1].buf.release();
         for (auto &g : I.gstore) if (g.second) g.second->release();
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
@@ -918,6 +933,8 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
         for (auto &p : c->inst) {
             p->d_fy.release(); p->d_fx.release(); p->d_psf.release(); p->d_wh.release(); p->d_wv.release();
             p->d_U.release(); p->d_AE.release();
+            p->ritz[0].buf.release(); p->ritz[1].buf.release();
+            for (auto &g : p->gstore) if (g.second) g.second->release();
         }
         c->inst.clear();
         for (int i = 0; i < n_inst; ++i) {
@@ -1101,6 +1118,7 @@ rsr_status rsr_set_recycle_space(rsr_ctx *c, int ii, const double *U_raw, long l
                 }
             return M;
         };
+        I.u_version += 1;
         I.Ahat = sym(blocks[0]);
         I.Ehat = sym(blocks[1]);
         I.Gaa = sym(blocks[2]);
@@ -1271,7 +1289,7 @@ rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
         if (ty < 4 || tx < 4 || ty > 64 || tx > 64 || (ty & (ty - 1)) || (tx & (tx - 1)))
             fail(RSR_E_ARG, "tile sides must be powers of two in [4, 64]");
         const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I));
-        if (cg_lds_bytes(tl) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
+        if (cg_lds_bytes(tl, 8) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
         set_device(c);
         I.ty = ty;
         I.tx = tx;
@@ -1292,62 +1310,83 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
             std::string line;
             while (std::getline(f, line)) {
                 if (line.rfind(key.str() + " ->", 0) == 0) {
-                    int ty = 0, tx = 0;
-                    if (sscanf(line.c_str() + key.str().size() + 3, "%d %d", &ty, &tx) == 2) {
+                    int ty = 0, tx = 0, gc = 0;
+                    if (sscanf(line.c_str() + key.str().size() + 3, "%d %d %d", &ty, &tx, &gc) == 3) {
                         I.ty = ty;
                         I.tx = tx;
+                        c->cg_gmax = gc;
                         upload_inst(c);
                         return;
                     }
                 }
             }
         }
+        // Time the hot kernel itself: a bounded persistent-CG solve of n_vec systems
+        // (40 iterations, shifts spread over 1e-3..1e-1) for every tile shape and
+        // grid cap; keep the fastest per iteration.
         const long n = I.n;
-        DBuf v, y;
-        v.ensure(sizeof(double) * n * n_vec);
-        y.ensure(sizeof(double) * n * n_vec);
+        DBuf bx;
+        bx.ensure(sizeof(double) * n * 2 * n_vec);
+        double *bvec = bx.as<double>(), *xvec = bvec + n * n_vec;
         hipStream_t s = nullptr;
-        HIPCHK(launch_fill(v.as<double>(), 1.0, n * n_vec, s));
-        const int cand[][2] = {{8, 32}, {16, 16}, {16, 32}, {32, 16}, {32, 32}, {8, 64}, {16, 64}, {32, 64}, {64, 32}};
+        HIPCHK(launch_fill(bvec, 1.0, n * n_vec, s));
+        std::vector<SysHost> sys(n_vec);
+        for (int j = 0; j < n_vec; ++j) {
+            SysHost &Y = sys[j];
+            Y.inst = ii;
+            Y.slot = j;
+            Y.gamma = std::pow(10.0, -3.0 + 2.0 * j / std::max(1, n_vec - 1));
+            Y.n = n;
+            Y.b = bvec + (size_t)j * n;
+            Y.x = xvec + (size_t)j * n;
+            Y.bnorm = std::sqrt((double)n);
+        }
+        alloc_ws(c, sys);
+        const int cand[][2] = {{16, 16}, {16, 32}, {32, 16}, {32, 32}, {8, 64}, {16, 64}};
+        const int gcaps[] = {128, 256, 512, 1024};
         double best = 1e30;
-        int bty = I.ty, btx = I.tx;
+        int bty = I.ty, btx = I.tx, bg = c->cg_gmax;
         const long mvA = c->mv_A, mvE = c->mv_E;
+        Opts o{0.0, 40, RSR_INIT_ZERO, 0, 0, 0, 0, 0.0, 0.0};
         for (auto &cd : cand) {
             const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I));
-            if (cg_lds_bytes(tl) > 160 * 1024) continue;
+            if (cg_lds_bytes(tl, (n_vec + 7) & ~7) > 160 * 1024) continue;
             I.ty = cd[0];
             I.tx = cd[1];
             upload_inst(c);
-            std::vector<ApplyJob> jobs(n_vec);
-            for (int j = 0; j < n_vec; ++j) jobs[j] = ApplyJob{ii, 0, 1.0, 0.5, v.as<double>() + j * n, y.as<double>() + j * n};
-            ApplyJob *dj = upload(c, c->d_jobs, jobs, s);
-            const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
-            HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, n_vec, lds, s));
-            HIPCHK(hipStreamSynchronize(s));
-            const int reps = 5;
-            HIPCHK(hipEventRecord(c->ev0, s));
-            for (int r = 0; r < reps; ++r)
-                HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, n_vec, lds, s));
-            HIPCHK(hipEventRecord(c->ev1, s));
-            HIPCHK(hipEventSynchronize(c->ev1));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-            if (ms < best) {
-                best = ms;
-                bty = cd[0];
-                btx = cd[1];
+            for (int gc : gcaps) {
+                c->cg_gmax = gc;
+                for (auto &Y : sys) {
+                    HIPCHK(launch_fill(Y.x, 0.0, n, s));
+                    HIPCHK(hipMemcpyAsync(Y.r, Y.b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                    Y.q = 0;
+                    Y.iters = 0;
+                }
+                std::vector<SysHost *> ptrs;
+                for (auto &Y : sys) ptrs.push_back(&Y);
+                c->last_cg_ms = 0.0;
+                run_cg(c, ptrs, o, s);
+                int its = 0;
+                for (auto &Y : sys) its = std::max(its, Y.iters);
+                const double per = c->last_cg_ms / std::max(1, its);
+                if (per < best) {
+                    best = per;
+                    bty = cd[0];
+                    btx = cd[1];
+                    bg = gc;
+                }
             }
         }
         c->mv_A = mvA;
         c->mv_E = mvE;
+        c->cg_gmax = bg;
         I.ty = bty;
         I.tx = btx;
         upload_inst(c);
-        v.release();
-        y.release();
+        bx.release();
         if (cache_path) {
             std::ofstream f(cache_path, std::ios::app);
-            f << key.str() << " -> " << bty << " " << btx << "\n";
+            f << key.str() << " -> " << bty << " " << btx << " " << bg << "\n";
         }
     });
 }

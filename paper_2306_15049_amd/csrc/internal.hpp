@@ -50,7 +50,8 @@ struct CGArgs {
     const InstDev *inst;
     double *partA;                 // [total tiles] p.w partials
     double *partB;                 // [total tiles][NVB] r.r and Z^T r partials
-    unsigned long long *bar;       // grid-barrier arrival counter, 0 at launch
+    unsigned long long *bar;       // barrier control block (BAR_BYTES, zero at launch): global counter,
+                                   // per-group arrival counters and release epochs, 256-byte lines
     int *abort_flag;               // set on barrier timeout
     int *out_iters;                // [nsys]
     int *out_status;               // [nsys] 1 converged, 2 maxit, -3 nonfinite, -4 not SPD
@@ -59,13 +60,16 @@ struct CGArgs {
     int G;                         // workgroups in the grid
     long long timeout_ticks;       // barrier wait limit in s_memrealtime ticks (100 MHz)
     int tile_lds;                  // doubles of dynamic LDS used by the stencil buffers
+    int msys;                      // capacity of the per-system LDS arrays (>= nsys)
     unsigned long long *stamps;    // optional [DBG_ITERS][8] phase timestamps of workgroup 0 (or null)
 };
 constexpr int DBG_ITERS = 64;
 
 // Launch plumbing implemented in kernels.hip.
 int tile_lds_doubles(int ty, int tx, int sy, int sx);
-size_t cg_lds_bytes(int tile_lds);
+size_t cg_lds_bytes(int tile_lds, int msys);
+constexpr int BAR_GROUPS = 8;                          // barrier groups (one per XCD when G % 8 == 0)
+constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
 hipError_t launch_cg(const CGArgs &a, int G, size_t lds, hipStream_t s, bool cooperative);
 int cg_max_blocks_per_cu(size_t lds);
 

@@ -18,6 +18,8 @@
 #include "internal.hpp"
 #include "stencil.hpp"
 
+#include <algorithm>
+
 #include <hip/hip_runtime.h>
 
 namespace rsr {
@@ -189,6 +191,7 @@ __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, d
     __shared__ double xs[GR][GT + 1];
     __shared__ double ys[GR][GT + 1];
     const GramJob J = jobs[blockIdx.z];
+    if (J.c <= 8) return;   // done by k_gram_small
     const int tiles_c = (J.c + GT - 1) / GT;
     const int tiles_a = (J.a + GT - 1) / GT;
     const int ot = blockIdx.y;
@@ -234,6 +237,63 @@ __global__ void k_gram_reduce(const GramJob *__restrict__ jobs, const double *__
     }
 }
 
+// Small products (a * c <= GSMALL, e.g. norms, W^T r, W^T Z): every thread runs
+// over its rows once with all a*c accumulators in registers, then the
+// workgroup reduces them in a fixed order.  Chunk partials use the same
+// scratch layout as k_gram (output tile 0), so k_gram_reduce finishes both.
+constexpr int GSMALL = 64;
+constexpr int GSMALL_A = 8;
+__global__ __launch_bounds__(NT) void k_gram_small(const GramJob *__restrict__ jobs, double *__restrict__ scratch)
+{
+    __shared__ double red[NT / 64][GSMALL];
+    const GramJob J = jobs[blockIdx.z];
+    if (J.c > GSMALL_A) return;
+    // rows ia0 .. ia0+7 of the output (a of any size is split over blockIdx.y)
+    const int ia0 = blockIdx.y * GSMALL_A;
+    if (ia0 >= J.a) return;
+    const int na = J.a - ia0 < GSMALL_A ? J.a - ia0 : GSMALL_A;
+    const long nchunk = (J.n + GCH - 1) / GCH;
+    if ((long)blockIdx.x >= nchunk) return;
+    const long r0 = (long)blockIdx.x * GCH;
+    const long r1 = r0 + GCH < J.n ? r0 + GCH : J.n;
+    double acc[GSMALL_A][GSMALL_A];
+#pragma unroll
+    for (int i = 0; i < GSMALL_A; ++i)
+#pragma unroll
+        for (int j = 0; j < GSMALL_A; ++j) acc[i][j] = 0.0;
+    for (long r = r0 + threadIdx.x; r < r1; r += NT) {
+        double xv[GSMALL_A], yv[GSMALL_A];
+#pragma unroll
+        for (int i = 0; i < GSMALL_A; ++i) xv[i] = i < na ? J.X[r + (long)(ia0 + i) * J.ldx] : 0.0;
+#pragma unroll
+        for (int j = 0; j < GSMALL_A; ++j) yv[j] = j < J.c ? J.Y[r + (long)j * J.ldy] : 0.0;
+#pragma unroll
+        for (int i = 0; i < GSMALL_A; ++i)
+#pragma unroll
+            for (int j = 0; j < GSMALL_A; ++j) acc[i][j] = fma(xv[i], yv[j], acc[i][j]);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < GSMALL_A; ++i)
+#pragma unroll
+        for (int j = 0; j < GSMALL_A; ++j)
+            if (i < na && j < J.c) {
+                const double v = wave_sum(acc[i][j]);
+                if (lane == 0) red[wid][i * GSMALL_A + j] = v;
+            }
+    __syncthreads();
+    if (threadIdx.x < GSMALL_A * GSMALL_A) {
+        const int i = threadIdx.x / GSMALL_A, j = threadIdx.x % GSMALL_A;
+        if (i < na && j < J.c) {
+            double v = 0.0;
+            for (int w = 0; w < NT / 64; ++w) v += red[w][i * GSMALL_A + j];
+            // k_gram's layout: output tile (gi / GT, 0), entry (gi % GT, j), chunk blockIdx.x
+            const int gi = ia0 + i;
+            scratch[J.sc_off + ((long)(gi / GT) * nchunk + blockIdx.x) * (GT * GT) + (gi % GT) * GT + j] = v;
+        }
+    }
+}
+
 size_t gram_scratch_doubles(const GramJob *jh, int njobs)
 {
     size_t t = 0;
@@ -249,16 +309,30 @@ hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, do
                        size_t scratch_doubles, hipStream_t s)
 {
     long maxchunk = 1, maxtiles = 1;
+    bool any_big = false, any_small = false;
     for (int i = 0; i < njobs; ++i) {
         const long nchunk = (jh[i].n + GCH - 1) / GCH;
         const long ntiles = (long)((jh[i].a + GT - 1) / GT) * ((jh[i].c + GT - 1) / GT);
         if (nchunk > maxchunk) maxchunk = nchunk;
         if (ntiles > maxtiles) maxtiles = ntiles;
         if (jh[i].sc_off + (size_t)(nchunk * ntiles * GT * GT) > scratch_doubles) return hipErrorInvalidValue;
+        const bool small = jh[i].c <= GSMALL_A;
+        any_small |= small;
+        any_big |= !small;
     }
-    hipLaunchKernelGGL(k_gram, dim3(maxchunk, maxtiles, njobs), dim3(NT), 0, s, jobs_dev, scratch);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (any_small) {
+        long maxa8 = 1;
+        for (int i = 0; i < njobs; ++i) maxa8 = std::max<long>(maxa8, (jh[i].a + GSMALL_A - 1) / GSMALL_A);
+        hipLaunchKernelGGL(k_gram_small, dim3(maxchunk, maxa8, njobs), dim3(NT), 0, s, jobs_dev, scratch);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (any_big) {
+        hipLaunchKernelGGL(k_gram, dim3(maxchunk, maxtiles, njobs), dim3(NT), 0, s, jobs_dev, scratch);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_gram_reduce, dim3(8, njobs), dim3(NT), 0, s, jobs_dev, scratch);
     return hipGetLastError();
 }

@@ -92,6 +92,43 @@ inline int spd_pinv(int n, const double *S, double rel, std::vector<double> &P)
     return rank;
 }
 
+// Solve S x = f for symmetric positive definite S by Cholesky after symmetric
+// diagonal scaling; returns false (x untouched) if a pivot is not positive
+// enough relative to its diagonal (numerically semidefinite).
+inline bool spd_solve(int n, const double *S, const double *f, double *x, double rel = 1e-13)
+{
+    std::vector<double> d(n), L((size_t)n * n, 0.0), y(n);
+    for (int i = 0; i < n; ++i) {
+        const double v = S[(size_t)i * n + i];
+        if (!(v > 0.0)) return false;
+        d[i] = 1.0 / std::sqrt(v);
+    }
+    for (int j = 0; j < n; ++j) {
+        double s = S[(size_t)j * n + j] * d[j] * d[j];
+        for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(s > rel)) return false;
+        const double ljj = std::sqrt(s);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = S[(size_t)i * n + j] * d[i] * d[j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double t = f[i] * d[i];
+        for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * y[k];
+        y[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * y[k];
+        y[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) x[i] = y[i] * d[i];
+    return true;
+}
+
 inline void matvec(int n, int m, const double *M, const double *x, double *y)  // y = M x, M n x m
 {
     for (int i = 0; i < n; ++i) {

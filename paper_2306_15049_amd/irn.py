@@ -40,6 +40,7 @@ class StepRecord:
     p: int = 0
     cg_kernel_ms: float = 0.0
     cg_items: int = 0
+    cg_launches: int = 0
 
 
 @dataclass
@@ -134,16 +135,12 @@ class OuterLoop:
                                                   cond_max=self.rp.cond_max)
         o = self._opts()
         iters, rel, rel0 = [], [], []
-        cg_ms, items = 0.0, 0
         if n_inst == 1:
             rc, st = ctx.solve(self.cfg.gammas, self.b[0], self.X[0], opts=o)
             stats = [st]
-            t = ctx.last_timing()
-            cg_ms, items = t[0], t[2]
         else:
             stats = self._solve_instances(o)
-            t = ctx.last_timing()
-            cg_ms, items = t[0], t[2]
+        cg_ms, launches, items = ctx.last_timing()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3
         a1, e1 = ctx.counters()
@@ -151,7 +148,7 @@ class OuterLoop:
             iters += [s["iters"] for s in st]
             rel += [s["relres_true"] for s in st]
             rel0 += [s["relres_init"] for s in st]
-        rec = StepRecord(self.k, wall, a1 - a0, e1 - e0, iters, rel, rel0, p_dim, cg_ms, items)
+        rec = StepRecord(self.k, wall, a1 - a0, e1 - e0, iters, rel, rel0, p_dim, cg_ms, items, launches)
         self.k += 1
         return rec
 
@@ -185,7 +182,7 @@ class OuterLoop:
         for _ in range(steps):
             r = self.step()
             if log is not None:
-                print(f"[{self.method}] k={r.k} wall={r.wall_ms:.2f} ms A={r.matvec_A} E={r.matvec_E} p={r.p} "
-                      f"iters={r.iters}", file=log, flush=True)
+                print(f"[{self.method}] k={r.k} wall={r.wall_ms:.2f} ms cg={r.cg_kernel_ms:.2f} ms A={r.matvec_A} "
+                      f"p={r.p} iters={r.iters} relres0={[f'{v:.1e}' for v in r.relres_init]}", file=log, flush=True)
             out.append(r)
         return out
