@@ -35,12 +35,13 @@ __device__ __forceinline__ unsigned long long realtime() { return __builtin_amdg
 // read with agent-scope coherent loads (sc1), which do not hit stale lines.
 // Writers publish with the release at the barrier arrival.  When the
 // assignment changes, one full agent-scope acquire is taken.
-__device__ __forceinline__ double cld(const double *p)
+__device__ __forceinline__ double cld(const gdbl *p)
 {
-    const unsigned long long v =
-        __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    typedef __attribute__((address_space(1))) unsigned long long gu64;
+    const unsigned long long v = __hip_atomic_load((const gu64 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return __longlong_as_double((long long)v);
 }
+__device__ __forceinline__ double cld(const double *p) { return cld(gp(p)); }
 
 // Grid barrier, two levels.  Workgroups are split into BAR_GROUPS groups
 // (workgroup b in group b % 8, i.e. one group per XCD under round-robin
@@ -203,9 +204,13 @@ __device__ void block_reduce_partials(const double *part, int base, int nch, int
     for (int j = 0; j < NVB; ++j) acc[j] = 0.0;
     for (int k = threadIdx.x; k < nch; k += NT) {
         const double *p = part + (long)(base + k) * nv + v0;
+        // branch-free so that all loads of a slot are in flight together; the
+        // clamped index stays inside the slot
+        double v[NVB];
 #pragma unroll
-        for (int j = 0; j < NVB; ++j)
-            if (j < cnt) acc[j] += cld(p + j);
+        for (int j = 0; j < NVB; ++j) v[j] = cld(p + (j < cnt ? j : cnt - 1));
+#pragma unroll
+        for (int j = 0; j < NVB; ++j) acc[j] += j < cnt ? v[j] : 0.0;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -239,15 +244,17 @@ __device__ __forceinline__ void flush_partials(const double (&acc)[NVB], int cnt
     if (threadIdx.x < cnt) {
         double sm = 0.0;
         for (int w = 0; w < NT / 64; ++w) sm += red[w * NVB + threadIdx.x];
-        part[slot * nv + threadIdx.x] = sm;
+        gp(part)[slot * nv + threadIdx.x] = sm;
     }
     __syncthreads();
 }
 
 constexpr int NB = 4;    // pixels per thread whose loads are issued together (tile interior)
 constexpr int NBW = 12;  // window rows per thread loaded together in phase 1
+constexpr int NBE = 2;   // interior pixels per thread whose local-basis loads are issued together
 
-__global__ __launch_bounds__(NT) void k_cg(CGArgs A)
+// at most 256 registers per lane keeps two waves per SIMD
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_cg(CGArgs A)
 {
     extern __shared__ double smem[];
     double *tile = smem;                          // stencil buffers / reduction scratch
@@ -311,11 +318,11 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
             // reference, every global store below would force them to be reloaded
             const SysDev &Yg = A.sys[s];
             const InstDev I = A.inst[Yg.inst];
-            double *__restrict__ Yx = Yg.x;
-            double *__restrict__ Yr = Yg.r;
-            const double *__restrict__ Ypa = Yg.pa;
-            const double *__restrict__ Yw = Yg.w;
-            const double *__restrict__ YZ = Yg.Z;
+            gdbl *__restrict__ Yx = gp(Yg.x);
+            gdbl *__restrict__ Yr = gp(Yg.r);
+            const gdbl *__restrict__ Ypa = gp(Yg.pa);
+            const gdbl *__restrict__ Yw = gp(Yg.w);
+            const gdbl *__restrict__ YZ = gp(Yg.Z);
             const long ldw = Yg.ldw;
             const int t = uni(item - As.pre[a]);
             const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
@@ -465,6 +472,7 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
                     pacc[0] = 0.0;
                     q = Y.q;
                     beta = it > 0 ? s_rho[s] / s_rho_old[s] : 0.0;
+                    if (threadIdx.x >= q && threadIdx.x < QMAX) s_c[threadIdx.x] = 0.0;   // unused columns
                     if (q > 0) {
                         // mu = Ginv (Z^T r) from the previous assignment's partials; c_{j+1} = beta c_j + mu
                         const int po = find_pos(O.act, mo, s);
@@ -477,28 +485,31 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
                             const double cn = fma(beta, cold, m);
                             s_c[threadIdx.x] = cn;
                             // the workgroup holding the system's first chunk publishes c_{j+1}
-                            if (chunk == N.pre[a] / ipbn) Y.cbuf[((it + 1) & 1) * QMAX + threadIdx.x] = cn;
+                            if (chunk == N.pre[a] / ipbn) gp(Y.cbuf)[((it + 1) & 1) * QMAX + threadIdx.x] = cn;
                         }
-                        __syncthreads();
                     }
+                    __syncthreads();
                 }
                 const InstDev I = A.inst[Y.inst];
                 const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx);
                 const int t = uni(item - N.pre[a]);
                 const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
                 // local copies (see phase 2): no reloads after the global stores
-                const double *__restrict__ pold = (it & 1) ? Y.p1 : Y.p0;
-                double *__restrict__ pnew = (it & 1) ? Y.p0 : Y.p1;
-                const double *__restrict__ Yr = Y.r;
-                const double *__restrict__ YW = Y.W;
-                const double *__restrict__ YZ = Y.Z;
-                double *__restrict__ Ypa = Y.pa;
-                double *__restrict__ Yw = Y.w;
+                const gdbl *__restrict__ pold = gp((it & 1) ? Y.p1 : Y.p0);
+                gdbl *__restrict__ pnew = gp((it & 1) ? Y.p0 : Y.p1);
+                const gdbl *__restrict__ Yr = gp(Y.r);
+                const gdbl *__restrict__ YW = gp(Y.W);
+                const gdbl *__restrict__ YZ = gp(Y.Z);
+                gdbl *__restrict__ Ypa = gp(Y.pa);
+                gdbl *__restrict__ Yw = gp(Y.w);
                 const long ldw = Y.ldw;
                 const double gam = Y.gamma;
                 double *pbuf = tile + g.offP;
                 // stage ph = r + beta ph_old on the window (all of a thread's loads
                 // issued together); keep the interior in pbuf
+                EWts ew;
+                tile_E_load(I, y0, x0, 0, gam, ew);   // in flight with the window loads
+                stage_taps(I, g, tile);
                 const WinMap wm = win_map(g.W0);
                 const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);     // window column of this thread
                 const int gx = x0 - g.hx + lj;
@@ -515,74 +526,75 @@ __global__ __launch_bounds__(NT) void k_cg(CGArgs A)
                         own[u] = colown && li >= g.hy && li < g.hy + I.ty;
                         gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
                     }
+                    // every window cell with coherent loads (halo cells were written by
+                    // other workgroups), branch-free so that all loads are in flight
+                    // together; masked lanes load element 0 and discard it
                     double rv[NBW], pv[NBW];
 #pragma unroll
-                    for (int u = 0; u < NBW; ++u) {
-                        // own interior: cached; halo cells belong to other tiles: coherent loads
-                        rv[u] = ok[u] ? (own[u] ? Yr[gi[u]] : cld(Yr + gi[u])) : 0.0;
-                        pv[u] = (ok[u] && it > 0) ? (own[u] ? pold[gi[u]] : cld(pold + gi[u])) : 0.0;
+                    for (int u = 0; u < NBW; ++u) rv[u] = cld(Yr + gi[u]);
+                    if (it > 0) {
+#pragma unroll
+                        for (int u = 0; u < NBW; ++u) pv[u] = cld(pold + gi[u]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < NBW; ++u) pv[u] = 0.0;
                     }
 #pragma unroll
                     for (int u = 0; u < NBW; ++u) {
                         const int li = li0 + u * wm.rs;
-                        if (lj < g.W0 && li < g.H0) {
-                            const double v = ok[u] ? fma(beta, pv[u], rv[u]) : 0.0;
-                            tile[li * g.P0 + lj] = v;
-                            if (ok[u] && own[u]) {
-                                pnew[gi[u]] = v;
-                                pbuf[(li - g.hy) * g.PE + (lj - g.hx)] = v;
-                            }
+                        const double v = ok[u] ? fma(beta, pv[u], rv[u]) : 0.0;
+                        double *d = (lj < g.W0 && li < g.H0) ? tile + li * g.P0 + lj : tile + g.offT + threadIdx.x;
+                        *d = v;
+                        if (ok[u] && own[u]) {
+                            pnew[gi[u]] = v;
+                            pbuf[(li - g.hy) * g.PE + (lj - g.hx)] = v;
                         }
                     }
                 }
                 __syncthreads();
                 if (item == lo) stamp(it, 6);
-                tile_E(I, g, tile, y0, x0, gam);
+                tile_E(I, g, tile, y0, x0, gam, ew);
                 tile_A(I, g, tile, y0, x0, 1.0);
                 if (item == lo) stamp(it, 7);
-                // interior: p = ph - W c, w = B ph - Z c, partial p.w
+                // interior: p = ph - W c, w = B ph - Z c, partial p.w; all 2q basis
+                // loads of a pixel batch are issued together
                 const double *ebuf = tile + g.offE;
                 const int ne = I.ty * I.tx;
-                for (int base = 0; base < ne; base += NT * NB) {
-                    long gi[NB];
-                    bool ok[NB];
+                for (int base = 0; base < ne; base += NT * NBE) {
+                    long gi[NBE];
+                    bool ok[NBE];
 #pragma unroll
-                    for (int u = 0; u < NB; ++u) {
+                    for (int u = 0; u < NBE; ++u) {
                         const int k = base + u * NT + threadIdx.x;
                         const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
                         ok[u] = k < ne && gy < I.ny && gx < I.nx;
                         gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
                     }
-                    double p[NB], w[NB];
+                    double wl[NBE][QMAX], zl[NBE][QMAX];
 #pragma unroll
-                    for (int u = 0; u < NB; ++u) {
+                    for (int u = 0; u < NBE; ++u)
+#pragma unroll
+                        for (int j = 0; j < QMAX; ++j) {
+                            wl[u][j] = (j < q && ok[u]) ? YW[j * ldw + gi[u]] : 0.0;
+                            zl[u][j] = (j < q && ok[u]) ? YZ[j * ldw + gi[u]] : 0.0;
+                        }
+#pragma unroll
+                    for (int u = 0; u < NBE; ++u) {
                         const int k = base + u * NT + threadIdx.x;
                         const int ii = ok[u] ? (k >> I.ltx) : 0, jj = ok[u] ? (k & (I.tx - 1)) : 0;
-                        p[u] = pbuf[ii * g.PE + jj];
-                        w[u] = ebuf[ii * g.PE + jj];
-                    }
-                    for (int j = 0; j < q; ++j) {
-                        const double cj = s_c[j];
-                        const double *Wj = YW + j * ldw, *Zj = YZ + j * ldw;
-                        double wl[NB], zl[NB];
+                        double p = pbuf[ii * g.PE + jj];
+                        double w = ebuf[ii * g.PE + jj];
 #pragma unroll
-                        for (int u = 0; u < NB; ++u) {
-                            wl[u] = ok[u] ? Wj[gi[u]] : 0.0;
-                            zl[u] = ok[u] ? Zj[gi[u]] : 0.0;
+                        for (int j = 0; j < QMAX; ++j) {
+                            p = fma(-s_c[j], wl[u][j], p);
+                            w = fma(-s_c[j], zl[u][j], w);
                         }
-#pragma unroll
-                        for (int u = 0; u < NB; ++u) {
-                            p[u] = fma(-cj, wl[u], p[u]);
-                            w[u] = fma(-cj, zl[u], w[u]);
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < NB; ++u)
                         if (ok[u]) {
-                            Ypa[gi[u]] = p[u];
-                            Yw[gi[u]] = w[u];
-                            pacc[0] = fma(p[u], w[u], pacc[0]);
+                            Ypa[gi[u]] = p;
+                            Yw[gi[u]] = w;
+                            pacc[0] = fma(p, w, pacc[0]);
                         }
+                    }
                 }
                 __syncthreads();
             }

@@ -84,7 +84,8 @@ struct Instance {
     int sep = 0;
     int ssq = 0;                       // separable path: zero-padded square size
     std::vector<double> fy, fx;
-    DBuf d_fy, d_fx, d_psf, d_wh, d_wv;
+    std::vector<double> band;          // banded factors of K^T K (separable path), see band_tables
+    DBuf d_fy, d_fx, d_psf, d_wh, d_wv, d_band;
     int ty = 16, tx = 16;
     // principal recycle space
     int p = 0;
@@ -162,6 +163,7 @@ void upload_inst(rsr_ctx *c)
         d.sx = eff_sx(I);
         d.fy = I.d_fy.as<double>();
         d.fx = I.d_fx.as<double>();
+        d.band = I.d_band.as<double>();
         d.psf = I.d_psf.as<double>();
         d.wh = I.d_wh.as<double>();
         d.wv = I.d_wv.as<double>();
@@ -282,6 +284,45 @@ std::vector<double> norms(rsr_ctx *c, const std::vector<const double *> &v, cons
 }
 
 // ---------------------------------------------------------- PSF factors --
+// Banded form of T^T T for the zero-boundary "same" 1-D convolution
+// (T v)[k] = sum_c f[c] v[k + r - c] (S = 2r + 1 taps; row factor of K along x,
+// column factor along y; K^T K = (Ty^T Ty) (x) (Tx^T Tx)).  Summing over every
+// k gives the Toeplitz part c(s) = sum_m f[m] f[m + s]; restricting k to the
+// line removes, for outputs and inputs both among the first r positions,
+//   Lc[j][i] = sum_{u = max(i,j)}^{r-1} f[u - j] f[u - i]     (k < 0), and for
+// the last r positions (j = n - r + p, i = n - r + q)
+//   Rc[p][q] = sum_{u = 0}^{min(p,q)} f[u + 2r - p] f[u + 2r - q]   (k >= n).
+// So (T^T T v)[j] = sum_{t=0}^{4r} c(2r - t) v[j - 2r + t] - [j < r] (Lc v)[j]
+// - [j >= n - r] (Rc v)[j - n + r], with v = 0 outside the line.
+// Layout of I.band: [band x: 4r+1][band y: 4r+1][Lx: r*r][Rx: r*r][Ly: r*r][Ry: r*r].
+void band_tables(Instance &I)
+{
+    const int S = I.ssq, r = S / 2, nb = 4 * r + 1, rr = r * r;
+    I.band.assign(2 * nb + 4 * rr, 0.0);
+    const std::vector<double> *fs[2] = {&I.fx, &I.fy};
+    for (int ax = 0; ax < 2; ++ax) {
+        const std::vector<double> &f = *fs[ax];
+        double *band = I.band.data() + ax * nb;
+        double *Lc = I.band.data() + 2 * nb + (2 * ax) * rr;
+        double *Rc = Lc + rr;
+        for (int t = 0; t < nb; ++t) {
+            const int sh = 2 * r - t;
+            double c = 0.0;
+            for (int m = 0; m < S; ++m)
+                if (m + sh >= 0 && m + sh < S) c += f[m] * f[m + sh];
+            band[t] = c;
+        }
+        for (int j = 0; j < r; ++j)
+            for (int i = 0; i < r; ++i) {
+                double l = 0.0, q = 0.0;
+                for (int u = std::max(i, j); u < r; ++u) l += f[u - j] * f[u - i];
+                for (int u = 0; u <= std::min(i, j); ++u) q += f[u + 2 * r - j] * f[u + 2 * r - i];
+                Lc[j * r + i] = l;
+                Rc[j * r + i] = q;
+            }
+    }
+}
+
 void factor_psf(Instance &I)
 {
     // rank-1 test: h = fy fx^T iff h equals the outer product built from its
@@ -319,6 +360,7 @@ void factor_psf(Instance &I)
         I.fx.assign(S, 0.0);
         for (int a = 0; a < sy; ++a) I.fy[(S - sy) / 2 + a] = fy[a];
         for (int c2 = 0; c2 < sx; ++c2) I.fx[(S - sx) / 2 + c2] = fx[c2];
+        band_tables(I);
     }
 }
 
@@ -900,7 +942,7 @@ void rsr_destroy(rsr_ctx *c)
     (void)hipDeviceSynchronize();
     for (auto &p : c->inst) {
         Instance &I = *p;
-        I.d_fy.release(); I.d_fx.release(); I.d_psf.release(); I.d_wh.release(); I.d_wv.release();
+        I.d_fy.release(); I.d_fx.release(); I.d_psf.release(); I.d_wh.release(); I.d_wv.release(); I.d_band.release();
         I.d_U.release(); I.d_AE.release();
         I.ritz[0].buf.release(); I.ritz[1].buf.release();
         for (auto &g : I.gstore) if (g.second) g.second->release();
@@ -932,6 +974,7 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
         HIPCHK(hipStreamSynchronize(s));
         for (auto &p : c->inst) {
             p->d_fy.release(); p->d_fx.release(); p->d_psf.release(); p->d_wh.release(); p->d_wv.release();
+            p->d_band.release();
             p->d_U.release(); p->d_AE.release();
             p->ritz[0].buf.release(); p->ritz[1].buf.release();
             for (auto &g : p->gstore) if (g.second) g.second->release();
@@ -952,6 +995,8 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
                 I->d_fx.ensure(sizeof(double) * I->ssq);
                 HIPCHK(hipMemcpy(I->d_fy.p, I->fy.data(), sizeof(double) * I->ssq, hipMemcpyHostToDevice));
                 HIPCHK(hipMemcpy(I->d_fx.p, I->fx.data(), sizeof(double) * I->ssq, hipMemcpyHostToDevice));
+                I->d_band.ensure(sizeof(double) * I->band.size());
+                HIPCHK(hipMemcpy(I->d_band.p, I->band.data(), sizeof(double) * I->band.size(), hipMemcpyHostToDevice));
             }
             I->d_wh.ensure(sizeof(double) * I->n);
             I->d_wv.ensure(sizeof(double) * I->n);

@@ -5,12 +5,22 @@
 
 namespace rsr {
 
+// Global-memory views.  Pointers read out of descriptors are generic to the
+// compiler, which then emits flat instructions; a flat load counts against
+// both the vector-memory and the LDS wait counters, so every LDS wait would
+// also wait for the global loads in flight.  Kernels read and write global
+// data through these address-space-1 views instead.
+typedef __attribute__((address_space(1))) double gdbl;
+__device__ __forceinline__ gdbl *gp(double *p) { return (gdbl *)p; }
+__device__ __forceinline__ const gdbl *gp(const double *p) { return (const gdbl *)p; }
+
 constexpr int NT = 256;        // threads per workgroup (4 wave64)
 constexpr int QMAX = 8;        // widest local (deflation) space per system
 constexpr int NVB = 1 + QMAX;  // values per partial in the update phase: r.r, Z^T r
 constexpr int MAXSYS = 512;    // systems per persistent launch
 constexpr int RB = 8;          // register-blocked outputs per thread in the stencil passes
 constexpr int MAXS = 31;       // largest separable PSF extent with a compiled path
+constexpr int TAPS = 64;       // LDS slots per staged band (4r + 1 <= 61 taps)
 
 // Device view of one instance (image geometry, PSF, weights, tiling).
 struct InstDev {
@@ -22,6 +32,7 @@ struct InstDev {
     int sy, sx;        // PSF extent (odd); for sep both equal the zero-padded square size
     const double *fy;  // [sy] column factor (sep)
     const double *fx;  // [sx] row factor (sep)
+    const double *band; // banded factors of K^T K and their end corrections (sep; layout in band_tables)
     const double *psf; // [sy*sx] (direct)
     const double *wh;  // [ny*nx] weights of x[i,j+1]-x[i,j]; 0 in the last column
     const double *wv;  // [ny*nx] weights of x[i+1,j]-x[i,j]; 0 in the last row

@@ -48,6 +48,9 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
     const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);
     const int gx = x0 - g.hx + lj;
     const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
+    EWts ew;
+    tile_E_load(I, y0, x0, 0, J.cE, ew);   // in flight with the window loads
+    stage_taps(I, g, lds);
     for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
         double v[NBW];
 #pragma unroll
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
             const int li = li0 + u * wm.rs;
             const int gy = y0 - g.hy + li;
             const bool ok = colok && li < g.H0 && gy >= 0 && gy < I.ny;
-            v[u] = ok ? vin[(long)gy * I.nx + gx] : 0.0;
+            v[u] = ok ? gp(vin)[(long)gy * I.nx + gx] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NBW; ++u) {
@@ -64,13 +67,13 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
         }
     }
     __syncthreads();
-    tile_E(I, g, lds, y0, x0, J.cE);
+    tile_E(I, g, lds, y0, x0, J.cE, ew);
     if (J.cA != 0.0) tile_A(I, g, lds, y0, x0, J.cA);
     const double *ebuf = lds + g.offE;
     for (int k = threadIdx.x; k < I.ty * I.tx; k += NT) {
         const int i = k >> I.ltx, j = k & (I.tx - 1);
         const int gy = y0 + i, gx = x0 + j;
-        if (gy < I.ny && gx < I.nx) J.y[(long)gy * I.nx + gx] = ebuf[i * g.PE + j];
+        if (gy < I.ny && gx < I.nx) gp(J.y)[(long)gy * I.nx + gx] = ebuf[i * g.PE + j];
     }
 }
 
@@ -209,8 +212,8 @@ __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, d
             const int rr = k % GR, cc = k / GR;
             const long row = rb + rr;
             const int xa = ia0 + cc, yc = jc0 + cc;
-            xs[rr][cc] = (row < r1 && xa < J.a) ? J.X[row + (long)xa * J.ldx] : 0.0;
-            ys[rr][cc] = (row < r1 && yc < J.c) ? J.Y[row + (long)yc * J.ldy] : 0.0;
+            xs[rr][cc] = (row < r1 && xa < J.a) ? gp(J.X)[row + (long)xa * J.ldx] : 0.0;
+            ys[rr][cc] = (row < r1 && yc < J.c) ? gp(J.Y)[row + (long)yc * J.ldy] : 0.0;
         }
         __syncthreads();
 #pragma unroll 8
@@ -264,9 +267,9 @@ __global__ __launch_bounds__(NT) void k_gram_small(const GramJob *__restrict__ j
     for (long r = r0 + threadIdx.x; r < r1; r += NT) {
         double xv[GSMALL_A], yv[GSMALL_A];
 #pragma unroll
-        for (int i = 0; i < GSMALL_A; ++i) xv[i] = i < na ? J.X[r + (long)(ia0 + i) * J.ldx] : 0.0;
+        for (int i = 0; i < GSMALL_A; ++i) xv[i] = i < na ? gp(J.X)[r + (long)(ia0 + i) * J.ldx] : 0.0;
 #pragma unroll
-        for (int j = 0; j < GSMALL_A; ++j) yv[j] = j < J.c ? J.Y[r + (long)j * J.ldy] : 0.0;
+        for (int j = 0; j < GSMALL_A; ++j) yv[j] = j < J.c ? gp(J.Y)[r + (long)j * J.ldy] : 0.0;
 #pragma unroll
         for (int i = 0; i < GSMALL_A; ++i)
 #pragma unroll
@@ -351,21 +354,21 @@ __global__ __launch_bounds__(NT) void k_combo(const ComboJob *__restrict__ jobs)
                 const int j = j0 + u;
                 double v = 0.0;
                 if (j < c) {
-                    if (J.Y0) v = J.Y0[r + (long)j * J.ldy0];
-                    else if (J.beta != 0.0) v = J.beta * J.Y[r + (long)j * J.ldy];
+                    if (J.Y0) v = gp(J.Y0)[r + (long)j * J.ldy0];
+                    else if (J.beta != 0.0) v = J.beta * gp(J.Y)[r + (long)j * J.ldy];
                 }
                 s[u] = v;
             }
             for (int k = 0; k < a; ++k) {
-                const double xv = J.X[r + (long)k * J.ldx];
-                const double *qk = J.Q + k;
+                const double xv = gp(J.X)[r + (long)k * J.ldx];
+                const gdbl *qk = gp(J.Q) + k;
 #pragma unroll
                 for (int u = 0; u < CJ; ++u)
                     if (j0 + u < c) s[u] = fma(xv, qk[(long)(j0 + u) * J.ldq], s[u]);
             }
 #pragma unroll
             for (int u = 0; u < CJ; ++u)
-                if (j0 + u < c) J.Y[r + (long)(j0 + u) * J.ldy] = s[u];
+                if (j0 + u < c) gp(J.Y)[r + (long)(j0 + u) * J.ldy] = s[u];
         }
     }
 }

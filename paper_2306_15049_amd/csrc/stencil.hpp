@@ -4,14 +4,16 @@
 // by the PSF and E = D^T W D (Section 2.1, eq. blkeqn).  A workgroup stages
 // its input on a (TY + 2hy) x (TX + 2hx) window in LDS (hy = 2 ry: K^T K
 // reaches two PSF radii) and then:
-//   * rank-1 PSF h = fy fx^T (square after zero padding, S taps): four 1-D
-//     passes -- x conv, x corr, y conv, y corr.  K^T K = (Ty^T Ty) (x) (Tx^T Tx)
-//     because the x and y factors commute; the forward pass output is masked
-//     to the image before its transpose reads it (zero boundary);
+//   * rank-1 PSF h = fy fx^T (square after zero padding, S = 2r + 1 taps):
+//     K^T K = (Ty^T Ty) (x) (Tx^T Tx), and each factor T^T T is a band of
+//     4r + 1 diagonals (the autocorrelation of the 1-D factor) except for an
+//     r x r correction at each end of a line (the terms of the zero boundary).
+//     So two banded passes -- along x over all window rows, then along y into
+//     the tile -- plus the end corrections on tiles that touch the image edge;
 //   * any other PSF: a direct 2-D conv then corr, masked in between;
 //   * E on the tile from the 5-point neighbourhood and the weight planes.
-// Each thread of a pass produces R consecutive outputs from a window of
-// R + S - 1 registers, so an output costs (R + S - 1) / R LDS reads and S FMAs.
+// Each thread of a banded pass produces R consecutive outputs from a sliding
+// register window, so an output costs (R + taps - 1) / R LDS reads.
 #pragma once
 #include "internal.hpp"
 
@@ -41,11 +43,11 @@ struct Geo {
     int hy, hx;        // halo of the staged input (2r, at least 1 for E)
     int oy, ox;        // hy - 2ry, hx - 2rx (0 or 1)
     int H0, W0, P0;    // staged input
-    int W1, P1;        // after the x conv pass
-    int P2;            // width-tx intermediates
-    int H3;            // rows after the y conv pass
+    int W1, P1;        // after the conv pass (direct path)
+    int P2;            // pitch of width-tx intermediates (banded x output)
+    int H3;            // rows after the conv pass (direct path)
     int PE;            // pitch of the output accumulator / interior copies
-    int off1, offE, offP, total;
+    int off1, offE, offP, offT, offF, total;   // offT: a slot per thread for discarded stores; offF: taps
 };
 
 __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx)
@@ -71,84 +73,185 @@ __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx)
     // instead of clamping every window load.
     const int pad = RB * (g.P0 > g.P1 ? g.P0 : g.P1) + RB;
     const int sz0 = g.H0 * g.P0 + pad;
-    const int sz1a = g.H0 * g.P1, sz1b = g.H3 * g.P2;
+    const int sz1a = g.H0 * g.P2, sz1b = g.H3 * g.P1;   // banded x output / direct conv output
     const int sz1 = (sz1a > sz1b ? sz1a : sz1b) + pad;
     g.off1 = (sz0 + 1) & ~1;
     g.offE = (g.off1 + sz1 + 1) & ~1;
     g.offP = (g.offE + ty * g.PE + 1) & ~1;
-    g.total = g.offP + ty * g.PE;
+    g.offT = g.offP + ty * g.PE;
+    g.offF = g.offT + NT;
+    g.total = g.offF + 2 * TAPS;
     return g;
 }
 
-// out[l][e] (=|+=) mask(e) * sum_c g[c] in[l][e + c] over nlines lines of nout
-// outputs; g = f (corr) or reversed f (conv).  Element e of line l is at
-// base + l*step_l + e*step_e.  Consecutive threads take consecutive lines.
-template <int S, int R>
-__device__ __forceinline__ void pass1d(const double *__restrict__ in, int in_e, int in_l, int /*nin*/,
-                                       double *__restrict__ out, int out_e, int out_l, int nlines,
-                                       int nout, const double *__restrict__ f, bool flip, bool acc,
-                                       int lo, int hi)
+// Copy the two bands (x at offF, y at offF + TAPS) into LDS; issued with the
+// window loads, read by the passes as broadcasts.
+__device__ __forceinline__ void stage_taps(const InstDev &I, const Geo &g, double *lds)
 {
-    double g[S];
-#pragma unroll
-    for (int c = 0; c < S; ++c) g[c] = f[flip ? S - 1 - c : c];
+    if (!I.sep) return;
+    const int nb = 4 * (I.sx / 2) + 1;
+    double *f = lds + g.offF;
+    const int t = threadIdx.x;
+    if (t < nb) f[t] = gp(I.band)[t];
+    else if (t >= 64 && t - 64 < nb) f[TAPS + t - 64] = gp(I.band)[nb + t - 64];
+}
+
+// out[l][e] (=|+=) sum_t b[t] in[l][e + t], t < NT_, over nlines lines of nout
+// outputs.  Element e of line l is at base + l*step_l + e*step_e; consecutive
+// threads take consecutive lines.  The taps are applied in chunks of CT so
+// that the register window stays at R + CT - 1 values.  The R accumulators are
+// independent FMA chains; stores past the end of a line go to the thread's
+// slot in `trash` instead of being skipped, so that no branch separates the
+// chains (a guarded store lets the compiler sink each chain into its own
+// block, which serialises them).
+template <int NT_, int R, int CT>
+__device__ __forceinline__ void pass_band(const double *__restrict__ in, int in_e, int in_l,
+                                          double *__restrict__ out, int out_e, int out_l, int nlines,
+                                          int nout, const double *__restrict__ b, bool acc,
+                                          double *__restrict__ trash)
+{
     const int nstrip = (nout + R - 1) / R;
     const int total = nlines * nstrip;
     for (int it = threadIdx.x; it < total; it += NT) {
         const int l = it % nlines;
         const int e0 = (it / nlines) * R;
         const double *src = in + l * in_l + e0 * in_e;
-        double win[R + S - 1];   // elements past nin land in the buffer padding
+        double a[R];
 #pragma unroll
-        for (int k = 0; k < R + S - 1; ++k) win[k] = src[k * in_e];
+        for (int k = 0; k < R; ++k) a[k] = 0.0;
+#pragma unroll
+        for (int c0 = 0; c0 < NT_; c0 += CT) {
+            constexpr int W = R + CT - 1;
+            double win[W];   // elements past the line land in the buffer padding
+#pragma unroll
+            for (int k = 0; k < W; ++k) win[k] = (c0 + k < NT_ + R - 1) ? src[(c0 + k) * in_e] : 0.0;
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                if (c0 + c < NT_) {
+                    const double t = b[c0 + c];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) a[k] = fma(t, win[k + c], a[k]);
+                }
+        }
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            double a = 0.0;
-#pragma unroll
-            for (int c = 0; c < S; ++c) a = fma(g[c], win[k + c], a);
             const int e = e0 + k;
-            if (e < nout) {
-                const double v = (e >= lo && e < hi) ? a : 0.0;
-                double *d = out + l * out_l + e * out_e;
-                if (acc) *d += v;
-                else *d = v;
-            }
+            double *d = e < nout ? out + l * out_l + e * out_e : trash + threadIdx.x;
+            if (acc) *d += a[k];
+            else *d = a[k];
         }
     }
 }
 
-// cA K^T K for a rank-1 square PSF of S taps: buf0 (staged input) -> ebuf (+=).
+// Image positions of a tile's span [a0, a0 + len) that need an end correction
+// of a band of radius r on a line of n: the left range [la, lb) (positions < r)
+// and the right range [ra, rb) (positions >= n - r, not already in the left
+// range), so every position appears once.
+struct EndSpan {
+    int la, nl, ra, nc;
+};
+__device__ __forceinline__ EndSpan end_span(int a0, int len, int n, int r)
+{
+    const int end = min(a0 + len, n);
+    const int lb = min(end, r);
+    const int nl = max(0, lb - a0);
+    const int ra = max(max(n - r, a0), a0 + nl);
+    const int nr = max(0, end - ra);
+    return EndSpan{a0, nl, ra, nl + nr};
+}
+
+// End corrections of the x band on the x-pass output (buf1 = H0 x tx): for
+// image columns j < r subtract (Lx v)[j], for j >= nx - r subtract (Rx v)[..],
+// v being the staged window row (zeros outside the image).  Items run over the
+// window rows times the tile's end columns only.
+template <int r>
+__device__ inline void band_fix_x(const InstDev &I, const Geo &g, const double *buf0, double *buf1, int x0)
+{
+    constexpr int nb = 4 * r + 1, rr = r * r;
+    const int nx = I.nx;
+    const gdbl *Lx = gp(I.band) + 2 * nb, *Rx = Lx + rr;
+    const EndSpan sp = end_span(x0, I.tx, nx, r);
+    for (int it = threadIdx.x; it < g.H0 * sp.nc; it += NT) {
+        const int l = it / sp.nc, c = it - l * sp.nc;
+        const int j = c < sp.nl ? sp.la + c : sp.ra + (c - sp.nl);
+        const double *row = buf0 + l * g.P0 + g.hx - x0;   // row[i] = v at image column i
+        double s0 = 0.0, s1 = 0.0;
+        if (j < r) {
+#pragma unroll
+            for (int i = 0; i < r; ++i) s0 = fma(Lx[j * r + i], row[i], s0);
+        }
+        if (j >= nx - r) {
+            const int p = j - (nx - r);
+#pragma unroll
+            for (int q = 0; q < r; ++q) s1 = fma(Rx[p * r + q], row[nx - r + q], s1);
+        }
+        buf1[l * g.P2 + (j - x0)] -= s0 + s1;
+    }
+}
+
+// End corrections of the y band, subtracted from the tile accumulator; the
+// inputs are the x-pass output rows (buf1 row k = image row y0 - hy + k).
+template <int r>
+__device__ inline void band_fix_y(const InstDev &I, const Geo &g, const double *buf1, double *ebuf, int y0)
+{
+    constexpr int nb = 4 * r + 1, rr = r * r;
+    const int tx = I.tx, ny = I.ny;
+    const gdbl *Ly = gp(I.band) + 2 * nb + 2 * rr, *Ry = Ly + rr;
+    const EndSpan sp = end_span(y0, I.ty, ny, r);
+    for (int it = threadIdx.x; it < sp.nc * tx; it += NT) {
+        const int c = it >> I.ltx, e = it & (tx - 1);
+        const int gy = c < sp.nl ? sp.la + c : sp.ra + (c - sp.nl);
+        const double *col = buf1 + (g.hy - y0) * g.P2 + e;   // col[k * P2] = value at image row k
+        double s0 = 0.0, s1 = 0.0;
+        if (gy < r) {
+#pragma unroll
+            for (int k = 0; k < r; ++k) s0 = fma(Ly[gy * r + k], col[k * g.P2], s0);
+        }
+        if (gy >= ny - r) {
+            const int p = gy - (ny - r);
+#pragma unroll
+            for (int q = 0; q < r; ++q) s1 = fma(Ry[p * r + q], col[(ny - r + q) * g.P2], s1);
+        }
+        ebuf[(gy - y0) * g.PE + e] -= s0 + s1;
+    }
+}
+
+// ebuf += cA K^T K v for a rank-1 square PSF of S = 2r + 1 taps (v staged in
+// buf0, bands staged by stage_taps).
 template <int S>
 __device__ void tile_A_sep(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
 {
-    constexpr int R = S <= 15 ? 8 : 4;
-    double *buf0 = lds, *buf1 = lds + g.off1, *ebuf = lds + g.offE;
+    constexpr int r = S / 2, NB = 4 * r + 1;
+    constexpr int R = NB <= 29 ? RB : 4;
+    constexpr int CT = NB <= 29 ? NB : 16;
+    double *buf0 = lds, *buf1 = lds + g.off1, *ebuf = lds + g.offE, *trash = lds + g.offT;
+    const double *bx = lds + g.offF, *by = lds + g.offF + TAPS;
     const int ty = I.ty, tx = I.tx;
-    // x conv: buf0 (cols from ox) -> buf1, masked to the image columns
-    pass1d<S, R>(buf0 + g.ox, 1, g.P0, g.W0 - g.ox, buf1, 1, g.P1, g.H0, g.W1, I.fx, true, false,
-                 g.rx - x0, I.nx - x0 + g.rx);
+    // x band over every window row: buf0 (from column ox) -> buf1 (H0 x tx)
+    pass_band<NB, R, CT>(buf0 + g.ox, 1, g.P0, buf1, 1, g.P2, g.H0, tx, bx, false, trash);
     __syncthreads();
-    // x corr: buf1 -> buf0 (pitch P2)
-    pass1d<S, R>(buf1, 1, g.P1, g.W1, buf0, 1, g.P2, g.H0, tx, I.fx, false, false, 0, tx);
-    __syncthreads();
-    // y conv: buf0 rows from oy -> buf1 (H3 x tx), masked to the image rows
-    pass1d<S, R>(buf0 + g.oy * g.P2, g.P2, 1, g.H0 - g.oy, buf1, g.P2, 1, tx, g.H3, I.fy, true, false,
-                 g.ry - y0, I.ny - y0 + g.ry);
-    __syncthreads();
-    if (cA != 1.0) {
-        for (int k = threadIdx.x; k < g.H3 * g.P2; k += NT) buf1[k] *= cA;
+    if (r > 0 && (x0 < r || x0 + tx > I.nx - r)) {
+        band_fix_x<r>(I, g, buf0, buf1, x0);
         __syncthreads();
     }
-    // y corr: buf1 -> ebuf (+=)
-    pass1d<S, R>(buf1, g.P2, 1, g.H3, ebuf, g.PE, 1, tx, ty, I.fy, false, true, 0, ty);
+    if (cA != 1.0) {
+        for (int k = threadIdx.x; k < g.H0 * g.P2; k += NT) buf1[k] *= cA;
+        __syncthreads();
+    }
+    // y band: buf1 (from row oy) -> ebuf (+=)
+    pass_band<NB, R, CT>(buf1 + g.oy * g.P2, g.P2, 1, ebuf, g.PE, 1, tx, ty, by, true, trash);
     __syncthreads();
+    if (r > 0 && (y0 < r || y0 + ty > I.ny - r)) {
+        band_fix_y<r>(I, g, buf1, ebuf, y0);
+        __syncthreads();
+    }
 }
 
 // Direct 2-D pass: out[i][j] (=|+=) mask * sum_{a,c} g[a][c] in[i+a][j+c] with
 // g = psf (corr) or the psf rotated by 180 degrees (conv).
 __device__ inline void pass2d(const double *__restrict__ in, int pin, double *__restrict__ out, int pout,
                               int rows, int cols, const double *__restrict__ h, int sy, int sx, bool flip,
-                              bool acc, int rlo, int rhi, int clo, int chi)
+                              bool acc, int rlo, int rhi, int clo, int chi, double *__restrict__ trash)
 {
     constexpr int R = 4;
     const int nstrip = (cols + R - 1) / R;
@@ -163,7 +266,7 @@ __device__ inline void pass2d(const double *__restrict__ in, int pin, double *__
         for (int ay = 0; ay < sy; ++ay) {
             const double *src = in + (i + ay) * pin;
             for (int cx = 0; cx < sx; ++cx) {
-                const double gv = flip ? h[(sy - 1 - ay) * sx + (sx - 1 - cx)] : h[ay * sx + cx];
+                const double gv = flip ? gp(h)[(sy - 1 - ay) * sx + (sx - 1 - cx)] : gp(h)[ay * sx + cx];
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     const int jj = j0 + k + cx;
@@ -173,29 +276,27 @@ __device__ inline void pass2d(const double *__restrict__ in, int pin, double *__
         }
         const bool rin = (i >= rlo && i < rhi);
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
+        for (int k = 0; k < R; ++k) {   // branch-free stores (see pass_band)
             const int j = j0 + k;
-            if (j < cols) {
-                const double v = (rin && j >= clo && j < chi) ? a[k] : 0.0;
-                double *d = out + i * pout + j;
-                if (acc) *d += v;
-                else *d = v;
-            }
+            const double v = (rin && j >= clo && j < chi) ? a[k] : 0.0;
+            double *d = j < cols ? out + i * pout + j : trash + threadIdx.x;
+            if (acc) *d += v;
+            else *d = v;
         }
     }
 }
 
 __device__ inline void tile_A_direct(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
 {
-    double *buf0 = lds, *buf1 = lds + g.off1, *ebuf = lds + g.offE;
+    double *buf0 = lds, *buf1 = lds + g.off1, *ebuf = lds + g.offE, *trash = lds + g.offT;
     pass2d(buf0 + g.oy * g.P0 + g.ox, g.P0, buf1, g.P1, g.H3, g.W1, I.psf, I.sy, I.sx, true, false, g.ry - y0,
-           I.ny - y0 + g.ry, g.rx - x0, I.nx - x0 + g.rx);
+           I.ny - y0 + g.ry, g.rx - x0, I.nx - x0 + g.rx, trash);
     __syncthreads();
     if (cA != 1.0) {
         for (int k = threadIdx.x; k < g.H3 * g.P1; k += NT) buf1[k] *= cA;
         __syncthreads();
     }
-    pass2d(buf1, g.P1, ebuf, g.PE, I.ty, I.tx, I.psf, I.sy, I.sx, false, true, 0, I.ty, 0, I.tx);
+    pass2d(buf1, g.P1, ebuf, g.PE, I.ty, I.tx, I.psf, I.sy, I.sx, false, true, 0, I.ty, 0, I.tx, trash);
     __syncthreads();
 }
 
@@ -216,50 +317,74 @@ __device__ inline void tile_A(const InstDev &I, const Geo &g, double *lds, int y
 #undef RSR_SEP
 }
 
-// ebuf = cE * E v on the tile (v staged in buf0).  Weight planes carry zeros
-// where a difference does not exist, so only neighbours outside the image need
-// a test.
-__device__ inline void tile_E(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cE)
+// E v on the tile in two steps so that the weight loads travel with the
+// window loads: tile_E_load fetches the four weights of each output pixel
+// (w_h at the pixel and its left neighbour, w_v at the pixel and the one above)
+// into registers, tile_E_apply combines them with the staged window.  Weight
+// planes carry zeros where a difference does not exist, so only neighbours
+// outside the image need a test.  Tiles of more than NT * NE pixels load
+// their weights in tile_E_apply.
+constexpr int NE = 4;   // output pixels per thread whose weights are held in registers
+
+struct EWts {
+    double c[NE], d[NE], l[NE], u[NE];
+};
+
+__device__ __forceinline__ void tile_E_load(const InstDev &I, int y0, int x0, int kbase, double cE, EWts &w)
 {
-    constexpr int NE = 4;   // outputs per thread whose weight loads are issued together
+    const int tx = I.tx, nx = I.nx, ny = I.ny, ne = I.ty * I.tx;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+        const int k = kbase + u * NT + threadIdx.x;
+        const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (tx - 1));
+        const bool ok = cE != 0.0 && k < ne && gy < ny && gx < nx;
+        const bool okl = ok && gx > 0, oku = ok && gy > 0;
+        // branch-free: masked lanes load element 0 and discard it
+        const long gi = ok ? (long)gy * nx + gx : 0;
+        const double c = gp(I.wh)[gi], d = gp(I.wv)[gi];
+        const double l = gp(I.wh)[okl ? gi - 1 : 0], up = gp(I.wv)[oku ? gi - nx : 0];
+        w.c[u] = ok ? c : 0.0;
+        w.d[u] = ok ? d : 0.0;
+        w.l[u] = okl ? l : 0.0;
+        w.u[u] = oku ? up : 0.0;
+    }
+}
+
+// ebuf (=) cE * E v for the NT * NE pixels from kbase, weights in w.
+__device__ __forceinline__ void tile_E_apply(const InstDev &I, const Geo &g, double *lds, int y0, int x0, int kbase,
+                                             double cE, const EWts &w)
+{
     const double *buf0 = lds;
     double *ebuf = lds + g.offE;
-    const int ty = I.ty, tx = I.tx, nx = I.nx, ny = I.ny, ne = ty * tx;
-    for (int base = 0; base < ne; base += NT * NE) {
-        long gi[NE];
-        bool ok[NE];
-        int gx[NE], gy[NE];
+    const int tx = I.tx, nx = I.nx, ny = I.ny, ne = I.ty * I.tx;
 #pragma unroll
-        for (int u = 0; u < NE; ++u) {
-            const int k = base + u * NT + threadIdx.x;
-            gy[u] = y0 + (k >> I.ltx);
-            gx[u] = x0 + (k & (tx - 1));
-            ok[u] = cE != 0.0 && k < ne && gy[u] < ny && gx[u] < nx;
-            gi[u] = ok[u] ? (long)gy[u] * nx + gx[u] : 0;
-        }
-        double wc[NE], wd[NE], wl[NE], wu[NE];
-#pragma unroll
-        for (int u = 0; u < NE; ++u) {
-            wc[u] = ok[u] ? I.wh[gi[u]] : 0.0;
-            wd[u] = ok[u] ? I.wv[gi[u]] : 0.0;
-            wl[u] = (ok[u] && gx[u] > 0) ? I.wh[gi[u] - 1] : 0.0;
-            wu[u] = (ok[u] && gy[u] > 0) ? I.wv[gi[u] - nx] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < NE; ++u) {
-            const int k = base + u * NT + threadIdx.x;
-            if (k < ne) {
-                const int i = k >> I.ltx, j = k & (tx - 1);
-                double e = 0.0;
-                if (ok[u]) {
-                    const double *c = buf0 + (g.hy + i) * g.P0 + (g.hx + j);
-                    e = (wl[u] + wc[u] + wu[u] + wd[u]) * c[0] - wl[u] * c[-1] - wc[u] * c[1] - wu[u] * c[-g.P0] -
-                        wd[u] * c[g.P0];
-                    e *= cE;
-                }
-                ebuf[i * g.PE + j] = e;
+    for (int u = 0; u < NE; ++u) {
+        const int k = kbase + u * NT + threadIdx.x;
+        if (k < ne) {
+            const int i = k >> I.ltx, j = k & (tx - 1);
+            const bool ok = cE != 0.0 && y0 + i < ny && x0 + j < nx;
+            double e = 0.0;
+            if (ok) {
+                const double *c = buf0 + (g.hy + i) * g.P0 + (g.hx + j);
+                e = (w.l[u] + w.c[u] + w.u[u] + w.d[u]) * c[0] - w.l[u] * c[-1] - w.c[u] * c[1] - w.u[u] * c[-g.P0] -
+                    w.d[u] * c[g.P0];
+                e *= cE;
             }
+            ebuf[i * g.PE + j] = e;
         }
+    }
+}
+
+// ebuf = cE * E v on the whole tile (v staged in buf0); w holds the weights
+// of the first NT * NE pixels (loaded beforehand by tile_E_load).
+__device__ inline void tile_E(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cE, const EWts &w)
+{
+    const int ne = I.ty * I.tx;
+    tile_E_apply(I, g, lds, y0, x0, 0, cE, w);
+    for (int base = NT * NE; base < ne; base += NT * NE) {
+        EWts v;
+        tile_E_load(I, y0, x0, base, cE, v);
+        tile_E_apply(I, g, lds, y0, x0, base, cE, v);
     }
     __syncthreads();
 }
