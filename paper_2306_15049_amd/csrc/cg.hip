@@ -194,74 +194,80 @@ __device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m,
     __syncthreads();
 }
 
-// Deterministic block-wide sum of cnt consecutive partial values of one
-// system: part[(base + k) * nv + v0 + j] over k < nch.  Result in out[0..cnt).
-__device__ void block_reduce_partials(const double *part, int base, int nch, int nv, int v0, int cnt, double *out,
+// Deterministic block-wide sum of cnt (<= NV) consecutive partial values of
+// one system: part[(base + k) * NVP + v0 + j] over k < nch.  Result in
+// out[0..cnt).
+template <int NV>
+__device__ void block_reduce_partials(const double *part, int base, int nch, int v0, int cnt, double *out,
                                       double *red)
 {
-    double acc[NVB];
+    double acc[NV];
 #pragma unroll
-    for (int j = 0; j < NVB; ++j) acc[j] = 0.0;
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     for (int k = threadIdx.x; k < nch; k += NT) {
-        const double *p = part + (long)(base + k) * nv + v0;
+        const double *p = part + (long)(base + k) * NVP + v0;
         // branch-free so that all loads of a slot are in flight together; the
         // clamped index stays inside the slot
-        double v[NVB];
+        double v[NV];
 #pragma unroll
-        for (int j = 0; j < NVB; ++j) v[j] = cld(p + (j < cnt ? j : cnt - 1));
+        for (int j = 0; j < NV; ++j) v[j] = cld(p + (j < cnt ? j : cnt - 1));
 #pragma unroll
-        for (int j = 0; j < NVB; ++j) acc[j] += j < cnt ? v[j] : 0.0;
+        for (int j = 0; j < NV; ++j) acc[j] += j < cnt ? v[j] : 0.0;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < NVB; ++j)
+    for (int j = 0; j < NV; ++j)
         if (j < cnt) {
             const double s = wave_sum(acc[j]);
-            if (lane == 0) red[wid * NVB + j] = s;
+            if (lane == 0) red[wid * NVP + j] = s;
         }
     __syncthreads();
     if (threadIdx.x < cnt) {
         double s = 0.0;
-        for (int w = 0; w < NT / 64; ++w) s += red[w * NVB + threadIdx.x];
+        for (int w = 0; w < NT / 64; ++w) s += red[w * NVP + threadIdx.x];
         out[threadIdx.x] = s;
     }
     __syncthreads();
 }
 
-// Block-reduce `cnt` per-thread accumulators (fixed order) and write them to
-// part[slot * nv + j].
-__device__ __forceinline__ void flush_partials(const double (&acc)[NVB], int cnt, double *part, long slot, int nv,
-                                               double *red)
+// Adds the block-wide sums of cnt per-thread values (fixed order) to acc[0..cnt).
+template <int NV>
+__device__ __forceinline__ void block_accumulate(const double (&v)[NV], int cnt, double *acc, double *red)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < NVB; ++j)
+    for (int j = 0; j < NV; ++j)
         if (j < cnt) {
-            const double sm = wave_sum(acc[j]);
-            if (lane == 0) red[wid * NVB + j] = sm;
+            const double s = wave_sum(v[j]);
+            if (lane == 0) red[wid * NVP + j] = s;
         }
     __syncthreads();
     if (threadIdx.x < cnt) {
-        double sm = 0.0;
-        for (int w = 0; w < NT / 64; ++w) sm += red[w * NVB + threadIdx.x];
-        gp(part)[slot * nv + threadIdx.x] = sm;
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w * NVP + threadIdx.x];
+        acc[threadIdx.x] += s;
     }
     __syncthreads();
 }
 
-constexpr int NB = 4;    // pixels per thread whose loads are issued together (tile interior)
-constexpr int NBW = 12;  // window rows per thread loaded together in phase 1
+constexpr int NBW = 6;   // window rows per thread whose loads are issued together
 constexpr int NBE = 2;   // interior pixels per thread whose local-basis loads are issued together
 
-// at most 256 registers per lane keeps two waves per SIMD
+// QT: widest local space of the launch (the loops over basis columns are
+// unrolled to QT).  Chunk partial layout: p.w, r.r, r.w, w.w, Z^T r[QT],
+// Z^T w[QT] in a slot of NVP values.
+// At most 256 registers per lane keeps two waves per SIMD.
+template <int QT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_cg(CGArgs A)
 {
+    constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
     extern __shared__ double smem[];
     double *tile = smem;                          // stencil buffers / reduction scratch
     const int ms = A.msys;                        // per-system arrays sized by the launch
-    double *s_rho = smem + A.tile_lds;            // [ms] current r.r
-    double *s_rho_old = s_rho + ms;               // [ms] previous r.r
-    int *ib = (int *)(s_rho_old + ms);
+    double *s_rho = smem + A.tile_lds;            // [ms] rho_j (one recurrence step from the exact rho_{j-1})
+    double *s_alpha = s_rho + ms;                 // [ms] alpha_{j-1}
+    double *s_beta = s_alpha + ms;                // [ms] beta_j
+    int *ib = (int *)(s_beta + ms);
     Assign S0, S1;   // two named assignments (a runtime-indexed array would live in scratch)
     S0.act = ib; ib += ms;
     S0.pre = ib; ib += ms + 1;
@@ -271,10 +277,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     S1.foff = ib; ib += ms + 1;
     const BarCtl bc = bar_ctl(A);
     __shared__ int s_m[2], s_ipb[2], s_tmp[NT / 64], s_flag;
-    __shared__ double s_red[(NT / 64) * NVB];
-    __shared__ double s_vals[NVB + 2];
-    __shared__ double s_c[QMAX];                  // c_{j+1} of the current system
-    __shared__ double s_alpha;
+    __shared__ double s_red[(NT / 64) * NVP];
+    __shared__ double s_vals[NVP];
+    __shared__ double s_acc[NVP];                 // partial sums of the current system over the chunk
+    __shared__ double s_z[QMAX];
+    __shared__ double s_c[QMAX];                  // c_j of the current system
 
     const int G = A.G;
     const int chunk = chunk_of_block(blockIdx.x, G);
@@ -284,93 +291,56 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __syncthreads();
     build_assign(A, S0, A.nsys, G, &s_m[0], &s_ipb[0], s_tmp);
 
-    // ---- phase 2 (and the initial reduction pass with update = false)
-    auto run_phase2 = [&](const Assign &As, int m, int ipb, bool update, int it) {
+    auto slot_of = [&](const Assign &As, int m, int ipb, int s) {
+        return A.sys[s].tile_base + (chunk - As.pre[find_pos(As.act, m, s)] / ipb);
+    };
+
+    // ---- initial pass: r_0.r_0 and Z^T r_0 into the partial slots read by iteration 0
+    {
+        const Assign &As = S0;
+        const int m = s_m[0], ipb = s_ipb[0];
         const int T = As.pre[m];
         const int lo = chunk * ipb;
         const int hi = lo + ipb < T ? lo + ipb : T;
-        if (lo >= hi) return;
-        int a = find_pos(As.pre, m, lo);
-        int cur_sys = -1;
-        double racc[NVB];
-        double alpha = 0.0;
-        int q = 0;
+        double *pout = A.part[1];
+        int a = lo < hi ? find_pos(As.pre, m, lo) : 0;
+        int cur_sys = -1, q = 0;
         for (int item = lo; item < hi; ++item) {
             while (item >= As.pre[a + 1]) ++a;
             const int s = uni(As.act[a]);
             if (s != cur_sys) {
-                if (cur_sys >= 0)
-                    flush_partials(racc, 1 + q, A.partB,
-                                   A.sys[cur_sys].tile_base + (chunk - As.pre[find_pos(As.act, m, cur_sys)] / ipb),
-                                   NVB, s_red);
+                if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
                 cur_sys = s;
                 q = A.sys[s].q;
-#pragma unroll
-                for (int j = 0; j < NVB; ++j) racc[j] = 0.0;
-                if (update) {
-                    block_reduce_partials(A.partA, A.sys[s].tile_base, As.foff[a + 1] - As.foff[a], 1, 0, 1,
-                                          s_vals, s_red);
-                    const double pw = s_vals[0];
-                    alpha = (pw > 0.0 && isfinite(pw)) ? s_rho[s] / pw : -1.0;   // -1: breakdown
-                }
+                if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
+                __syncthreads();
             }
-            // copies of the system's pointers and the instance geometry: read through a
-            // reference, every global store below would force them to be reloaded
-            const SysDev &Yg = A.sys[s];
-            const InstDev I = A.inst[Yg.inst];
-            gdbl *__restrict__ Yx = gp(Yg.x);
-            gdbl *__restrict__ Yr = gp(Yg.r);
-            const gdbl *__restrict__ Ypa = gp(Yg.pa);
-            const gdbl *__restrict__ Yw = gp(Yg.w);
-            const gdbl *__restrict__ YZ = gp(Yg.Z);
-            const long ldw = Yg.ldw;
+            const SysDev &Y = A.sys[s];
+            const InstDev I = A.inst[Y.inst];
+            const gdbl *__restrict__ Yr = gp(Y.rb[0]);
+            const gdbl *__restrict__ YZ = gp(Y.Z);
+            const long ldw = Y.ldw;
             const int t = uni(item - As.pre[a]);
             const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
             const int ne = I.ty * I.tx;
-            for (int base = 0; base < ne; base += NT * NB) {
-                long gi[NB];
-                bool ok[NB];
+            double v[NVT];
 #pragma unroll
-                for (int u = 0; u < NB; ++u) {
-                    const int k = base + u * NT + threadIdx.x;
-                    const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
-                    ok[u] = k < ne && gy < I.ny && gx < I.nx;
-                    gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
-                }
-                double rv[NB], xv[NB], pv[NB], wv[NB], zv[NB][QMAX];
+            for (int j = 0; j < NVT; ++j) v[j] = 0.0;
+            for (int k = threadIdx.x; k < ne; k += NT) {
+                const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
+                if (gy < I.ny && gx < I.nx) {
+                    const int gi = gy * I.nx + gx;
+                    const double r = Yr[gi];
+                    v[1] = fma(r, r, v[1]);
 #pragma unroll
-                for (int u = 0; u < NB; ++u) {
-                    rv[u] = ok[u] ? Yr[gi[u]] : 0.0;
-                    if (update && alpha >= 0.0) {
-                        xv[u] = ok[u] ? Yx[gi[u]] : 0.0;
-                        pv[u] = ok[u] ? Ypa[gi[u]] : 0.0;
-                        wv[u] = ok[u] ? Yw[gi[u]] : 0.0;
-                    }
-#pragma unroll
-                    for (int j = 0; j < QMAX; ++j) zv[u][j] = (j < q && ok[u]) ? YZ[j * ldw + gi[u]] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < NB; ++u) {
-                    double rn = rv[u];
-                    if (update && alpha >= 0.0 && ok[u]) {
-                        Yx[gi[u]] = fma(alpha, pv[u], xv[u]);
-                        rn = fma(-alpha, wv[u], rn);
-                        Yr[gi[u]] = rn;
-                    }
-                    racc[0] = fma(rn, rn, racc[0]);
-#pragma unroll
-                    for (int j = 0; j < QMAX; ++j) racc[1 + j] = fma(zv[u][j], rn, racc[1 + j]);
+                    for (int j = 0; j < QT; ++j)
+                        if (j < q) v[4 + j] = fma(YZ[j * ldw + gi], r, v[4 + j]);
                 }
             }
-            if (update && alpha < 0.0) racc[0] = -1e300 / (double)NT;   // propagate breakdown
+            block_accumulate<NVT>(v, NVT, s_acc, s_red);
         }
-        if (cur_sys >= 0)
-            flush_partials(racc, 1 + q, A.partB,
-                           A.sys[cur_sys].tile_base + (chunk - As.pre[find_pos(As.act, m, cur_sys)] / ipb), NVB,
-                           s_red);
-    };
-
-    run_phase2(S0, s_m[0], s_ipb[0], false, -1);
+        if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+    }
     int nbar = 0;
     if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
 
@@ -379,51 +349,84 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     };
     for (int it = 0;; ++it) {
         stamp(it, 0);
-        // ---- r.r of every active system (partials of assignment O) and decisions
+        // (selects, not A.part[i]: a runtime index into the argument block would copy it to scratch)
+        const double *pprev = (it & 1) ? A.part[0] : A.part[1];   // written by the previous phase (or the initial pass)
+        double *pcur = (it & 1) ? A.part[1] : A.part[0];
+        // ---- p.w, r.r, r.w, w.w of every active system and the decisions
         Assign O = cur ? S1 : S0;
         const int mo = s_m[cur];
+        const int ipbo = s_ipb[cur];
         const int F = O.foff[mo];
-        double *flat = tile;
+        double *fl = tile;   // [4][F] then [4][mo]
         for (int f = threadIdx.x; f < F; f += NT) {
             const int l = find_pos(O.foff, mo, f);
-            flat[f] = cld(A.partB + (long)(A.sys[O.act[l]].tile_base + (f - O.foff[l])) * NVB);
+            const double *p = pprev + (long)(A.sys[O.act[l]].tile_base + (f - O.foff[l])) * NVP;
+            const double v0 = cld(p), v1 = cld(p + 1), v2 = cld(p + 2), v3 = cld(p + 3);
+            fl[f] = v0;
+            fl[F + f] = v1;
+            fl[2 * F + f] = v2;
+            fl[3 * F + f] = v3;
+        }
+        __syncthreads();
+        double *sums = fl + 4 * F;   // [4][mo]
+        if (mo <= 16) {
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+            for (int a = wid; a < mo; a += NT / 64) {
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int k = O.foff[a] + lane; k < O.foff[a + 1]; k += 64)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] += fl[u * F + k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double sv = wave_sum(v[u]);
+                    if (lane == 0) sums[u * mo + a] = sv;
+                }
+            }
+        } else {
+            for (int a = threadIdx.x; a < mo; a += NT) {
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int k = O.foff[a]; k < O.foff[a + 1]; ++k)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] += fl[u * F + k];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sums[u * mo + a] = v[u];
+            }
         }
         __syncthreads();
         Assign N = cur ? S0 : S1;
         int *keep = N.pre;       // scratch, rebuilt by build_assign
         int *newpos = N.foff;    // scratch
-        if (mo <= 16) {
-            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-            for (int a = wid; a < mo; a += NT / 64) {
-                double v = 0.0;
-                for (int k = O.foff[a] + lane; k < O.foff[a + 1]; k += 64) v += flat[k];
-                v = wave_sum(v);
-                if (lane == 0) flat[F + a] = v;
-            }
-        } else {
-            for (int a = threadIdx.x; a < mo; a += NT) {
-                double v = 0.0;
-                for (int k = O.foff[a]; k < O.foff[a + 1]; ++k) v += flat[k];
-                flat[F + a] = v;
-            }
-        }
-        __syncthreads();
         for (int a = threadIdx.x; a < mo; a += NT) {
             const int s = O.act[a];
-            const double rho = flat[F + a];
+            const double pw = sums[a], rr = sums[mo + a], rw = sums[2 * mo + a], ww = sums[3 * mo + a];
+            double rho, alpha = 0.0, beta = 0.0;
             int st = 0;
-            if (!isfinite(rho)) st = -3;
-            else if (rho < 0.0) st = -4;
-            else if (sqrt(rho) <= A.sys[s].tolabs) st = 1;
-            else if (it >= A.maxit) st = 2;
-            s_rho_old[s] = s_rho[s];
+            if (it == 0) {
+                rho = rr;
+                if (!isfinite(rr)) st = -3;
+            } else {
+                // alpha_{j-1} from the exact rho_{j-1}; rho_j = ||r_{j-1} - alpha w_{j-1}||^2 expanded
+                alpha = rr / pw;
+                rho = fma(alpha, fma(alpha, ww, -2.0 * rw), rr);
+                if (rho < 0.0) rho = 0.0;
+                beta = rho / rr;
+                if (!isfinite(pw) || !isfinite(rr) || !isfinite(rho)) st = -3;
+                else if (!(pw > 0.0)) st = -4;
+            }
+            if (st == 0) {
+                if (sqrt(rho) <= A.sys[s].tolabs) st = 1;
+                else if (it >= A.maxit) st = 2;
+            }
             s_rho[s] = rho;
+            s_alpha[s] = alpha;
+            s_beta[s] = beta;
             keep[a] = (st == 0);
             newpos[a] = (st == 0);
             if (st != 0 && blockIdx.x == 0) {
                 A.out_status[s] = st;
                 A.out_iters[s] = it;
                 A.out_rho[s] = rho;
+                A.out_alpha[s] = st > 0 ? alpha : 0.0;   // x_j = x_{j-1} + alpha p_{j-1} is applied after the launch
             }
         }
         __syncthreads();
@@ -442,50 +445,57 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         const int mn = s_m[cur ^ 1];
         if (mn == 0) break;
-        // tiles move between workgroups when the active set shrinks: drop cached copies
-        if (mn != mo) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        build_assign(A, N, mn, G, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp);
-        const int ipbn = s_ipb[cur ^ 1];
+        if (mn != mo) {
+            // tiles move between workgroups when the active set shrinks: drop cached copies
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            build_assign(A, N, mn, G, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp);
+        } else {
+            N = O;   // unchanged: keep the assignment (and its buffers)
+        }
+        const bool flip = mn != mo;
+        const int ipbn = flip ? s_ipb[cur ^ 1] : ipbo;
         stamp(it, 1);
 
-        // ---- phase 1 under N
+        // ---- the iteration's one phase under N
         {
             const int T = N.pre[mn];
             const int lo = chunk * ipbn;
             const int hi = lo + ipbn < T ? lo + ipbn : T;
             int a = lo < hi ? find_pos(N.pre, mn, lo) : 0;
             int cur_sys = -1;
-            double pacc[NVB];
-            pacc[0] = 0.0;
             int q = 0;
-            double beta = 0.0;
+            double alpha = 0.0, beta = 0.0;
             for (int item = lo; item < hi; ++item) {
                 while (item >= N.pre[a + 1]) ++a;
                 const int s = uni(N.act[a]);
                 const SysDev &Y = A.sys[s];
                 if (s != cur_sys) {
-                    if (cur_sys >= 0)
-                        flush_partials(pacc, 1, A.partA,
-                                       A.sys[cur_sys].tile_base + (chunk - N.pre[find_pos(N.act, mn, cur_sys)] / ipbn),
-                                       1, s_red);
+                    if (cur_sys >= 0 && threadIdx.x < NVP)
+                        gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
                     cur_sys = s;
-                    pacc[0] = 0.0;
                     q = Y.q;
-                    beta = it > 0 ? s_rho[s] / s_rho_old[s] : 0.0;
+                    alpha = s_alpha[s];
+                    beta = s_beta[s];
+                    if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
                     if (threadIdx.x >= q && threadIdx.x < QMAX) s_c[threadIdx.x] = 0.0;   // unused columns
                     if (q > 0) {
-                        // mu = Ginv (Z^T r) from the previous assignment's partials; c_{j+1} = beta c_j + mu
+                        // Z^T r_j = Z^T r_{j-1} - alpha Z^T w_{j-1}; mu = Ginv Z^T r_j; c_j = beta c_{j-1} + mu
+                        // (c_{j-1} is fetched first so that it travels with the partial-sum loads)
+                        const double cold =
+                            (it > 0 && threadIdx.x < q) ? cld(Y.cbuf + ((it + 1) & 1) * QMAX + threadIdx.x) : 0.0;
                         const int po = find_pos(O.act, mo, s);
-                        block_reduce_partials(A.partB, Y.tile_base, O.foff[po + 1] - O.foff[po], NVB, 1, q, s_vals,
-                                              s_red);
+                        block_reduce_partials<(QT > 0 ? 2 * QT : 1)>(pprev, Y.tile_base, O.foff[po + 1] - O.foff[po], 4,
+                                                                   2 * QT, s_vals, s_red);
+                        if (threadIdx.x < q)
+                            s_z[threadIdx.x] = fma(-alpha, s_vals[QT + threadIdx.x], s_vals[threadIdx.x]);
+                        __syncthreads();
                         if (threadIdx.x < q) {
                             double m = 0.0;
-                            for (int j = 0; j < q; ++j) m += Y.Ginv[threadIdx.x * QMAX + j] * s_vals[j];
-                            const double cold = it > 0 ? cld(Y.cbuf + (it & 1) * QMAX + threadIdx.x) : 0.0;
+                            for (int j = 0; j < q; ++j) m += Y.Ginv[threadIdx.x * QMAX + j] * s_z[j];
                             const double cn = fma(beta, cold, m);
                             s_c[threadIdx.x] = cn;
-                            // the workgroup holding the system's first chunk publishes c_{j+1}
-                            if (chunk == N.pre[a] / ipbn) gp(Y.cbuf)[((it + 1) & 1) * QMAX + threadIdx.x] = cn;
+                            // the workgroup holding the system's first chunk publishes c_j
+                            if (chunk == N.pre[a] / ipbn) gp(Y.cbuf)[(it & 1) * QMAX + threadIdx.x] = cn;
                         }
                     }
                     __syncthreads();
@@ -494,19 +504,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx);
                 const int t = uni(item - N.pre[a]);
                 const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
-                // local copies (see phase 2): no reloads after the global stores
-                const gdbl *__restrict__ pold = gp((it & 1) ? Y.p1 : Y.p0);
-                gdbl *__restrict__ pnew = gp((it & 1) ? Y.p0 : Y.p1);
-                const gdbl *__restrict__ Yr = gp(Y.r);
+                // local copies: no reloads after the global stores
+                const int pj = it & 1, pk = (it + 1) & 1;      // buffers of step j and of step j - 1
+                const gdbl *__restrict__ rsrc = gp(it > 0 ? Y.rb[pk] : Y.rb[0]);
+                gdbl *__restrict__ rdst = gp(Y.rb[pj]);
+                const gdbl *__restrict__ wsrc = gp(Y.wb[pk]);
+                gdbl *__restrict__ wdst = gp(Y.wb[pj]);
+                const gdbl *__restrict__ psrc = gp(Y.pb[pk]);
+                gdbl *__restrict__ pdst = gp(Y.pb[pj]);
                 const gdbl *__restrict__ YW = gp(Y.W);
                 const gdbl *__restrict__ YZ = gp(Y.Z);
                 gdbl *__restrict__ Ypa = gp(Y.pa);
-                gdbl *__restrict__ Yw = gp(Y.w);
+                gdbl *__restrict__ Yx = gp(Y.x);
                 const long ldw = Y.ldw;
                 const double gam = Y.gamma;
                 double *pbuf = tile + g.offP;
-                // stage ph = r + beta ph_old on the window (all of a thread's loads
-                // issued together); keep the interior in pbuf
+                double *rbuf = tile + g.offR;
+                // stage ph_j = r_j + beta ph_{j-1} with r_j = r_{j-1} - alpha w_{j-1} on the
+                // window (halo recomputed from the neighbours' step j-1 vectors); keep the
+                // interior of ph_j and r_j in LDS
                 EWts ew;
                 tile_E_load(I, y0, x0, 0, gam, ew);   // in flight with the window loads
                 stage_taps(I, g, tile);
@@ -516,7 +532,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
                 const bool colown = lj >= g.hx && lj < g.hx + I.tx;
                 for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
-                    long gi[NBW];
+                    int gi[NBW];
                     bool ok[NBW], own[NBW];
 #pragma unroll
                     for (int u = 0; u < NBW; ++u) {
@@ -524,30 +540,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         const int gy = y0 - g.hy + li;
                         ok[u] = colok && li < g.H0 && gy >= 0 && gy < I.ny;
                         own[u] = colown && li >= g.hy && li < g.hy + I.ty;
-                        gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
+                        gi[u] = ok[u] ? gy * I.nx + gx : 0;
                     }
                     // every window cell with coherent loads (halo cells were written by
                     // other workgroups), branch-free so that all loads are in flight
                     // together; masked lanes load element 0 and discard it
-                    double rv[NBW], pv[NBW];
+                    double rv[NBW], wv[NBW], pv[NBW];
 #pragma unroll
-                    for (int u = 0; u < NBW; ++u) rv[u] = cld(Yr + gi[u]);
+                    for (int u = 0; u < NBW; ++u) rv[u] = cld(rsrc + gi[u]);
                     if (it > 0) {
 #pragma unroll
-                        for (int u = 0; u < NBW; ++u) pv[u] = cld(pold + gi[u]);
+                        for (int u = 0; u < NBW; ++u) {
+                            wv[u] = cld(wsrc + gi[u]);
+                            pv[u] = cld(psrc + gi[u]);
+                        }
                     } else {
 #pragma unroll
-                        for (int u = 0; u < NBW; ++u) pv[u] = 0.0;
+                        for (int u = 0; u < NBW; ++u) wv[u] = pv[u] = 0.0;
                     }
 #pragma unroll
                     for (int u = 0; u < NBW; ++u) {
                         const int li = li0 + u * wm.rs;
-                        const double v = ok[u] ? fma(beta, pv[u], rv[u]) : 0.0;
+                        const double rj = fma(-alpha, wv[u], rv[u]);
+                        const double ph = ok[u] ? fma(beta, pv[u], rj) : 0.0;
                         double *d = (lj < g.W0 && li < g.H0) ? tile + li * g.P0 + lj : tile + g.offT + threadIdx.x;
-                        *d = v;
+                        *d = ph;
                         if (ok[u] && own[u]) {
-                            pnew[gi[u]] = v;
-                            pbuf[(li - g.hy) * g.PE + (lj - g.hx)] = v;
+                            if (it > 0) rdst[gi[u]] = rj;
+                            pdst[gi[u]] = ph;
+                            const int ii = (li - g.hy) * g.PE + (lj - g.hx);
+                            pbuf[ii] = ph;
+                            rbuf[ii] = rj;
                         }
                     }
                 }
@@ -556,86 +579,116 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 tile_E(I, g, tile, y0, x0, gam, ew);
                 tile_A(I, g, tile, y0, x0, 1.0);
                 if (item == lo) stamp(it, 7);
-                // interior: p = ph - W c, w = B ph - Z c, partial p.w; all 2q basis
-                // loads of a pixel batch are issued together
+                // interior: x_j = x_{j-1} + alpha p_{j-1}; p_j = ph_j - W c_j; w_j = B ph_j - Z c_j;
+                // partials p.w, r.r, r.w, w.w, Z^T r, Z^T w (all 2q basis loads of a pixel batch together)
                 const double *ebuf = tile + g.offE;
                 const int ne = I.ty * I.tx;
+                double v[NVT];
+#pragma unroll
+                for (int j = 0; j < NVT; ++j) v[j] = 0.0;
                 for (int base = 0; base < ne; base += NT * NBE) {
-                    long gi[NBE];
+                    int gi[NBE];
                     bool ok[NBE];
 #pragma unroll
                     for (int u = 0; u < NBE; ++u) {
                         const int k = base + u * NT + threadIdx.x;
                         const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
                         ok[u] = k < ne && gy < I.ny && gx < I.nx;
-                        gi[u] = ok[u] ? (long)gy * I.nx + gx : 0;
+                        gi[u] = ok[u] ? gy * I.nx + gx : 0;
                     }
-                    double wl[NBE][QMAX], zl[NBE][QMAX];
+                    double wl[NBE][QT > 0 ? QT : 1], zl[NBE][QT > 0 ? QT : 1], xo[NBE], po[NBE];
 #pragma unroll
-                    for (int u = 0; u < NBE; ++u)
+                    for (int u = 0; u < NBE; ++u) {
 #pragma unroll
-                        for (int j = 0; j < QMAX; ++j) {
+                        for (int j = 0; j < QT; ++j) {
                             wl[u][j] = (j < q && ok[u]) ? YW[j * ldw + gi[u]] : 0.0;
                             zl[u][j] = (j < q && ok[u]) ? YZ[j * ldw + gi[u]] : 0.0;
                         }
+                        xo[u] = Yx[gi[u]];
+                        po[u] = Ypa[gi[u]];
+                    }
 #pragma unroll
                     for (int u = 0; u < NBE; ++u) {
                         const int k = base + u * NT + threadIdx.x;
                         const int ii = ok[u] ? (k >> I.ltx) : 0, jj = ok[u] ? (k & (I.tx - 1)) : 0;
                         double p = pbuf[ii * g.PE + jj];
                         double w = ebuf[ii * g.PE + jj];
+                        const double rj = rbuf[ii * g.PE + jj];
 #pragma unroll
-                        for (int j = 0; j < QMAX; ++j) {
+                        for (int j = 0; j < QT; ++j) {
                             p = fma(-s_c[j], wl[u][j], p);
                             w = fma(-s_c[j], zl[u][j], w);
                         }
                         if (ok[u]) {
+                            if (it > 0) Yx[gi[u]] = fma(alpha, po[u], xo[u]);
                             Ypa[gi[u]] = p;
-                            Yw[gi[u]] = w;
-                            pacc[0] = fma(p, w, pacc[0]);
+                            wdst[gi[u]] = w;
+                            v[0] = fma(p, w, v[0]);
+                            v[1] = fma(rj, rj, v[1]);
+                            v[2] = fma(rj, w, v[2]);
+                            v[3] = fma(w, w, v[3]);
+#pragma unroll
+                            for (int j = 0; j < QT; ++j) {
+                                v[4 + j] = fma(zl[u][j], rj, v[4 + j]);
+                                v[4 + QT + j] = fma(zl[u][j], w, v[4 + QT + j]);
+                            }
                         }
                     }
                 }
-                __syncthreads();
+                block_accumulate<NVT>(v, NVT, s_acc, s_red);
             }
-            if (cur_sys >= 0)
-                flush_partials(pacc, 1, A.partA,
-                               A.sys[cur_sys].tile_base + (chunk - N.pre[find_pos(N.act, mn, cur_sys)] / ipbn), 1,
-                               s_red);
+            if (cur_sys >= 0 && threadIdx.x < NVP)
+                gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
         }
         stamp(it, 2);
         if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
         stamp(it, 3);
-        run_phase2(N, mn, ipbn, true, it);
-        stamp(it, 4);
-        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
-        stamp(it, 5);
-        cur ^= 1;
+        if (flip) cur ^= 1;
     }
+}
+
+int cg_tile_lds(int tile_lds, int msys)
+{
+    // the tile region doubles as the scratch of the per-iteration reduction:
+    // 4 values for each of at most G + 2 msys chunk partials (G <= 1024) and 4 sums per system
+    const int need = 4 * (1024 + 2 * msys) + 4 * msys;
+    return tile_lds > need ? tile_lds : need;
 }
 
 size_t cg_lds_bytes(int tile_lds, int msys)
 {
-    const size_t d = (size_t)tile_lds + 2 * (size_t)msys;            // tile + rho arrays
+    const size_t d = (size_t)tile_lds + 3 * (size_t)msys;            // tile + rho, alpha, beta arrays
     const size_t ints = 2 * (size_t)(msys + 2 * (msys + 1)) + 2;     // two assignments
     return d * sizeof(double) + ints * sizeof(int);
 }
 
-int cg_max_blocks_per_cu(size_t lds)
+// Compiled widths of the local space; a launch uses the smallest one >= its widest q.
+static const void *cg_kernel(int qt)
+{
+    switch (qt) {
+    case 0: return (const void *)k_cg<0>;
+    case 3: return (const void *)k_cg<3>;
+    case 5: return (const void *)k_cg<5>;
+    default: return (const void *)k_cg<QMAX>;
+    }
+}
+
+int cg_width(int qmax)
+{
+    return qmax <= 0 ? 0 : qmax <= 3 ? 3 : qmax <= 5 ? 5 : QMAX;
+}
+
+int cg_max_blocks_per_cu(size_t lds, int qt)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cg, NT, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cg_kernel(qt), NT, lds) != hipSuccess) return 0;
     return nb;
 }
 
-hipError_t launch_cg(const CGArgs &a, int G, size_t lds, hipStream_t s, bool cooperative)
+hipError_t launch_cg(const CGArgs &a, int qt, int G, size_t lds, hipStream_t s)
 {
-    if (cooperative) {
-        void *args[] = {(void *)&a};
-        return hipLaunchCooperativeKernel((const void *)k_cg, dim3(G), dim3(NT), args, (unsigned)lds, s);
-    }
-    hipLaunchKernelGGL(k_cg, dim3(G), dim3(NT), lds, s, a);
-    return hipGetLastError();
+    void *args[] = {(void *)&a};
+    return hipLaunchCooperativeKernel(cg_kernel(qt), dim3(G), dim3(NT), args, (unsigned)lds, s);
 }
 
 }  // namespace rsr

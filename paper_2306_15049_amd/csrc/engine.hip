@@ -379,7 +379,7 @@ struct SysHost {
     long n;
     const double *b;
     double *x;
-    double *r, *p0, *p1, *w, *xinit, *rt, *pa;   // workspace vectors
+    double *r, *r1, *p0, *p1, *w, *w1, *xinit, *rt, *pa;   // workspace vectors (r, w, p ping-pong in CG)
     double *cbuf;                             // [2][QMAX]
     double *W, *Z;                            // QMAX columns each
     int q = 0;
@@ -423,10 +423,12 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         d.gamma = Y.gamma;
         d.tolabs = o.tol * Y.bnorm;
         d.x = Y.x;
-        d.r = Y.r;
-        d.p0 = Y.p0;
-        d.p1 = Y.p1;
-        d.w = Y.w;
+        d.rb[0] = Y.r;
+        d.rb[1] = Y.r1;
+        d.wb[0] = Y.w;
+        d.wb[1] = Y.w1;
+        d.pb[0] = Y.p0;
+        d.pb[1] = Y.p1;
         d.pa = Y.pa;
         d.cbuf = Y.cbuf;
         d.W = Y.W;
@@ -436,20 +438,24 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
             for (int b2 = 0; b2 < Y.q; ++b2) d.Ginv[a * QMAX + b2] = Y.Ginv[a * Y.q + b2];
     }
     SysDev *dsys = upload(c, c->d_sys, hd, s);
-    c->d_partA.ensure(sizeof(double) * tiles);
-    c->d_partB.ensure(sizeof(double) * tiles * NVB);
+    c->d_partA.ensure(sizeof(double) * tiles * NVP);
+    c->d_partB.ensure(sizeof(double) * tiles * NVP);
     c->d_ctl.ensure(BAR_BYTES);
-    c->d_out.ensure((sizeof(int) * 2 + sizeof(double)) * m + 64);
+    c->d_out.ensure((sizeof(int) * 2 + 2 * sizeof(double)) * m + 64);
     HIPCHK(launch_fill(c->d_ctl.as<double>(), 0.0, BAR_BYTES / sizeof(double), s));
     int *out_iters = (int *)c->d_out.p;
     int *out_status = out_iters + m;
     double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
+    double *out_alpha = out_rho + m;
     HIPCHK(hipMemsetAsync(c->d_out.p, 0, sizeof(int) * 2 * m, s));
 
-    const int tl = max_tile_lds(c);
     const int msys = (m + 7) & ~7;
+    const int tl = cg_tile_lds(max_tile_lds(c), msys);
     const size_t lds = cg_lds_bytes(tl, msys);
-    int bpc = cg_max_blocks_per_cu(lds);
+    int qmax = 0;
+    for (auto *Y : sy) qmax = std::max(qmax, Y->q);
+    const int qt = cg_width(qmax);
+    int bpc = cg_max_blocks_per_cu(lds, qt);
     if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
     int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
     if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
@@ -463,13 +469,14 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.nsys = m;
     a.sys = dsys;
     a.inst = c->d_inst.as<InstDev>();
-    a.partA = c->d_partA.as<double>();
-    a.partB = c->d_partB.as<double>();
+    a.part[0] = c->d_partA.as<double>();
+    a.part[1] = c->d_partB.as<double>();
     a.bar = (unsigned long long *)c->d_ctl.p;
     a.abort_flag = (int *)((char *)c->d_ctl.p + 256);
     a.out_iters = out_iters;
     a.out_status = out_status;
     a.out_rho = out_rho;
+    a.out_alpha = out_alpha;
     a.maxit = o.maxit;
     a.G = G;
     a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * 30.0);   // 30 s
@@ -483,13 +490,13 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         a.stamps = (unsigned long long *)c->d_dbg.p;
     }
     HIPCHK(hipEventRecord(c->ev0, s));
-    HIPCHK(launch_cg(a, G, lds, s, true));
+    HIPCHK(launch_cg(a, qt, G, lds, s));
     HIPCHK(hipEventRecord(c->ev1, s));
     std::vector<int> hi(2 * m + 8);
-    std::vector<double> hr(m);
+    std::vector<double> hr(2 * m);   // final r.r, then the pending step alpha
     int abort_h = 0;
     HIPCHK(hipMemcpyAsync(hi.data(), out_iters, sizeof(int) * 2 * m, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hr.data(), out_rho, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hr.data(), out_rho, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&abort_h, a.abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     float ms = 0.f;
@@ -497,21 +504,20 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     if (dbg) {
         std::vector<unsigned long long> st(DBG_ITERS * 8);
         HIPCHK(hipMemcpy(st.data(), c->d_dbg.p, sizeof(unsigned long long) * st.size(), hipMemcpyDeviceToHost));
-        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        double acc[5] = {0, 0, 0, 0, 0};
         int n = 0;
-        for (int i = 1; i < DBG_ITERS && i + 1 < hi[0] && st[i * 8 + 5]; ++i, ++n) {
-            for (int k = 0; k < 5; ++k) acc[k] += (double)(st[i * 8 + k + 1] - st[i * 8 + k]);
+        for (int i = 1; i < DBG_ITERS && i + 1 < hi[0] && st[i * 8 + 3]; ++i, ++n) {
+            for (int k = 0; k < 3; ++k) acc[k] += (double)(st[i * 8 + k + 1] - st[i * 8 + k]);
             if (st[i * 8 + 6] && st[i * 8 + 7]) {
-                acc[5] += (double)(st[i * 8 + 6] - st[i * 8 + 1]);
-                acc[6] += (double)(st[i * 8 + 7] - st[i * 8 + 6]);
+                acc[3] += (double)(st[i * 8 + 6] - st[i * 8 + 1]);
+                acc[4] += (double)(st[i * 8 + 7] - st[i * 8 + 6]);
             }
         }
         const double tk = c->wall_khz / 1000.0;
         if (n > 0)
-            fprintf(stderr, "[rsr cg stamps] G=%d iters=%d us: reduce+assign %.2f phase1 %.2f (first item: setup+load %.2f "
-                            "stencil %.2f) bar1 %.2f phase2 %.2f bar2 %.2f\n",
-                    G, n, acc[0] / n / tk, acc[1] / n / tk, acc[5] / n / tk, acc[6] / n / tk, acc[2] / n / tk,
-                    acc[3] / n / tk, acc[4] / n / tk);
+            fprintf(stderr, "[rsr cg stamps] G=%d iters=%d us: reduce+assign %.2f phase %.2f (first item: setup+load %.2f "
+                            "stencil %.2f) barrier %.2f\n",
+                    G, n, acc[0] / n / tk, acc[1] / n / tk, acc[3] / n / tk, acc[4] / n / tk, acc[2] / n / tk);
     }
     c->last_cg_ms += ms;
     c->last_launches += 1;
@@ -526,6 +532,16 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         Y.status = hi[m + i];
         c->last_items += (long)hi[i] * hd[i].ntiles;
     }
+    // the kernel leaves the last step x += alpha p of each finished system to here
+    std::vector<ComboJob> fj;
+    std::vector<std::vector<double>> fq;
+    for (int i = 0; i < m; ++i)
+        if (hr[m + i] != 0.0) {
+            SysHost &Y = *sy[i];
+            fj.push_back(ComboJob{Y.pa, Y.n, 1, nullptr, 1, Y.x, Y.n, 1, 1.0, nullptr, 0, Y.n});
+            fq.push_back(std::vector<double>{hr[m + i]});
+        }
+    if (!fj.empty()) combo(c, fj, fq, s);
 }
 
 // Galerkin correction with the local space: x += W y, r -= Z y, y = G^+ W^T r.
@@ -861,14 +877,16 @@ void store_corrections(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
 
 void alloc_ws(rsr_ctx *c, std::vector<SysHost> &sys)
 {
-    // per system: r p0 p1 w xinit rt + W, Z (QMAX each)
+    // per system: r r1 w1 p0 p1 w xinit rt pa + W, Z (QMAX each)
     size_t tot = 0;
-    for (auto &Y : sys) tot += (size_t)Y.n * (7 + 2 * QMAX) + 2 * QMAX + 64;
+    for (auto &Y : sys) tot += (size_t)Y.n * (9 + 2 * QMAX) + 2 * QMAX + 64;
     c->d_ws.ensure(sizeof(double) * tot);
     double *p = c->d_ws.as<double>();
     for (auto &Y : sys) {
         const long n = Y.n;
         Y.r = p; p += n;
+        Y.r1 = p; p += n;
+        Y.w1 = p; p += n;
         Y.p0 = p; p += n;
         Y.p1 = p; p += n;
         Y.w = p; p += n;
@@ -966,6 +984,7 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
             if (r.ny <= 0 || r.nx <= 0 || r.sy <= 0 || r.sx <= 0 || !(r.sy & 1) || !(r.sx & 1) || !r.psf_host)
                 fail(RSR_E_ARG, "instance " + std::to_string(i) + ": sizes must be positive and the PSF odd");
             if (r.sy > 63 || r.sx > 63) fail(RSR_E_ARG, "PSF larger than 63 x 63");
+            if ((long)r.ny * r.nx >= (1L << 31)) fail(RSR_E_ARG, "image of 2^31 pixels or more");
             for (int k = 0; k < r.sy * r.sx; ++k)
                 if (!std::isfinite(r.psf_host[k])) fail(RSR_E_NONFINITE, "non-finite PSF entry");
         }
@@ -1334,7 +1353,7 @@ rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
         if (ty < 4 || tx < 4 || ty > 64 || tx > 64 || (ty & (ty - 1)) || (tx & (tx - 1)))
             fail(RSR_E_ARG, "tile sides must be powers of two in [4, 64]");
         const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I));
-        if (cg_lds_bytes(tl, 8) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
+        if (cg_lds_bytes(cg_tile_lds(tl, 8), 8) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
         set_device(c);
         I.ty = ty;
         I.tx = tx;
@@ -1395,7 +1414,8 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         Opts o{0.0, 40, RSR_INIT_ZERO, 0, 0, 0, 0, 0.0, 0.0};
         for (auto &cd : cand) {
             const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I));
-            if (cg_lds_bytes(tl, (n_vec + 7) & ~7) > 160 * 1024) continue;
+            const int ms8 = (n_vec + 7) & ~7;
+            if (cg_lds_bytes(cg_tile_lds(tl, ms8), ms8) > 160 * 1024) continue;
             I.ty = cd[0];
             I.tx = cd[1];
             upload_inst(c);

@@ -16,7 +16,7 @@ __device__ __forceinline__ const gdbl *gp(const double *p) { return (const gdbl 
 
 constexpr int NT = 256;        // threads per workgroup (4 wave64)
 constexpr int QMAX = 8;        // widest local (deflation) space per system
-constexpr int NVB = 1 + QMAX;  // values per partial in the update phase: r.r, Z^T r
+constexpr int NVP = 4 + 2 * QMAX;   // values per chunk partial: p.w, r.r, r.w, w.w, Z^T r[QMAX], Z^T w[QMAX]
 constexpr int MAXSYS = 512;    // systems per persistent launch
 constexpr int RB = 8;          // register-blocked outputs per thread in the stencil passes
 constexpr int MAXS = 31;       // largest separable PSF extent with a compiled path
@@ -46,8 +46,11 @@ struct SysDev {
     int tile_base;     // offset of this system's partial slots
     double gamma;
     double tolabs;     // tol * ||b||
-    double *x, *r, *p0, *p1, *w;
-    double *pa;        // actual search direction p = ph - W c (ph ping-pongs in p0/p1)
+    double *x;
+    double *rb[2];     // residual r_j in rb[j & 1] (rb[0] holds the starting residual)
+    double *wb[2];     // w_j = B p_j in wb[j & 1]
+    double *pb[2];     // undeflated direction ph_j in pb[j & 1]
+    double *pa;        // search direction p_j = ph_j - W c_j
     double *cbuf;      // [2][QMAX] deflation coefficients c_j, double-buffered by iteration parity
     const double *W;   // [q][ldw] local basis (deflation), column-major
     const double *Z;   // [q][ldw] B W
@@ -59,14 +62,14 @@ struct CGArgs {
     int nsys;
     const SysDev *sys;
     const InstDev *inst;
-    double *partA;                 // [total tiles] p.w partials
-    double *partB;                 // [total tiles][NVB] r.r and Z^T r partials
+    double *part[2];               // [total tiles][NVP] chunk partials, double-buffered by iteration parity
     unsigned long long *bar;       // barrier control block (BAR_BYTES, zero at launch): global counter,
                                    // per-group arrival counters and release epochs, 256-byte lines
     int *abort_flag;               // set on barrier timeout
     int *out_iters;                // [nsys]
     int *out_status;               // [nsys] 1 converged, 2 maxit, -3 nonfinite, -4 not SPD
     double *out_rho;               // [nsys] final recursive r.r
+    double *out_alpha;             // [nsys] step still to apply after the launch: x += alpha p (p in pa)
     int maxit;
     int G;                         // workgroups in the grid
     long long timeout_ticks;       // barrier wait limit in s_memrealtime ticks (100 MHz)
@@ -78,11 +81,13 @@ constexpr int DBG_ITERS = 64;
 
 // Launch plumbing implemented in kernels.hip.
 int tile_lds_doubles(int ty, int tx, int sy, int sx);
+int cg_tile_lds(int tile_lds, int msys);      // tile LDS rounded up to the reduction scratch
 size_t cg_lds_bytes(int tile_lds, int msys);
 constexpr int BAR_GROUPS = 8;                          // barrier groups (one per XCD when G % 8 == 0)
 constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
-hipError_t launch_cg(const CGArgs &a, int G, size_t lds, hipStream_t s, bool cooperative);
-int cg_max_blocks_per_cu(size_t lds);
+int cg_width(int qmax);                           // compiled local-space width for a widest q
+hipError_t launch_cg(const CGArgs &a, int qt, int G, size_t lds, hipStream_t s);
+int cg_max_blocks_per_cu(size_t lds, int qt);
 
 struct ApplyJob {              // y = cA K^T K v + cE E v   (or K / K^T alone)
     int inst;

@@ -47,7 +47,8 @@ struct Geo {
     int P2;            // pitch of width-tx intermediates (banded x output)
     int H3;            // rows after the conv pass (direct path)
     int PE;            // pitch of the output accumulator / interior copies
-    int off1, offE, offP, offT, offF, total;   // offT: a slot per thread for discarded stores; offF: taps
+    int off1, offE, offP, offR, offT, offF, total;   // offP/offR: interior copies; offT: a slot per thread
+                                                     // for discarded stores; offF: bands
 };
 
 __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx)
@@ -78,7 +79,8 @@ __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx)
     g.off1 = (sz0 + 1) & ~1;
     g.offE = (g.off1 + sz1 + 1) & ~1;
     g.offP = (g.offE + ty * g.PE + 1) & ~1;
-    g.offT = g.offP + ty * g.PE;
+    g.offR = g.offP + ty * g.PE;
+    g.offT = g.offR + ty * g.PE;
     g.offF = g.offT + NT;
     g.total = g.offF + 2 * TAPS;
     return g;
@@ -165,7 +167,7 @@ __device__ __forceinline__ EndSpan end_span(int a0, int len, int n, int r)
 // v being the staged window row (zeros outside the image).  Items run over the
 // window rows times the tile's end columns only.
 template <int r>
-__device__ inline void band_fix_x(const InstDev &I, const Geo &g, const double *buf0, double *buf1, int x0)
+__device__ __forceinline__ void band_fix_x(const InstDev &I, const Geo &g, const double *buf0, double *buf1, int x0)
 {
     constexpr int nb = 4 * r + 1, rr = r * r;
     const int nx = I.nx;
@@ -192,7 +194,7 @@ __device__ inline void band_fix_x(const InstDev &I, const Geo &g, const double *
 // End corrections of the y band, subtracted from the tile accumulator; the
 // inputs are the x-pass output rows (buf1 row k = image row y0 - hy + k).
 template <int r>
-__device__ inline void band_fix_y(const InstDev &I, const Geo &g, const double *buf1, double *ebuf, int y0)
+__device__ __forceinline__ void band_fix_y(const InstDev &I, const Geo &g, const double *buf1, double *ebuf, int y0)
 {
     constexpr int nb = 4 * r + 1, rr = r * r;
     const int tx = I.tx, ny = I.ny;
@@ -219,7 +221,7 @@ __device__ inline void band_fix_y(const InstDev &I, const Geo &g, const double *
 // ebuf += cA K^T K v for a rank-1 square PSF of S = 2r + 1 taps (v staged in
 // buf0, bands staged by stage_taps).
 template <int S>
-__device__ void tile_A_sep(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
+__device__ __forceinline__ void tile_A_sep(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
 {
     constexpr int r = S / 2, NB = 4 * r + 1;
     constexpr int R = NB <= 29 ? RB : 4;
@@ -249,7 +251,7 @@ __device__ void tile_A_sep(const InstDev &I, const Geo &g, double *lds, int y0, 
 
 // Direct 2-D pass: out[i][j] (=|+=) mask * sum_{a,c} g[a][c] in[i+a][j+c] with
 // g = psf (corr) or the psf rotated by 180 degrees (conv).
-__device__ inline void pass2d(const double *__restrict__ in, int pin, double *__restrict__ out, int pout,
+__device__ __forceinline__ void pass2d(const double *__restrict__ in, int pin, double *__restrict__ out, int pout,
                               int rows, int cols, const double *__restrict__ h, int sy, int sx, bool flip,
                               bool acc, int rlo, int rhi, int clo, int chi, double *__restrict__ trash)
 {
@@ -286,7 +288,7 @@ __device__ inline void pass2d(const double *__restrict__ in, int pin, double *__
     }
 }
 
-__device__ inline void tile_A_direct(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
+__device__ __forceinline__ void tile_A_direct(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
 {
     double *buf0 = lds, *buf1 = lds + g.off1, *ebuf = lds + g.offE, *trash = lds + g.offT;
     pass2d(buf0 + g.oy * g.P0 + g.ox, g.P0, buf1, g.P1, g.H3, g.W1, I.psf, I.sy, I.sx, true, false, g.ry - y0,
@@ -301,7 +303,7 @@ __device__ inline void tile_A_direct(const InstDev &I, const Geo &g, double *lds
 }
 
 // ebuf += cA K^T K (staged input in buf0, which is overwritten).
-__device__ inline void tile_A(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
+__device__ __forceinline__ void tile_A(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
 {
     if (!I.sep) {
         tile_A_direct(I, g, lds, y0, x0, cA);
@@ -377,7 +379,7 @@ __device__ __forceinline__ void tile_E_apply(const InstDev &I, const Geo &g, dou
 
 // ebuf = cE * E v on the whole tile (v staged in buf0); w holds the weights
 // of the first NT * NE pixels (loaded beforehand by tile_E_load).
-__device__ inline void tile_E(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cE, const EWts &w)
+__device__ __forceinline__ void tile_E(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cE, const EWts &w)
 {
     const int ne = I.ty * I.tx;
     tile_E_apply(I, g, lds, y0, x0, 0, cE, w);
