@@ -195,13 +195,12 @@ __device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m,
 }
 
 // Deterministic block-wide sum of cnt (<= NV) consecutive partial values of
-// one system: part[(base + k) * NVP + v0 + j] over k < nch.  Result in
-// out[0..cnt).
+// one system: part[(base + k) * NVP + v0 + j] over k < nch, in two steps.
+// partial_load: each thread accumulates the slots k = threadIdx.x + i * NT in
+// registers; block_sum: wave sums, then the waves in order, into out[0..cnt).
 template <int NV>
-__device__ void block_reduce_partials(const double *part, int base, int nch, int v0, int cnt, double *out,
-                                      double *red)
+__device__ __forceinline__ void partial_load(const double *part, int base, int nch, int v0, int cnt, double (&acc)[NV])
 {
-    double acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     for (int k = threadIdx.x; k < nch; k += NT) {
@@ -214,6 +213,11 @@ __device__ void block_reduce_partials(const double *part, int base, int nch, int
 #pragma unroll
         for (int j = 0; j < NV; ++j) acc[j] += j < cnt ? v[j] : 0.0;
     }
+}
+
+template <int NV>
+__device__ void block_sum(const double (&acc)[NV], int cnt, double *out, double *red)
+{
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j)
@@ -228,6 +232,15 @@ __device__ void block_reduce_partials(const double *part, int base, int nch, int
         out[threadIdx.x] = s;
     }
     __syncthreads();
+}
+
+template <int NV>
+__device__ void block_reduce_partials(const double *part, int base, int nch, int v0, int cnt, double *out,
+                                      double *red)
+{
+    double acc[NV];
+    partial_load<NV>(part, base, nch, v0, cnt, acc);
+    block_sum<NV>(acc, cnt, out, red);
 }
 
 // Adds the block-wide sums of cnt per-thread values (fixed order) to acc[0..cnt).

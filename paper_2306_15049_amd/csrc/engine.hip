@@ -122,6 +122,15 @@ struct rsr_ctx {
     DBuf d_ws;                         // per-system vectors of a solve
     DBuf d_dbg;                        // optional phase timestamps
     DBuf d_tmp;                        // misc n-vectors
+    // staging arena for launch descriptors and coefficients: pinned host and
+    // device halves bump-allocated in step, reset whenever the stream is drained,
+    // so that launches whose inputs come from the host need no synchronisation
+    DBuf ar_dev;
+    char *ar_host = nullptr;
+    size_t ar_cap = 0, ar_used = 0;
+    // optional host-side stage timing of the solves (diagnostics, RSR_HOST_PROF)
+    bool hprof = false;
+    double hprof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     // counters and timing
     long mv_A = 0, mv_E = 0;
     int cg_gmax = 1024;                // cap on persistent-kernel workgroups (autotuned)
@@ -180,6 +189,64 @@ template <class T> T *upload(rsr_ctx *c, DBuf &buf, const std::vector<T> &v, hip
     return buf.as<T>();
 }
 
+// Drains the stream; the staging arena can then be reused from the start.
+void sync(rsr_ctx *c, hipStream_t s)
+{
+    HIPCHK(hipStreamSynchronize(s));
+    c->ar_used = 0;
+}
+
+// Wall time of a solve stage, accumulated when stage timing is on (the stream
+// is drained at both ends so that the device work of the stage is included).
+struct StageTimer {
+    rsr_ctx *c;
+    hipStream_t s;
+    int k;
+    std::chrono::steady_clock::time_point t0;
+    StageTimer(rsr_ctx *c_, hipStream_t s_, int k_) : c(c_), s(s_), k(k_)
+    {
+        if (c->hprof) {
+            sync(c, s);
+            t0 = std::chrono::steady_clock::now();
+        }
+    }
+    ~StageTimer()
+    {
+        if (c->hprof) {
+            (void)hipStreamSynchronize(s);
+            c->hprof_ms[k] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+    }
+};
+
+// Copies v into the staging arena (pinned host -> device, asynchronous) and
+// returns its device address, valid until the next sync().
+template <class T> T *stage(rsr_ctx *c, const std::vector<T> &v, hipStream_t s)
+{
+    const size_t nb = sizeof(T) * v.size();
+    const size_t bytes = (std::max<size_t>(nb, 1) + 255) & ~(size_t)255;
+    if (c->ar_used + bytes > c->ar_cap) {
+        sync(c, s);
+        if (bytes > c->ar_cap) {
+            const size_t cap = std::max<size_t>(bytes, (size_t)1 << 20);
+            if (c->ar_host) (void)hipHostFree(c->ar_host);
+            c->ar_host = nullptr;
+            c->ar_cap = 0;
+            HIPCHK(hipHostMalloc((void **)&c->ar_host, cap, hipHostMallocDefault));
+            c->ar_dev.ensure(cap);
+            c->ar_cap = cap;
+        }
+    }
+    char *h = c->ar_host + c->ar_used;
+    char *d = c->ar_dev.as<char>() + c->ar_used;
+    if (nb) {
+        memcpy(h, v.data(), nb);
+        HIPCHK(hipMemcpyAsync(d, h, nb, hipMemcpyHostToDevice, s));
+    }
+    c->ar_used += bytes;
+    return (T *)d;
+}
+
 int max_tile_lds(rsr_ctx *c)
 {
     int m = 2048;
@@ -196,13 +263,11 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
     Instance &I = get_inst(c, ii);
     std::vector<ApplyJob> jobs(nvec);
     for (int j = 0; j < nvec; ++j) jobs[j] = ApplyJob{ii, 0, cA, cE, v + j * ldv, y + j * ldy};
-    DBuf &jb = jobbuf ? *jobbuf : c->d_jobs;
-    ApplyJob *dj = upload(c, jb, jobs, s);
+    ApplyJob *dj = jobbuf ? upload(c, *jobbuf, jobs, s) : stage(c, jobs, s);
     const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
     HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, nvec, lds, s));
     if (cA != 0.0) c->mv_A += nvec;
     if (cE != 0.0) c->mv_E += nvec;
-    if (jobbuf == nullptr) HIPCHK(hipStreamSynchronize(s));   // job buffer reuse
 }
 
 void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
@@ -212,14 +277,13 @@ void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
     for (auto &j : jobs) by[j.inst].push_back(j);
     for (auto &kv : by) {
         Instance &I = get_inst(c, kv.first);
-        ApplyJob *dj = upload(c, c->d_jobs, kv.second, s);
+        ApplyJob *dj = stage(c, kv.second, s);
         const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
         HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[kv.first], dj, (int)kv.second.size(), lds, s));
         for (auto &j : kv.second) {
             if (j.cA != 0.0) c->mv_A++;
             if (j.cE != 0.0) c->mv_E++;
         }
-        HIPCHK(hipStreamSynchronize(s));
     }
 }
 
@@ -239,11 +303,11 @@ std::vector<std::vector<double>> gram(rsr_ctx *c, std::vector<GramJob> jobs, hip
         sc += gram_scratch_doubles(&j, 1);
     }
     c->d_gram_scratch.ensure(sizeof(double) * std::max<size_t>(1, sc));
-    GramJob *dj = upload(c, c->d_jobs, jobs, s);
+    GramJob *dj = stage(c, jobs, s);
     HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), c->d_gram_scratch.as<double>(), sc, s));
     std::vector<double> h(coff);
     HIPCHK(hipMemcpyAsync(h.data(), c->d_small.p, sizeof(double) * coff, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    sync(c, s);
     o = 0;
     for (size_t k = 0; k < jobs.size(); ++k) {
         out[k].assign(h.begin() + o, h.begin() + o + (size_t)jobs[k].a * jobs[k].c);
@@ -265,11 +329,10 @@ void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector
         off.push_back(all.size());
         all.insert(all.end(), q.begin(), q.end());
     }
-    double *dq = upload(c, c->d_small, all, s);
+    double *dq = stage(c, all, s);
     for (size_t k = 0; k < jobs.size(); ++k) jobs[k].Q = dq + off[k];
-    ComboJob *dj = upload(c, c->d_jobs, jobs, s);
+    ComboJob *dj = stage(c, jobs, s);
     HIPCHK(launch_combo(dj, jobs.data(), (int)jobs.size(), s));
-    HIPCHK(hipStreamSynchronize(s));
 }
 
 std::vector<double> norms(rsr_ctx *c, const std::vector<const double *> &v, const std::vector<long> &n,
@@ -498,7 +561,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     HIPCHK(hipMemcpyAsync(hi.data(), out_iters, sizeof(int) * 2 * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hr.data(), out_rho, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&abort_h, a.abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    sync(c, s);
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     if (dbg) {
@@ -706,6 +769,7 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
                  hipStream_t s)
 {
     // b norms
+    std::unique_ptr<StageTimer> tm(new StageTimer(c, s, 0));
     {
         std::vector<const double *> v;
         std::vector<long> n;
@@ -714,6 +778,7 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         for (size_t i = 0; i < sy.size(); ++i) sy[i]->bnorm = bn[i];
     }
     // initial guess
+    tm.reset(new StageTimer(c, s, 1));
     std::vector<ComboJob> cj;
     std::vector<std::vector<double>> qs;
     std::vector<ApplyJob> aj;
@@ -791,6 +856,7 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         combo(c, cj, qs, s);
     }
     // keep x_init for the correction g = x - x_init
+    tm.reset(new StageTimer(c, s, 2));
     for (auto *Y : sy) HIPCHK(hipMemcpyAsync(Y->xinit, Y->x, sizeof(double) * Y->n, hipMemcpyDeviceToDevice, s));
     {
         std::vector<const double *> v;
@@ -801,8 +867,11 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
             sy[i]->relres_init = sy[i]->bnorm > 0 ? rn[i] / sy[i]->bnorm : 0.0;
     }
     // local spaces and Galerkin correction
+    tm.reset(new StageTimer(c, s, 3));
     build_local(c, sy, o, g_prev_shift, s);
+    tm.reset(new StageTimer(c, s, 4));
     local_correction(c, sy, s);
+    tm.reset();
 
     // CG with true-residual acceptance
     std::vector<SysHost *> todo;
@@ -818,7 +887,9 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     }
     for (int attempt = 0; attempt <= 3 && !todo.empty(); ++attempt) {
         Opts oo = o;
+        tm.reset(new StageTimer(c, s, 5));
         run_cg(c, todo, oo, s);
+        tm.reset(new StageTimer(c, s, 6));
         // true residual rt = b - B x
         std::vector<ApplyJob> tj;
         for (auto *Y : todo) {
@@ -934,6 +1005,7 @@ rsr_status rsr_create(rsr_ctx **out, int dev)
     if (dev < 0 || dev >= ndev) return RSR_E_ARG;
     rsr_ctx *c = new rsr_ctx();
     c->dev = dev;
+    c->hprof = getenv("RSR_HOST_PROF") != nullptr;
     rsr_status st = guard(c, [&] {
         set_device(c);
         hipDeviceProp_t prop;
@@ -956,6 +1028,10 @@ rsr_status rsr_create(rsr_ctx **out, int dev)
 void rsr_destroy(rsr_ctx *c)
 {
     if (!c) return;
+    if (c->hprof)
+        fprintf(stderr, "[rsr host stages] ms: bnorm %.1f init %.1f r0 %.1f local %.1f correct %.1f cg %.1f "
+                        "true-res %.1f store %.1f\n", c->hprof_ms[0], c->hprof_ms[1], c->hprof_ms[2], c->hprof_ms[3],
+                c->hprof_ms[4], c->hprof_ms[5], c->hprof_ms[6], c->hprof_ms[7]);
     (void)hipSetDevice(c->dev);
     (void)hipDeviceSynchronize();
     for (auto &p : c->inst) {
@@ -966,8 +1042,9 @@ void rsr_destroy(rsr_ctx *c)
         for (auto &g : I.gstore) if (g.second) g.second->release();
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
-                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg})
+                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev})
         b->release();
+    if (c->ar_host) (void)hipHostFree(c->ar_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -990,7 +1067,7 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
         }
         set_device(c);
         hipStream_t s = S(stream);
-        HIPCHK(hipStreamSynchronize(s));
+        sync(c, s);
         for (auto &p : c->inst) {
             p->d_fy.release(); p->d_fx.release(); p->d_psf.release(); p->d_wh.release(); p->d_wv.release();
             p->d_band.release();
@@ -1023,7 +1100,7 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
             c->inst.push_back(std::move(I));
         }
         upload_inst(c);
-        HIPCHK(hipStreamSynchronize(s));
+        sync(c, s);
     });
 }
 
@@ -1076,7 +1153,7 @@ rsr_status rsr_apply(rsr_ctx *c, int ii, int op, double gamma, const double *v, 
             for (int j = 0; j < n_vec; ++j) jobs[j] = ApplyJob{ii, op, 0.0, 0.0, v + j * ld, y + j * ld};
             ApplyJob *dj = upload(c, c->d_jobs, jobs, s);
             HIPCHK(launch_blur(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, n_vec, s));
-            HIPCHK(hipStreamSynchronize(s));
+            sync(c, s);
             return;
         }
         double cA = 0.0, cE = 0.0;
@@ -1237,6 +1314,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 std::vector<SysHost *> grp;
                 for (int i = i0; i < std::min(m, i0 + MAXSYS); ++i) grp.push_back(&sys[i]);
                 solve_group(c, grp, o, nullptr, s);
+                StageTimer tsc(c, s, 7);
                 store_corrections(c, grp, s);
             }
         } else {
@@ -1246,7 +1324,10 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 std::vector<SysHost *> one{&sys[i]};
                 if (i > 0 && sys[i].inst != sys[i - 1].inst) gp = nullptr;
                 solve_group(c, one, o, o.use_prev_shift ? gp : nullptr, s);
-                store_corrections(c, one, s);
+                {
+                    StageTimer tsc(c, s, 7);
+                    store_corrections(c, one, s);
+                }
                 if (o.use_prev_shift) {
                     Instance &I = *c->inst[sys[i].inst];
                     gprev.ensure(sizeof(double) * I.n);
@@ -1255,7 +1336,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                     gp = gprev.as<double>();
                 }
             }
-            HIPCHK(hipStreamSynchronize(s));
+            sync(c, s);
             gprev.release();
         }
         bool all = true;
@@ -1275,7 +1356,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 t.relres_true = Y.relres_true;
             }
         }
-        HIPCHK(hipStreamSynchronize(s));
+        sync(c, s);
         if (!all) throw Err{RSR_NOT_CONVERGED, "some systems did not reach tol"};
     });
 }
@@ -1323,7 +1404,7 @@ rsr_status rsr_adjoint(rsr_ctx *c, const rsr_solve_desc *d, const double *X, con
                            I.nx, wh, wv, db, dg.as<double>(), nch, s));
         std::vector<double> h((size_t)nch * m);
         HIPCHK(hipMemcpyAsync(h.data(), dg.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        sync(c, s);
         if (dgamma_host)
             for (int l = 0; l < m; ++l) {
                 double sm = 0.0;
