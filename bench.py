@@ -41,16 +41,36 @@ def host_cores() -> int:
 def cg_alg_bytes_per_px_iter(q: int, m_share: int) -> float:
     """Algorithmic HBM bytes per pixel per CG iteration of one system.
 
-    phase 1 reads r, p_old and q local basis columns, writes p_new and w;
-    phase 2 reads p_new, w, x, r and q columns of Z, writes x and r; the two
-    weight planes (16 B/px) are shared by the m_share systems of a launch.
+    One iteration reads r_{j-1}, w_{j-1}, ph_{j-1}, x, p_{j-1} and the q
+    columns of W and of Z, and writes r_j, ph_j, x, p_j and w_j (each pixel
+    once; the halo re-reads are not algorithmic); the two weight planes
+    (16 B/px) are shared by the m_share systems of a launch.
     """
     return 80.0 + 16.0 * q + 16.0 / max(1, m_share)
 
 
 def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
-    """K^T K as four 1-D passes of s taps (2 flops each), E (13), vector updates."""
-    return 8.0 * s + 13.0 + 12.0 + 4.0 * q
+    """K^T K as two banded passes of 2s - 1 taps (2 flops each), E (13), the
+    vector updates and the p.w, r.r, r.w, w.w, Z^T r, Z^T w partial sums."""
+    return 8.0 * s - 4.0 + 13.0 + 14.0 + 8.0 * q
+
+
+# HBM bytes per k_cg launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on
+# the timed recycled steps of this workload (FETCH_SIZE scaled by 2.0, WRITE_SIZE by
+# 1.0: the factors a 256 MiB device copy gives), keyed by the hash of the kernel
+# sources they were taken on; any other kernel build reports null.
+MEASURED_TRAFFIC = {("C2", "34ecac63ee608b96"): 724.77e6}
+KERNEL_SOURCES = ["paper_2306_15049_amd/csrc/cg.hip", "paper_2306_15049_amd/csrc/stencil.hpp",
+                  "paper_2306_15049_amd/csrc/internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(cfg, plain_matvecs_per_step: float, cap_iters: int):
@@ -88,6 +108,8 @@ def main():
     ap.add_argument("--mode", choices=["sequential", "batched"], default=None,
                     help="solve mode of the recycled method (default: the workload's own)")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device three times (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design note, "
@@ -101,6 +123,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8, "copies": 3}))
+        return
     cfg = synth.config(args.config)
     ctx = rsr.Context(0)
     M = len(cfg.gammas)
@@ -169,8 +200,10 @@ def main():
         tot_ms += r.cg_kernel_ms
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_cg (persistent deflated CG, phase 1 stencil + phase 2 update)",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": MEASURED_TRAFFIC.get((cfg.name, kernel_source_hash())) if head_mode == (
+                rsr.SEQUENTIAL if seq_default else rsr.BATCHED) else None,
+            "kernel": "k_cg (persistent deflated CG, one stencil + update phase per iteration)",
             "alg_bytes_per_px_iter": cg_alg_bytes_per_px_iter(q_eff, 1),
             "fp64_tflops": tot_flops / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0,
             "cg_kernel_ms_per_step": tot_ms / args.steps,
