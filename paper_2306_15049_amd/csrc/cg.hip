@@ -466,6 +466,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             N = O;   // unchanged: keep the assignment (and its buffers)
         }
         const bool flip = mn != mo;
+        if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) A.stamps[it * 8 + 4] = mn;
         const int ipbn = flip ? s_ipb[cur ^ 1] : ipbo;
         stamp(it, 1);
 

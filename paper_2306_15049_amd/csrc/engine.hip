@@ -30,6 +30,7 @@
 #include <fstream>
 #include <functional>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <sstream>
 #include <string>
@@ -128,6 +129,11 @@ struct rsr_ctx {
     DBuf ar_dev;
     char *ar_host = nullptr;
     size_t ar_cap = 0, ar_used = 0;
+    // per-call caches of right-hand-side quantities shared by the shifts of one
+    // rsr_solve_shift_set (the same b for every shift): ||b|| and U^T b or
+    // [AU EU]^T b, keyed by (b, instance, init); cleared at the start of each call
+    std::map<std::pair<const double *, int>, double> bnorm_cache;
+    std::map<std::tuple<const double *, int, int>, std::vector<double>> rhs_cache;
     // optional host-side stage timing of the solves (diagnostics, RSR_HOST_PROF)
     bool hprof = false;
     double hprof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -577,6 +583,19 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
             }
         }
         const double tk = c->wall_khz / 1000.0;
+        // iteration time by number of active systems (workgroup 0's loop-top stamps)
+        std::map<int, std::pair<double, int>> byact;
+        for (int i = 0; i + 1 < DBG_ITERS && st[(i + 1) * 8]; ++i) {
+            auto &e = byact[(int)st[i * 8 + 4]];
+            e.first += (double)(st[(i + 1) * 8] - st[i * 8]);
+            e.second += 1;
+        }
+        if (!byact.empty()) {
+            fprintf(stderr, "[rsr cg stamps] us/iteration by active systems:");
+            for (auto &kv : byact) fprintf(stderr, " %d:%.1f(x%d)", kv.first, kv.second.first / kv.second.second / tk,
+                                           kv.second.second);
+            fprintf(stderr, "\n");
+        }
         if (n > 0)
             fprintf(stderr, "[rsr cg stamps] G=%d iters=%d us: reduce+assign %.2f phase %.2f (first item: setup+load %.2f "
                             "stencil %.2f) barrier %.2f\n",
@@ -768,14 +787,29 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
 void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const double *g_prev_shift,
                  hipStream_t s)
 {
-    // b norms
+    // b norms (once per distinct right-hand side of the call)
     std::unique_ptr<StageTimer> tm(new StageTimer(c, s, 0));
     {
         std::vector<const double *> v;
         std::vector<long> n;
-        for (auto *Y : sy) { v.push_back(Y->b); n.push_back(Y->n); }
-        auto bn = norms(c, v, n, s);
-        for (size_t i = 0; i < sy.size(); ++i) sy[i]->bnorm = bn[i];
+        std::vector<SysHost *> need;
+        for (auto *Y : sy) {
+            auto it = c->bnorm_cache.find({Y->b, Y->inst});
+            if (it != c->bnorm_cache.end()) {
+                Y->bnorm = it->second;
+            } else {
+                v.push_back(Y->b);
+                n.push_back(Y->n);
+                need.push_back(Y);
+            }
+        }
+        if (!need.empty()) {
+            auto bn = norms(c, v, n, s);
+            for (size_t i = 0; i < need.size(); ++i) {
+                need[i]->bnorm = bn[i];
+                c->bnorm_cache[{need[i]->b, need[i]->inst}] = bn[i];
+            }
+        }
     }
     // initial guess
     tm.reset(new StageTimer(c, s, 1));
@@ -809,19 +843,28 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     qs.clear();
     // principal-space guesses (one small solve per shift, Section 4.1)
     std::vector<GramJob> gj;
-    std::vector<SysHost *> prin;
+    std::vector<SysHost *> prin, fresh;
     for (auto *Yp : sy) {
         SysHost &Y = *Yp;
         Instance &I = *c->inst[Y.inst];
         if (!((o.init == RSR_INIT_MR || o.init == RSR_INIT_GALERKIN) && I.p > 0 && I.ae_valid)) continue;
         prin.push_back(&Y);
+        if (c->rhs_cache.count({Y.b, Y.inst, o.init})) continue;
+        fresh.push_back(&Y);
         if (o.init == RSR_INIT_MR)
             gj.push_back(GramJob{I.d_AE.as<double>(), I.n, 2 * I.p, Y.b, Y.n, 1, Y.n, nullptr, 0});
         else
             gj.push_back(GramJob{I.d_U.as<double>(), I.n, I.p, Y.b, Y.n, 1, Y.n, nullptr, 0});
     }
     if (!prin.empty()) {
-        auto rhs = gram(c, gj, s);
+        // [AU EU]^T b (or U^T b) once per right-hand side of the call
+        if (!fresh.empty()) {
+            auto got = gram(c, gj, s);
+            for (size_t k = 0; k < fresh.size(); ++k)
+                c->rhs_cache[{fresh[k]->b, fresh[k]->inst, o.init}] = got[k];
+        }
+        std::vector<std::vector<double>> rhs;
+        for (auto *Y : prin) rhs.push_back(c->rhs_cache[{Y->b, Y->inst, o.init}]);
         for (size_t k = 0; k < prin.size(); ++k) {
             SysHost &Y = *prin[k];
             Instance &I = *c->inst[Y.inst];
@@ -1301,6 +1344,8 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
         set_device(c);
         hipStream_t s = S(stream);
         alloc_ws(c, sys);
+        c->bnorm_cache.clear();
+        c->rhs_cache.clear();
         Opts o{d->tol, d->maxit, d->init, d->n_ritz, d->use_prev_k, d->use_prev_shift, d->split_I, d->gamma_JL,
                d->gamma_JR};
         c->last_cg_ms = 0.0;

@@ -77,7 +77,7 @@ struct CGArgs {
     int msys;                      // capacity of the per-system LDS arrays (>= nsys)
     unsigned long long *stamps;    // optional [DBG_ITERS][8] phase timestamps of workgroup 0 (or null)
 };
-constexpr int DBG_ITERS = 64;
+constexpr int DBG_ITERS = 1024;
 
 // Launch plumbing implemented in kernels.hip.
 int tile_lds_doubles(int ty, int tx, int sy, int sx);
