@@ -295,10 +295,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __shared__ double s_acc[NVP];                 // partial sums of the current system over the chunk
     __shared__ double s_z[QMAX];
     __shared__ double s_c[QMAX];                  // c_j of the current system
+    // LDS copies of the current system's descriptor and of its instance: a
+    // workgroup keeps the same system from one iteration to the next while the
+    // assignment is unchanged, so these are refetched only when it changes
+    __shared__ SysDev s_sd;
+    __shared__ InstDev s_id;
+    __shared__ int s_sd_sys;
 
     const int G = A.G;
     const int chunk = chunk_of_block(blockIdx.x, G);
     int cur = 0;
+    if (threadIdx.x == 0) s_sd_sys = -1;
 
     for (int k = threadIdx.x; k < A.nsys; k += NT) S0.act[k] = k;
     __syncthreads();
@@ -482,7 +489,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             for (int item = lo; item < hi; ++item) {
                 while (item >= N.pre[a + 1]) ++a;
                 const int s = uni(N.act[a]);
-                const SysDev &Y = A.sys[s];
+                if (s != s_sd_sys) {
+                    // descriptor words, then the instance's (two dependent loads, only
+                    // when the workgroup moves to another system)
+                    static_assert(sizeof(SysDev) % 8 == 0 && sizeof(InstDev) % 8 == 0, "descriptor size");
+                    constexpr int NSD = (int)(sizeof(SysDev) / 8), NID = (int)(sizeof(InstDev) / 8);
+                    const unsigned long long *src = (const unsigned long long *)(A.sys + s);
+                    if (threadIdx.x < NSD) ((unsigned long long *)&s_sd)[threadIdx.x] = src[threadIdx.x];
+                    const int ii = A.sys[s].inst;
+                    const unsigned long long *isrc = (const unsigned long long *)(A.inst + ii);
+                    if (threadIdx.x >= 128 && threadIdx.x - 128 < NID)
+                        ((unsigned long long *)&s_id)[threadIdx.x - 128] = isrc[threadIdx.x - 128];
+                    __syncthreads();
+                    if (threadIdx.x == 0) s_sd_sys = s;
+                }
+                const SysDev &Y = s_sd;
                 if (s != cur_sys) {
                     if (cur_sys >= 0 && threadIdx.x < NVP)
                         gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
@@ -514,7 +535,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     }
                     __syncthreads();
                 }
-                const InstDev I = A.inst[Y.inst];
+                const InstDev &I = s_id;
                 const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx);
                 const int t = uni(item - N.pre[a]);
                 const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
