@@ -8,16 +8,22 @@
 // so that p = ph - W c and B p = B ph - Z c: the stencil runs on ph (two
 // loads per halo pixel) and W, Z are read on the tile interior only.
 //
-// One iteration is two grid-wide phases separated by grid barriers:
-//   phase 1: ph = r + beta ph (halo recomputed, ping-pong buffers),
-//            w = B ph - Z c, p = ph - W c, partial p.w;
-//   phase 2: alpha = rho / p.w, x += alpha p, r -= alpha w, partial r.r, Z^T r.
+// One iteration is one grid-wide phase between two grid barriers.  At the
+// top every workgroup reduces the previous phase's partials p.w, r.r, r.w, w.w
+// and takes alpha_{j-1} = rho_{j-1} / p.w and rho_j = ||r_{j-1} - alpha w||^2
+// (expanded from the three reduced products); the phase then recomputes
+// r_j = r_{j-1} - alpha w_{j-1} and ph_j = r_j + beta ph_{j-1} on each tile's
+// window (halo included, ping-pong buffers), applies B to ph_j, forms
+// w_j = B ph_j - Z c_j and p_j = ph_j - W c_j, advances x by the previous step
+// and leaves the partials of the next top.  The last x update is applied after
+// the launch.
 // The active systems' tiles are concatenated and split into G contiguous
 // chunks (one per workgroup, XCD-aware), each chunk's partials land in their
 // own slots, and every workgroup reduces the slots it needs in a fixed order,
 // so all workgroups take identical decisions and results are deterministic.
 // A system leaves the launch once sqrt(r.r) <= tol ||b|| (or on maxit /
-// breakdown) and the remaining tiles are re-split over the whole grid.
+// breakdown); the remaining tiles are re-split, and the grid shrinks to the
+// workgroups that still hold tiles.
 #include "internal.hpp"
 #include "stencil.hpp"
 
@@ -61,8 +67,7 @@ struct BarCtl {
     unsigned long long *arr;    // group arrival counter of this workgroup
     unsigned long long *rel;    // group release epoch of this workgroup
     int *abort_flag;
-    unsigned long long gsize;   // workgroups in this group
-    unsigned long long ngrp;    // groups
+    int ngrp;                   // groups
 };
 
 __device__ __forceinline__ BarCtl bar_ctl(const CGArgs &A)
@@ -75,8 +80,7 @@ __device__ __forceinline__ BarCtl bar_ctl(const CGArgs &A)
     b.arr = (unsigned long long *)(base + 256 * (2 + grp));
     b.rel = (unsigned long long *)(base + 256 * (2 + BAR_GROUPS + grp));
     b.abort_flag = A.abort_flag;
-    b.gsize = (unsigned long long)(A.G / ngrp);
-    b.ngrp = (unsigned long long)ngrp;
+    b.ngrp = ngrp;
     return b;
 }
 
@@ -94,16 +98,24 @@ __device__ __forceinline__ bool spin_until(unsigned long long *word, unsigned lo
     return true;
 }
 
-__device__ __forceinline__ bool grid_barrier(const BarCtl &b, unsigned long long k, long long timeout, int *s_flag)
+// The grid can shrink during the launch (workgroups past the new size leave
+// at a loop top), so the arrivals a group counter has seen are tracked in LDS:
+// *s_arr is the count before this barrier, and the group's size is the
+// current grid size *s_g over the group count.  Only thread 0 touches *s_arr.
+__device__ __forceinline__ bool grid_barrier(const BarCtl &b, unsigned long long k, long long timeout, int *s_flag,
+                                             unsigned long long *s_arr, const int *s_g)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long t0 = realtime();
         bool ok;
+        const unsigned long long gsize = (unsigned long long)(*s_g / b.ngrp);
         const unsigned long long old = __hip_atomic_fetch_add(b.arr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == k * b.gsize - 1) {
+        const unsigned long long before = *s_arr;
+        *s_arr = before + gsize;
+        if (old == before + gsize - 1) {
             __hip_atomic_fetch_add(b.glob, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            ok = spin_until(b.glob, k * b.ngrp, b.abort_flag, t0, timeout);
+            ok = spin_until(b.glob, k * (unsigned long long)b.ngrp, b.abort_flag, t0, timeout);
             if (ok) __hip_atomic_store(b.rel, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             ok = spin_until(b.rel, k, b.abort_flag, t0, timeout);
@@ -175,7 +187,14 @@ __device__ __forceinline__ int find_pos(const int *v, int n, int key)   // last 
     return l;
 }
 
-__device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m, int *s_ipb, int *tmp)
+// With shrink set (and G a multiple of 8) the grid may also shrink once every
+// workgroup holds at most one tile (T <= G): it drops to T rounded up to a
+// multiple of 8.  The workgroups past it would only wait at the barriers and
+// reduce partials.  While T > G the grid is kept whole, since the active set
+// only shrinks and the workgroups that leave cannot come back.  The new grid
+// size is left in *s_g.
+__device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m, int *s_ipb, int *tmp, bool shrink,
+                             int *s_g)
 {
     for (int k = threadIdx.x; k < m; k += NT) S.pre[k] = A.sys[S.act[k]].ntiles;
     __syncthreads();
@@ -183,7 +202,14 @@ __device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m,
     if (threadIdx.x == 0) {
         S.pre[m] = T;
         *s_m = m;
-        *s_ipb = T > 0 ? (T + G - 1) / G : 1;
+        const int ipb = T > 0 ? (T + G - 1) / G : 1;
+        *s_ipb = ipb;
+        int gn = G;
+        if (shrink && G % 8 == 0 && T > 0 && T <= G) {
+            gn = (T + 7) & ~7;
+            if (gn < 8) gn = 8;
+        }
+        *s_g = gn;
     }
     __syncthreads();
     const int ipb = *s_ipb;
@@ -290,6 +316,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     S1.foff = ib; ib += ms + 1;
     const BarCtl bc = bar_ctl(A);
     __shared__ int s_m[2], s_ipb[2], s_tmp[NT / 64], s_flag;
+    __shared__ int s_g;                           // current grid size (shrinks as systems leave)
+    __shared__ unsigned long long s_arr;          // arrivals counted on this workgroup's group counter
     __shared__ double s_red[(NT / 64) * NVP];
     __shared__ double s_vals[NVP];
     __shared__ double s_acc[NVP];                 // partial sums of the current system over the chunk
@@ -302,16 +330,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __shared__ InstDev s_id;
     __shared__ int s_sd_sys;
 
-    const int G = A.G;
-    const int chunk = chunk_of_block(blockIdx.x, G);
     int cur = 0;
-    if (threadIdx.x == 0) s_sd_sys = -1;
+    if (threadIdx.x == 0) {
+        s_sd_sys = -1;
+        s_arr = 0;
+    }
 
     for (int k = threadIdx.x; k < A.nsys; k += NT) S0.act[k] = k;
     __syncthreads();
-    build_assign(A, S0, A.nsys, G, &s_m[0], &s_ipb[0], s_tmp);
+    build_assign(A, S0, A.nsys, A.G, &s_m[0], &s_ipb[0], s_tmp, false, &s_g);
 
-    auto slot_of = [&](const Assign &As, int m, int ipb, int s) {
+    auto slot_of = [&](const Assign &As, int m, int ipb, int s, int chunk) {
         return A.sys[s].tile_base + (chunk - As.pre[find_pos(As.act, m, s)] / ipb);
     };
 
@@ -319,6 +348,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     {
         const Assign &As = S0;
         const int m = s_m[0], ipb = s_ipb[0];
+        const int chunk = chunk_of_block(blockIdx.x, A.G);
         const int T = As.pre[m];
         const int lo = chunk * ipb;
         const int hi = lo + ipb < T ? lo + ipb : T;
@@ -329,7 +359,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             while (item >= As.pre[a + 1]) ++a;
             const int s = uni(As.act[a]);
             if (s != cur_sys) {
-                if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+                if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
                 cur_sys = s;
                 q = A.sys[s].q;
                 if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
@@ -359,10 +389,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
             block_accumulate<NVT>(v, NVT, s_acc, s_red);
         }
-        if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+        if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
     }
     int nbar = 0;
-    if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
+    if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
 
     auto stamp = [&](int it, int k) {
         if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) A.stamps[it * 8 + k] = realtime();
@@ -468,18 +498,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         if (mn != mo) {
             // tiles move between workgroups when the active set shrinks: drop cached copies
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            build_assign(A, N, mn, G, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp);
+            const int gold = s_g;
+            build_assign(A, N, mn, gold, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp, true, &s_g);
+            // every workgroup takes the same decision; the ones past the new grid
+            // have published all they wrote at the last barrier
+            if ((int)blockIdx.x >= s_g) return;
         } else {
             N = O;   // unchanged: keep the assignment (and its buffers)
         }
         const bool flip = mn != mo;
-        if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) A.stamps[it * 8 + 4] = mn;
+        if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) {
+            A.stamps[it * 8 + 4] = mn;
+            A.stamps[it * 8 + 5] = s_g;
+        }
         const int ipbn = flip ? s_ipb[cur ^ 1] : ipbo;
         stamp(it, 1);
 
         // ---- the iteration's one phase under N
         {
             const int T = N.pre[mn];
+            const int chunk = chunk_of_block(blockIdx.x, s_g);
             const int lo = chunk * ipbn;
             const int hi = lo + ipbn < T ? lo + ipbn : T;
             int a = lo < hi ? find_pos(N.pre, mn, lo) : 0;
@@ -506,7 +544,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 const SysDev &Y = s_sd;
                 if (s != cur_sys) {
                     if (cur_sys >= 0 && threadIdx.x < NVP)
-                        gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+                        gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
                     cur_sys = s;
                     q = Y.q;
                     alpha = s_alpha[s];
@@ -536,7 +574,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     __syncthreads();
                 }
                 const InstDev &I = s_id;
-                const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx);
+                const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx, I.sep);
                 const int t = uni(item - N.pre[a]);
                 const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
                 // local copies: no reloads after the global stores
@@ -673,10 +711,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 block_accumulate<NVT>(v, NVT, s_acc, s_red);
             }
             if (cur_sys >= 0 && threadIdx.x < NVP)
-                gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+                gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
         }
         stamp(it, 2);
-        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag)) return;
+        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
         stamp(it, 3);
         if (flip) cur ^= 1;
     }

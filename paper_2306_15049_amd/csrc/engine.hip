@@ -256,7 +256,7 @@ template <class T> T *stage(rsr_ctx *c, const std::vector<T> &v, hipStream_t s)
 int max_tile_lds(rsr_ctx *c)
 {
     int m = 2048;
-    for (auto &p : c->inst) m = std::max(m, tile_lds_doubles(p->ty, p->tx, eff_sy(*p), eff_sx(*p)));
+    for (auto &p : c->inst) m = std::max(m, tile_lds_doubles(p->ty, p->tx, eff_sy(*p), eff_sx(*p), p->sep));
     return m;
 }
 
@@ -270,7 +270,7 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
     std::vector<ApplyJob> jobs(nvec);
     for (int j = 0; j < nvec; ++j) jobs[j] = ApplyJob{ii, 0, cA, cE, v + j * ldv, y + j * ldy};
     ApplyJob *dj = jobbuf ? upload(c, *jobbuf, jobs, s) : stage(c, jobs, s);
-    const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
+    const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I), I.sep);
     HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, nvec, lds, s));
     if (cA != 0.0) c->mv_A += nvec;
     if (cE != 0.0) c->mv_E += nvec;
@@ -284,7 +284,7 @@ void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
     for (auto &kv : by) {
         Instance &I = get_inst(c, kv.first);
         ApplyJob *dj = stage(c, kv.second, s);
-        const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I));
+        const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I), I.sep);
         HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[kv.first], dj, (int)kv.second.size(), lds, s));
         for (auto &j : kv.second) {
             if (j.cA != 0.0) c->mv_A++;
@@ -531,7 +531,8 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         const int v = atoi(cap);
         if (v >= 8) G = std::min(G, v);
     }
-    G = (int)std::min<long>(G, std::max<long>(8, tiles));
+    // no more workgroups than tiles (rounded up to the 8 XCDs)
+    G = (int)std::min<long>(G, (std::max<long>(8, tiles) + 7) & ~7L);
     if (G >= 8) G -= G % 8;
 
     CGArgs a;
@@ -584,16 +585,18 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         }
         const double tk = c->wall_khz / 1000.0;
         // iteration time by number of active systems (workgroup 0's loop-top stamps)
-        std::map<int, std::pair<double, int>> byact;
+        // (key: active systems, grid size of that iteration)
+        std::map<std::pair<int, int>, std::pair<double, int>> byact;
         for (int i = 0; i + 1 < DBG_ITERS && st[(i + 1) * 8]; ++i) {
-            auto &e = byact[(int)st[i * 8 + 4]];
+            auto &e = byact[{(int)st[i * 8 + 4], (int)st[i * 8 + 5]}];
             e.first += (double)(st[(i + 1) * 8] - st[i * 8]);
             e.second += 1;
         }
         if (!byact.empty()) {
             fprintf(stderr, "[rsr cg stamps] us/iteration by active systems:");
-            for (auto &kv : byact) fprintf(stderr, " %d:%.1f(x%d)", kv.first, kv.second.first / kv.second.second / tk,
-                                           kv.second.second);
+            for (auto &kv : byact)
+                fprintf(stderr, " %d:%.1f(x%d,G%d)", kv.first.first, kv.second.first / kv.second.second / tk,
+                        kv.second.second, kv.first.second);
             fprintf(stderr, "\n");
         }
         if (n > 0)
@@ -1478,7 +1481,7 @@ rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
         Instance &I = get_inst(c, ii);
         if (ty < 4 || tx < 4 || ty > 64 || tx > 64 || (ty & (ty - 1)) || (tx & (tx - 1)))
             fail(RSR_E_ARG, "tile sides must be powers of two in [4, 64]");
-        const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I));
+        const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I), I.sep);
         if (cg_lds_bytes(cg_tile_lds(tl, 8), 8) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
         set_device(c);
         I.ty = ty;
@@ -1539,7 +1542,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         const long mvA = c->mv_A, mvE = c->mv_E;
         Opts o{0.0, 40, RSR_INIT_ZERO, 0, 0, 0, 0, 0.0, 0.0};
         for (auto &cd : cand) {
-            const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I));
+            const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I), I.sep);
             const int ms8 = (n_vec + 7) & ~7;
             if (cg_lds_bytes(cg_tile_lds(tl, ms8), ms8) > 160 * 1024) continue;
             I.ty = cd[0];

@@ -80,7 +80,7 @@ struct CGArgs {
 constexpr int DBG_ITERS = 1024;
 
 // Launch plumbing implemented in kernels.hip.
-int tile_lds_doubles(int ty, int tx, int sy, int sx);
+int tile_lds_doubles(int ty, int tx, int sy, int sx, int sep);
 int cg_tile_lds(int tile_lds, int msys);      // tile LDS rounded up to the reduction scratch
 size_t cg_lds_bytes(int tile_lds, int msys);
 constexpr int BAR_GROUPS = 8;                          // barrier groups (one per XCD when G % 8 == 0)

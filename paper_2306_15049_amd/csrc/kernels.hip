@@ -24,9 +24,9 @@
 
 namespace rsr {
 
-int tile_lds_doubles(int ty, int tx, int sy, int sx)
+int tile_lds_doubles(int ty, int tx, int sy, int sx, int sep)
 {
-    const Geo g = make_geo(ty, tx, sy, sx);
+    const Geo g = make_geo(ty, tx, sy, sx, sep);
     return g.total < 2048 ? 2048 : g.total;   // the persistent kernel reuses it as reduction scratch
 }
 
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
     const int ntile = I.nty * I.ntx;
     if ((int)blockIdx.x >= ntile) return;
     const int y0 = (blockIdx.x / I.ntx) * I.ty, x0 = (blockIdx.x % I.ntx) * I.tx;
-    const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx);
+    const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx, I.sep);
     constexpr int NBW = 12;   // window rows per thread whose loads are issued together
     const double *__restrict__ vin = J.v;
     const WinMap wm = win_map(g.W0);

@@ -51,7 +51,7 @@ struct Geo {
                                                      // for discarded stores; offF: bands
 };
 
-__host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx)
+__host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx, int sep)
 {
     Geo g;
     g.ry = sy / 2;
@@ -68,14 +68,13 @@ __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx)
     g.P2 = tx | 1;
     g.H3 = ty + 2 * g.ry;
     g.PE = tx | 1;
-    // Passes read up to RB-1 elements past the end of a line (row passes) or
-    // RB-1 lines past the last one (column passes); those values feed only
-    // outputs beyond the line, which are never stored, so the buffers are padded
-    // instead of clamping every window load.
-    const int pad = RB * (g.P0 > g.P1 ? g.P0 : g.P1) + RB;
-    const int sz0 = g.H0 * g.P0 + pad;
-    const int sz1a = g.H0 * g.P2, sz1b = g.H3 * g.P1;   // banded x output / direct conv output
-    const int sz1 = (sz1a > sz1b ? sz1a : sz1b) + pad;
+    // The banded passes read up to RB - 1 elements past the end of a line (the x
+    // pass, when RB does not divide tx) or RB - 1 lines past the last one (the y
+    // pass, when RB does not divide ty); those values feed only outputs beyond
+    // the line, which are never stored, so the buffers are padded instead of
+    // clamping every window load.  The direct path clamps its reads.
+    const int sz0 = g.H0 * g.P0 + RB;
+    const int sz1 = sep ? g.H0 * g.P2 + RB * g.P2 + RB : g.H3 * g.P1;
     g.off1 = (sz0 + 1) & ~1;
     g.offE = (g.off1 + sz1 + 1) & ~1;
     g.offP = (g.offE + ty * g.PE + 1) & ~1;
