@@ -53,7 +53,8 @@ __device__ __forceinline__ double cld(const double *p) { return cld(gp(p)); }
 // (workgroup b in group b % 8, i.e. one group per XCD under round-robin
 // dispatch).  Each workgroup publishes its stores with one agent-scope release
 // on its group's arrival counter; the last arriver of a group (the counter
-// reaching k * group size at barrier k) increments the global counter and,
+// reaching the group's total arrivals up to this barrier) increments the
+// global counter and,
 // once all groups have arrived, releases its group through the group's epoch
 // word.  One contended counter of G arrivals becomes G/8 arrivals per group
 // counter plus 8 on the global one, and every group polls its own word.
@@ -114,9 +115,15 @@ __device__ __forceinline__ bool grid_barrier(const BarCtl &b, unsigned long long
         const unsigned long long before = *s_arr;
         *s_arr = before + gsize;
         if (old == before + gsize - 1) {
-            __hip_atomic_fetch_add(b.glob, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // Relaxed: every workgroup of the group wrote its L2 back in the
+            // release of its own arrival, which completed before that arrival
+            // was counted, so the group's data is in memory before this
+            // increment can happen; the same holds for the release word below.
+            // (A release here would write the L2 back once more on the
+            // barrier's critical path.)
+            __hip_atomic_fetch_add(b.glob, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok = spin_until(b.glob, k * (unsigned long long)b.ngrp, b.abort_flag, t0, timeout);
-            if (ok) __hip_atomic_store(b.rel, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (ok) __hip_atomic_store(b.rel, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             ok = spin_until(b.rel, k, b.abort_flag, t0, timeout);
         }
@@ -159,6 +166,7 @@ __device__ int block_excl_scan(int *v, int n, int *tmp)
 // tiles concatenated, split into G chunks of ipb items.
 struct Assign {
     int *act;    // [MAXSYS] system ids, ascending
+    int *tb;     // [MAXSYS] their first partial slots (a copy of tile_base: no global load at the loop top)
     int *pre;    // [MAXSYS+1] tile prefix
     int *foff;   // [MAXSYS+1] prefix of chunk counts (flat partial offsets)
 };
@@ -196,7 +204,10 @@ __device__ __forceinline__ int find_pos(const int *v, int n, int key)   // last 
 __device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m, int *s_ipb, int *tmp, bool shrink,
                              int *s_g)
 {
-    for (int k = threadIdx.x; k < m; k += NT) S.pre[k] = A.sys[S.act[k]].ntiles;
+    for (int k = threadIdx.x; k < m; k += NT) {
+        S.pre[k] = A.sys[S.act[k]].ntiles;
+        S.tb[k] = A.sys[S.act[k]].tile_base;
+    }
     __syncthreads();
     const int T = block_excl_scan(S.pre, m, tmp);
     if (threadIdx.x == 0) {
@@ -220,22 +231,27 @@ __device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m,
     __syncthreads();
 }
 
+// Chunk partials are stored value-major: value v of slot k at part[v * ps + k]
+// (ps = slots of the launch), so that the reductions, which read one value of
+// many consecutive slots per instruction, touch whole cache lines.
+//
 // Deterministic block-wide sum of cnt (<= NV) consecutive partial values of
-// one system: part[(base + k) * NVP + v0 + j] over k < nch, in two steps.
+// one system: part[(v0 + j) * ps + base + k] over k < nch, in two steps.
 // partial_load: each thread accumulates the slots k = threadIdx.x + i * NT in
 // registers; block_sum: wave sums, then the waves in order, into out[0..cnt).
 template <int NV>
-__device__ __forceinline__ void partial_load(const double *part, int base, int nch, int v0, int cnt, double (&acc)[NV])
+__device__ __forceinline__ void partial_load(const double *part, int ps, int base, int nch, int v0, int cnt,
+                                             double (&acc)[NV])
 {
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     for (int k = threadIdx.x; k < nch; k += NT) {
-        const double *p = part + (long)(base + k) * NVP + v0;
+        const double *p = part + v0 * ps + base + k;
         // branch-free so that all loads of a slot are in flight together; the
-        // clamped index stays inside the slot
+        // clamped index stays inside the used values
         double v[NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = cld(p + (j < cnt ? j : cnt - 1));
+        for (int j = 0; j < NV; ++j) v[j] = cld(p + (j < cnt ? j : cnt - 1) * ps);
 #pragma unroll
         for (int j = 0; j < NV; ++j) acc[j] += j < cnt ? v[j] : 0.0;
     }
@@ -261,11 +277,11 @@ __device__ void block_sum(const double (&acc)[NV], int cnt, double *out, double 
 }
 
 template <int NV>
-__device__ void block_reduce_partials(const double *part, int base, int nch, int v0, int cnt, double *out,
+__device__ void block_reduce_partials(const double *part, int ps, int base, int nch, int v0, int cnt, double *out,
                                       double *red)
 {
     double acc[NV];
-    partial_load<NV>(part, base, nch, v0, cnt, acc);
+    partial_load<NV>(part, ps, base, nch, v0, cnt, acc);
     block_sum<NV>(acc, cnt, out, red);
 }
 
@@ -303,15 +319,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     extern __shared__ double smem[];
     double *tile = smem;                          // stencil buffers / reduction scratch
     const int ms = A.msys;                        // per-system arrays sized by the launch
-    double *s_rho = smem + A.tile_lds;            // [ms] rho_j (one recurrence step from the exact rho_{j-1})
+    double *taps = smem + A.tile_lds;             // bands and end corrections of the staged instance
+    double *s_rho = taps + A.taps_lds;            // [ms] rho_j (one recurrence step from the exact rho_{j-1})
     double *s_alpha = s_rho + ms;                 // [ms] alpha_{j-1}
     double *s_beta = s_alpha + ms;                // [ms] beta_j
     int *ib = (int *)(s_beta + ms);
     Assign S0, S1;   // two named assignments (a runtime-indexed array would live in scratch)
     S0.act = ib; ib += ms;
+    S0.tb = ib; ib += ms;
     S0.pre = ib; ib += ms + 1;
     S0.foff = ib; ib += ms + 1;
     S1.act = ib; ib += ms;
+    S1.tb = ib; ib += ms;
     S1.pre = ib; ib += ms + 1;
     S1.foff = ib; ib += ms + 1;
     const BarCtl bc = bar_ctl(A);
@@ -329,10 +348,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __shared__ SysDev s_sd;
     __shared__ InstDev s_id;
     __shared__ int s_sd_sys;
+    __shared__ int s_taps_inst;                   // instance whose constants are in taps (or -1)
 
+    const int PS = A.pstride;                     // slots per value plane of the partials
     int cur = 0;
     if (threadIdx.x == 0) {
         s_sd_sys = -1;
+        s_taps_inst = -1;
         s_arr = 0;
     }
 
@@ -341,7 +363,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     build_assign(A, S0, A.nsys, A.G, &s_m[0], &s_ipb[0], s_tmp, false, &s_g);
 
     auto slot_of = [&](const Assign &As, int m, int ipb, int s, int chunk) {
-        return A.sys[s].tile_base + (chunk - As.pre[find_pos(As.act, m, s)] / ipb);
+        const int a = find_pos(As.act, m, s);
+        return As.tb[a] + (chunk - As.pre[a] / ipb);
     };
 
     // ---- initial pass: r_0.r_0 and Z^T r_0 into the partial slots read by iteration 0
@@ -359,7 +382,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             while (item >= As.pre[a + 1]) ++a;
             const int s = uni(As.act[a]);
             if (s != cur_sys) {
-                if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+                if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(int)threadIdx.x * PS + slot_of(As, m, ipb, cur_sys, chunk)] = s_acc[threadIdx.x];
                 cur_sys = s;
                 q = A.sys[s].q;
                 if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
@@ -389,14 +412,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
             block_accumulate<NVT>(v, NVT, s_acc, s_red);
         }
-        if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(long)slot_of(As, m, ipb, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+        if (cur_sys >= 0 && threadIdx.x < NVP) gp(pout)[(int)threadIdx.x * PS + slot_of(As, m, ipb, cur_sys, chunk)] = s_acc[threadIdx.x];
     }
     int nbar = 0;
     if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
 
     auto stamp = [&](int it, int k) {
-        if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) A.stamps[it * 8 + k] = realtime();
+        if (A.stamps && threadIdx.x == 0) {
+            if (blockIdx.x == 0 && it < DBG_ITERS) A.stamps[it * DBG_SLOTS + k] = realtime();
+            // every workgroup's phase times over a few iterations, with its hardware slot
+            if (k < 4 && it >= DBG_WG_IT0 && it < DBG_WG_IT0 + DBG_WG_NIT && blockIdx.x < DBG_WG_MAX) {
+                unsigned long long *w = A.stamps + DBG_ITERS * DBG_SLOTS + ((it - DBG_WG_IT0) * DBG_WG_MAX + blockIdx.x) * 8;
+                w[k] = realtime();
+                if (k == 0) {
+                    w[4] = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID: wave, SIMD, CU, SH, SE
+                    w[5] = __builtin_amdgcn_s_getreg((31 << 11) | 20);   // XCC_ID
+                }
+            }
+        }
     };
+    // (kept in LDS: registers are the binding resource across the stencil)
+    __shared__ int s_clast;   // last system of the previous phase: s_c holds its c_{j-1}
+    __shared__ int s_zsys;    // system whose c_j the loop top formed (or -1)
+    if (threadIdx.x == 0) s_clast = -1;
     for (int it = 0;; ++it) {
         stamp(it, 0);
         // (selects, not A.part[i]: a runtime index into the argument block would copy it to scratch)
@@ -407,17 +445,56 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         const int mo = s_m[cur];
         const int ipbo = s_ipb[cur];
         const int F = O.foff[mo];
+        // Steady state of a deflated system: when this workgroup's chunk lies in
+        // one system, the one it finished the previous phase with, the system's
+        // Z^T r / Z^T w partials are loaded here together with the flat
+        // partials below, and c_j is formed from the c_{j-1} kept in s_c -- one
+        // global round trip fewer than at a system switch inside the phase.
+        int zsys = -1, zfirst = 0;
+        bool zok = false;
+        double accz[QT > 0 ? 2 * QT : 1];
+        if (threadIdx.x == 0) s_zsys = -1;
+        if constexpr (QT > 0) {
+            const int c_last = s_clast;
+            const int chunk = chunk_of_block(blockIdx.x, s_g);
+            const int lo = chunk * ipbo;
+            const int hi = lo + ipbo < O.pre[mo] ? lo + ipbo : O.pre[mo];
+            if (lo < hi && c_last >= 0 && s_sd_sys == c_last && s_sd.q > 0) {
+                const int a0 = find_pos(O.pre, mo, lo);
+                const int nch = O.foff[a0 + 1] - O.foff[a0];
+                if (O.act[a0] == c_last && hi <= O.pre[a0 + 1] && nch <= NT) {
+                    zsys = c_last;
+                    zfirst = chunk == O.pre[a0] / ipbo;
+                    // one slot per thread, no accumulation here: the values are first
+                    // used after the flat loads below are issued, so both are in flight
+                    // together (the sums equal those of partial_load, as 0 + v = v)
+                    zok = threadIdx.x < nch;
+                    const int k = zok ? threadIdx.x : 0;
+                    const double *pz = pprev + 4 * PS + s_sd.tile_base + k;
+#pragma unroll
+                    for (int j = 0; j < 2 * QT; ++j) accz[j] = cld(pz + j * PS);
+                }
+            }
+        }
         double *fl = tile;   // [4][F] then [4][mo]
         for (int f = threadIdx.x; f < F; f += NT) {
             const int l = find_pos(O.foff, mo, f);
-            const double *p = pprev + (long)(A.sys[O.act[l]].tile_base + (f - O.foff[l])) * NVP;
-            const double v0 = cld(p), v1 = cld(p + 1), v2 = cld(p + 2), v3 = cld(p + 3);
+            const double *p = pprev + O.tb[l] + (f - O.foff[l]);
+            const double v0 = cld(p), v1 = cld(p + PS), v2 = cld(p + 2 * PS), v3 = cld(p + 3 * PS);
             fl[f] = v0;
             fl[F + f] = v1;
             fl[2 * F + f] = v2;
             fl[3 * F + f] = v3;
         }
         __syncthreads();
+        stamp(it, 8);
+        if constexpr (QT > 0) {
+            if (zsys >= 0) {   // Z^T r_{j-1}, Z^T w_{j-1}
+#pragma unroll
+                for (int j = 0; j < 2 * QT; ++j) accz[j] = zok ? accz[j] : 0.0;
+                block_sum<2 * QT>(accz, 2 * QT, s_vals, s_red);
+            }
+        }
         double *sums = fl + 4 * F;   // [4][mo]
         if (mo <= 16) {
             const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -443,6 +520,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
         }
         __syncthreads();
+        stamp(it, 9);
         Assign N = cur ? S0 : S1;
         int *keep = N.pre;       // scratch, rebuilt by build_assign
         int *newpos = N.foff;    // scratch
@@ -481,7 +559,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         __syncthreads();
         // compact the active list (keep ascending order)
-        {
+        if (mo <= 64) {
+            // one wave: ballot of the flags, position = flags set in lower lanes
+            if (threadIdx.x < 64) {
+                const bool k = (int)threadIdx.x < mo && keep[threadIdx.x];
+                const unsigned long long msk = __ballot(k);
+                const int pos = __popcll(msk & ((1ull << threadIdx.x) - 1ull));
+                if (k) N.act[pos] = O.act[threadIdx.x];
+                if (threadIdx.x == 0) s_m[cur ^ 1] = __popcll(msk);
+            }
+            __syncthreads();
+        } else {
             int kk[2];
             for (int u = 0; u < 2; ++u) kk[u] = (2 * threadIdx.x + u < mo) ? keep[2 * threadIdx.x + u] : 0;
             __syncthreads();
@@ -494,6 +582,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             __syncthreads();
         }
         const int mn = s_m[cur ^ 1];
+        stamp(it, 10);
         if (mn == 0) break;
         if (mn != mo) {
             // tiles move between workgroups when the active set shrinks: drop cached copies
@@ -508,10 +597,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         const bool flip = mn != mo;
         if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS) {
-            A.stamps[it * 8 + 4] = mn;
-            A.stamps[it * 8 + 5] = s_g;
+            A.stamps[it * DBG_SLOTS + 4] = mn;
+            A.stamps[it * DBG_SLOTS + 5] = s_g;
         }
         const int ipbn = flip ? s_ipb[cur ^ 1] : ipbo;
+        stamp(it, 11);
+        if constexpr (QT > 0) {
+            if (zsys >= 0 && !flip) {
+                // mu = Ginv (Z^T r_{j-1} - alpha Z^T w_{j-1}); c_j = beta c_{j-1} + mu
+                const SysDev &Y = s_sd;
+                const int q = Y.q;
+                if (threadIdx.x == 0) s_zsys = zsys;   // read inside the phase, after the syncs below
+                if (threadIdx.x < q)
+                    s_z[threadIdx.x] = fma(-s_alpha[zsys], s_vals[QT + threadIdx.x], s_vals[threadIdx.x]);
+                __syncthreads();
+                if (threadIdx.x < q) {
+                    double m = 0.0;
+                    for (int j = 0; j < q; ++j) m += Y.Ginv[threadIdx.x * QMAX + j] * s_z[j];
+                    const double cn = fma(s_beta[zsys], s_c[threadIdx.x], m);
+                    s_c[threadIdx.x] = cn;
+                    if (zfirst) gp(Y.cbuf)[(it & 1) * QMAX + threadIdx.x] = cn;
+                }
+                __syncthreads();
+            }
+        }
         stamp(it, 1);
 
         // ---- the iteration's one phase under N
@@ -540,24 +649,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         ((unsigned long long *)&s_id)[threadIdx.x - 128] = isrc[threadIdx.x - 128];
                     __syncthreads();
                     if (threadIdx.x == 0) s_sd_sys = s;
+                    if (ii != s_taps_inst) {
+                        // the instance's constants stay in LDS until another instance comes
+                        stage_taps(s_id, taps);
+                        __syncthreads();
+                        if (threadIdx.x == 0) s_taps_inst = ii;
+                    }
                 }
                 const SysDev &Y = s_sd;
                 if (s != cur_sys) {
                     if (cur_sys >= 0 && threadIdx.x < NVP)
-                        gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+                        gp(pcur)[(int)threadIdx.x * PS + slot_of(N, mn, ipbn, cur_sys, chunk)] = s_acc[threadIdx.x];
                     cur_sys = s;
                     q = Y.q;
                     alpha = s_alpha[s];
                     beta = s_beta[s];
                     if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
                     if (threadIdx.x >= q && threadIdx.x < QMAX) s_c[threadIdx.x] = 0.0;   // unused columns
-                    if (q > 0) {
+                    if (q > 0 && s != s_zsys) {
                         // Z^T r_j = Z^T r_{j-1} - alpha Z^T w_{j-1}; mu = Ginv Z^T r_j; c_j = beta c_{j-1} + mu
                         // (c_{j-1} is fetched first so that it travels with the partial-sum loads)
                         const double cold =
                             (it > 0 && threadIdx.x < q) ? cld(Y.cbuf + ((it + 1) & 1) * QMAX + threadIdx.x) : 0.0;
                         const int po = find_pos(O.act, mo, s);
-                        block_reduce_partials<(QT > 0 ? 2 * QT : 1)>(pprev, Y.tile_base, O.foff[po + 1] - O.foff[po], 4,
+                        block_reduce_partials<(QT > 0 ? 2 * QT : 1)>(pprev, PS, Y.tile_base, O.foff[po + 1] - O.foff[po], 4,
                                                                    2 * QT, s_vals, s_red);
                         if (threadIdx.x < q)
                             s_z[threadIdx.x] = fma(-alpha, s_vals[QT + threadIdx.x], s_vals[threadIdx.x]);
@@ -598,7 +713,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 // interior of ph_j and r_j in LDS
                 EWts ew;
                 tile_E_load(I, y0, x0, 0, gam, ew);   // in flight with the window loads
-                stage_taps(I, g, tile);
                 const WinMap wm = win_map(g.W0);
                 const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);     // window column of this thread
                 const int gx = x0 - g.hx + lj;
@@ -650,7 +764,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 __syncthreads();
                 if (item == lo) stamp(it, 6);
                 tile_E(I, g, tile, y0, x0, gam, ew);
-                tile_A(I, g, tile, y0, x0, 1.0);
+                tile_A(I, g, tile, taps, y0, x0, 1.0);
                 if (item == lo) stamp(it, 7);
                 // interior: x_j = x_{j-1} + alpha p_{j-1}; p_j = ph_j - W c_j; w_j = B ph_j - Z c_j;
                 // partials p.w, r.r, r.w, w.w, Z^T r, Z^T w (all 2q basis loads of a pixel batch together)
@@ -711,7 +825,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 block_accumulate<NVT>(v, NVT, s_acc, s_red);
             }
             if (cur_sys >= 0 && threadIdx.x < NVP)
-                gp(pcur)[(long)slot_of(N, mn, ipbn, cur_sys, chunk) * NVP + threadIdx.x] = s_acc[threadIdx.x];
+                gp(pcur)[(int)threadIdx.x * PS + slot_of(N, mn, ipbn, cur_sys, chunk)] = s_acc[threadIdx.x];
+            if (threadIdx.x == 0) s_clast = cur_sys;   // read after the barrier
         }
         stamp(it, 2);
         if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
@@ -728,10 +843,10 @@ int cg_tile_lds(int tile_lds, int msys)
     return tile_lds > need ? tile_lds : need;
 }
 
-size_t cg_lds_bytes(int tile_lds, int msys)
+size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys)
 {
-    const size_t d = (size_t)tile_lds + 3 * (size_t)msys;            // tile + rho, alpha, beta arrays
-    const size_t ints = 2 * (size_t)(msys + 2 * (msys + 1)) + 2;     // two assignments
+    const size_t d = (size_t)tile_lds + taps_lds + 3 * (size_t)msys;   // tile, constants, rho, alpha, beta
+    const size_t ints = 2 * (size_t)(2 * msys + 2 * (msys + 1)) + 2; // two assignments
     return d * sizeof(double) + ints * sizeof(int);
 }
 

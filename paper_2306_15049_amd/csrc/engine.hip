@@ -260,6 +260,19 @@ int max_tile_lds(rsr_ctx *c)
     return m;
 }
 
+int max_taps_lds(rsr_ctx *c)
+{
+    int m = 0;
+    for (auto &p : c->inst) m = std::max(m, taps_lds_doubles(eff_sy(*p), p->sep));
+    return m;
+}
+
+// LDS of the one-tile apply kernel: the tile buffers, then the instance's constants
+size_t apply_lds_bytes(const Instance &I)
+{
+    return sizeof(double) * (tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I), I.sep) + taps_lds_doubles(eff_sy(I), I.sep));
+}
+
 // ----------------------------------------------------------- operators --
 // y_j = cA A v_j + cE E v_j for nvec vectors of one instance.
 void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ldv, double *y, long ldy,
@@ -270,7 +283,7 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
     std::vector<ApplyJob> jobs(nvec);
     for (int j = 0; j < nvec; ++j) jobs[j] = ApplyJob{ii, 0, cA, cE, v + j * ldv, y + j * ldy};
     ApplyJob *dj = jobbuf ? upload(c, *jobbuf, jobs, s) : stage(c, jobs, s);
-    const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I), I.sep);
+    const size_t lds = apply_lds_bytes(I);
     HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, nvec, lds, s));
     if (cA != 0.0) c->mv_A += nvec;
     if (cE != 0.0) c->mv_E += nvec;
@@ -284,7 +297,7 @@ void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
     for (auto &kv : by) {
         Instance &I = get_inst(c, kv.first);
         ApplyJob *dj = stage(c, kv.second, s);
-        const size_t lds = sizeof(double) * tile_lds_doubles(I.ty, I.tx, eff_sy(I), eff_sx(I), I.sep);
+        const size_t lds = apply_lds_bytes(I);
         HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[kv.first], dj, (int)kv.second.size(), lds, s));
         for (auto &j : kv.second) {
             if (j.cA != 0.0) c->mv_A++;
@@ -520,7 +533,8 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
 
     const int msys = (m + 7) & ~7;
     const int tl = cg_tile_lds(max_tile_lds(c), msys);
-    const size_t lds = cg_lds_bytes(tl, msys);
+    const int taps_lds = max_taps_lds(c);
+    const size_t lds = cg_lds_bytes(tl, taps_lds, msys);
     int qmax = 0;
     for (auto *Y : sy) qmax = std::max(qmax, Y->q);
     const int qt = cg_width(qmax);
@@ -541,6 +555,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.inst = c->d_inst.as<InstDev>();
     a.part[0] = c->d_partA.as<double>();
     a.part[1] = c->d_partB.as<double>();
+    a.pstride = (int)tiles;
     a.bar = (unsigned long long *)c->d_ctl.p;
     a.abort_flag = (int *)((char *)c->d_ctl.p + 256);
     a.out_iters = out_iters;
@@ -551,12 +566,13 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.G = G;
     a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * 30.0);   // 30 s
     a.tile_lds = tl;
+    a.taps_lds = taps_lds;
     a.msys = msys;
     a.stamps = nullptr;
     const bool dbg = getenv("RSR_CG_STAMPS") != nullptr;   // phase timing of workgroup 0 (diagnostics)
     if (dbg) {
-        c->d_dbg.ensure(sizeof(unsigned long long) * DBG_ITERS * 8);
-        HIPCHK(launch_fill((double *)c->d_dbg.p, 0.0, DBG_ITERS * 8, s));
+        c->d_dbg.ensure(sizeof(unsigned long long) * DBG_WORDS);
+        HIPCHK(launch_fill((double *)c->d_dbg.p, 0.0, (long)DBG_WORDS, s));
         a.stamps = (unsigned long long *)c->d_dbg.p;
     }
     HIPCHK(hipEventRecord(c->ev0, s));
@@ -572,24 +588,68 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     if (dbg) {
-        std::vector<unsigned long long> st(DBG_ITERS * 8);
+        std::vector<unsigned long long> st(DBG_WORDS);
         HIPCHK(hipMemcpy(st.data(), c->d_dbg.p, sizeof(unsigned long long) * st.size(), hipMemcpyDeviceToHost));
-        double acc[5] = {0, 0, 0, 0, 0};
-        int n = 0;
-        for (int i = 1; i < DBG_ITERS && i + 1 < hi[0] && st[i * 8 + 3]; ++i, ++n) {
-            for (int k = 0; k < 3; ++k) acc[k] += (double)(st[i * 8 + k + 1] - st[i * 8 + k]);
-            if (st[i * 8 + 6] && st[i * 8 + 7]) {
-                acc[3] += (double)(st[i * 8 + 6] - st[i * 8 + 1]);
-                acc[4] += (double)(st[i * 8 + 7] - st[i * 8 + 6]);
+        {
+            // per-workgroup spread of a few iterations: the phase (assignment to
+            // barrier arrival) of every workgroup, the slowest one and its CU, and
+            // how many CUs hold more than one workgroup
+            const double tk0 = c->wall_khz / 1000.0;
+            for (int i = 0; i < DBG_WG_NIT; ++i) {
+                const unsigned long long *w = st.data() + DBG_ITERS * DBG_SLOTS + (size_t)i * DBG_WG_MAX * 8;
+                std::vector<std::pair<double, int>> ph;
+                std::map<long, int> per_cu;
+                double end_max = 0.0, top_max = 0.0, rel_max = 0.0;
+                int b_end = -1, b_top = -1;
+                unsigned long long t0 = ~0ull;
+                for (int b = 0; b < std::min(G, DBG_WG_MAX); ++b)
+                    if (w[b * 8] && w[b * 8 + 2]) t0 = std::min(t0, w[b * 8]);
+                for (int b = 0; b < std::min(G, DBG_WG_MAX); ++b) {
+                    const unsigned long long *e = w + b * 8;
+                    if (!e[0] || !e[2]) continue;
+                    ph.push_back({(double)(e[2] - e[1]) / tk0, b});
+                    const double te = (double)(e[2] - t0) / tk0, tt = (double)(e[1] - e[0]) / tk0;
+                    if (te > end_max) { end_max = te; b_end = b; }
+                    if (tt > top_max) { top_max = tt; b_top = b; }
+                    if (e[3]) rel_max = std::max(rel_max, (double)(e[3] - t0) / tk0);
+                    const long hw = (long)(e[4] & 0xff00) | ((long)(e[5] & 0xf) << 16);   // CU, SH, SE, XCC
+                    per_cu[hw]++;
+                }
+                if (ph.empty()) continue;
+                std::sort(ph.begin(), ph.end());
+                int shared = 0;
+                for (auto &kv : per_cu) shared += kv.second > 1;
+                const int bmax = ph.back().second;
+                const unsigned long long *e = w + bmax * 8;
+                fprintf(stderr,
+                        "[rsr cg stamps] it %d: %zu wgs, phase us min %.2f med %.2f max %.2f (wg %d, hwid 0x%llx xcc %llu, "
+                        "ends %.2f after the first top); last arrival %.2f (wg %d), longest top %.2f (wg %d), "
+                        "last release seen %.2f; CUs with >1 wg: %d\n",
+                        DBG_WG_IT0 + i, ph.size(), ph.front().first, ph[ph.size() / 2].first, ph.back().first, bmax,
+                        e[4], e[5] & 0xf, (double)(e[2] - t0) / tk0, end_max, b_end, top_max, b_top, rel_max, shared);
             }
+        }
+        double acc[5] = {0, 0, 0, 0, 0}, top[5] = {0, 0, 0, 0, 0};
+        int n = 0;
+        for (int i = 1; i < DBG_ITERS && i + 1 < hi[0] && st[i * DBG_SLOTS + 3]; ++i, ++n) {
+            for (int k = 0; k < 3; ++k) acc[k] += (double)(st[i * DBG_SLOTS + k + 1] - st[i * DBG_SLOTS + k]);
+            if (st[i * DBG_SLOTS + 6] && st[i * DBG_SLOTS + 7]) {
+                acc[3] += (double)(st[i * DBG_SLOTS + 6] - st[i * DBG_SLOTS + 1]);
+                acc[4] += (double)(st[i * DBG_SLOTS + 7] - st[i * DBG_SLOTS + 6]);
+            }
+            // the loop top: flat loads, sums, decisions and compaction, assignment, local-space step
+            const int kk[6] = {0, 8, 9, 10, 11, 1};
+            for (int u = 0; u < 5; ++u)
+                if (st[i * DBG_SLOTS + kk[u]] && st[i * DBG_SLOTS + kk[u + 1]])
+                    top[u] += (double)(st[i * DBG_SLOTS + kk[u + 1]] - st[i * DBG_SLOTS + kk[u]]);
         }
         const double tk = c->wall_khz / 1000.0;
         // iteration time by number of active systems (workgroup 0's loop-top stamps)
         // (key: active systems, grid size of that iteration)
         std::map<std::pair<int, int>, std::pair<double, int>> byact;
-        for (int i = 0; i + 1 < DBG_ITERS && st[(i + 1) * 8]; ++i) {
-            auto &e = byact[{(int)st[i * 8 + 4], (int)st[i * 8 + 5]}];
-            e.first += (double)(st[(i + 1) * 8] - st[i * 8]);
+        for (int i = 0; i + 1 < DBG_ITERS && st[(i + 1) * DBG_SLOTS]; ++i) {
+            auto &e = byact[{(int)st[i * DBG_SLOTS + 4], (int)st[i * DBG_SLOTS + 5]}];
+            e.first += (double)(st[(i + 1) * DBG_SLOTS] - st[i * DBG_SLOTS]);
             e.second += 1;
         }
         if (!byact.empty()) {
@@ -601,8 +661,9 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         }
         if (n > 0)
             fprintf(stderr, "[rsr cg stamps] G=%d iters=%d us: reduce+assign %.2f phase %.2f (first item: setup+load %.2f "
-                            "stencil %.2f) barrier %.2f\n",
-                    G, n, acc[0] / n / tk, acc[1] / n / tk, acc[3] / n / tk, acc[4] / n / tk, acc[2] / n / tk);
+                            "stencil %.2f) barrier %.2f; top: loads %.2f sums %.2f decide %.2f assign %.2f local %.2f\n",
+                    G, n, acc[0] / n / tk, acc[1] / n / tk, acc[3] / n / tk, acc[4] / n / tk, acc[2] / n / tk,
+                    top[0] / n / tk, top[1] / n / tk, top[2] / n / tk, top[3] / n / tk, top[4] / n / tk);
     }
     c->last_cg_ms += ms;
     c->last_launches += 1;
@@ -1482,7 +1543,8 @@ rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
         if (ty < 4 || tx < 4 || ty > 64 || tx > 64 || (ty & (ty - 1)) || (tx & (tx - 1)))
             fail(RSR_E_ARG, "tile sides must be powers of two in [4, 64]");
         const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I), I.sep);
-        if (cg_lds_bytes(cg_tile_lds(tl, 8), 8) > 160 * 1024) fail(RSR_E_ARG, "tile too large for LDS");
+        if (cg_lds_bytes(cg_tile_lds(tl, 8), taps_lds_doubles(eff_sy(I), I.sep), 8) > 160 * 1024)
+            fail(RSR_E_ARG, "tile too large for LDS");
         set_device(c);
         I.ty = ty;
         I.tx = tx;
@@ -1544,7 +1606,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         for (auto &cd : cand) {
             const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I), I.sep);
             const int ms8 = (n_vec + 7) & ~7;
-            if (cg_lds_bytes(cg_tile_lds(tl, ms8), ms8) > 160 * 1024) continue;
+            if (cg_lds_bytes(cg_tile_lds(tl, ms8), taps_lds_doubles(eff_sy(I), I.sep), ms8) > 160 * 1024) continue;
             I.ty = cd[0];
             I.tx = cd[1];
             upload_inst(c);

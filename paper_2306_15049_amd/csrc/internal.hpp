@@ -62,7 +62,8 @@ struct CGArgs {
     int nsys;
     const SysDev *sys;
     const InstDev *inst;
-    double *part[2];               // [total tiles][NVP] chunk partials, double-buffered by iteration parity
+    double *part[2];               // [NVP][pstride] chunk partials (value-major), double-buffered by iteration parity
+    int pstride;                   // slots per value plane (>= total tiles of the launch)
     unsigned long long *bar;       // barrier control block (BAR_BYTES, zero at launch): global counter,
                                    // per-group arrival counters and release epochs, 256-byte lines
     int *abort_flag;               // set on barrier timeout
@@ -74,15 +75,19 @@ struct CGArgs {
     int G;                         // workgroups in the grid
     long long timeout_ticks;       // barrier wait limit in s_memrealtime ticks (100 MHz)
     int tile_lds;                  // doubles of dynamic LDS used by the stencil buffers
+    int taps_lds;                  // doubles of dynamic LDS for an instance's bands and end corrections
     int msys;                      // capacity of the per-system LDS arrays (>= nsys)
     unsigned long long *stamps;    // optional [DBG_ITERS][8] phase timestamps of workgroup 0 (or null)
 };
-constexpr int DBG_ITERS = 1024;
+constexpr int DBG_ITERS = 1024, DBG_SLOTS = 16;   // workgroup 0's stamps: [DBG_ITERS][DBG_SLOTS]
+constexpr int DBG_WG_IT0 = 100, DBG_WG_NIT = 8, DBG_WG_MAX = 1024;   // per-workgroup stamps: [DBG_WG_NIT][DBG_WG_MAX][8]
+constexpr size_t DBG_WORDS = (size_t)DBG_ITERS * DBG_SLOTS + (size_t)DBG_WG_NIT * DBG_WG_MAX * 8;
 
 // Launch plumbing implemented in kernels.hip.
 int tile_lds_doubles(int ty, int tx, int sy, int sx, int sep);
+int taps_lds_doubles(int s, int sep);         // an instance's bands and end corrections (PSF extent s)
 int cg_tile_lds(int tile_lds, int msys);      // tile LDS rounded up to the reduction scratch
-size_t cg_lds_bytes(int tile_lds, int msys);
+size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys);
 constexpr int BAR_GROUPS = 8;                          // barrier groups (one per XCD when G % 8 == 0)
 constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
 int cg_width(int qmax);                           // compiled local-space width for a widest q

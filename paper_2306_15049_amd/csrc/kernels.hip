@@ -30,6 +30,8 @@ int tile_lds_doubles(int ty, int tx, int sy, int sx, int sep)
     return g.total < 2048 ? 2048 : g.total;   // the persistent kernel reuses it as reduction scratch
 }
 
+int taps_lds_doubles(int s, int sep) { return taps_doubles(s, sep); }
+
 // ---------------------------------------------------------- apply kernel --
 // y = cA A v + cE E v for one tile per workgroup; blockIdx.y selects the job.
 __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
@@ -48,9 +50,10 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
     const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);
     const int gx = x0 - g.hx + lj;
     const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
+    double *taps = lds + g.total;
     EWts ew;
     tile_E_load(I, y0, x0, 0, J.cE, ew);   // in flight with the window loads
-    stage_taps(I, g, lds);
+    stage_taps(I, taps);
     for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
         double v[NBW];
 #pragma unroll
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
     }
     __syncthreads();
     tile_E(I, g, lds, y0, x0, J.cE, ew);
-    if (J.cA != 0.0) tile_A(I, g, lds, y0, x0, J.cA);
+    if (J.cA != 0.0) tile_A(I, g, lds, taps, y0, x0, J.cA);
     const double *ebuf = lds + g.offE;
     for (int k = threadIdx.x; k < I.ty * I.tx; k += NT) {
         const int i = k >> I.ltx, j = k & (I.tx - 1);

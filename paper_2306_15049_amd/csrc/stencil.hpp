@@ -19,11 +19,33 @@
 
 namespace rsr {
 
+// Lane move of a double by a DPP pattern (two 32-bit moves); lanes outside
+// ROWS, and lanes whose source does not exist, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), returned to every lane.
+// DPP moves instead of LDS-crossbar shuffles: two quad swaps and the half-row
+// and row mirrors leave each 16-lane row's sum in all its lanes, the row-15
+// and row-31 broadcasts then accumulate the rows so that lane 63 holds the
+// total, which is read out as a scalar.  The order of the additions is fixed.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp_mov<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp_mov<0x140, 0xf>(v);   // row_mirror
+    v += dpp_mov<0x142, 0xa>(v);   // row_bcast15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xc>(v);   // row_bcast31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -47,8 +69,8 @@ struct Geo {
     int P2;            // pitch of width-tx intermediates (banded x output)
     int H3;            // rows after the conv pass (direct path)
     int PE;            // pitch of the output accumulator / interior copies
-    int off1, offE, offP, offR, offT, offF, total;   // offP/offR: interior copies; offT: a slot per thread
-                                                     // for discarded stores; offF: bands
+    int off1, offE, offP, offR, offT, total;   // offP/offR: interior copies; offT: a slot per thread
+                                               // for discarded stores
 };
 
 __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx, int sep)
@@ -80,21 +102,27 @@ __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx, int sep)
     g.offP = (g.offE + ty * g.PE + 1) & ~1;
     g.offR = g.offP + ty * g.PE;
     g.offT = g.offR + ty * g.PE;
-    g.offF = g.offT + NT;
-    g.total = g.offF + 2 * TAPS;
+    g.total = g.offT + NT;
     return g;
 }
 
-// Copy the two bands (x at offF, y at offF + TAPS) into LDS; issued with the
-// window loads, read by the passes as broadcasts.
-__device__ __forceinline__ void stage_taps(const InstDev &I, const Geo &g, double *lds)
+// LDS of an instance's separable-path constants, kept apart from the tile
+// buffers: the x band at 0, the y band at TAPS, then the four r x r end
+// corrections Lx, Rx, Ly, Ry (the layout of InstDev::band after its bands).
+__host__ __device__ inline int taps_doubles(int s, int sep) { return sep ? 2 * TAPS + 4 * (s / 2) * (s / 2) : 0; }
+
+// Copy the bands and end corrections into LDS (read as broadcasts by the
+// passes and the end fixes).
+__device__ __forceinline__ void stage_taps(const InstDev &I, double *taps)
 {
     if (!I.sep) return;
-    const int nb = 4 * (I.sx / 2) + 1;
-    double *f = lds + g.offF;
-    const int t = threadIdx.x;
-    if (t < nb) f[t] = gp(I.band)[t];
-    else if (t >= 64 && t - 64 < nb) f[TAPS + t - 64] = gp(I.band)[nb + t - 64];
+    const int r = I.sx / 2, nb = 4 * r + 1, nc = 4 * r * r;
+    const gdbl *src = gp(I.band);
+    for (int k = threadIdx.x; k < nb; k += NT) {
+        taps[k] = src[k];
+        taps[TAPS + k] = src[nb + k];
+    }
+    for (int k = threadIdx.x; k < nc; k += NT) taps[2 * TAPS + k] = src[2 * nb + k];
 }
 
 // out[l][e] (=|+=) sum_t b[t] in[l][e + t], t < NT_, over nlines lines of nout
@@ -166,11 +194,12 @@ __device__ __forceinline__ EndSpan end_span(int a0, int len, int n, int r)
 // v being the staged window row (zeros outside the image).  Items run over the
 // window rows times the tile's end columns only.
 template <int r>
-__device__ __forceinline__ void band_fix_x(const InstDev &I, const Geo &g, const double *buf0, double *buf1, int x0)
+__device__ __forceinline__ void band_fix_x(const InstDev &I, const Geo &g, const double *buf0, double *buf1, int x0,
+                                           const double *Lx)
 {
-    constexpr int nb = 4 * r + 1, rr = r * r;
+    constexpr int rr = r * r;
     const int nx = I.nx;
-    const gdbl *Lx = gp(I.band) + 2 * nb, *Rx = Lx + rr;
+    const double *Rx = Lx + rr;
     const EndSpan sp = end_span(x0, I.tx, nx, r);
     for (int it = threadIdx.x; it < g.H0 * sp.nc; it += NT) {
         const int l = it / sp.nc, c = it - l * sp.nc;
@@ -193,11 +222,12 @@ __device__ __forceinline__ void band_fix_x(const InstDev &I, const Geo &g, const
 // End corrections of the y band, subtracted from the tile accumulator; the
 // inputs are the x-pass output rows (buf1 row k = image row y0 - hy + k).
 template <int r>
-__device__ __forceinline__ void band_fix_y(const InstDev &I, const Geo &g, const double *buf1, double *ebuf, int y0)
+__device__ __forceinline__ void band_fix_y(const InstDev &I, const Geo &g, const double *buf1, double *ebuf, int y0,
+                                           const double *Ly)
 {
-    constexpr int nb = 4 * r + 1, rr = r * r;
+    constexpr int rr = r * r;
     const int tx = I.tx, ny = I.ny;
-    const gdbl *Ly = gp(I.band) + 2 * nb + 2 * rr, *Ry = Ly + rr;
+    const double *Ry = Ly + rr;
     const EndSpan sp = end_span(y0, I.ty, ny, r);
     for (int it = threadIdx.x; it < sp.nc * tx; it += NT) {
         const int c = it >> I.ltx, e = it & (tx - 1);
@@ -218,32 +248,41 @@ __device__ __forceinline__ void band_fix_y(const InstDev &I, const Geo &g, const
 }
 
 // ebuf += cA K^T K v for a rank-1 square PSF of S = 2r + 1 taps (v staged in
-// buf0, bands staged by stage_taps).
+// buf0, bands and end corrections staged in taps by stage_taps).
 template <int S>
-__device__ __forceinline__ void tile_A_sep(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
+__device__ __forceinline__ void tile_A_sep(const InstDev &I, const Geo &g, double *lds, const double *taps, int y0,
+                                           int x0, double cA)
 {
     constexpr int r = S / 2, NB = 4 * r + 1;
     constexpr int R = NB <= 29 ? RB : 4;
     constexpr int CT = NB <= 29 ? NB : 16;
     double *buf0 = lds, *buf1 = lds + g.off1, *ebuf = lds + g.offE, *trash = lds + g.offT;
-    const double *bx = lds + g.offF, *by = lds + g.offF + TAPS;
+    const double *bx = taps, *by = taps + TAPS;
     const int ty = I.ty, tx = I.tx;
     // x band over every window row: buf0 (from column ox) -> buf1 (H0 x tx)
     pass_band<NB, R, CT>(buf0 + g.ox, 1, g.P0, buf1, 1, g.P2, g.H0, tx, bx, false, trash);
     __syncthreads();
     if (r > 0 && (x0 < r || x0 + tx > I.nx - r)) {
-        band_fix_x<r>(I, g, buf0, buf1, x0);
+        band_fix_x<r>(I, g, buf0, buf1, x0, taps + 2 * TAPS);
         __syncthreads();
     }
     if (cA != 1.0) {
         for (int k = threadIdx.x; k < g.H0 * g.P2; k += NT) buf1[k] *= cA;
         __syncthreads();
     }
-    // y band: buf1 (from row oy) -> ebuf (+=)
-    pass_band<NB, R, CT>(buf1 + g.oy * g.P2, g.P2, 1, ebuf, g.PE, 1, tx, ty, by, true, trash);
+    // y band: buf1 (from row oy) -> ebuf (+=).  Its lines are the tile's tx
+    // columns of ty outputs: with R outputs per thread a 16 x 32 tile would
+    // occupy one wave, so columns are cut into strips of 4 (or 2) outputs to
+    // keep every wave busy; the pass is bound by the latency of its FMA chains,
+    // not by the extra window reads.
+    constexpr int RY = R < 4 ? R : 4;
+    if (tx * ((ty + RY - 1) / RY) >= NT)
+        pass_band<NB, RY, CT>(buf1 + g.oy * g.P2, g.P2, 1, ebuf, g.PE, 1, tx, ty, by, true, trash);
+    else
+        pass_band<NB, 2, CT>(buf1 + g.oy * g.P2, g.P2, 1, ebuf, g.PE, 1, tx, ty, by, true, trash);
     __syncthreads();
     if (r > 0 && (y0 < r || y0 + ty > I.ny - r)) {
-        band_fix_y<r>(I, g, buf1, ebuf, y0);
+        band_fix_y<r>(I, g, buf1, ebuf, y0, taps + 2 * TAPS + 2 * r * r);
         __syncthreads();
     }
 }
@@ -302,14 +341,15 @@ __device__ __forceinline__ void tile_A_direct(const InstDev &I, const Geo &g, do
 }
 
 // ebuf += cA K^T K (staged input in buf0, which is overwritten).
-__device__ __forceinline__ void tile_A(const InstDev &I, const Geo &g, double *lds, int y0, int x0, double cA)
+__device__ __forceinline__ void tile_A(const InstDev &I, const Geo &g, double *lds, const double *taps, int y0,
+                                       int x0, double cA)
 {
     if (!I.sep) {
         tile_A_direct(I, g, lds, y0, x0, cA);
         return;
     }
 #define RSR_SEP(SS) \
-    case SS: tile_A_sep<SS>(I, g, lds, y0, x0, cA); break;
+    case SS: tile_A_sep<SS>(I, g, lds, taps, y0, x0, cA); break;
     switch (I.sy) {
         RSR_SEP(1) RSR_SEP(3) RSR_SEP(5) RSR_SEP(7) RSR_SEP(9) RSR_SEP(11) RSR_SEP(13) RSR_SEP(15)
         RSR_SEP(17) RSR_SEP(19) RSR_SEP(21) RSR_SEP(23) RSR_SEP(25) RSR_SEP(27) RSR_SEP(29) RSR_SEP(31)
