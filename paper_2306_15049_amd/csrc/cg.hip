@@ -323,7 +323,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     double *s_rho = taps + A.taps_lds;            // [ms] rho_j (one recurrence step from the exact rho_{j-1})
     double *s_alpha = s_rho + ms;                 // [ms] alpha_{j-1}
     double *s_beta = s_alpha + ms;                // [ms] beta_j
-    int *ib = (int *)(s_beta + ms);
+    double *s_tol = s_beta + ms;                  // [ms] the systems' absolute tolerances
+    int *ib = (int *)(s_tol + ms);
     Assign S0, S1;   // two named assignments (a runtime-indexed array would live in scratch)
     S0.act = ib; ib += ms;
     S0.tb = ib; ib += ms;
@@ -358,7 +359,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         s_arr = 0;
     }
 
-    for (int k = threadIdx.x; k < A.nsys; k += NT) S0.act[k] = k;
+    for (int k = threadIdx.x; k < A.nsys; k += NT) {
+        S0.act[k] = k;
+        s_tol[k] = A.sys[k].tolabs;
+    }
     __syncthreads();
     build_assign(A, S0, A.nsys, A.G, &s_m[0], &s_ipb[0], s_tmp, false, &s_g);
 
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 else if (!(pw > 0.0)) st = -4;
             }
             if (st == 0) {
-                if (sqrt(rho) <= A.sys[s].tolabs) st = 1;
+                if (sqrt(rho) <= s_tol[s]) st = 1;
                 else if (it >= A.maxit) st = 2;
             }
             s_rho[s] = rho;
@@ -688,6 +692,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     }
                     __syncthreads();
                 }
+                if (item == lo) stamp(it, 12);
                 const InstDev &I = s_id;
                 const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx, I.sep);
                 const int t = uni(item - N.pre[a]);
@@ -822,7 +827,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         }
                     }
                 }
+                if (item == lo) stamp(it, 13);
                 block_accumulate<NVT>(v, NVT, s_acc, s_red);
+                if (item == lo) stamp(it, 14);
             }
             if (cur_sys >= 0 && threadIdx.x < NVP)
                 gp(pcur)[(int)threadIdx.x * PS + slot_of(N, mn, ipbn, cur_sys, chunk)] = s_acc[threadIdx.x];
@@ -845,7 +852,7 @@ int cg_tile_lds(int tile_lds, int msys)
 
 size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys)
 {
-    const size_t d = (size_t)tile_lds + taps_lds + 3 * (size_t)msys;   // tile, constants, rho, alpha, beta
+    const size_t d = (size_t)tile_lds + taps_lds + 4 * (size_t)msys;   // tile, constants, rho, alpha, beta, tol
     const size_t ints = 2 * (size_t)(2 * msys + 2 * (msys + 1)) + 2; // two assignments
     return d * sizeof(double) + ints * sizeof(int);
 }

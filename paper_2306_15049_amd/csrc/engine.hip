@@ -123,6 +123,9 @@ struct rsr_ctx {
     DBuf d_ws;                         // per-system vectors of a solve
     DBuf d_dbg;                        // optional phase timestamps
     DBuf d_tmp;                        // misc n-vectors
+    DBuf d_rcC, d_rcQ;                 // recycle-space candidates and their orthonormal basis (kept: no
+                                       // allocation, and no free that drains the device, per update)
+    DBuf d_gprev;                      // previous shift's correction in sequential solves
     // staging arena for launch descriptors and coefficients: pinned host and
     // device halves bump-allocated in step, reset whenever the stream is drained,
     // so that launches whose inputs come from the host need no synchronisation
@@ -629,7 +632,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
                         e[4], e[5] & 0xf, (double)(e[2] - t0) / tk0, end_max, b_end, top_max, b_top, rel_max, shared);
             }
         }
-        double acc[5] = {0, 0, 0, 0, 0}, top[5] = {0, 0, 0, 0, 0};
+        double acc[5] = {0, 0, 0, 0, 0}, top[5] = {0, 0, 0, 0, 0}, ph[5] = {0, 0, 0, 0, 0};
         int n = 0;
         for (int i = 1; i < DBG_ITERS && i + 1 < hi[0] && st[i * DBG_SLOTS + 3]; ++i, ++n) {
             for (int k = 0; k < 3; ++k) acc[k] += (double)(st[i * DBG_SLOTS + k + 1] - st[i * DBG_SLOTS + k]);
@@ -642,6 +645,11 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
             for (int u = 0; u < 5; ++u)
                 if (st[i * DBG_SLOTS + kk[u]] && st[i * DBG_SLOTS + kk[u + 1]])
                     top[u] += (double)(st[i * DBG_SLOTS + kk[u + 1]] - st[i * DBG_SLOTS + kk[u]]);
+            // the first item: system switch, window staging, stencil, epilogue, partial sums
+            const int kp[6] = {1, 12, 6, 7, 13, 14};
+            for (int u = 0; u < 5; ++u)
+                if (st[i * DBG_SLOTS + kp[u]] && st[i * DBG_SLOTS + kp[u + 1]])
+                    ph[u] += (double)(st[i * DBG_SLOTS + kp[u + 1]] - st[i * DBG_SLOTS + kp[u]]);
         }
         const double tk = c->wall_khz / 1000.0;
         // iteration time by number of active systems (workgroup 0's loop-top stamps)
@@ -661,9 +669,11 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         }
         if (n > 0)
             fprintf(stderr, "[rsr cg stamps] G=%d iters=%d us: reduce+assign %.2f phase %.2f (first item: setup+load %.2f "
-                            "stencil %.2f) barrier %.2f; top: loads %.2f sums %.2f decide %.2f assign %.2f local %.2f\n",
+                            "stencil %.2f) barrier %.2f; top: loads %.2f sums %.2f decide %.2f assign %.2f local %.2f; "
+                            "item: switch %.2f window %.2f stencil %.2f epilogue %.2f partials %.2f\n",
                     G, n, acc[0] / n / tk, acc[1] / n / tk, acc[3] / n / tk, acc[4] / n / tk, acc[2] / n / tk,
-                    top[0] / n / tk, top[1] / n / tk, top[2] / n / tk, top[3] / n / tk, top[4] / n / tk);
+                    top[0] / n / tk, top[1] / n / tk, top[2] / n / tk, top[3] / n / tk, top[4] / n / tk, ph[0] / n / tk,
+                    ph[1] / n / tk, ph[2] / n / tk, ph[3] / n / tk, ph[4] / n / tk);
     }
     c->last_cg_ms += ms;
     c->last_launches += 1;
@@ -1149,7 +1159,8 @@ void rsr_destroy(rsr_ctx *c)
         for (auto &g : I.gstore) if (g.second) g.second->release();
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
-                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev})
+                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
+                    &c->d_gprev})
         b->release();
     if (c->ar_host) (void)hipHostFree(c->ar_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1292,7 +1303,7 @@ rsr_status rsr_set_recycle_space(rsr_ctx *c, int ii, const double *U_raw, long l
             return;
         }
         // candidate block C = [U W~(:, 1:nr), U_raw]
-        DBuf Cb;
+        DBuf &Cb = c->d_rcC;
         Cb.ensure(sizeof(double) * (size_t)m * n);
         double *C = Cb.as<double>();
         if (nr > 0) {
@@ -1312,7 +1323,7 @@ rsr_status rsr_set_recycle_space(rsr_ctx *c, int ii, const double *U_raw, long l
         // keep sigma_1 / sigma_i < cond_max (and above the FP64 resolution of
         // the Gram route), Q = C V_k diag(1/sigma_k); a second pass restores
         // orthonormality to rounding level.
-        DBuf Qb;
+        DBuf &Qb = c->d_rcQ;
         Qb.ensure(sizeof(double) * (size_t)m * n);
         double *Q = Qb.as<double>();
         int keep = 0;
@@ -1374,8 +1385,6 @@ rsr_status rsr_set_recycle_space(rsr_ctx *c, int ii, const double *U_raw, long l
         I.Gee = sym(blocks[4]);
         I.ae_valid = true;
         if (p_kept) *p_kept = p;
-        Cb.release();
-        Qb.release();
     });
 }
 
@@ -1427,7 +1436,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 store_corrections(c, grp, s);
             }
         } else {
-            DBuf gprev;
+            DBuf &gprev = c->d_gprev;
             const double *gp = nullptr;
             for (int i = 0; i < m; ++i) {
                 std::vector<SysHost *> one{&sys[i]};
@@ -1446,7 +1455,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 }
             }
             sync(c, s);
-            gprev.release();
+
         }
         bool all = true;
         for (int i = 0; i < m; ++i) {

@@ -1,5 +1,5 @@
 // Host-side small dense linear algebra (p <= a few hundred) for the recycling
-// steps: symmetric eigendecomposition by cyclic Jacobi rotations and solves
+// steps: symmetric eigendecomposition (tridiagonal QR, Jacobi fallback) and solves
 // with a truncated eigen-pseudo-inverse.  Matrices are row-major.
 #pragma once
 #include <algorithm>
@@ -8,9 +8,10 @@
 
 namespace rsr {
 
-// Eigenpairs of the symmetric n x n matrix S (row-major): S = V diag(w) V^T.
-// w ascending; V column j (V[i*n + j]) is the eigenvector of w[j].
-inline void sym_eig(int n, const double *S, std::vector<double> &w, std::vector<double> &V)
+// Eigenpairs of the symmetric n x n matrix S (row-major) by cyclic Jacobi
+// rotations: S = V diag(w) V^T, w ascending, V column j (V[i*n + j]) the
+// eigenvector of w[j].  The fallback of sym_eig.
+inline void sym_eig_jacobi(int n, const double *S, std::vector<double> &w, std::vector<double> &V)
 {
     std::vector<double> a(S, S + (size_t)n * n);
     V.assign((size_t)n * n, 0.0);
@@ -59,6 +60,122 @@ inline void sym_eig(int n, const double *S, std::vector<double> &w, std::vector<
         for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + idx[j]];
     }
     V.swap(Vs);
+}
+
+// Eigenpairs of the symmetric n x n matrix S (row-major) in two stages, as in
+// Golub and Van Loan (Householder tridiagonalization, then the implicit
+// symmetric QR step with Wilkinson shifts):
+//  1. for k = 0 .. n-3 a reflector H_k = I - beta v v^T zeroes column k below
+//     the subdiagonal; the trailing block is updated as B - v w^T - w v^T with
+//     p = beta B v, w = p - (beta/2)(p^T v) v, and Q = H_0 H_1 ... accumulates;
+//  2. the tridiagonal T (diagonal d, subdiagonal e) is diagonalised by chasing
+//     a bulge with plane rotations from the top of each unreduced block, the
+//     shift being the eigenvalue of the trailing 2 x 2 nearer its last entry;
+//     the rotations are applied to the columns of V (initially Q).
+// Returns false if some block fails to converge (the caller then falls back).
+inline bool sym_eig_tridiag(int n, const double *S, std::vector<double> &w, std::vector<double> &V)
+{
+    std::vector<double> A(S, S + (size_t)n * n), d(n), e(n > 0 ? n : 1, 0.0);
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    std::vector<double> v(n), p(n), wv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;   // length of the reflector (rows k+1 .. n-1)
+        double xn = 0.0;
+        for (int i = 0; i < m; ++i) xn += A[(size_t)(k + 1 + i) * n + k] * A[(size_t)(k + 1 + i) * n + k];
+        xn = std::sqrt(xn);
+        if (xn == 0.0) continue;
+        const double x0 = A[(size_t)(k + 1) * n + k];
+        const double alpha = x0 >= 0.0 ? -xn : xn;   // H x = alpha e_1 without cancellation
+        for (int i = 0; i < m; ++i) v[i] = A[(size_t)(k + 1 + i) * n + k];
+        v[0] -= alpha;
+        double vv = 0.0;
+        for (int i = 0; i < m; ++i) vv += v[i] * v[i];
+        if (vv == 0.0) continue;
+        const double beta = 2.0 / vv;
+        // p = beta B v over the trailing block, then w = p - (beta/2)(p.v) v
+        double pv = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double *row = &A[(size_t)(k + 1 + i) * n + k + 1];
+            double acc = 0.0;
+            for (int j = 0; j < m; ++j) acc += row[j] * v[j];
+            p[i] = beta * acc;
+            pv += p[i] * v[i];
+        }
+        const double kk = 0.5 * beta * pv;
+        for (int i = 0; i < m; ++i) wv[i] = p[i] - kk * v[i];
+        for (int i = 0; i < m; ++i) {
+            double *row = &A[(size_t)(k + 1 + i) * n + k + 1];
+            for (int j = 0; j < m; ++j) row[j] -= v[i] * wv[j] + wv[i] * v[j];
+        }
+        A[(size_t)(k + 1) * n + k] = A[(size_t)k * n + k + 1] = alpha;
+        for (int i = 1; i < m; ++i) A[(size_t)(k + 1 + i) * n + k] = A[(size_t)k * n + k + 1 + i] = 0.0;
+        // V <- V H_k on columns k+1 .. n-1
+        for (int r = 0; r < n; ++r) {
+            double *row = &V[(size_t)r * n + k + 1];
+            double acc = 0.0;
+            for (int j = 0; j < m; ++j) acc += row[j] * v[j];
+            acc *= beta;
+            for (int j = 0; j < m; ++j) row[j] -= acc * v[j];
+        }
+    }
+    for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+    for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
+    const double eps = 2.220446049250313e-16;
+    int hi = n - 1, guard = 0;
+    while (hi > 0) {
+        if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+            e[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+        if (++guard > 60 * n) return false;
+        // Wilkinson shift from the trailing 2 x 2 of the block [lo, hi]
+        const double dl = 0.5 * (d[hi - 1] - d[hi]), eh = e[hi - 1];
+        const double den = dl + (dl >= 0.0 ? 1.0 : -1.0) * std::hypot(dl, eh);
+        const double mu = den != 0.0 ? d[hi] - eh * eh / den : d[hi];
+        double x = d[lo] - mu, z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, z);
+            const double c = r != 0.0 ? x / r : 1.0, sn = r != 0.0 ? z / r : 0.0;
+            if (k > lo) e[k - 1] = r;   // the bulge is absorbed
+            const double a = d[k], b = e[k], dd = d[k + 1];
+            d[k] = c * c * a + 2.0 * c * sn * b + sn * sn * dd;
+            d[k + 1] = sn * sn * a - 2.0 * c * sn * b + c * c * dd;
+            e[k] = c * sn * (dd - a) + (c * c - sn * sn) * b;
+            if (k + 1 < hi) {
+                z = sn * e[k + 1];   // new bulge at (k + 2, k)
+                e[k + 1] *= c;
+                x = e[k];
+            }
+            for (int r2 = 0; r2 < n; ++r2) {
+                double *row = &V[(size_t)r2 * n];
+                const double vk = row[k], vk1 = row[k + 1];
+                row[k] = c * vk + sn * vk1;
+                row[k + 1] = -sn * vk + c * vk1;
+            }
+        }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+    w.resize(n);
+    std::vector<double> Vs((size_t)n * n);
+    for (int j = 0; j < n; ++j) {
+        w[j] = d[idx[j]];
+        for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + idx[j]];
+    }
+    V.swap(Vs);
+    return true;
+}
+
+// Eigenpairs of the symmetric n x n matrix S (row-major): S = V diag(w) V^T,
+// w ascending, V column j (V[i*n + j]) the eigenvector of w[j].
+inline void sym_eig(int n, const double *S, std::vector<double> &w, std::vector<double> &V)
+{
+    if (!sym_eig_tridiag(n, S, w, V)) sym_eig_jacobi(n, S, w, V);
 }
 
 // Pseudo-inverse of a symmetric positive semidefinite n x n matrix S with the

@@ -1,0 +1,73 @@
+"""Host eigensolvers of the recycling steps (tridiagonal QR and Jacobi).
+
+Checked against what the mathematics fixes: S V = V diag(w), V^T V = I, and
+the eigenvalues of LAPACK (numpy.linalg.eigvalsh) on random symmetric,
+badly scaled and nearly diagonal matrices, including n = 0, 1, 2.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "native", "smalldense_check.cpp")
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("sd") / "smalldense_check")
+    subprocess.run([gxx, "-O2", "-std=c++17", SRC, "-o", out], check=True)
+    return out
+
+
+def _run(exe, S):
+    n = S.shape[0]
+    txt = f"{n}\n" + "\n".join(repr(float(v)) for v in S.ravel()) + "\n"
+    res = subprocess.run([exe], input=txt, capture_output=True, text=True, check=True)
+    vals = np.array([float(t) for t in res.stdout.split()])
+    ok = int(vals[0])
+    k = 1
+    out = []
+    for _ in range(2):
+        w = vals[k:k + n]
+        k += n
+        V = vals[k:k + n * n].reshape(n, n)
+        k += n * n
+        out.append((w, V))
+    return ok, out
+
+
+def _mats(rng):
+    yield np.zeros((0, 0))
+    yield np.array([[3.0]])
+    yield np.array([[2.0, 1.0], [1.0, 2.0]])
+    for n in (5, 17, 40, 60):
+        B = rng.standard_normal((n, n))
+        yield B + B.T                                            # indefinite
+        D = np.diag(10.0 ** rng.uniform(-10, 2, n))
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        yield Q @ D @ Q.T                                        # graded SPD
+        T = np.diag(1.0 + np.arange(n) % 3) + 1e-3 * (np.eye(n, k=1) + np.eye(n, k=-1))
+        yield T                                                  # clustered, nearly diagonal
+
+
+def test_eigensolvers_against_lapack(exe):
+    rng = np.random.default_rng(11)
+    for S in _mats(rng):
+        S = 0.5 * (S + S.T)
+        n = S.shape[0]
+        ok, routes = _run(exe, S)
+        assert ok == 1
+        ref = np.linalg.eigvalsh(S) if n else np.zeros(0)
+        scale = max(1.0, np.abs(S).max()) if n else 1.0
+        for w, V in routes:
+            assert np.all(np.diff(w) >= 0)
+            np.testing.assert_allclose(w, ref, rtol=0, atol=1e-12 * scale)
+            if n:
+                assert np.abs(S @ V - V * w).max() <= 1e-12 * scale
+                assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
