@@ -49,6 +49,16 @@ def cg_alg_bytes_per_px_iter(q: int, m_share: int) -> float:
     return 80.0 + 16.0 * q + 16.0 / max(1, m_share)
 
 
+def desc_problems(cfg, s_taps: int) -> str:
+    """One instance: its size and PSF; several: their count and size range."""
+    pr = cfg.problems
+    if len(pr) == 1:
+        return f"{pr[0].ny}x{pr[0].nx} deblur, PSF {s_taps}x{s_taps} sigma={pr[0].sigma}"
+    sides = sorted({p.ny for p in pr})
+    return (f"{len(pr)} deblurring instances, sides {sides[0]}..{sides[-1]}, "
+            f"PSF sigma {min(p.sigma for p in pr):.2f}..{max(p.sigma for p in pr):.2f}")
+
+
 def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
     """K^T K as two banded passes of 2s - 1 taps (2 flops each), E (13), the
     vector updates and the p.w, r.r, r.w, w.w, Z^T r, Z^T w partial sums."""
@@ -59,7 +69,7 @@ def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
 # the timed recycled steps of this workload (FETCH_SIZE scaled by 2.0, WRITE_SIZE by
 # 1.0: the factors a 256 MiB device copy gives), keyed by the hash of the kernel
 # sources they were taken on; any other kernel build reports null.
-MEASURED_TRAFFIC = {("C2", "34ecac63ee608b96"): 724.77e6}
+MEASURED_TRAFFIC = {("C2", "18bac6894920acba"): 723.52e6}
 KERNEL_SOURCES = ["paper_2306_15049_amd/csrc/cg.hip", "paper_2306_15049_amd/csrc/stencil.hpp",
                   "paper_2306_15049_amd/csrc/internal.hpp"]
 
@@ -184,19 +194,23 @@ def main():
     # roofline of the dominant kernel (persistent CG) over the timed recycled steps
     pr0 = cfg.problems[0]
     s_taps = pr0.psf.shape[0]
-    n_px = pr0.ny * pr0.nx
     q_eff = cfg.q
     tot_bytes = 0.0
     tot_flops = 0.0
     tot_ms = 0.0
     tot_iters = 0
+    M = len(cfg.gammas)
     for r in recs:
-        its = sum(r.iters)
-        tot_iters += its
-        m_share = 1 if head_mode == rsr.SEQUENTIAL else len(cfg.gammas)
+        tot_iters += sum(r.iters)
+        m_share = 1 if head_mode == rsr.SEQUENTIAL else M
         q = q_eff if r.k > 0 else 1
-        tot_bytes += its * n_px * cg_alg_bytes_per_px_iter(q, m_share)
-        tot_flops += its * n_px * cg_alg_flops_per_px_iter(s_taps, q)
+        # systems are ordered instance-major (M shifts per instance); each
+        # counts with its own instance's size and PSF
+        for j, its in enumerate(r.iters):
+            pr = cfg.problems[j // M]
+            npx = pr.ny * pr.nx
+            tot_bytes += its * npx * cg_alg_bytes_per_px_iter(q, m_share)
+            tot_flops += its * npx * cg_alg_flops_per_px_iter(pr.psf.shape[0], q)
         tot_ms += r.cg_kernel_ms
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -228,7 +242,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded rectangle phantom, Gaussian PSF, 1% noise)",
-        "config": {"workload": f"{cfg.name}: {pr0.ny}x{pr0.nx} deblur, PSF {s_taps}x{s_taps} sigma={pr0.sigma}, "
+        "config": {"workload": f"{cfg.name}: {desc_problems(cfg, s_taps)}, "
                                f"{len(cfg.gammas)} shifts 1e-5..1e1, p={cfg.p}, q={cfg.q}, "
                                f"{'one shift at a time' if head_mode == rsr.SEQUENTIAL else 'all shifts batched'}, "
                                f"tol={cfg.tol}",
