@@ -257,16 +257,41 @@ __device__ __forceinline__ void partial_load(const double *part, int ps, int bas
     }
 }
 
+// The wave's sums of cnt (<= NV) per-lane values into wred[0..cnt): up to 16
+// values through one transposing reduction (wave_sum16), the rest (and sets of
+// at most 4) one by one.
+template <int NV>
+__device__ __forceinline__ void wave_partials(const double (&v)[NV], int cnt, double *wred)
+{
+    const int lane = threadIdx.x & 63;
+    if constexpr (NV > 4) {
+        constexpr int N1 = NV < 16 ? NV : 16;
+        double first[N1];
+#pragma unroll
+        for (int j = 0; j < N1; ++j) first[j] = v[j];
+        const double s = wave_sum16<N1>(first);
+        if (lane < N1 && lane < cnt) wred[lane] = s;
+#pragma unroll
+        for (int j = 16; j < NV; ++j)
+            if (j < cnt) {
+                const double s2 = wave_sum(v[j]);
+                if (lane == 0) wred[j] = s2;
+            }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < cnt) {
+                const double s2 = wave_sum(v[j]);
+                if (lane == 0) wred[j] = s2;
+            }
+    }
+}
+
 template <int NV>
 __device__ void block_sum(const double (&acc)[NV], int cnt, double *out, double *red)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < cnt) {
-            const double s = wave_sum(acc[j]);
-            if (lane == 0) red[wid * NVP + j] = s;
-        }
+    const int wid = threadIdx.x >> 6;
+    wave_partials<NV>(acc, cnt, red + wid * NVP);
     __syncthreads();
     if (threadIdx.x < cnt) {
         double s = 0.0;
@@ -289,13 +314,8 @@ __device__ void block_reduce_partials(const double *part, int ps, int base, int 
 template <int NV>
 __device__ __forceinline__ void block_accumulate(const double (&v)[NV], int cnt, double *acc, double *red)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < cnt) {
-            const double s = wave_sum(v[j]);
-            if (lane == 0) red[wid * NVP + j] = s;
-        }
+    const int wid = threadIdx.x >> 6;
+    wave_partials<NV>(v, cnt, red + wid * NVP);
     __syncthreads();
     if (threadIdx.x < cnt) {
         double s = 0.0;

@@ -48,6 +48,38 @@ __device__ __forceinline__ double wave_sum(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Sums over the 64 lanes of up to 16 values at once (all lanes active).  The
+// values are transposed while they are reduced: at each of four DPP steps a
+// lane keeps half of its remaining values, adds its partner's copy of that
+// half and hands the other half over (partners: row mirror, half-row mirror,
+// lane ^ 3, lane ^ 1), so 8 + 4 + 2 + 1 moves leave lane i of every 16-lane
+// row with the row's sum of value i; two exchanges across rows (lane ^ 16,
+// lane ^ 32) finish the sums.  Returns, in every lane, the wave total of value
+// (lane & 15), 0 past NV.  Sixteen separate wave_sum calls would take 96
+// moves.  The order of the additions is fixed.
+template <int NV>
+__device__ __forceinline__ double wave_sum16(const double (&v)[NV])
+{
+    static_assert(NV <= 16, "at most 16 values");
+    const int i = threadIdx.x & 15;
+    auto val = [&](int k) { return k < NV ? v[k] : 0.0; };
+    double a[8], b[4], c[2];
+    const bool hA = i & 8, hB = i & 4, hC = i & 2, hD = i & 1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        a[k] = (hA ? val(k + 8) : val(k)) + dpp_mov<0x140, 0xf>(hA ? val(k) : val(k + 8));   // row_mirror
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        b[k] = (hB ? a[k + 4] : a[k]) + dpp_mov<0x141, 0xf>(hB ? a[k] : a[k + 4]);   // row_half_mirror
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        c[k] = (hC ? b[k + 2] : b[k]) + dpp_mov<0x1B, 0xf>(hC ? b[k] : b[k + 2]);   // quad_perm [3,2,1,0]
+    double d = (hD ? c[1] : c[0]) + dpp_mov<0xB1, 0xf>(hD ? c[0] : c[1]);       // quad_perm [1,0,3,2]
+    d += __shfl_xor(d, 16, 64);
+    d += __shfl_xor(d, 32, 64);
+    return d;
+}
+
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Staged-window traversal without integer division: a row of the window is
