@@ -343,7 +343,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     double *s_rho = taps + A.taps_lds;            // [ms] rho_j (one recurrence step from the exact rho_{j-1})
     double *s_alpha = s_rho + ms;                 // [ms] alpha_{j-1}
     double *s_beta = s_alpha + ms;                // [ms] beta_j
-    double *s_tol = s_beta + ms;                  // [ms] the systems' absolute tolerances
+    double *s_tol = s_beta + ms;                  // [ms] squared absolute tolerances (tol ||b||)^2
     int *ib = (int *)(s_tol + ms);
     Assign S0, S1;   // two named assignments (a runtime-indexed array would live in scratch)
     S0.act = ib; ib += ms;
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
     for (int k = threadIdx.x; k < A.nsys; k += NT) {
         S0.act[k] = k;
-        s_tol[k] = A.sys[k].tolabs;
+        s_tol[k] = A.sys[k].tolabs * A.sys[k].tolabs;   // compared with rho = ||r||^2
     }
     __syncthreads();
     build_assign(A, S0, A.nsys, A.G, &s_m[0], &s_ipb[0], s_tmp, false, &s_g);
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 else if (!(pw > 0.0)) st = -4;
             }
             if (st == 0) {
-                if (sqrt(rho) <= s_tol[s]) st = 1;
+                if (rho <= s_tol[s]) st = 1;
                 else if (it >= A.maxit) st = 2;
             }
             s_rho[s] = rho;

@@ -233,21 +233,37 @@ __device__ __forceinline__ void band_fix_x(const InstDev &I, const Geo &g, const
     const int nx = I.nx;
     const double *Rx = Lx + rr;
     const EndSpan sp = end_span(x0, I.tx, nx, r);
-    for (int it = threadIdx.x; it < g.H0 * sp.nc; it += NT) {
-        const int l = it / sp.nc, c = it - l * sp.nc;
-        const int j = c < sp.nl ? sp.la + c : sp.ra + (c - sp.nl);
-        const double *row = buf0 + l * g.P0 + g.hx - x0;   // row[i] = v at image column i
-        double s0 = 0.0, s1 = 0.0;
-        if (j < r) {
+    const int total = g.H0 * sp.nc;
+    // two items per thread per round, their loads in flight together (a 16-row
+    // tile at r = 7 has 44 x 7 items: one round instead of two)
+    for (int it0 = threadIdx.x; it0 < total; it0 += 2 * NT) {
+        double s[2];
+        int dst[2];
+        bool val[2];
 #pragma unroll
-            for (int i = 0; i < r; ++i) s0 = fma(Lx[j * r + i], row[i], s0);
-        }
-        if (j >= nx - r) {
-            const int p = j - (nx - r);
+        for (int h = 0; h < 2; ++h) {
+            const int it = it0 + h * NT;
+            val[h] = it < total;
+            const int itc = val[h] ? it : it0;
+            const int l = itc / sp.nc, c = itc - l * sp.nc;
+            const int j = c < sp.nl ? sp.la + c : sp.ra + (c - sp.nl);
+            const double *row = buf0 + l * g.P0 + g.hx - x0;   // row[i] = v at image column i
+            double s0 = 0.0, s1 = 0.0;
+            if (j < r) {
 #pragma unroll
-            for (int q = 0; q < r; ++q) s1 = fma(Rx[p * r + q], row[nx - r + q], s1);
+                for (int i = 0; i < r; ++i) s0 = fma(Lx[j * r + i], row[i], s0);
+            }
+            if (j >= nx - r) {
+                const int p = j - (nx - r);
+#pragma unroll
+                for (int q = 0; q < r; ++q) s1 = fma(Rx[p * r + q], row[nx - r + q], s1);
+            }
+            s[h] = s0 + s1;
+            dst[h] = l * g.P2 + (j - x0);
         }
-        buf1[l * g.P2 + (j - x0)] -= s0 + s1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (val[h]) buf1[dst[h]] -= s[h];
     }
 }
 
