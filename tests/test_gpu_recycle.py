@@ -148,6 +148,25 @@ def test_recycled_outer_loop_c1(ctx, mode):
     assert total > 0
 
 
+@pytest.mark.parametrize("mode", [rsr.SEQUENTIAL, rsr.BATCHED])
+def test_recycled_outer_loop_widest_local_space(ctx, mode):
+    # 6 Ritz vectors plus the corrections: q reaches 8, the widest compiled width
+    cfg = synth.config("C1")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    rp = irn.RecycleParams(p=cfg.p, q=8, n_ritz=6)
+    loop = irn.OuterLoop(ctx, cfg, "recycled", rp=rp, mode=mode)
+    loop.b[0] = to_dev(b)
+    for k in range(cfg.outer_steps):
+        print(f"widest local space: outer step k={k} mode={mode}", flush=True)
+        loop.step()
+        wh, wv = (to_host(t) for t in ctx.get_weights(0))
+        X = to_host(loop.X[0])
+        for l, g in enumerate(cfg.gammas):
+            rel = oracle.true_relres(pr.psf, wh, wv, g, b, X[l])
+            assert rel <= 1e-8, (k, l, rel)
+
+
 def test_recycled_solution_gate_tight_tolerance(ctx):
     cfg = synth.config("C1")
     pr = cfg.problems[0]
