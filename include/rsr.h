@@ -99,6 +99,20 @@ typedef struct {
     double gamma_JR;          /* shift defining the right group's Ritz block   */
     long ld_b;                /* column stride of b (0: all systems share b)   */
     long ld_x;                /* column stride of X                            */
+    /* Principal-space seeding (sequential mode, when the first system's instance
+     * has no recycle space yet): the first system's CG records its first
+     * seed_lanczos residuals and coefficients (CG-Lanczos); its solution and
+     * the seed_p - 1 Ritz vectors of the Lanczos tridiagonal with the smallest
+     * Ritz values become the principal space (through Algorithm 1, at most
+     * seed_p columns), and the remaining systems use
+     * the minimum-residual initial guess and seed_n_ritz Ritz vectors in their
+     * local spaces (Sec. 5.2, the initial principal space from the first solve).
+     * The library keeps seed_lanczos x ny*nx doubles of device memory for the
+     * recorded residuals.  Negative sizes, seed_n_ritz above 8 (the widest local
+     * space), or seeding in batched mode: RSR_E_ARG.  seed_lanczos = 0: off.   */
+    int seed_lanczos;
+    int seed_p;
+    int seed_n_ritz;
 } rsr_solve_desc;
 
 typedef struct {

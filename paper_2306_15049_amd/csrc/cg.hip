@@ -688,6 +688,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     q = Y.q;
                     alpha = s_alpha[s];
                     beta = s_beta[s];
+                    // Lanczos capture: alpha_{j-1}, beta_{j-1} and rho_j of step j = it
+                    if (Y.nlz > 0 && threadIdx.x == 0 && chunk == N.pre[a] / ipbn) {
+                        if (it >= 1 && it <= Y.nlz) {
+                            gp(Y.lzc)[it - 1] = alpha;
+                            gp(Y.lzc)[Y.nlz + it - 1] = beta;
+                        }
+                        if (it < Y.nlz) gp(Y.lzc)[2 * Y.nlz + it] = s_rho[s];
+                    }
                     if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
                     if (threadIdx.x >= q && threadIdx.x < QMAX) s_c[threadIdx.x] = 0.0;   // unused columns
                     if (q > 0 && s != s_zsys) {
@@ -779,6 +787,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         *d = ph;
                         if (ok[u] && own[u]) {
                             if (it > 0) rdst[gi[u]] = rj;
+                            if (it < Y.nlz) gp(Y.lz)[it * Y.ldw + gi[u]] = rj;   // Lanczos capture of r_j
                             pdst[gi[u]] = ph;
                             const int ii = (li - g.hy) * g.PE + (lj - g.hx);
                             pbuf[ii] = ph;

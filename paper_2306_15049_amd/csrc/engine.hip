@@ -126,6 +126,7 @@ struct rsr_ctx {
     DBuf d_rcC, d_rcQ;                 // recycle-space candidates and their orthonormal basis (kept: no
                                        // allocation, and no free that drains the device, per update)
     DBuf d_gprev;                      // previous shift's correction in sequential solves
+    DBuf d_lz, d_lzc, d_lzr;           // CG-Lanczos capture (residuals, coefficients) and its Ritz vectors
     // staging arena for launch descriptors and coefficients: pinned host and
     // device halves bump-allocated in step, reset whenever the stream is drained,
     // so that launches whose inputs come from the host need no synchronisation
@@ -473,6 +474,10 @@ struct SysHost {
     int iters = 0, restarts = 0, mvA = 0, mvE = 0, status = 0;
     double relres_init = 0.0, relres_true = 0.0;
     bool done = false;
+    // CG-Lanczos capture of the first launch (principal-space seeding)
+    double *lz = nullptr, *lzc = nullptr;
+    long nlz = 0;
+    int lz_its = 0;            // iterations of the captured launch
 };
 
 struct Opts {
@@ -521,6 +526,9 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         d.ldw = Y.n;
         for (int a = 0; a < Y.q; ++a)
             for (int b2 = 0; b2 < Y.q; ++b2) d.Ginv[a * QMAX + b2] = Y.Ginv[a * Y.q + b2];
+        d.lz = Y.lz;
+        d.lzc = Y.lzc;
+        d.nlz = Y.nlz;
     }
     SysDev *dsys = upload(c, c->d_sys, hd, s);
     c->d_partA.ensure(sizeof(double) * tiles * NVP);
@@ -680,6 +688,10 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     if (abort_h) fail(RSR_E_TIMEOUT, "persistent CG barrier timed out");
     for (int i = 0; i < m; ++i) {
         SysHost &Y = *sy[i];
+        if (Y.nlz > 0) {   // only the first launch of a system is captured
+            Y.lz_its = hi[i];
+            Y.nlz = 0;
+        }
         Y.iters += hi[i];
         Y.mvA += hi[i];
         Y.mvE += hi[i];
@@ -1160,7 +1172,7 @@ void rsr_destroy(rsr_ctx *c)
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
                     &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
-                    &c->d_gprev})
+                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr})
         b->release();
     if (c->ar_host) (void)hipHostFree(c->ar_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1283,109 +1295,159 @@ rsr_status rsr_apply(rsr_ctx *c, int ii, int op, double gamma, const double *v, 
     });
 }
 
+// Principal recycle space (Alg. 1, Sec. 5.2): see rsr_set_recycle_space.  Returns
+// the dimension kept.
+int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int ncols, int n_retain,
+                           double gamma_retain, int p_max, double cond_max, hipStream_t s)
+{
+    Instance &I = get_inst(c, ii);
+    if (ncols < 0 || n_retain < 0 || p_max < 0) fail(RSR_E_ARG, "negative sizes");
+    if (ncols > 0 && (!U_raw || ld < I.n)) fail(RSR_E_ARG, "U_raw null or ld < ny*nx");
+    if (!(cond_max > 1.0)) fail(RSR_E_ARG, "cond_max must exceed 1");
+    set_device(c);
+    const long n = I.n;
+    const int nr = std::min(n_retain, I.p);
+    const int m = nr + ncols;
+    if (m == 0 || p_max == 0) {
+        I.p = 0;
+        I.ae_valid = false;
+        return 0;
+    }
+    // candidate block C = [U W~(:, 1:nr), U_raw]
+    DBuf &Cb = c->d_rcC;
+    Cb.ensure(sizeof(double) * (size_t)m * n);
+    double *C = Cb.as<double>();
+    if (nr > 0) {
+        const int p = I.p;
+        std::vector<double> H((size_t)p * p), w, V;
+        for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + gamma_retain * I.Ehat[k];
+        sym_eig(p, H.data(), w, V);
+        std::vector<double> Wt((size_t)p * nr);
+        for (int j = 0; j < nr; ++j)
+            for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
+        combo(c, {ComboJob{I.d_U.as<double>(), n, p, nullptr, p, C, n, nr, 0.0, nullptr, 0, n}}, {Wt}, s);
+    }
+    for (int j = 0; j < ncols; ++j)
+        HIPCHK(hipMemcpyAsync(C + (size_t)(nr + j) * n, U_raw + (size_t)j * ld, sizeof(double) * n,
+                              hipMemcpyDeviceToDevice, s));
+    // Algorithm 1 through the Gram matrix: C^T C = V diag(sigma^2) V^T,
+    // keep sigma_1 / sigma_i < cond_max (and above the FP64 resolution of
+    // the Gram route), Q = C V_k diag(1/sigma_k); a second pass restores
+    // orthonormality to rounding level.
+    DBuf &Qb = c->d_rcQ;
+    Qb.ensure(sizeof(double) * (size_t)m * n);
+    double *Q = Qb.as<double>();
+    int keep = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double *X = pass == 0 ? C : Q;
+        const int mm = pass == 0 ? m : keep;
+        auto Gm = gram(c, {GramJob{X, n, mm, X, n, mm, n, nullptr, 0}}, s)[0];
+        std::vector<double> w, V;
+        sym_eig(mm, Gm.data(), w, V);
+        const double lmax = w.empty() ? 0.0 : w.back();
+        if (!(lmax > 0.0) || !std::isfinite(lmax)) fail(RSR_E_RANK, "recycle candidates are zero or non-finite");
+        std::vector<int> idx;
+        for (int k = mm - 1; k >= 0; --k) {
+            const double lam = w[k];
+            const bool ok = pass == 0 ? (lam > lmax / (cond_max * cond_max) && lam > lmax * 1e-14) : lam > 0.0;
+            if (ok) idx.push_back(k);
+        }
+        if (pass == 0 && (int)idx.size() > p_max) idx.resize(p_max);
+        keep = (int)idx.size();
+        if (keep == 0) fail(RSR_E_RANK, "recycle space empty after stabilisation");
+        std::vector<double> T((size_t)mm * keep);   // column-major mm x keep
+        for (int j = 0; j < keep; ++j) {
+            const double sc = 1.0 / std::sqrt(w[idx[j]]);
+            for (int i = 0; i < mm; ++i) T[(size_t)j * mm + i] = V[(size_t)i * mm + idx[j]] * sc;
+        }
+        if (pass == 0) {
+            combo(c, {ComboJob{C, n, mm, nullptr, mm, Q, n, keep, 0.0, nullptr, 0, n}}, {T}, s);
+        } else {
+            I.d_U.ensure(sizeof(double) * (size_t)keep * n);
+            combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {T}, s);
+        }
+    }
+    const int p = keep;
+    I.p = p;
+    // A U and E U (p applications each), then the small blocks
+    I.d_AE.ensure(sizeof(double) * (size_t)2 * p * n);
+    double *AU = I.d_AE.as<double>(), *EU = AU + (size_t)p * n;
+    apply_op(c, ii, 1.0, 0.0, I.d_U.as<double>(), n, AU, n, p, s);
+    apply_op(c, ii, 0.0, 1.0, I.d_U.as<double>(), n, EU, n, p, s);
+    auto blocks = gram(c,
+                       {GramJob{I.d_U.as<double>(), n, p, AU, n, p, n, nullptr, 0},
+                        GramJob{I.d_U.as<double>(), n, p, EU, n, p, n, nullptr, 0},
+                        GramJob{AU, n, p, AU, n, p, n, nullptr, 0}, GramJob{AU, n, p, EU, n, p, n, nullptr, 0},
+                        GramJob{EU, n, p, EU, n, p, n, nullptr, 0}},
+                       s);
+    auto sym = [p](std::vector<double> M) {
+        for (int i = 0; i < p; ++i)
+            for (int j = i + 1; j < p; ++j) {
+                const double v = 0.5 * (M[(size_t)i * p + j] + M[(size_t)j * p + i]);
+                M[(size_t)i * p + j] = M[(size_t)j * p + i] = v;
+            }
+        return M;
+    };
+    I.u_version += 1;
+    I.Ahat = sym(blocks[0]);
+    I.Ehat = sym(blocks[1]);
+    I.Gaa = sym(blocks[2]);
+    I.Gae = blocks[3];
+    I.Gee = sym(blocks[4]);
+    I.ae_valid = true;
+    return p;
+}
+
 rsr_status rsr_set_recycle_space(rsr_ctx *c, int ii, const double *U_raw, long ld, int ncols, int n_retain,
                                  double gamma_retain, int p_max, double cond_max, int *p_kept, void *stream)
 {
     return guard(c, [&] {
-        Instance &I = get_inst(c, ii);
-        if (ncols < 0 || n_retain < 0 || p_max < 0) fail(RSR_E_ARG, "negative sizes");
-        if (ncols > 0 && (!U_raw || ld < I.n)) fail(RSR_E_ARG, "U_raw null or ld < ny*nx");
-        if (!(cond_max > 1.0)) fail(RSR_E_ARG, "cond_max must exceed 1");
-        set_device(c);
-        hipStream_t s = S(stream);
-        const long n = I.n;
-        const int nr = std::min(n_retain, I.p);
-        const int m = nr + ncols;
         if (p_kept) *p_kept = 0;
-        if (m == 0 || p_max == 0) {
-            I.p = 0;
-            I.ae_valid = false;
-            return;
-        }
-        // candidate block C = [U W~(:, 1:nr), U_raw]
-        DBuf &Cb = c->d_rcC;
-        Cb.ensure(sizeof(double) * (size_t)m * n);
-        double *C = Cb.as<double>();
-        if (nr > 0) {
-            const int p = I.p;
-            std::vector<double> H((size_t)p * p), w, V;
-            for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + gamma_retain * I.Ehat[k];
-            sym_eig(p, H.data(), w, V);
-            std::vector<double> Wt((size_t)p * nr);
-            for (int j = 0; j < nr; ++j)
-                for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
-            combo(c, {ComboJob{I.d_U.as<double>(), n, p, nullptr, p, C, n, nr, 0.0, nullptr, 0, n}}, {Wt}, s);
-        }
-        for (int j = 0; j < ncols; ++j)
-            HIPCHK(hipMemcpyAsync(C + (size_t)(nr + j) * n, U_raw + (size_t)j * ld, sizeof(double) * n,
-                                  hipMemcpyDeviceToDevice, s));
-        // Algorithm 1 through the Gram matrix: C^T C = V diag(sigma^2) V^T,
-        // keep sigma_1 / sigma_i < cond_max (and above the FP64 resolution of
-        // the Gram route), Q = C V_k diag(1/sigma_k); a second pass restores
-        // orthonormality to rounding level.
-        DBuf &Qb = c->d_rcQ;
-        Qb.ensure(sizeof(double) * (size_t)m * n);
-        double *Q = Qb.as<double>();
-        int keep = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-            const double *X = pass == 0 ? C : Q;
-            const int mm = pass == 0 ? m : keep;
-            auto Gm = gram(c, {GramJob{X, n, mm, X, n, mm, n, nullptr, 0}}, s)[0];
-            std::vector<double> w, V;
-            sym_eig(mm, Gm.data(), w, V);
-            const double lmax = w.empty() ? 0.0 : w.back();
-            if (!(lmax > 0.0) || !std::isfinite(lmax)) fail(RSR_E_RANK, "recycle candidates are zero or non-finite");
-            std::vector<int> idx;
-            for (int k = mm - 1; k >= 0; --k) {
-                const double lam = w[k];
-                const bool ok = pass == 0 ? (lam > lmax / (cond_max * cond_max) && lam > lmax * 1e-14) : lam > 0.0;
-                if (ok) idx.push_back(k);
-            }
-            if (pass == 0 && (int)idx.size() > p_max) idx.resize(p_max);
-            keep = (int)idx.size();
-            if (keep == 0) fail(RSR_E_RANK, "recycle space empty after stabilisation");
-            std::vector<double> T((size_t)mm * keep);   // column-major mm x keep
-            for (int j = 0; j < keep; ++j) {
-                const double sc = 1.0 / std::sqrt(w[idx[j]]);
-                for (int i = 0; i < mm; ++i) T[(size_t)j * mm + i] = V[(size_t)i * mm + idx[j]] * sc;
-            }
-            if (pass == 0) {
-                combo(c, {ComboJob{C, n, mm, nullptr, mm, Q, n, keep, 0.0, nullptr, 0, n}}, {T}, s);
-            } else {
-                I.d_U.ensure(sizeof(double) * (size_t)keep * n);
-                combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {T}, s);
-            }
-        }
-        const int p = keep;
-        I.p = p;
-        // A U and E U (p applications each), then the small blocks
-        I.d_AE.ensure(sizeof(double) * (size_t)2 * p * n);
-        double *AU = I.d_AE.as<double>(), *EU = AU + (size_t)p * n;
-        apply_op(c, ii, 1.0, 0.0, I.d_U.as<double>(), n, AU, n, p, s);
-        apply_op(c, ii, 0.0, 1.0, I.d_U.as<double>(), n, EU, n, p, s);
-        auto blocks = gram(c,
-                           {GramJob{I.d_U.as<double>(), n, p, AU, n, p, n, nullptr, 0},
-                            GramJob{I.d_U.as<double>(), n, p, EU, n, p, n, nullptr, 0},
-                            GramJob{AU, n, p, AU, n, p, n, nullptr, 0}, GramJob{AU, n, p, EU, n, p, n, nullptr, 0},
-                            GramJob{EU, n, p, EU, n, p, n, nullptr, 0}},
-                           s);
-        auto sym = [p](std::vector<double> M) {
-            for (int i = 0; i < p; ++i)
-                for (int j = i + 1; j < p; ++j) {
-                    const double v = 0.5 * (M[(size_t)i * p + j] + M[(size_t)j * p + i]);
-                    M[(size_t)i * p + j] = M[(size_t)j * p + i] = v;
-                }
-            return M;
-        };
-        I.u_version += 1;
-        I.Ahat = sym(blocks[0]);
-        I.Ehat = sym(blocks[1]);
-        I.Gaa = sym(blocks[2]);
-        I.Gae = blocks[3];
-        I.Gee = sym(blocks[4]);
-        I.ae_valid = true;
+        const int p = set_recycle_space_impl(c, ii, U_raw, ld, ncols, n_retain, gamma_retain, p_max, cond_max,
+                                             S(stream));
         if (p_kept) *p_kept = p;
     });
+}
+
+// Principal space from the CG-Lanczos data of one solve (Sec. 5.2: the Ritz
+// vectors of the first system's Krylov space seed U).  With CG coefficients
+// alpha_j and beta_j = rho_{j+1}/rho_j, the residuals v_j = r_j / ||r_j|| satisfy
+// B V = V T + (residual) e_m^T, with T tridiagonal:
+//   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},   T_j,j+1 = -sqrt(beta_j)/alpha_j.
+// The seed_p - 1 eigenvectors of T with the smallest Ritz values give the Ritz
+// vectors V s; with the solve's solution x in front, Algorithm 1 turns them
+// into U (with AU, EU and the blocks).
+// Returns the principal dimension (0 if fewer than two steps were recorded).
+int seed_from_lanczos(rsr_ctx *c, const SysHost &Y, long nlz, int seed_p, hipStream_t s)
+{
+    const int m = (int)std::min<long>(nlz, (long)Y.lz_its - 1);   // steps with alpha and beta recorded
+    if (m < 2 || seed_p <= 0) return 0;
+    std::vector<double> co((size_t)3 * nlz);
+    HIPCHK(hipMemcpyAsync(co.data(), c->d_lzc.p, sizeof(double) * co.size(), hipMemcpyDeviceToHost, s));
+    sync(c, s);
+    const double *al = co.data(), *be = co.data() + nlz, *rho = co.data() + 2 * nlz;
+    std::vector<double> T((size_t)m * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        if (!(al[j] > 0.0) || !(rho[j] > 0.0)) return 0;
+        T[(size_t)j * m + j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+        if (j + 1 < m) T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] = -std::sqrt(be[j]) / al[j];
+    }
+    std::vector<double> w, V;
+    sym_eig(m, T.data(), w, V);
+    // candidates [x, Ritz vectors with the k smallest Ritz values]: the first
+    // solve's solution leads, as in the seeded space of Sec. 5.2
+    const int k = std::min(seed_p - 1, m);
+    c->d_lzr.ensure(sizeof(double) * (size_t)(k + 1) * Y.n);
+    double *cand = c->d_lzr.as<double>();
+    HIPCHK(hipMemcpyAsync(cand, Y.x, sizeof(double) * Y.n, hipMemcpyDeviceToDevice, s));
+    if (k > 0) {
+        std::vector<double> Q((size_t)m * k);   // column-major m x k: Ritz coefficients over the raw residuals
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < m; ++j) Q[(size_t)i * m + j] = V[(size_t)j * m + i] / std::sqrt(rho[j]);
+        combo(c, {ComboJob{c->d_lz.as<double>(), Y.n, m, nullptr, m, cand + Y.n, Y.n, k, 0.0, nullptr, 0, Y.n}},
+              {Q}, s);
+    }
+    return set_recycle_space_impl(c, Y.inst, cand, Y.n, k + 1, 0, 0.0, seed_p, 1e10, s);
 }
 
 rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X,
@@ -1399,6 +1461,9 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
         if (!(d->tol > 0.0)) fail(RSR_E_ARG, "tol must be positive");
         if (d->init < 0 || d->init > 3) fail(RSR_E_ARG, "unknown init");
         if (d->n_ritz < 0 || d->n_ritz > QMAX) fail(RSR_E_ARG, "n_ritz out of range");
+        if (d->seed_lanczos < 0 || d->seed_p < 0 || d->seed_n_ritz < 0 || d->seed_n_ritz > QMAX)
+            fail(RSR_E_ARG, "seed sizes out of range");
+        if (d->seed_lanczos > 0 && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "seeding needs sequential mode");
         if (d->mode != RSR_BATCHED && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "unknown mode");
         std::vector<SysHost> sys(m);
         for (int i = 0; i < m; ++i) {
@@ -1438,6 +1503,17 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
         } else {
             DBuf &gprev = c->d_gprev;
             const double *gp = nullptr;
+            // principal-space seeding from the first system's CG-Lanczos data
+            const bool seed = d->seed_lanczos > 0 && c->inst[sys[0].inst]->p == 0;
+            if (seed) {
+                const long nlz = d->seed_lanczos;
+                c->d_lz.ensure(sizeof(double) * (size_t)nlz * sys[0].n);
+                c->d_lzc.ensure(sizeof(double) * (size_t)3 * nlz);
+                HIPCHK(launch_fill(c->d_lzc.as<double>(), 0.0, 3 * nlz, s));
+                sys[0].lz = c->d_lz.as<double>();
+                sys[0].lzc = c->d_lzc.as<double>();
+                sys[0].nlz = nlz;
+            }
             for (int i = 0; i < m; ++i) {
                 std::vector<SysHost *> one{&sys[i]};
                 if (i > 0 && sys[i].inst != sys[i - 1].inst) gp = nullptr;
@@ -1445,6 +1521,11 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 {
                     StageTimer tsc(c, s, 7);
                     store_corrections(c, one, s);
+                }
+                if (seed && i == 0 && seed_from_lanczos(c, sys[0], d->seed_lanczos, d->seed_p, s) > 0) {
+                    // the remaining systems start from the seeded principal space
+                    o.init = RSR_INIT_MR;
+                    o.n_ritz = std::min(d->seed_n_ritz, QMAX);
                 }
                 if (o.use_prev_shift) {
                     Instance &I = *c->inst[sys[i].inst];

@@ -56,6 +56,11 @@ struct SysDev {
     const double *Z;   // [q][ldw] B W
     long ldw;
     double Ginv[QMAX * QMAX];   // pseudo-inverse of W^T Z (row-major q x q)
+    // optional Lanczos capture (nlz > 0): residuals r_j, j < nlz, into lz[j * ldw + i]
+    // and the coefficients alpha_j, beta_j, rho_j into lzc[0..nlz), [nlz..2 nlz), [2 nlz..3 nlz)
+    double *lz;
+    double *lzc;
+    long nlz;
 };
 
 struct CGArgs {

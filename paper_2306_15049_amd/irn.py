@@ -48,6 +48,9 @@ class RecycleParams:
     p: int
     q: int = 5
     n_ritz: int = 3
+    seed_lanczos: int = 0     # k = 0, sequential: CG-Lanczos steps of the first shift that seed U (0: off)
+    seed_p: int = 30          # Ritz vectors of those steps kept as the seeded U
+    seed_n_ritz: int = 3      # Ritz vectors in the local spaces of the shifts after the seed
     split_frac: float = 0.75
     beta: float = 1e-4
     cond_max: float = 1e10
@@ -112,10 +115,14 @@ class OuterLoop:
         jl = max(1, min(split, M)) - 1            # J_L = split (1-based)
         jr = max(split, M - 2)                    # J_R = M - 1 (1-based)
         seq = self.mode == rsr.SEQUENTIAL
+        seed = seq and self.k == 0 and self.rp.seed_lanczos > 0
         return rsr.SolveOptions(tol=self.tol, mode=self.mode, init=self.rp.init if self.k > 0 else rsr.INIT_ZERO,
                                 n_ritz=self.rp.n_ritz if self.k > 0 else 0, use_prev_k=self.k > 0,
                                 use_prev_shift=seq, split_I=split, gamma_JL=float(g[jl]),
-                                gamma_JR=float(g[min(jr, M - 1)]))
+                                gamma_JR=float(g[min(jr, M - 1)]),
+                                seed_lanczos=self.rp.seed_lanczos if seed else 0,
+                                seed_p=min(self.rp.seed_p, self.rp.p) if seed else 0,
+                                seed_n_ritz=self.rp.seed_n_ritz if seed else 0)
 
     def step(self) -> StepRecord:
         import torch
@@ -140,6 +147,8 @@ class OuterLoop:
             stats = [st]
         else:
             stats = self._solve_instances(o)
+        if self.k == 0 and self.method != "plain" and n_inst == 1:
+            p_dim = ctx.recycle_info(0)[0]   # a principal space seeded during the solve
         cg_ms, launches, items = ctx.last_timing()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3

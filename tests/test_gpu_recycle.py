@@ -8,6 +8,8 @@
 * The full recycled outer loop (weights -> principal space -> local spaces ->
   deflated CG) on the 32 x 32 workload, sequential and batched: residual gate
   at 1e-8 and solution gate at 1e-12 against dense Cholesky.
+* Seeding at k = 0 from the first solve's CG-Lanczos data: Range(U) holds the
+  oracle's smallest Ritz vectors and the first solution; a seeded outer loop.
 * Uneven instances with different PSFs in one batched launch.
 """
 import numpy as np
@@ -160,6 +162,63 @@ def test_recycled_outer_loop_widest_local_space(ctx, mode):
     for k in range(cfg.outer_steps):
         print(f"widest local space: outer step k={k} mode={mode}", flush=True)
         loop.step()
+        wh, wv = (to_host(t) for t in ctx.get_weights(0))
+        X = to_host(loop.X[0])
+        for l, g in enumerate(cfg.gammas):
+            rel = oracle.true_relres(pr.psf, wh, wv, g, b, X[l])
+            assert rel <= 1e-8, (k, l, rel)
+
+
+def test_lanczos_seed_spans_the_smallest_ritz_vectors(ctx):
+    # Seeding at k = 0 (Sec. 5.2): the first system's CG doubles as Lanczos, and U
+    # is built from its solution and the Ritz vectors with the k smallest Ritz
+    # values.  The oracle side forms the Lanczos basis from plain CG's normalised
+    # residuals and projects B onto it directly, without the alpha/beta recurrence
+    # the library uses.
+    import torch
+    n, m, k = 24, 14, 4
+    pr, b, wh, wv = _setup(ctx, n=n)
+    gam = [1e-3, 1e-2, 0.1]
+    o = rsr.SolveOptions(tol=1e-8, mode=rsr.SEQUENTIAL, use_prev_shift=True, seed_lanczos=m, seed_p=k + 1,
+                         seed_n_ritz=0)
+    X = torch.zeros((len(gam), n, n), dtype=torch.float64, device="cuda")
+    print(f"seeded solve n={n} m={m} k={k}", flush=True)
+    rc, st = ctx.solve(gam, to_dev(b), X, opts=o)
+    assert all(s["converged"] for s in st), st
+    p, Ahat, Ehat = ctx.recycle_info(0)
+    assert p == k + 1
+    U = to_host(ctx.recycle_basis(0)).reshape(p, -1).T
+    np.testing.assert_allclose(U.T @ U, np.eye(p), atol=1e-12)
+    _, ost, R, _ = oracle.cg(pr.psf, wh, wv, gam[0], b, tol=1e-8, record=m)
+    assert ost["iters"] > m and len(R) == m
+    Rf = R.reshape(m, -1)
+    V = Rf.T / np.linalg.norm(Rf, axis=1)
+    Bm = dense.dense_B(pr.psf, wh, wv, gam[0])
+    th, S = np.linalg.eigh(V.T @ Bm @ V)
+    assert th[k] - th[k - 1] > 1e-2 * th[-1]          # the k-dimensional space is well separated
+    Qy, _ = np.linalg.qr(V @ S[:, :k])
+    assert np.linalg.norm(Qy - U @ (U.T @ Qy), 2) < 1e-8    # sine of the largest principal angle
+    # the first solution is in Range(U): the exact one lies within the residual bound of it
+    xs = dense.cholesky_solve(Bm, b).ravel()
+    bound = 1e-8 * np.linalg.norm(b) / np.linalg.eigvalsh(Bm)[0]
+    assert np.linalg.norm(xs - U @ (U.T @ xs)) <= 1.01 * bound
+    for l, g in enumerate(gam):
+        assert oracle.true_relres(pr.psf, wh, wv, g, b, to_host(X[l])) <= 1e-8, l
+
+
+def test_seeded_outer_loop_c1(ctx):
+    # the outer loop with a seeded k = 0: every shift still meets the residual gate
+    cfg = synth.config("C1")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    rp = irn.RecycleParams(p=cfg.p, seed_lanczos=40, seed_p=10, seed_n_ritz=3)
+    loop = irn.OuterLoop(ctx, cfg, "recycled", rp=rp, mode=rsr.SEQUENTIAL)
+    loop.b[0] = to_dev(b)
+    for k in range(3):
+        print(f"seeded outer loop: step k={k}", flush=True)
+        rec = loop.step()
+        if k == 0:
+            assert 0 < rec.p <= 10
         wh, wv = (to_host(t) for t in ctx.get_weights(0))
         X = to_host(loop.X[0])
         for l, g in enumerate(cfg.gammas):
