@@ -329,10 +329,11 @@ constexpr int NBW = 6;   // window rows per thread whose loads are issued togeth
 constexpr int NBE = 2;   // interior pixels per thread whose local-basis loads are issued together
 
 // QT: widest local space of the launch (the loops over basis columns are
-// unrolled to QT).  Chunk partial layout: p.w, r.r, r.w, w.w, Z^T r[QT],
+// unrolled to QT).  LZ: the launch records CG-Lanczos data for the systems that
+// ask for it (a separate instantiation, so launches without it carry no trace).  Chunk partial layout: p.w, r.r, r.w, w.w, Z^T r[QT],
 // Z^T w[QT] in a slot of NVP values.
 // At most 256 registers per lane keeps two waves per SIMD.
-template <int QT>
+template <int QT, bool LZ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_cg(CGArgs A)
 {
     constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     alpha = s_alpha[s];
                     beta = s_beta[s];
                     // Lanczos capture: alpha_{j-1}, beta_{j-1} and rho_j of step j = it
-                    if (Y.nlz > 0 && threadIdx.x == 0 && chunk == N.pre[a] / ipbn) {
+                    if (LZ && Y.nlz > 0 && threadIdx.x == 0 && chunk == N.pre[a] / ipbn) {
                         if (it >= 1 && it <= Y.nlz) {
                             gp(Y.lzc)[it - 1] = alpha;
                             gp(Y.lzc)[Y.nlz + it - 1] = beta;
@@ -787,7 +788,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         *d = ph;
                         if (ok[u] && own[u]) {
                             if (it > 0) rdst[gi[u]] = rj;
-                            if (it < Y.nlz) gp(Y.lz)[it * Y.ldw + gi[u]] = rj;   // Lanczos capture of r_j
+                            if (LZ && it < Y.nlz) gp(Y.lz)[it * Y.ldw + gi[u]] = rj;   // Lanczos capture of r_j
                             pdst[gi[u]] = ph;
                             const int ii = (li - g.hy) * g.PE + (lj - g.hx);
                             pbuf[ii] = ph;
@@ -887,13 +888,15 @@ size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys)
 }
 
 // Compiled widths of the local space; a launch uses the smallest one >= its widest q.
-static const void *cg_kernel(int qt)
+// The capturing variant exists for q = 0 (a first solve) and the widest space.
+static const void *cg_kernel(int qt, bool lz)
 {
+    if (lz) return qt == 0 ? (const void *)k_cg<0, true> : (const void *)k_cg<QMAX, true>;
     switch (qt) {
-    case 0: return (const void *)k_cg<0>;
-    case 3: return (const void *)k_cg<3>;
-    case 5: return (const void *)k_cg<5>;
-    default: return (const void *)k_cg<QMAX>;
+    case 0: return (const void *)k_cg<0, false>;
+    case 3: return (const void *)k_cg<3, false>;
+    case 5: return (const void *)k_cg<5, false>;
+    default: return (const void *)k_cg<QMAX, false>;
     }
 }
 
@@ -902,17 +905,17 @@ int cg_width(int qmax)
     return qmax <= 0 ? 0 : qmax <= 3 ? 3 : qmax <= 5 ? 5 : QMAX;
 }
 
-int cg_max_blocks_per_cu(size_t lds, int qt)
+int cg_max_blocks_per_cu(size_t lds, int qt, bool lz)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cg_kernel(qt), NT, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cg_kernel(qt, lz), NT, lds) != hipSuccess) return 0;
     return nb;
 }
 
-hipError_t launch_cg(const CGArgs &a, int qt, int G, size_t lds, hipStream_t s)
+hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s)
 {
     void *args[] = {(void *)&a};
-    return hipLaunchCooperativeKernel(cg_kernel(qt), dim3(G), dim3(NT), args, (unsigned)lds, s);
+    return hipLaunchCooperativeKernel(cg_kernel(qt, lz), dim3(G), dim3(NT), args, (unsigned)lds, s);
 }
 
 }  // namespace rsr

@@ -547,9 +547,13 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     const int taps_lds = max_taps_lds(c);
     const size_t lds = cg_lds_bytes(tl, taps_lds, msys);
     int qmax = 0;
-    for (auto *Y : sy) qmax = std::max(qmax, Y->q);
-    const int qt = cg_width(qmax);
-    int bpc = cg_max_blocks_per_cu(lds, qt);
+    bool lz = false;   // some system records CG-Lanczos data in this launch
+    for (auto *Y : sy) {
+        qmax = std::max(qmax, Y->q);
+        lz = lz || Y->nlz > 0;
+    }
+    const int qt = lz && qmax > 0 ? QMAX : cg_width(qmax);
+    int bpc = cg_max_blocks_per_cu(lds, qt, lz);
     if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
     int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
     if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
@@ -587,7 +591,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         a.stamps = (unsigned long long *)c->d_dbg.p;
     }
     HIPCHK(hipEventRecord(c->ev0, s));
-    HIPCHK(launch_cg(a, qt, G, lds, s));
+    HIPCHK(launch_cg(a, qt, lz, G, lds, s));
     HIPCHK(hipEventRecord(c->ev1, s));
     std::vector<int> hi(2 * m + 8);
     std::vector<double> hr(2 * m);   // final r.r, then the pending step alpha

@@ -96,8 +96,8 @@ size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys);
 constexpr int BAR_GROUPS = 8;                          // barrier groups (one per XCD when G % 8 == 0)
 constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
 int cg_width(int qmax);                           // compiled local-space width for a widest q
-hipError_t launch_cg(const CGArgs &a, int qt, int G, size_t lds, hipStream_t s);
-int cg_max_blocks_per_cu(size_t lds, int qt);
+hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s);
+int cg_max_blocks_per_cu(size_t lds, int qt, bool lz);
 
 struct ApplyJob {              // y = cA K^T K v + cE E v   (or K / K^T alone)
     int inst;
