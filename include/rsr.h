@@ -148,6 +148,31 @@ rsr_status rsr_update_weights(rsr_ctx *ctx, int inst, const double *w_h, const d
 rsr_status rsr_weights_from_image(rsr_ctx *ctx, int inst, const double *x, double beta,
                                   void *stream);
 
+/* The edge weights of Sec. 2.1, applied to the instance's current weights.
+ * With D_{k-1} = W^{1/2} per difference and q = D_{k-1} L x (x: device
+ * [ny*nx], L the forward differences), w = 1 - (|q| / max|q|)^p per
+ * difference and D_k = diag(w) D_{k-1}; W is replaced by D_k^2.  Starting from
+ * unit weights (after rsr_set_operators) the first call gives D_1 = diag(w).
+ * The difference with the largest |q| gets weight 0; if x is constant the
+ * weights are unchanged.  p > 0 (the paper leaves it open).  Invalidates the
+ * cached A U / E U products like rsr_update_weights.  Bad p or null x:
+ * RSR_E_ARG.                                                                 */
+rsr_status rsr_weights_edge_rule(rsr_ctx *ctx, int inst, const double *x, double p, void *stream);
+
+/* The L-curve of a shift set (Sec. 2.1, Sec. 2.2): for each system l of m,
+ *   rho[l] = ||K x_l - d||_2  and  eta[l] = ||D_k L x_l||_2 = (x_l^T E_k x_l)^{1/2}
+ * with the instance's current weights.  X: device, system l at X + l*ld_x
+ * (ld_x ignored if m = 1); d: device [ny*nx] data; gammas: host [m], positive
+ * and strictly increasing (gamma = lambda^2).  rho, eta: host [m] outputs;
+ * kappa: host [m] or NULL, the curvature at each interior point (NaN at the
+ * ends).  The curvature is that of (log rho, log eta) as a function of
+ * log lambda, from three-point finite differences on the uneven grid, signed
+ * so that the corner is positive; *corner is the interior index with the
+ * largest curvature (the L-curve choice of the shift), -1 if m < 3.
+ * Synchronises the stream.  Bad sizes or gammas: RSR_E_ARG.                  */
+rsr_status rsr_lcurve(rsr_ctx *ctx, int inst, int m, const double *gammas, const double *X, long ld_x,
+                      const double *d, double *rho, double *eta, double *kappa, int *corner, void *stream);
+
 /* Copy the instance's current weights to device buffers w_h, w_v [ny*nx].  */
 rsr_status rsr_get_weights(rsr_ctx *ctx, int inst, double *w_h, double *w_v, void *stream);
 

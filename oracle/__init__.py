@@ -9,7 +9,9 @@ method's arithmetic.
 
 ``oracle.c`` holds the operators and plain CG as direct loops (built into
 ``liboracle.so`` with gcc); ``dense.py`` holds the dense/closed-form checks
-and the recycling steps (Sections 4-5) written with NumPy/SciPy primitives.
+and the recycling steps (Sections 4-5) written with NumPy/SciPy primitives;
+``outer.py`` holds the outer-iteration steps of Section 2.1 (edge weights,
+L-curve corner, stopping rule).
 """
 from __future__ import annotations
 

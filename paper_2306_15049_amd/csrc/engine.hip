@@ -127,6 +127,7 @@ struct rsr_ctx {
                                        // allocation, and no free that drains the device, per update)
     DBuf d_gprev;                      // previous shift's correction in sequential solves
     DBuf d_lz, d_lzc, d_lzr;           // CG-Lanczos capture (residuals, coefficients) and its Ritz vectors
+    DBuf d_aux;                        // workgroup partials of the edge-weight and L-curve reductions
     // staging arena for launch descriptors and coefficients: pinned host and
     // device halves bump-allocated in step, reset whenever the stream is drained,
     // so that launches whose inputs come from the host need no synchronisation
@@ -1176,7 +1177,7 @@ void rsr_destroy(rsr_ctx *c)
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
                     &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
-                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr})
+                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux})
         b->release();
     if (c->ar_host) (void)hipHostFree(c->ar_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1258,6 +1259,84 @@ rsr_status rsr_weights_from_image(rsr_ctx *c, int ii, const double *x, double be
         set_device(c);
         HIPCHK(launch_weights(x, beta, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny, I.nx, S(stream)));
         I.ae_valid = false;
+    });
+}
+
+rsr_status rsr_weights_edge_rule(rsr_ctx *c, int ii, const double *x, double p, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (!x) fail(RSR_E_ARG, "null image");
+        if (!(p > 0.0) || !std::isfinite(p)) fail(RSR_E_ARG, "exponent p must be positive");
+        set_device(c);
+        c->d_aux.ensure(sizeof(double) * edge_rule_parts());
+        HIPCHK(launch_edge_rule(x, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny, I.nx, p, c->d_aux.as<double>(),
+                                S(stream)));
+        I.ae_valid = false;
+    });
+}
+
+// Corner of the discrete L-curve (Sec. 2.1): the interior point of largest
+// signed curvature of (u, v) = (log rho, log eta) as functions of
+// t = log lambda = (log gamma) / 2.  First and second derivatives are the
+// three-point finite differences on the (possibly uneven) t grid; the curvature
+// is (u' v'' - u'' v') / (u'^2 + v'^2)^(3/2), positive where the curve turns
+// from falling steeply (small lambda) to running flat (large lambda).
+// Returns -1 when fewer than three points or no finite curvature exist.
+static int lcurve_corner(int m, const double *gam, const double *rho, const double *eta, double *kappa)
+{
+    int best = -1;
+    double kb = -INFINITY;
+    for (int i = 0; i < m; ++i) {
+        if (kappa) kappa[i] = NAN;
+        if (i == 0 || i == m - 1) continue;
+        const double t0 = 0.5 * std::log(gam[i - 1]), t1 = 0.5 * std::log(gam[i]), t2 = 0.5 * std::log(gam[i + 1]);
+        const double hm = t1 - t0, hp = t2 - t1, den = hm * hp * (hm + hp);
+        const double u0 = std::log(rho[i - 1]), u1 = std::log(rho[i]), u2 = std::log(rho[i + 1]);
+        const double v0 = std::log(eta[i - 1]), v1 = std::log(eta[i]), v2 = std::log(eta[i + 1]);
+        const double du = (hm * hm * u2 - hp * hp * u0 - (hm * hm - hp * hp) * u1) / den;
+        const double dv = (hm * hm * v2 - hp * hp * v0 - (hm * hm - hp * hp) * v1) / den;
+        const double ddu = 2.0 * (hm * u2 - (hm + hp) * u1 + hp * u0) / den;
+        const double ddv = 2.0 * (hm * v2 - (hm + hp) * v1 + hp * v0) / den;
+        const double k = (du * ddv - ddu * dv) / std::pow(du * du + dv * dv, 1.5);
+        if (kappa) kappa[i] = k;
+        if (std::isfinite(k) && k > kb) {
+            kb = k;
+            best = i;
+        }
+    }
+    return best;
+}
+
+rsr_status rsr_lcurve(rsr_ctx *c, int ii, int m, const double *gammas, const double *X, long ld_x, const double *d,
+                      double *rho, double *eta, double *kappa, int *corner, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (m <= 0 || !gammas || !X || !d || !rho || !eta || !corner) fail(RSR_E_ARG, "null argument or m <= 0");
+        if (m > 1 && ld_x < I.n) fail(RSR_E_ARG, "ld_x smaller than ny*nx");
+        for (int i = 0; i < m; ++i) {
+            if (!(gammas[i] > 0.0) || !std::isfinite(gammas[i])) fail(RSR_E_ARG, "gamma must be positive");
+            if (i > 0 && !(gammas[i] > gammas[i - 1])) fail(RSR_E_ARG, "gammas must increase");
+        }
+        set_device(c);
+        hipStream_t s = S(stream);
+        const int nb = lcurve_parts(I.n);
+        c->d_aux.ensure(sizeof(double) * 2 * (size_t)m * nb);
+        HIPCHK(launch_lcurve(c->d_inst.as<InstDev>(), ii, I.n, m, X, m > 1 ? ld_x : I.n, d, c->d_aux.as<double>(), s));
+        std::vector<double> h((size_t)2 * m * nb);
+        HIPCHK(hipMemcpyAsync(h.data(), c->d_aux.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        sync(c, s);
+        for (int i = 0; i < m; ++i) {
+            double sr = 0.0, se = 0.0;
+            for (int k = 0; k < nb; ++k) {
+                sr += h[2 * ((size_t)i * nb + k)];
+                se += h[2 * ((size_t)i * nb + k) + 1];
+            }
+            rho[i] = std::sqrt(sr);
+            eta[i] = std::sqrt(se);
+        }
+        *corner = lcurve_corner(m, gammas, rho, eta, kappa);
     });
 }
 

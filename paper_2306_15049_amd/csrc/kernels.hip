@@ -182,6 +182,149 @@ hipError_t launch_fill(double *p, double v, long n, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------- edge weights of Sec. 2.1 --
+// With D_{k-1} = W_{k-1}^{1/2} per difference and q = D_{k-1} L x, the rule is
+// w = 1 - (|q| / max|q|)^p and D_k = diag(w) D_{k-1}, so W_k = w^2 W_{k-1}.
+// Stage 1 writes one maximum of |q| per workgroup; stage 2 has every
+// workgroup fold those maxima itself and then rescales its weights in place.
+constexpr int EDGE_BLOCKS = 256;   // stage-1 workgroups (grid-stride)
+
+__device__ inline double block_max(double v, double *sm)
+{
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double r = sm[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(NT) void k_edge_max(const double *__restrict__ x, const double *__restrict__ wh,
+                                                 const double *__restrict__ wv, int ny, int nx,
+                                                 double *__restrict__ part)
+{
+    __shared__ double sm[NT];
+    const long n = (long)ny * nx;
+    double m = 0.0;
+    for (long gi = blockIdx.x * (long)NT + threadIdx.x; gi < n; gi += (long)gridDim.x * NT) {
+        const int i = gi / nx, j = gi % nx;
+        const double xc = x[gi];
+        if (j < nx - 1) m = fmax(m, sqrt(wh[gi]) * fabs(x[gi + 1] - xc));
+        if (i < ny - 1) m = fmax(m, sqrt(wv[gi]) * fabs(x[gi + nx] - xc));
+    }
+    m = block_max(m, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__device__ inline double edge_factor(double q, double qmax, double p)
+{
+    // q = qmax gives 0; a flat image (qmax = 0) leaves the weights unchanged
+    if (!(qmax > 0.0)) return 1.0;
+    const double w = 1.0 - pow(q / qmax, p);
+    return w * w;
+}
+
+__global__ __launch_bounds__(NT) void k_edge_rule(const double *__restrict__ x, double *__restrict__ wh,
+                                                  double *__restrict__ wv, int ny, int nx,
+                                                  const double *__restrict__ part, int npart, double p)
+{
+    __shared__ double sm[NT];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < npart; k += NT) m = fmax(m, part[k]);
+    const double qmax = block_max(m, sm);
+    const long n = (long)ny * nx;
+    for (long gi = blockIdx.x * (long)NT + threadIdx.x; gi < n; gi += (long)gridDim.x * NT) {
+        const int i = gi / nx, j = gi % nx;
+        const double xc = x[gi];
+        if (j < nx - 1) {
+            const double W = wh[gi];
+            wh[gi] = edge_factor(sqrt(W) * fabs(x[gi + 1] - xc), qmax, p) * W;
+        } else {
+            wh[gi] = 0.0;
+        }
+        if (i < ny - 1) {
+            const double W = wv[gi];
+            wv[gi] = edge_factor(sqrt(W) * fabs(x[gi + nx] - xc), qmax, p) * W;
+        } else {
+            wv[gi] = 0.0;
+        }
+    }
+}
+
+int edge_rule_parts() { return EDGE_BLOCKS; }
+
+hipError_t launch_edge_rule(const double *x, double *wh, double *wv, int ny, int nx, double p, double *part,
+                            hipStream_t s)
+{
+    const long n = (long)ny * nx;
+    const int g1 = std::min(EDGE_BLOCKS, grid_for(n));
+    hipLaunchKernelGGL(k_edge_max, dim3(g1), dim3(NT), 0, s, x, wh, wv, ny, nx, part);
+    hipLaunchKernelGGL(k_edge_rule, dim3(grid_for(n)), dim3(NT), 0, s, x, wh, wv, ny, nx, part, g1, p);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ L-curve coordinates --
+// For system y (blockIdx.y): per-workgroup partial sums of (K x - d)^2 and of
+// the weighted squared differences sum_e W_e (L x)_e^2 = x^T E x.  K x is the
+// direct zero-boundary convolution (setup-grade, straight from global memory).
+__global__ __launch_bounds__(NT) void k_lcurve(const InstDev *__restrict__ insts, int ii,
+                                               const double *__restrict__ X, long ld_x,
+                                               const double *__restrict__ d, double *__restrict__ part)
+{
+    __shared__ double sr[NT], se[NT];
+    const InstDev I = insts[ii];
+    const double *__restrict__ x = X + blockIdx.y * ld_x;
+    const long n = (long)I.ny * I.nx;
+    const int cy = I.sy / 2, cx = I.sx / 2;
+    double ar = 0.0, ae = 0.0;
+    for (long gi = blockIdx.x * (long)NT + threadIdx.x; gi < n; gi += (long)gridDim.x * NT) {
+        const int i = gi / I.nx, j = gi % I.nx;
+        double kx = 0.0;
+        for (int a = 0; a < I.sy; ++a) {
+            const int yi = i + cy - a;
+            if (yi < 0 || yi >= I.ny) continue;
+            for (int c = 0; c < I.sx; ++c) {
+                const int xj = j + cx - c;
+                if (xj < 0 || xj >= I.nx) continue;
+                const double h = I.sep ? I.fy[a] * I.fx[c] : I.psf[a * I.sx + c];
+                kx = fma(h, x[(long)yi * I.nx + xj], kx);
+            }
+        }
+        const double r = kx - d[gi];
+        ar = fma(r, r, ar);
+        const double xc = x[gi];
+        if (j < I.nx - 1) { const double t = x[gi + 1] - xc; ae = fma(I.wh[gi] * t, t, ae); }
+        if (i < I.ny - 1) { const double t = x[gi + I.nx] - xc; ae = fma(I.wv[gi] * t, t, ae); }
+    }
+    sr[threadIdx.x] = ar;
+    se[threadIdx.x] = ae;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sr[threadIdx.x] += sr[threadIdx.x + w];
+            se[threadIdx.x] += se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *o = part + 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+        o[0] = sr[0];
+        o[1] = se[0];
+    }
+}
+
+int lcurve_parts(long n) { return std::min(256, grid_for(n)); }
+
+hipError_t launch_lcurve(const InstDev *inst_dev, int ii, long n, int m, const double *X, long ld_x,
+                         const double *d, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lcurve, dim3(lcurve_parts(n), m), dim3(NT), 0, s, inst_dev, ii, X, ld_x, d, part);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------ tall-skinny products --
 // C = X^T Y for n x a and n x c panels.  Grid: (row chunks, output tiles of
 // 16 x 16, jobs).  Each workgroup stages 64-row slabs of 16 X columns and 16 Y

@@ -41,6 +41,7 @@ class StepRecord:
     cg_kernel_ms: float = 0.0
     cg_items: int = 0
     cg_launches: int = 0
+    l_star: int = -1          # shift index whose solution drives the next weights
 
 
 @dataclass
@@ -74,8 +75,15 @@ class OuterLoop:
 
     def __init__(self, ctx: rsr.Context, cfg: synth.Config, method: str, rp: Optional[RecycleParams] = None,
                  tol: Optional[float] = None, tiles: Optional[Dict[int, tuple]] = None,
-                 mode: Optional[int] = None):
+                 mode: Optional[int] = None, weight_rule: str = "irn", edge_p: float = 2.0,
+                 lcurve: bool = False, stop_repeats: int = 3):
+        """weight_rule: "irn" (W = ((D x)^2 + beta)^(-1/2)) or "edge" (the cumulative edge
+        rule of Sec. 2.1 with exponent edge_p).  lcurve: choose the shift that drives the
+        next weights at the L-curve corner after every step; otherwise the middle shift.
+        The loop reports `stopped` once that choice has repeated stop_repeats times."""
         import torch
+        if weight_rule not in ("irn", "edge"):
+            raise ValueError("weight_rule must be 'irn' or 'edge'")
         self.ctx = ctx
         self.cfg = cfg
         self.method = method
@@ -88,13 +96,29 @@ class OuterLoop:
         if tiles:
             for i, t in tiles.items():
                 ctx.set_tile(i, *t)
-        self.b = []
+        self.b, self.d = [], []
         for i, pr in enumerate(cfg.problems):
-            _, b = rhs_on_device(ctx, i, pr)
+            d, b = rhs_on_device(ctx, i, pr)
             self.b.append(b)
+            self.d.append(d)
         self.X = [torch.zeros((self.M, p.ny, p.nx), dtype=torch.float64, device="cuda") for p in cfg.problems]
         self.k = 0
-        self.l_star = int(math.ceil(self.M / 2)) - 1
+        self.weight_rule = weight_rule
+        self.edge_p = float(edge_p)
+        self.lcurve = lcurve
+        self.stop_repeats = stop_repeats
+        self.l_stars = [int(math.ceil(self.M / 2)) - 1] * len(cfg.problems)
+        self.l_history: List[tuple] = []
+
+    @property
+    def l_star(self) -> int:
+        return self.l_stars[0]
+
+    @property
+    def stopped(self) -> bool:
+        """The outer stopping rule: the same choice for stop_repeats consecutive steps."""
+        h = self.l_history
+        return len(h) >= self.stop_repeats and len(set(h[-self.stop_repeats:])) == 1
 
     def reset(self):
         for i in range(len(self.cfg.problems)):
@@ -105,6 +129,8 @@ class OuterLoop:
         for i, t in enumerate(tiles):
             self.ctx.set_tile(i, *t)
         self.k = 0
+        self.l_stars = [int(math.ceil(self.M / 2)) - 1] * len(self.cfg.problems)
+        self.l_history = []
 
     def _opts(self) -> rsr.SolveOptions:
         M = self.M
@@ -134,7 +160,10 @@ class OuterLoop:
         p_dim = 0
         if self.k > 0:
             for i in range(n_inst):
-                ctx.weights_from_image(i, self.X[i][self.l_star], self.rp.beta)
+                if self.weight_rule == "edge":
+                    ctx.weights_edge_rule(i, self.X[i][self.l_stars[i]], self.edge_p)
+                else:
+                    ctx.weights_from_image(i, self.X[i][self.l_stars[i]], self.rp.beta)
                 if self.method != "plain":
                     n_retain = max(0, self.rp.p - self.M)
                     p_dim = ctx.set_recycle_space(i, self.X[i], n_retain=n_retain,
@@ -150,6 +179,12 @@ class OuterLoop:
         if self.k == 0 and self.method != "plain" and n_inst == 1:
             p_dim = ctx.recycle_info(0)[0]   # a principal space seeded during the solve
         cg_ms, launches, items = ctx.last_timing()
+        if self.lcurve:
+            for i in range(n_inst):
+                c = ctx.lcurve(self.cfg.gammas, self.X[i], self.d[i], inst=i)[3]
+                if c >= 0:
+                    self.l_stars[i] = c
+            self.l_history.append(tuple(self.l_stars))
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3
         a1, e1 = ctx.counters()
@@ -157,7 +192,8 @@ class OuterLoop:
             iters += [s["iters"] for s in st]
             rel += [s["relres_true"] for s in st]
             rel0 += [s["relres_init"] for s in st]
-        rec = StepRecord(self.k, wall, a1 - a0, e1 - e0, iters, rel, rel0, p_dim, cg_ms, items, launches)
+        rec = StepRecord(self.k, wall, a1 - a0, e1 - e0, iters, rel, rel0, p_dim, cg_ms, items, launches,
+                         self.l_stars[0])
         self.k += 1
         return rec
 

@@ -26,7 +26,7 @@ EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_se
            "rsr_update_weights", "rsr_weights_from_image", "rsr_get_weights", "rsr_apply",
            "rsr_set_recycle_space", "rsr_solve_shift_set", "rsr_adjoint", "rsr_autotune", "rsr_get_tile",
            "rsr_set_tile", "rsr_get_recycle_info", "rsr_get_recycle_basis", "rsr_get_counters",
-           "rsr_last_solve_timing"]
+           "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve"]
 
 
 class RsrError(RuntimeError):
@@ -98,6 +98,8 @@ def load():
     L.rsr_get_recycle_basis.argtypes = [P, I, P, L_, P]
     L.rsr_get_counters.argtypes = [P, ctypes.POINTER(L_), ctypes.POINTER(L_)]
     L.rsr_last_solve_timing.argtypes = [P, pD, pI, ctypes.POINTER(L_)]
+    L.rsr_weights_edge_rule.argtypes = [P, I, P, D, P]
+    L.rsr_lcurve.argtypes = [P, I, I, pD, P, L_, P, pD, pD, pD, pI, P]
     for name in EXPORTS:
         if name not in ("rsr_destroy", "rsr_last_error", "rsr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -180,6 +182,22 @@ class Context:
 
     def weights_from_image(self, inst: int, x, beta: float = 1e-4):
         self._check(self.lib.rsr_weights_from_image(self.h, inst, _ptr(x), float(beta), _stream()))
+
+    def weights_edge_rule(self, inst: int, x, p: float = 2.0):
+        """W <- w^2 W with w = 1 - (|q|/max|q|)^p, q = W^(1/2) L x (the edge rule of Sec. 2.1)."""
+        self._check(self.lib.rsr_weights_edge_rule(self.h, inst, _ptr(x), float(p), _stream()))
+
+    def lcurve(self, gammas: Sequence[float], X, d, inst: int = 0):
+        """L-curve of the solutions X [m, ny, nx] against data d: (rho, eta, kappa, corner)."""
+        m = len(gammas)
+        g = np.ascontiguousarray(gammas, dtype=np.float64)
+        rho, eta, kap = np.zeros(m), np.zeros(m), np.zeros(m)
+        corner = ctypes.c_int(-1)
+        pd = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.rsr_lcurve(self.h, inst, m, g.ctypes.data_as(pd), _ptr(X), int(X[0].numel()), _ptr(d),
+                                        rho.ctypes.data_as(pd), eta.ctypes.data_as(pd), kap.ctypes.data_as(pd),
+                                        ctypes.byref(corner), _stream()))
+        return rho, eta, kap, corner.value
 
     def get_weights(self, inst: int):
         import torch

@@ -1,0 +1,136 @@
+"""GPU parity of the outer-iteration steps of Section 2.1 against the oracle.
+
+* rsr_weights_edge_rule: the edge weights w = 1 - (|q| / max|q|)^p with
+  D_k = diag(w) D_{k-1}, on ragged shapes, several exponents, from random
+  weights, and twice in a row (cumulative), element by element.
+* rsr_lcurve: rho = ||K x - d||, eta = ||D_k L x||, the curvature of the
+  log-log curve and its corner, against the oracle on solutions of a small
+  problem, and on the 256 x 256 workload's sizes.
+* The outer loop with the L-curve choice of the shift and the edge rule: the
+  residual gate at every step and the weights against the oracle's rule.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense, outer
+from paper_2306_15049_amd import irn, rsr, synth
+from conftest import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("shape,p", [((37, 29), 2.0), ((16, 64), 1.0), ((65, 33), 3.5), ((2, 40), 2.0)])
+def test_edge_rule_matches_oracle(ctx, shape, p):
+    ny, nx = shape
+    rng = np.random.default_rng(ny * 100 + nx)
+    ctx.set_operators([shape], [synth.gaussian_psf(1.0, 5)])
+    wh = rng.uniform(0.2, 1.0, shape)
+    wv = rng.uniform(0.2, 1.0, shape)
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    wh[:, -1] = 0.0
+    wv[-1, :] = 0.0
+    for step in range(2):
+        x = rng.uniform(0, 1, shape)
+        print(f"edge rule shape={shape} p={p} step={step}", flush=True)
+        ctx.weights_edge_rule(0, to_dev(x), p)
+        wh, wv = outer.edge_rule(x, wh, wv, p)
+        gh, gv = (to_host(t) for t in ctx.get_weights(0))
+        np.testing.assert_allclose(gh, wh, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(gv, wv, rtol=1e-13, atol=1e-15)
+        assert min(gh.min(), gv.min()) == 0.0 and gh.max() <= 1.0
+
+
+def test_edge_rule_flat_image_and_bad_exponent(ctx):
+    ctx.set_operators([(12, 10)], [synth.gaussian_psf(1.0, 5)])
+    w0 = [to_host(t) for t in ctx.get_weights(0)]
+    ctx.weights_edge_rule(0, to_dev(np.full((12, 10), 0.7)), 2.0)
+    w1 = [to_host(t) for t in ctx.get_weights(0)]
+    np.testing.assert_array_equal(w1[0], w0[0])
+    np.testing.assert_array_equal(w1[1], w0[1])
+    with pytest.raises(rsr.RsrError):
+        ctx.weights_edge_rule(0, to_dev(np.zeros((12, 10))), 0.0)
+
+
+def _solutions(pr, wh, wv, gammas):
+    Am = dense.dense_A(pr.psf, pr.ny, pr.nx)
+    Em = dense.dense_E(wh, wv)
+    _, b = oracle.rhs(pr)
+    return np.stack([dense.cholesky_solve(Am + g * Em, b).reshape(pr.ny, pr.nx) for g in gammas])
+
+
+def test_lcurve_matches_oracle_on_exact_solutions(ctx):
+    pr = synth.make_problem(17, 20, 18, 1.5, 7, 3)
+    d, _ = oracle.rhs(pr)
+    gammas = np.logspace(-6, 1, 12)
+    wh, wv = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    X = _solutions(pr, wh, wv, gammas)
+    ctx.set_operators([(pr.ny, pr.nx)], [pr.psf])
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    print("lcurve 20x18, 12 shifts", flush=True)
+    rho, eta, kap, corner = ctx.lcurve(gammas, to_dev(X), to_dev(d))
+    rho_o, eta_o = outer.lcurve_points(pr.psf, wh, wv, X, d)
+    np.testing.assert_allclose(rho, rho_o, rtol=1e-12)
+    np.testing.assert_allclose(eta, eta_o, rtol=1e-12)
+    kap_o = outer.lcurve_curvature(gammas, rho_o, eta_o)
+    assert np.isnan(kap[0]) and np.isnan(kap[-1])
+    np.testing.assert_allclose(kap[1:-1], kap_o[1:-1], rtol=1e-7, atol=1e-9 * np.nanmax(np.abs(kap_o)))
+    c_o = outer.lcurve_corner(gammas, rho_o, eta_o)
+    ks = np.sort(kap_o[1:-1])
+    assert ks[-1] - ks[-2] > 1e-6 * abs(ks[-1])   # the corner is unambiguous
+    assert corner == c_o
+    # rho rises and eta falls with the shift (Tikhonov monotonicity)
+    assert (np.diff(rho) > 0).all() and (np.diff(eta) < 0).all()
+
+
+def test_lcurve_full_size_and_argument_checks(ctx):
+    cfg = synth.config("C2")
+    pr = cfg.problems[0]
+    d, _ = oracle.rhs(pr)
+    rng = np.random.default_rng(8)
+    X = np.stack([pr.x_true + s * rng.standard_normal(pr.x_true.shape) for s in (0.0, 0.01, 0.1)])
+    ctx.set_operators([(pr.ny, pr.nx)], [pr.psf])
+    wh, wv = oracle.weights(pr.x_true)
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    gammas = [1e-3, 1e-2, 1e-1]
+    print("lcurve 256x256, 3 systems", flush=True)
+    rho, eta, kap, corner = ctx.lcurve(gammas, to_dev(X), to_dev(d))
+    rho_o, eta_o = outer.lcurve_points(pr.psf, wh, wv, X, d)
+    np.testing.assert_allclose(rho, rho_o, rtol=1e-11)
+    np.testing.assert_allclose(eta, eta_o, rtol=1e-11)
+    assert corner == 1
+    with pytest.raises(rsr.RsrError):
+        ctx.lcurve([1e-3, 1e-3, 1e-1], to_dev(X), to_dev(d))      # not increasing
+    with pytest.raises(rsr.RsrError):
+        ctx.lcurve([-1.0, 1e-2, 1e-1], to_dev(X), to_dev(d))      # not positive
+
+
+@pytest.mark.parametrize("mode", [rsr.SEQUENTIAL, rsr.BATCHED])
+def test_outer_loop_with_lcurve_and_edge_rule(ctx, mode):
+    cfg = synth.config("C1")
+    pr = cfg.problems[0]
+    d, b = oracle.rhs(pr)
+    loop = irn.OuterLoop(ctx, cfg, "recycled", mode=mode, weight_rule="edge", edge_p=2.0, lcurve=True)
+    loop.b[0] = to_dev(b)
+    loop.d[0] = to_dev(d)
+    wh, wv = (to_host(t) for t in ctx.get_weights(0))
+    for k in range(4):
+        print(f"outer loop with L-curve and edge rule: k={k} mode={mode}", flush=True)
+        X_prev = to_host(loop.X[0]).copy()
+        l_prev = loop.l_star
+        rec = loop.step()
+        if k > 0:
+            wh, wv = outer.edge_rule(X_prev[l_prev], wh, wv, 2.0)
+        gh, gv = (to_host(t) for t in ctx.get_weights(0))
+        np.testing.assert_allclose(gh, wh, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(gv, wv, rtol=1e-12, atol=1e-14)
+        X = to_host(loop.X[0])
+        for l, g in enumerate(cfg.gammas):
+            rel = oracle.true_relres(pr.psf, wh, wv, g, b, X[l])
+            assert rel <= 1e-8, (k, l, rel)
+        rho_o, eta_o = outer.lcurve_points(pr.psf, wh, wv, X, d)
+        kap_o = outer.lcurve_curvature(cfg.gammas, rho_o, eta_o)
+        assert 0 < rec.l_star < len(cfg.gammas) - 1
+        # the oracle's corner, or a point whose curvature ties with it to rounding
+        assert kap_o[rec.l_star] >= np.nanmax(kap_o) * (1 - 1e-9), (rec.l_star, kap_o)
+    assert loop.stopped == outer.stop_rule(loop.l_history)
