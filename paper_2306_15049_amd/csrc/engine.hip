@@ -16,6 +16,7 @@
 //   4. accepts on the recomputed true residual, restarting if needed, and keeps
 //      the correction g = x - x0 for the next shift / outer step.
 #include "internal.hpp"
+#include "outer.hpp"
 #include "smalldense.hpp"
 #include "../../include/rsr.h"
 
@@ -30,6 +31,7 @@
 #include <fstream>
 #include <functional>
 #include <map>
+#include <set>
 #include <tuple>
 #include <memory>
 #include <sstream>
@@ -122,7 +124,7 @@ struct rsr_ctx {
     DBuf d_jobs, d_gram_scratch, d_small, d_sys, d_partA, d_partB, d_ctl, d_out;
     DBuf d_ws;                         // per-system vectors of a solve
     DBuf d_dbg;                        // optional phase timestamps
-    DBuf d_tmp;                        // misc n-vectors
+    DBuf d_tmp;                        // grouped initial guesses x0, r0 before they are copied out
     DBuf d_rcC, d_rcQ;                 // recycle-space candidates and their orthonormal basis (kept: no
                                        // allocation, and no free that drains the device, per update)
     DBuf d_gprev;                      // previous shift's correction in sequential solves
@@ -357,6 +359,25 @@ void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector
     for (size_t k = 0; k < jobs.size(); ++k) jobs[k].Q = dq + off[k];
     ComboJob *dj = stage(c, jobs, s);
     HIPCHK(launch_combo(dj, jobs.data(), (int)jobs.size(), s));
+}
+
+// dst_k = src_k for a list of vectors, in one launch (a combination with the
+// single coefficient 1, which reproduces every finite value exactly)
+struct CopyJob {
+    const double *src;
+    double *dst;
+    long n;
+};
+void copy_many(rsr_ctx *c, const std::vector<CopyJob> &v, hipStream_t s)
+{
+    if (v.empty()) return;
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
+    for (const auto &j : v) {
+        cj.push_back(ComboJob{j.src, j.n, 1, nullptr, 1, j.dst, j.n, 1, 0.0, nullptr, 0, j.n});
+        qs.push_back(std::vector<double>{1.0});
+    }
+    combo(c, cj, qs, s);
 }
 
 std::vector<double> norms(rsr_ctx *c, const std::vector<const double *> &v, const std::vector<long> &n,
@@ -830,7 +851,9 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         if (o.use_prev_shift && g_prev_shift) gcols.push_back(g_prev_shift);
         for (const double *gv : gcols) {
             if (q >= QMAX) break;
-            HIPCHK(hipMemcpyAsync(Y.W + (size_t)q * Y.n, gv, sizeof(double) * Y.n, hipMemcpyDeviceToDevice, s));
+            // W[:, q] = g, a copy folded into the same combination launch
+            cj.push_back(ComboJob{gv, Y.n, 1, nullptr, 1, Y.W + (size_t)q * Y.n, Y.n, 1, 0.0, nullptr, 0, Y.n});
+            qs.push_back(std::vector<double>{1.0});
             aj.push_back(ApplyJob{Y.inst, 0, 1.0, Y.gamma, Y.W + (size_t)q * Y.n, Y.Z + (size_t)q * Y.n});
             Y.mvA += 1;
             Y.mvE += 1;
@@ -935,12 +958,15 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     // principal-space guesses (one small solve per shift, Section 4.1)
     std::vector<GramJob> gj;
     std::vector<SysHost *> prin, fresh;
+    std::set<std::tuple<const double *, int, int>> queued;
     for (auto *Yp : sy) {
         SysHost &Y = *Yp;
         Instance &I = *c->inst[Y.inst];
         if (!((o.init == RSR_INIT_MR || o.init == RSR_INIT_GALERKIN) && I.p > 0 && I.ae_valid)) continue;
         prin.push_back(&Y);
-        if (c->rhs_cache.count({Y.b, Y.inst, o.init})) continue;
+        const auto key = std::make_tuple((const double *)Y.b, Y.inst, o.init);
+        if (c->rhs_cache.count(key) || queued.count(key)) continue;   // once per right-hand side
+        queued.insert(key);
         fresh.push_back(&Y);
         if (o.init == RSR_INIT_MR)
             gj.push_back(GramJob{I.d_AE.as<double>(), I.n, 2 * I.p, Y.b, Y.n, 1, Y.n, nullptr, 0});
@@ -956,6 +982,17 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         }
         std::vector<std::vector<double>> rhs;
         for (auto *Y : prin) rhs.push_back(c->rhs_cache[{Y->b, Y->inst, o.init}]);
+        // systems that share an instance and a right-hand side form one
+        // combination each for x0 and r0 (the panels U, [AU EU] are read once
+        // per group); the columns land in scratch and are copied out together
+        struct InitGrp {
+            int inst;
+            const double *b;
+            std::vector<SysHost *> sys;
+            std::vector<double> Qx, Qr;
+        };
+        std::vector<InitGrp> grp;
+        grp.reserve(prin.size());
         for (size_t k = 0; k < prin.size(); ++k) {
             SysHost &Y = *prin[k];
             Instance &I = *c->inst[Y.inst];
@@ -980,18 +1017,48 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
                 matvec(p, p, P.data(), f.data(), q.data());
             }
             // x = U q ; r = b - [AU EU] [q; g q]
-            cj.push_back(ComboJob{I.d_U.as<double>(), I.n, p, nullptr, p, Y.x, Y.n, 1, 0.0, nullptr, 0, Y.n});
-            qs.push_back(q);
-            std::vector<double> q2(2 * p);
-            for (int i = 0; i < p; ++i) { q2[i] = -q[i]; q2[p + i] = -g * q[i]; }
-            cj.push_back(ComboJob{I.d_AE.as<double>(), I.n, 2 * p, nullptr, 2 * p, Y.r, Y.n, 1, 0.0, Y.b, Y.n, Y.n});
-            qs.push_back(q2);
+            InitGrp *G = nullptr;
+            for (auto &e : grp)
+                if (e.inst == Y.inst && e.b == Y.b) G = &e;
+            if (!G) {
+                grp.push_back(InitGrp{Y.inst, Y.b, {}, {}, {}});
+                G = &grp.back();
+            }
+            G->sys.push_back(&Y);
+            G->Qx.insert(G->Qx.end(), q.begin(), q.end());
+            for (int i = 0; i < p; ++i) G->Qr.push_back(-q[i]);
+            for (int i = 0; i < p; ++i) G->Qr.push_back(-g * q[i]);
+        }
+        size_t tot = 0;
+        for (auto &e : grp) tot += 2 * e.sys.size() * (size_t)c->inst[e.inst]->n;
+        c->d_tmp.ensure(sizeof(double) * tot);
+        double *T = c->d_tmp.as<double>();
+        std::vector<CopyJob> out;
+        for (auto &e : grp) {
+            Instance &I = *c->inst[e.inst];
+            const int p = I.p, m = (int)e.sys.size();
+            const long n = I.n;
+            double *Tx = T, *Tr = T + (size_t)m * n;
+            T += (size_t)2 * m * n;
+            cj.push_back(ComboJob{I.d_U.as<double>(), n, p, nullptr, p, Tx, n, m, 0.0, nullptr, 0, n});
+            qs.push_back(e.Qx);
+            cj.push_back(ComboJob{I.d_AE.as<double>(), n, 2 * p, nullptr, 2 * p, Tr, n, m, 0.0, e.b, 0, n});
+            qs.push_back(e.Qr);
+            for (int j = 0; j < m; ++j) {
+                out.push_back(CopyJob{Tx + (size_t)j * n, e.sys[j]->x, n});
+                out.push_back(CopyJob{Tr + (size_t)j * n, e.sys[j]->r, n});
+            }
         }
         combo(c, cj, qs, s);
+        copy_many(c, out, s);
     }
     // keep x_init for the correction g = x - x_init
     tm.reset(new StageTimer(c, s, 2));
-    for (auto *Y : sy) HIPCHK(hipMemcpyAsync(Y->xinit, Y->x, sizeof(double) * Y->n, hipMemcpyDeviceToDevice, s));
+    {
+        std::vector<CopyJob> xc;
+        for (auto *Y : sy) xc.push_back(CopyJob{Y->x, Y->xinit, Y->n});
+        copy_many(c, xc, s);
+    }
     {
         std::vector<const double *> v;
         std::vector<long> n;
@@ -1410,9 +1477,13 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
             for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
         combo(c, {ComboJob{I.d_U.as<double>(), n, p, nullptr, p, C, n, nr, 0.0, nullptr, 0, n}}, {Wt}, s);
     }
-    for (int j = 0; j < ncols; ++j)
-        HIPCHK(hipMemcpyAsync(C + (size_t)(nr + j) * n, U_raw + (size_t)j * ld, sizeof(double) * n,
-                              hipMemcpyDeviceToDevice, s));
+    if (ncols > 0 && ld == n) {
+        HIPCHK(hipMemcpyAsync(C + (size_t)nr * n, U_raw, sizeof(double) * ncols * n, hipMemcpyDeviceToDevice, s));
+    } else {
+        std::vector<CopyJob> uc;
+        for (int j = 0; j < ncols; ++j) uc.push_back(CopyJob{U_raw + (size_t)j * ld, C + (size_t)(nr + j) * n, n});
+        copy_many(c, uc, s);
+    }
     // Algorithm 1 through the Gram matrix: C^T C = V diag(sigma^2) V^T,
     // keep sigma_1 / sigma_i < cond_max (and above the FP64 resolution of
     // the Gram route), Q = C V_k diag(1/sigma_k); a second pass restores
@@ -1425,6 +1496,13 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
         const double *X = pass == 0 ? C : Q;
         const int mm = pass == 0 ? m : keep;
         auto Gm = gram(c, {GramJob{X, n, mm, X, n, mm, n, nullptr, 0}}, s)[0];
+        std::vector<double> Tc;
+        if (pass == 1 && chol_qr_factor(mm, Gm.data(), Tc)) {
+            // Q^T Q is close to I: Cholesky QR restores orthonormality (same span)
+            I.d_U.ensure(sizeof(double) * (size_t)keep * n);
+            combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {Tc}, s);
+            break;
+        }
         std::vector<double> w, V;
         sym_eig(mm, Gm.data(), w, V);
         const double lmax = w.empty() ? 0.0 : w.back();

@@ -117,14 +117,6 @@ hipError_t launch_weights(const double *x, double beta, double *wh, double *wv, 
 hipError_t launch_copy_weights(const double *wh_in, const double *wv_in, double *wh, double *wv,
                                int ny, int nx, hipStream_t s);
 hipError_t launch_fill(double *p, double v, long n, hipStream_t s);
-// edge weights of Sec. 2.1 in place; part: device scratch of edge_rule_parts() doubles
-int edge_rule_parts();
-hipError_t launch_edge_rule(const double *x, double *wh, double *wv, int ny, int nx, double p, double *part,
-                            hipStream_t s);
-// L-curve sums of m systems; part: device scratch of 2 * m * lcurve_parts(n) doubles
-int lcurve_parts(long n);
-hipError_t launch_lcurve(const InstDev *inst_dev, int ii, long n, int m, const double *X, long ld_x,
-                         const double *d, double *part, hipStream_t s);
 
 // Tall-skinny products over n rows:
 //   C[i][j] = sum_r X[r + i*ldx] * Y[r + j*ldy],  i < a, j < c      (gram)

@@ -16,6 +16,7 @@
 //   * the persistent CG kernel lives in cg.hip; this file holds the
 //     operator-application, weight, tall-skinny and gradient kernels.
 #include "internal.hpp"
+#include "outer.hpp"
 #include "stencil.hpp"
 
 #include <algorithm>
@@ -328,12 +329,23 @@ hipError_t launch_lcurve(const InstDev *inst_dev, int ii, long n, int m, const d
 // ------------------------------------------------ tall-skinny products --
 // C = X^T Y for n x a and n x c panels.  Grid: (row chunks, output tiles of
 // 16 x 16, jobs).  Each workgroup stages 64-row slabs of 16 X columns and 16 Y
-// columns in LDS; each thread owns one output of the 16 x 16 tile and a
-// quarter of the slab rows, then the four quarters are summed in a fixed
-// order.  Chunk partials go to scratch and k_gram_reduce sums them in order.
+// columns in LDS; each thread owns one output of the 16 x 16 tile.  The next
+// slab's loads are issued into registers before the current slab's FMAs, so
+// one slab is always in flight.  Chunks are short enough to give several
+// workgroups per CU on 256^2 images.  Chunk partials go to scratch and
+// k_gram_reduce sums them in order.
 constexpr int GT = 16;       // output tile edge
 constexpr int GR = 64;       // rows per slab
-constexpr int GCH = 4096;    // rows per chunk
+constexpr int GLD = GR * GT / NT;   // slab elements per thread and panel
+
+// rows per chunk: about 64 chunks, between 512 and 4096 rows, a whole number of slabs
+__host__ __device__ inline long gram_chunk_rows(long n)
+{
+    long c = (n / 64 + GR - 1) / GR * GR;
+    return c < 512 ? 512 : (c > 4096 ? 4096 : c);
+}
+
+__host__ __device__ inline long gram_chunks(long n) { return (n + gram_chunk_rows(n) - 1) / gram_chunk_rows(n); }
 
 __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, double *__restrict__ scratch)
 {
@@ -345,23 +357,36 @@ __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, d
     const int tiles_a = (J.a + GT - 1) / GT;
     const int ot = blockIdx.y;
     if (ot >= tiles_a * tiles_c) return;
-    const long nchunk = (J.n + GCH - 1) / GCH;
+    const long nchunk = gram_chunks(J.n);
     if ((long)blockIdx.x >= nchunk) return;
     const int ia0 = (ot / tiles_c) * GT, jc0 = (ot % tiles_c) * GT;
-    const long r0 = (long)blockIdx.x * GCH;
-    const long r1 = r0 + GCH < J.n ? r0 + GCH : J.n;
+    const long gch = gram_chunk_rows(J.n);
+    const long r0 = (long)blockIdx.x * gch;
+    const long r1 = r0 + gch < J.n ? r0 + gch : J.n;
     const int oi = threadIdx.x % GT, oj = (threadIdx.x / GT) % GT;   // output (oi, oj) ... 256 = 16x16
-    double acc = 0.0;
-    for (long rb = r0; rb < r1; rb += GR) {
-        // stage slab: GR rows x GT cols of X and of Y (column-major panels)
-        for (int k = threadIdx.x; k < GR * GT; k += NT) {
+    double vx[GLD], vy[GLD];
+    auto load = [&](long rb) {
+#pragma unroll
+        for (int u = 0; u < GLD; ++u) {
+            const int k = threadIdx.x + u * NT;
             const int rr = k % GR, cc = k / GR;
             const long row = rb + rr;
             const int xa = ia0 + cc, yc = jc0 + cc;
-            xs[rr][cc] = (row < r1 && xa < J.a) ? gp(J.X)[row + (long)xa * J.ldx] : 0.0;
-            ys[rr][cc] = (row < r1 && yc < J.c) ? gp(J.Y)[row + (long)yc * J.ldy] : 0.0;
+            vx[u] = (row < r1 && xa < J.a) ? gp(J.X)[row + (long)xa * J.ldx] : 0.0;
+            vy[u] = (row < r1 && yc < J.c) ? gp(J.Y)[row + (long)yc * J.ldy] : 0.0;
+        }
+    };
+    double acc = 0.0;
+    load(r0);
+    for (long rb = r0; rb < r1; rb += GR) {
+#pragma unroll
+        for (int u = 0; u < GLD; ++u) {
+            const int k = threadIdx.x + u * NT;
+            xs[k % GR][k / GR] = vx[u];
+            ys[k % GR][k / GR] = vy[u];
         }
         __syncthreads();
+        if (rb + GR < r1) load(rb + GR);   // in flight during this slab's FMAs
 #pragma unroll 8
         for (int rr = 0; rr < GR; ++rr) acc = fma(xs[rr][oi], ys[rr][oj], acc);
         __syncthreads();
@@ -374,13 +399,14 @@ __global__ void k_gram_reduce(const GramJob *__restrict__ jobs, const double *__
 {
     const GramJob J = jobs[blockIdx.y];
     const int tiles_c = (J.c + GT - 1) / GT;
-    const long nchunk = (J.n + GCH - 1) / GCH;
+    const long nchunk = gram_chunks(J.n);
     const int total = J.a * J.c;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
         const int i = k / J.c, j = k % J.c;
         const int ot = (i / GT) * tiles_c + (j / GT);
         const double *src = scratch + J.sc_off + (long)ot * nchunk * (GT * GT) + (i % GT) * GT + (j % GT);
         double s = 0.0;
+#pragma unroll 8
         for (long ch = 0; ch < nchunk; ++ch) s += src[ch * (GT * GT)];
         J.C[k] = s;
     }
@@ -401,10 +427,11 @@ __global__ __launch_bounds__(NT) void k_gram_small(const GramJob *__restrict__ j
     const int ia0 = blockIdx.y * GSMALL_A;
     if (ia0 >= J.a) return;
     const int na = J.a - ia0 < GSMALL_A ? J.a - ia0 : GSMALL_A;
-    const long nchunk = (J.n + GCH - 1) / GCH;
+    const long nchunk = gram_chunks(J.n);
     if ((long)blockIdx.x >= nchunk) return;
-    const long r0 = (long)blockIdx.x * GCH;
-    const long r1 = r0 + GCH < J.n ? r0 + GCH : J.n;
+    const long gch = gram_chunk_rows(J.n);
+    const long r0 = (long)blockIdx.x * gch;
+    const long r1 = r0 + gch < J.n ? r0 + gch : J.n;
     double acc[GSMALL_A][GSMALL_A];
 #pragma unroll
     for (int i = 0; i < GSMALL_A; ++i)
@@ -447,7 +474,7 @@ size_t gram_scratch_doubles(const GramJob *jh, int njobs)
 {
     size_t t = 0;
     for (int i = 0; i < njobs; ++i) {
-        const long nchunk = (jh[i].n + GCH - 1) / GCH;
+        const long nchunk = gram_chunks(jh[i].n);
         const long ntiles = (long)((jh[i].a + GT - 1) / GT) * ((jh[i].c + GT - 1) / GT);
         t += (size_t)(nchunk * ntiles * GT * GT);
     }
@@ -460,7 +487,7 @@ hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, do
     long maxchunk = 1, maxtiles = 1;
     bool any_big = false, any_small = false;
     for (int i = 0; i < njobs; ++i) {
-        const long nchunk = (jh[i].n + GCH - 1) / GCH;
+        const long nchunk = gram_chunks(jh[i].n);
         const long ntiles = (long)((jh[i].a + GT - 1) / GT) * ((jh[i].c + GT - 1) / GT);
         if (nchunk > maxchunk) maxchunk = nchunk;
         if (ntiles > maxtiles) maxtiles = ntiles;
@@ -482,39 +509,76 @@ hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, do
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_gram_reduce, dim3(8, njobs), dim3(NT), 0, s, jobs_dev, scratch);
+    long outs = 1;
+    for (int i = 0; i < njobs; ++i) outs = std::max<long>(outs, (long)jh[i].a * jh[i].c);
+    const int gr = (int)std::min<long>(64, (outs + NT - 1) / NT);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(gr, njobs), dim3(NT), 0, s, jobs_dev, scratch);
     return hipGetLastError();
 }
 
 // Y = beta Y + X Q (or Y = Y0 + X Q) over n rows; Q is a x c, column-major.
-constexpr int CJ = 16;   // output columns per register chunk
+// Grid: (row blocks, jobs, 16-column chunks of Y).  Each thread owns one row
+// and 16 outputs.  The workgroup stages its a x 16 block of Q in LDS (in
+// passes of CQ rows when a is larger), so the coefficients are broadcast LDS
+// reads; the loads of 8 X columns are issued together before their FMAs.
+// The sum over k runs in order, the same for every launch shape.
+constexpr int CJ = 16;    // output columns per register chunk
+constexpr int CK = 8;     // X columns loaded together
+constexpr int CQ = 256;   // Q rows staged in LDS per pass
 __global__ __launch_bounds__(NT) void k_combo(const ComboJob *__restrict__ jobs)
 {
+    __shared__ double qs[CQ * CJ];
     const ComboJob J = jobs[blockIdx.y];
     const int a = J.a, c = J.c;
-    for (long r = blockIdx.x * (long)NT + threadIdx.x; r < J.n; r += (long)gridDim.x * NT) {
-        for (int j0 = 0; j0 < c; j0 += CJ) {
-            double s[CJ];
+    const int j0 = blockIdx.z * CJ;
+    if (j0 >= c) return;
+    const int cu = c - j0 < CJ ? c - j0 : CJ;   // live columns of this chunk
+    bool staged = false;
+    for (long rb = blockIdx.x * (long)NT; rb < J.n; rb += (long)gridDim.x * NT) {
+        const long r = rb + threadIdx.x;
+        const bool live = r < J.n;
+        double s[CJ];
 #pragma unroll
-            for (int u = 0; u < CJ; ++u) {
-                const int j = j0 + u;
-                double v = 0.0;
-                if (j < c) {
-                    if (J.Y0) v = gp(J.Y0)[r + (long)j * J.ldy0];
-                    else if (J.beta != 0.0) v = J.beta * gp(J.Y)[r + (long)j * J.ldy];
+        for (int u = 0; u < CJ; ++u) {
+            double v = 0.0;
+            if (live && u < cu) {
+                if (J.Y0) v = gp(J.Y0)[r + (long)(j0 + u) * J.ldy0];
+                else if (J.beta != 0.0) v = J.beta * gp(J.Y)[r + (long)(j0 + u) * J.ldy];
+            }
+            s[u] = v;
+        }
+        for (int kb = 0; kb < a; kb += CQ) {
+            const int ka = a - kb < CQ ? a - kb : CQ;
+            if (!(staged && a <= CQ)) {   // one pass covers Q: stage it once
+                __syncthreads();
+                for (int e = threadIdx.x; e < ka * CJ; e += NT) {
+                    const int k = e / CJ, u = e % CJ;
+                    qs[e] = u < cu ? gp(J.Q)[(kb + k) + (long)(j0 + u) * J.ldq] : 0.0;
                 }
-                s[u] = v;
+                __syncthreads();
+                staged = true;
             }
-            for (int k = 0; k < a; ++k) {
-                const double xv = gp(J.X)[r + (long)k * J.ldx];
-                const gdbl *qk = gp(J.Q) + k;
+            if (live) {
+                for (int k0 = 0; k0 < ka; k0 += CK) {
+                    double xv[CK];
 #pragma unroll
-                for (int u = 0; u < CJ; ++u)
-                    if (j0 + u < c) s[u] = fma(xv, qk[(long)(j0 + u) * J.ldq], s[u]);
+                    for (int t = 0; t < CK; ++t)
+                        xv[t] = k0 + t < ka ? gp(J.X)[r + (long)(kb + k0 + t) * J.ldx] : 0.0;
+#pragma unroll
+                    for (int t = 0; t < CK; ++t) {
+                        if (k0 + t < ka) {
+                            const double *qk = qs + (k0 + t) * CJ;
+#pragma unroll
+                            for (int u = 0; u < CJ; ++u) s[u] = fma(xv[t], qk[u], s[u]);
+                        }
+                    }
+                }
             }
+        }
+        if (live) {
 #pragma unroll
             for (int u = 0; u < CJ; ++u)
-                if (j0 + u < c) gp(J.Y)[r + (long)(j0 + u) * J.ldy] = s[u];
+                if (u < cu) gp(J.Y)[r + (long)(j0 + u) * J.ldy] = s[u];
         }
     }
 }
@@ -522,10 +586,14 @@ __global__ __launch_bounds__(NT) void k_combo(const ComboJob *__restrict__ jobs)
 hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jh, int njobs, hipStream_t s)
 {
     long nmax = 1;
-    for (int i = 0; i < njobs; ++i) if (jh[i].n > nmax) nmax = jh[i].n;
+    int cch = 1;
+    for (int i = 0; i < njobs; ++i) {
+        if (jh[i].n > nmax) nmax = jh[i].n;
+        cch = std::max(cch, (jh[i].c + CJ - 1) / CJ);
+    }
     int gx = grid_for(nmax);
     if (gx > 2048) gx = 2048;
-    hipLaunchKernelGGL(k_combo, dim3(gx, njobs), dim3(NT), 0, s, jobs_dev);
+    hipLaunchKernelGGL(k_combo, dim3(gx, njobs, cch), dim3(NT), 0, s, jobs_dev);
     return hipGetLastError();
 }
 

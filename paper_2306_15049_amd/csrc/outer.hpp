@@ -1,0 +1,17 @@
+// Launchers of the outer-iteration kernels (edge weights and L-curve sums of
+// Section 2.1), defined in kernels.hip.
+#pragma once
+#include "internal.hpp"
+
+namespace rsr {
+
+// edge weights of Sec. 2.1 in place; part: device scratch of edge_rule_parts() doubles
+int edge_rule_parts();
+hipError_t launch_edge_rule(const double *x, double *wh, double *wv, int ny, int nx, double p, double *part,
+                            hipStream_t s);
+// L-curve sums of m systems; part: device scratch of 2 * m * lcurve_parts(n) doubles
+int lcurve_parts(long n);
+hipError_t launch_lcurve(const InstDev *inst_dev, int ii, long n, int m, const double *X, long ld_x,
+                         const double *d, double *part, hipStream_t s);
+
+}  // namespace rsr

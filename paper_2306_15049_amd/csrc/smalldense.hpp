@@ -246,6 +246,39 @@ inline bool spd_solve(int n, const double *S, const double *f, double *x, double
     return true;
 }
 
+// Cholesky QR factor of a Gram matrix: for symmetric positive definite G
+// (n x n, row-major) with G = L L^T, writes T = L^{-T} (column-major n x n,
+// upper triangular), so that Q T has orthonormal columns when G = Q^T Q.
+// Returns false (T untouched) if a pivot is not positive.
+inline bool chol_qr_factor(int n, const double *G, std::vector<double> &T)
+{
+    std::vector<double> L((size_t)n * n, 0.0), Li((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double s = G[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(s > 0.0)) return false;
+        const double ljj = std::sqrt(s);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = G[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    // Li = L^{-1} (lower triangular), column by column of the identity
+    for (int c = 0; c < n; ++c)
+        for (int i = c; i < n; ++i) {
+            double t = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) t -= L[(size_t)i * n + k] * Li[(size_t)k * n + c];
+            Li[(size_t)i * n + c] = t / L[(size_t)i * n + i];
+        }
+    // T = Li^T; column-major T[j * n + i] = T(i, j) = Li(j, i)
+    T.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i <= j; ++i) T[(size_t)j * n + i] = Li[(size_t)j * n + i];
+    return true;
+}
+
 inline void matvec(int n, int m, const double *M, const double *x, double *y)  // y = M x, M n x m
 {
     for (int i = 0; i < n; ++i) {

@@ -71,3 +71,37 @@ def test_eigensolvers_against_lapack(exe):
             if n:
                 assert np.abs(S @ V - V * w).max() <= 1e-12 * scale
                 assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
+
+
+def test_cholesky_qr_factor():
+    # Q T has orthonormal columns and spans Range(Q); T is upper triangular;
+    # an indefinite matrix is refused
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    import tempfile
+    src = os.path.join(HERE, "native", "cholqr_check.cpp")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "cholqr_check")
+        subprocess.run([gxx, "-O2", "-std=c++17", src, "-o", exe], check=True)
+
+        def run(G):
+            n = G.shape[0]
+            txt = f"{n}\n" + "\n".join(repr(float(v)) for v in G.ravel()) + "\n"
+            out = subprocess.run([exe], input=txt, capture_output=True, text=True, check=True).stdout.split()
+            if int(out[0]) == 0:
+                return None
+            return np.array([float(t) for t in out[1:]]).reshape(n, n).T   # column-major -> T[i, j]
+
+        rng = np.random.default_rng(5)
+        for n, k in ((200, 1), (300, 7), (500, 40)):
+            Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+            Q = Q @ (np.eye(k) + 1e-6 * rng.standard_normal((k, k)))     # nearly orthonormal, as in the second pass
+            T = run(Q.T @ Q)
+            assert T is not None
+            np.testing.assert_allclose(np.tril(T, -1), 0.0, atol=0)
+            U = Q @ T
+            np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-13)
+            P = Q @ np.linalg.pinv(Q)
+            assert np.linalg.norm(U - P @ U) < 1e-12
+        assert run(np.array([[1.0, 2.0], [2.0, 1.0]])) is None
