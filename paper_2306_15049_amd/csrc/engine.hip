@@ -1463,9 +1463,14 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
         I.ae_valid = false;
         return 0;
     }
+    // Buffers are sized for the largest space this call allows (p_max kept
+    // columns, p_max + ncols candidates), so that a space that grows over the
+    // outer steps does not reallocate (a free drains the device).  U and
+    // [AU EU] are resized only where they are rewritten: the candidates read U.
+    const size_t pcap = (size_t)std::max(p_max, 1);
     // candidate block C = [U W~(:, 1:nr), U_raw]
     DBuf &Cb = c->d_rcC;
-    Cb.ensure(sizeof(double) * (size_t)m * n);
+    Cb.ensure(sizeof(double) * std::max((size_t)m, pcap + ncols) * n);
     double *C = Cb.as<double>();
     if (nr > 0) {
         const int p = I.p;
@@ -1489,7 +1494,7 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
     // the Gram route), Q = C V_k diag(1/sigma_k); a second pass restores
     // orthonormality to rounding level.
     DBuf &Qb = c->d_rcQ;
-    Qb.ensure(sizeof(double) * (size_t)m * n);
+    Qb.ensure(sizeof(double) * std::max((size_t)m, pcap + ncols) * n);
     double *Q = Qb.as<double>();
     int keep = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -1499,7 +1504,7 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
         std::vector<double> Tc;
         if (pass == 1 && chol_qr_factor(mm, Gm.data(), Tc)) {
             // Q^T Q is close to I: Cholesky QR restores orthonormality (same span)
-            I.d_U.ensure(sizeof(double) * (size_t)keep * n);
+            I.d_U.ensure(sizeof(double) * std::max((size_t)keep, pcap) * n);
             combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {Tc}, s);
             break;
         }
@@ -1524,14 +1529,14 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
         if (pass == 0) {
             combo(c, {ComboJob{C, n, mm, nullptr, mm, Q, n, keep, 0.0, nullptr, 0, n}}, {T}, s);
         } else {
-            I.d_U.ensure(sizeof(double) * (size_t)keep * n);
+            I.d_U.ensure(sizeof(double) * std::max((size_t)keep, pcap) * n);
             combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {T}, s);
         }
     }
     const int p = keep;
     I.p = p;
     // A U and E U (p applications each), then the small blocks
-    I.d_AE.ensure(sizeof(double) * (size_t)2 * p * n);
+    I.d_AE.ensure(sizeof(double) * (size_t)2 * std::max((size_t)p, pcap) * n);
     double *AU = I.d_AE.as<double>(), *EU = AU + (size_t)p * n;
     apply_op(c, ii, 1.0, 0.0, I.d_U.as<double>(), n, AU, n, p, s);
     apply_op(c, ii, 0.0, 1.0, I.d_U.as<double>(), n, EU, n, p, s);

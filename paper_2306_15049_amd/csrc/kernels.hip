@@ -327,43 +327,53 @@ hipError_t launch_lcurve(const InstDev *inst_dev, int ii, long n, int m, const d
 }
 
 // ------------------------------------------------ tall-skinny products --
-// C = X^T Y for n x a and n x c panels.  Grid: (row chunks, output tiles of
-// 16 x 16, jobs).  Each workgroup stages 64-row slabs of 16 X columns and 16 Y
-// columns in LDS; each thread owns one output of the 16 x 16 tile.  The next
-// slab's loads are issued into registers before the current slab's FMAs, so
-// one slab is always in flight.  Chunks are short enough to give several
-// workgroups per CU on 256^2 images.  Chunk partials go to scratch and
-// k_gram_reduce sums them in order.
-constexpr int GT = 16;       // output tile edge
-constexpr int GR = 64;       // rows per slab
-constexpr int GLD = GR * GT / NT;   // slab elements per thread and panel
+// C = X^T Y for n x a and n x c panels.  Grid: (row chunks, 64 x 64 output
+// blocks, jobs).  Each workgroup stages 32-row slabs of up to 64 X columns and
+// 64 Y columns in LDS and each thread accumulates a 4 x 4 register block of
+// the output (rows ti + 16u, columns tj + 16v), so every panel element is read
+// once per output block.  The next slab's loads are issued into registers
+// before the current slab's FMAs.  Chunk partials go to scratch in 16 x 16
+// output tiles and k_gram_reduce sums them in order; every output sums its
+// rows in order, so the result does not depend on the launch shape.
+constexpr int GT = 16;       // output tile edge of the partial-sum layout
+constexpr int GB = 64;       // output block edge per workgroup
+constexpr int GR = 32;       // rows per slab
+constexpr int GLD = GR * GB / NT;   // slab elements per thread and panel
 
-// rows per chunk: about 64 chunks, between 512 and 4096 rows, a whole number of slabs
-__host__ __device__ inline long gram_chunk_rows(long n)
+// rows per chunk, a whole number of slabs: about 256 chunks (256..4096 rows)
+// for the blocked products, about 64 (512..4096 rows) for the small ones
+// (c <= 8), whose per-workgroup reduction is the larger fixed cost
+__host__ __device__ inline long gram_chunk_rows(long n, int c)
 {
-    long c = (n / 64 + GR - 1) / GR * GR;
-    return c < 512 ? 512 : (c > 4096 ? 4096 : c);
+    const long per = c <= 8 ? 64 : 256, lo = c <= 8 ? 512 : 256;
+    const long r = (n / per + 63) / 64 * 64;
+    return r < lo ? lo : (r > 4096 ? 4096 : r);
 }
 
-__host__ __device__ inline long gram_chunks(long n) { return (n + gram_chunk_rows(n) - 1) / gram_chunk_rows(n); }
+__host__ __device__ inline long gram_chunks(long n, int c)
+{
+    return (n + gram_chunk_rows(n, c) - 1) / gram_chunk_rows(n, c);
+}
 
 __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, double *__restrict__ scratch)
 {
-    __shared__ double xs[GR][GT + 1];
-    __shared__ double ys[GR][GT + 1];
+    __shared__ double xs[GR][GB + 1];
+    __shared__ double ys[GR][GB + 1];
     const GramJob J = jobs[blockIdx.z];
     if (J.c <= 8) return;   // done by k_gram_small
-    const int tiles_c = (J.c + GT - 1) / GT;
-    const int tiles_a = (J.a + GT - 1) / GT;
-    const int ot = blockIdx.y;
-    if (ot >= tiles_a * tiles_c) return;
-    const long nchunk = gram_chunks(J.n);
+    const int blocks_c = (J.c + GB - 1) / GB;
+    const int blocks_a = (J.a + GB - 1) / GB;
+    const int ob = blockIdx.y;
+    if (ob >= blocks_a * blocks_c) return;
+    const long nchunk = gram_chunks(J.n, J.c);
     if ((long)blockIdx.x >= nchunk) return;
-    const int ia0 = (ot / tiles_c) * GT, jc0 = (ot % tiles_c) * GT;
-    const long gch = gram_chunk_rows(J.n);
+    const int ia0 = (ob / blocks_c) * GB, jc0 = (ob % blocks_c) * GB;
+    const int na = J.a - ia0 < GB ? J.a - ia0 : GB;
+    const int nc = J.c - jc0 < GB ? J.c - jc0 : GB;
+    const long gch = gram_chunk_rows(J.n, J.c);
     const long r0 = (long)blockIdx.x * gch;
     const long r1 = r0 + gch < J.n ? r0 + gch : J.n;
-    const int oi = threadIdx.x % GT, oj = (threadIdx.x / GT) % GT;   // output (oi, oj) ... 256 = 16x16
+    const int ti = threadIdx.x % 16, tj = threadIdx.x / 16;
     double vx[GLD], vy[GLD];
     auto load = [&](long rb) {
 #pragma unroll
@@ -371,12 +381,15 @@ __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, d
             const int k = threadIdx.x + u * NT;
             const int rr = k % GR, cc = k / GR;
             const long row = rb + rr;
-            const int xa = ia0 + cc, yc = jc0 + cc;
-            vx[u] = (row < r1 && xa < J.a) ? gp(J.X)[row + (long)xa * J.ldx] : 0.0;
-            vy[u] = (row < r1 && yc < J.c) ? gp(J.Y)[row + (long)yc * J.ldy] : 0.0;
+            vx[u] = (row < r1 && cc < na) ? gp(J.X)[row + (long)(ia0 + cc) * J.ldx] : 0.0;
+            vy[u] = (row < r1 && cc < nc) ? gp(J.Y)[row + (long)(jc0 + cc) * J.ldy] : 0.0;
         }
     };
-    double acc = 0.0;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     load(r0);
     for (long rb = r0; rb < r1; rb += GR) {
 #pragma unroll
@@ -387,19 +400,39 @@ __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, d
         }
         __syncthreads();
         if (rb + GR < r1) load(rb + GR);   // in flight during this slab's FMAs
-#pragma unroll 8
-        for (int rr = 0; rr < GR; ++rr) acc = fma(xs[rr][oi], ys[rr][oj], acc);
+#pragma unroll 4
+        for (int rr = 0; rr < GR; ++rr) {
+            double xv[4], yv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = xs[rr][ti + 16 * u];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) yv[v] = ys[rr][tj + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(xv[u], yv[v], acc[u][v]);
+        }
         __syncthreads();
     }
-    const long off = J.sc_off + ((long)ot * nchunk + blockIdx.x) * (GT * GT);
-    scratch[off + oi * GT + oj] = acc;
+    const int tiles_c = (J.c + GT - 1) / GT;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = ia0 + ti + 16 * u, j = jc0 + tj + 16 * v;
+            if (i < J.a && j < J.c) {
+                const int ot = (i / GT) * tiles_c + j / GT;
+                scratch[J.sc_off + ((long)ot * nchunk + blockIdx.x) * (GT * GT) + (i % GT) * GT + (j % GT)] =
+                    acc[u][v];
+            }
+        }
 }
 
 __global__ void k_gram_reduce(const GramJob *__restrict__ jobs, const double *__restrict__ scratch)
 {
     const GramJob J = jobs[blockIdx.y];
     const int tiles_c = (J.c + GT - 1) / GT;
-    const long nchunk = gram_chunks(J.n);
+    const long nchunk = gram_chunks(J.n, J.c);
     const int total = J.a * J.c;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
         const int i = k / J.c, j = k % J.c;
@@ -427,9 +460,9 @@ __global__ __launch_bounds__(NT) void k_gram_small(const GramJob *__restrict__ j
     const int ia0 = blockIdx.y * GSMALL_A;
     if (ia0 >= J.a) return;
     const int na = J.a - ia0 < GSMALL_A ? J.a - ia0 : GSMALL_A;
-    const long nchunk = gram_chunks(J.n);
+    const long nchunk = gram_chunks(J.n, J.c);
     if ((long)blockIdx.x >= nchunk) return;
-    const long gch = gram_chunk_rows(J.n);
+    const long gch = gram_chunk_rows(J.n, J.c);
     const long r0 = (long)blockIdx.x * gch;
     const long r1 = r0 + gch < J.n ? r0 + gch : J.n;
     double acc[GSMALL_A][GSMALL_A];
@@ -474,7 +507,7 @@ size_t gram_scratch_doubles(const GramJob *jh, int njobs)
 {
     size_t t = 0;
     for (int i = 0; i < njobs; ++i) {
-        const long nchunk = gram_chunks(jh[i].n);
+        const long nchunk = gram_chunks(jh[i].n, jh[i].c);
         const long ntiles = (long)((jh[i].a + GT - 1) / GT) * ((jh[i].c + GT - 1) / GT);
         t += (size_t)(nchunk * ntiles * GT * GT);
     }
@@ -484,13 +517,12 @@ size_t gram_scratch_doubles(const GramJob *jh, int njobs)
 hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, double *scratch,
                        size_t scratch_doubles, hipStream_t s)
 {
-    long maxchunk = 1, maxtiles = 1;
+    long maxchunk = 1;
     bool any_big = false, any_small = false;
     for (int i = 0; i < njobs; ++i) {
-        const long nchunk = gram_chunks(jh[i].n);
+        const long nchunk = gram_chunks(jh[i].n, jh[i].c);
         const long ntiles = (long)((jh[i].a + GT - 1) / GT) * ((jh[i].c + GT - 1) / GT);
         if (nchunk > maxchunk) maxchunk = nchunk;
-        if (ntiles > maxtiles) maxtiles = ntiles;
         if (jh[i].sc_off + (size_t)(nchunk * ntiles * GT * GT) > scratch_doubles) return hipErrorInvalidValue;
         const bool small = jh[i].c <= GSMALL_A;
         any_small |= small;
@@ -505,7 +537,10 @@ hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, do
         if (e != hipSuccess) return e;
     }
     if (any_big) {
-        hipLaunchKernelGGL(k_gram, dim3(maxchunk, maxtiles, njobs), dim3(NT), 0, s, jobs_dev, scratch);
+        long maxblocks = 1;
+        for (int i = 0; i < njobs; ++i)
+            maxblocks = std::max<long>(maxblocks, (long)((jh[i].a + GB - 1) / GB) * ((jh[i].c + GB - 1) / GB));
+        hipLaunchKernelGGL(k_gram, dim3(maxchunk, maxblocks, njobs), dim3(NT), 0, s, jobs_dev, scratch);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
