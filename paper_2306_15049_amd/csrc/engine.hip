@@ -95,8 +95,16 @@ struct Instance {
     DBuf d_U, d_AE;   // U: p columns; AE: [AU | EU], 2p columns; stride n
     std::vector<double> Ahat, Ehat, Gaa, Gae, Gee;   // p x p row-major
     bool ae_valid = false;
-    // latest correction g = x - x0 per shift slot
-    std::map<int, std::unique_ptr<DBuf>> gstore;
+    // latest correction g = x - x0 per shift slot: column gcol[slot] of gpool
+    // (one allocation for all slots, grown geometrically when a slot is new)
+    std::map<int, int> gcol;
+    DBuf gpool;
+    int gpool_cols = 0;
+    double *gslot(int slot)
+    {
+        auto it = gcol.find(slot);
+        return it == gcol.end() ? nullptr : gpool.as<double>() + (size_t)it->second * n;
+    }
     // Ritz blocks [R | AR | ER] per shift group, valid for the current U (version)
     long u_version = 0;
     struct RitzBlock {
@@ -105,6 +113,14 @@ struct Instance {
         int nr = 0;
         DBuf buf;
     } ritz[2];
+    // eigenpairs of Ahat + gamma Ehat for the current U: the retained Ritz
+    // vectors of the next principal space, computed on the host while a CG
+    // launch runs (the first launch after U changes, at its smallest shift)
+    struct EigPre {
+        long version = -1;
+        double gamma = 0.0;
+        std::vector<double> w, V;
+    } eig_pre;
 };
 
 inline int eff_sy(const Instance &I) { return I.sep ? I.ssq : I.sy; }
@@ -361,6 +377,26 @@ void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector
     HIPCHK(launch_combo(dj, jobs.data(), (int)jobs.size(), s));
 }
 
+// Eigenpairs (ascending) of Ahat + gamma Ehat for the instance's current U,
+// from the cache when it holds this U version and shift.
+void retained_eig(Instance &I, double gamma, std::vector<double> &w, std::vector<double> &V)
+{
+    auto &E = I.eig_pre;
+    if (E.version == I.u_version && E.gamma == gamma && (int)E.w.size() == I.p) {
+        w = E.w;
+        V = E.V;
+        return;
+    }
+    const int p = I.p;
+    std::vector<double> H((size_t)p * p);
+    for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + gamma * I.Ehat[k];
+    sym_eig(p, H.data(), w, V);
+    E.version = I.u_version;
+    E.gamma = gamma;
+    E.w = w;
+    E.V = V;
+}
+
 // dst_k = src_k for a list of vectors, in one launch (a combination with the
 // single coefficient 1, which reproduces every finite value exactly)
 struct CopyJob {
@@ -615,6 +651,16 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     HIPCHK(hipEventRecord(c->ev0, s));
     HIPCHK(launch_cg(a, qt, lz, G, lds, s));
     HIPCHK(hipEventRecord(c->ev1, s));
+    // host work that does not depend on this launch, done while it runs
+    for (auto *Y : sy) {
+        Instance &I = *c->inst[Y->inst];
+        if (I.p == 0 || !I.ae_valid || I.eig_pre.version == I.u_version) continue;
+        double g = Y->gamma;
+        for (auto *Z : sy)
+            if (Z->inst == Y->inst) g = std::min(g, Z->gamma);
+        std::vector<double> w, V;
+        retained_eig(I, g, w, V);
+    }
     std::vector<int> hi(2 * m + 8);
     std::vector<double> hr(2 * m);   // final r.r, then the pending step alpha
     int abort_h = 0;
@@ -845,8 +891,7 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         // previous corrections
         std::vector<const double *> gcols;
         if (o.use_prev_k) {
-            auto gi = I.gstore.find(Y.slot);
-            if (gi != I.gstore.end() && gi->second && gi->second->p) gcols.push_back(gi->second->as<double>());
+            if (double *gv = I.gslot(Y.slot)) gcols.push_back(gv);
         }
         if (o.use_prev_shift && g_prev_shift) gcols.push_back(g_prev_shift);
         for (const double *gv : gcols) {
@@ -907,23 +952,20 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         std::vector<const double *> v;
         std::vector<long> n;
         std::vector<SysHost *> need;
+        std::set<std::pair<const double *, int>> queued;
         for (auto *Y : sy) {
-            auto it = c->bnorm_cache.find({Y->b, Y->inst});
-            if (it != c->bnorm_cache.end()) {
-                Y->bnorm = it->second;
-            } else {
-                v.push_back(Y->b);
-                n.push_back(Y->n);
-                need.push_back(Y);
-            }
+            const auto key = std::make_pair((const double *)Y->b, Y->inst);
+            if (c->bnorm_cache.count(key) || queued.count(key)) continue;   // once per right-hand side
+            queued.insert(key);
+            v.push_back(Y->b);
+            n.push_back(Y->n);
+            need.push_back(Y);
         }
         if (!need.empty()) {
             auto bn = norms(c, v, n, s);
-            for (size_t i = 0; i < need.size(); ++i) {
-                need[i]->bnorm = bn[i];
-                c->bnorm_cache[{need[i]->b, need[i]->inst}] = bn[i];
-            }
+            for (size_t i = 0; i < need.size(); ++i) c->bnorm_cache[{need[i]->b, need[i]->inst}] = bn[i];
         }
+        for (auto *Y : sy) Y->bnorm = c->bnorm_cache[{Y->b, Y->inst}];
     }
     // initial guess
     tm.reset(new StageTimer(c, s, 1));
@@ -937,8 +979,11 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         int init = o.init;
         if ((init == RSR_INIT_MR || init == RSR_INIT_GALERKIN) && (I.p == 0 || !I.ae_valid)) init = RSR_INIT_ZERO;
         if (init == RSR_INIT_ZERO) {
-            HIPCHK(launch_fill(Y.x, 0.0, Y.n, s));
-            HIPCHK(hipMemcpyAsync(Y.r, Y.b, sizeof(double) * Y.n, hipMemcpyDeviceToDevice, s));
+            // x = 0 (a combination of no columns) and r = b, in the launch shared by all systems
+            cj.push_back(ComboJob{nullptr, Y.n, 0, nullptr, 0, Y.x, Y.n, 1, 0.0, nullptr, 0, Y.n});
+            qs.push_back(std::vector<double>{});
+            cj.push_back(ComboJob{Y.b, Y.n, 1, nullptr, 1, Y.r, Y.n, 1, 0.0, nullptr, 0, Y.n});
+            qs.push_back(std::vector<double>{1.0});
         } else if (init == RSR_INIT_GIVEN) {
             aj.push_back(ApplyJob{Y.inst, 0, 1.0, Y.gamma, Y.x, Y.r});
             Y.mvA++;
@@ -1135,13 +1180,28 @@ void store_corrections(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
 {
     std::vector<ComboJob> cj;
     std::vector<std::vector<double>> qs;
+    // columns for slots seen for the first time
     for (auto *Y : sy) {
         Instance &I = *c->inst[Y->inst];
-        auto &slot = I.gstore[Y->slot];
-        if (!slot) slot.reset(new DBuf());
-        slot->ensure(sizeof(double) * Y->n);
+        if (I.gcol.count(Y->slot)) continue;
+        const int col = (int)I.gcol.size();
+        I.gcol[Y->slot] = col;
+        if (col < I.gpool_cols) continue;
+        const int cap = std::max({col + 1, 2 * I.gpool_cols, 8});
+        DBuf nb;
+        nb.ensure(sizeof(double) * (size_t)cap * I.n);
+        if (I.gpool_cols > 0)
+            HIPCHK(hipMemcpyAsync(nb.p, I.gpool.p, sizeof(double) * (size_t)I.gpool_cols * I.n,
+                                  hipMemcpyDeviceToDevice, s));
+        std::swap(nb.p, I.gpool.p);
+        std::swap(nb.bytes, I.gpool.bytes);
+        nb.release();   // drains the device, so the copy above has landed
+        I.gpool_cols = cap;
+    }
+    for (auto *Y : sy) {
+        Instance &I = *c->inst[Y->inst];
         // g = x - xinit
-        cj.push_back(ComboJob{Y->xinit, Y->n, 1, nullptr, 1, slot->as<double>(), Y->n, 1, 0.0, Y->x, Y->n, Y->n});
+        cj.push_back(ComboJob{Y->xinit, Y->n, 1, nullptr, 1, I.gslot(Y->slot), Y->n, 1, 0.0, Y->x, Y->n, Y->n});
         qs.push_back(std::vector<double>{-1.0});
     }
     combo(c, cj, qs, s);
@@ -1240,7 +1300,7 @@ void rsr_destroy(rsr_ctx *c)
         I.d_fy.release(); I.d_fx.release(); I.d_psf.release(); I.d_wh.release(); I.d_wv.release(); I.d_band.release();
         I.d_U.release(); I.d_AE.release();
         I.ritz[0].buf.release(); I.ritz[1].buf.release();
-        for (auto &g : I.gstore) if (g.second) g.second->release();
+        I.gpool.release();
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
                     &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
@@ -1275,7 +1335,7 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
             p->d_band.release();
             p->d_U.release(); p->d_AE.release();
             p->ritz[0].buf.release(); p->ritz[1].buf.release();
-            for (auto &g : p->gstore) if (g.second) g.second->release();
+            p->gpool.release();
         }
         c->inst.clear();
         for (int i = 0; i < n_inst; ++i) {
@@ -1474,9 +1534,8 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
     double *C = Cb.as<double>();
     if (nr > 0) {
         const int p = I.p;
-        std::vector<double> H((size_t)p * p), w, V;
-        for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + gamma_retain * I.Ehat[k];
-        sym_eig(p, H.data(), w, V);
+        std::vector<double> w, V;
+        retained_eig(I, gamma_retain, w, V);
         std::vector<double> Wt((size_t)p * nr);
         for (int j = 0; j < nr; ++j)
             for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
@@ -1696,7 +1755,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 if (o.use_prev_shift) {
                     Instance &I = *c->inst[sys[i].inst];
                     gprev.ensure(sizeof(double) * I.n);
-                    HIPCHK(hipMemcpyAsync(gprev.p, I.gstore[sys[i].slot]->p, sizeof(double) * I.n,
+                    HIPCHK(hipMemcpyAsync(gprev.p, I.gslot(sys[i].slot), sizeof(double) * I.n,
                                           hipMemcpyDeviceToDevice, s));
                     gp = gprev.as<double>();
                 }
