@@ -159,6 +159,24 @@ rsr_status rsr_weights_from_image(rsr_ctx *ctx, int inst, const double *x, doubl
  * RSR_E_ARG.                                                                 */
 rsr_status rsr_weights_edge_rule(rsr_ctx *ctx, int inst, const double *x, double p, void *stream);
 
+/* Correction space for the principal-space update (Sec. 5.2, eq. delta).
+ * With the instance's current weights W_k and the previous ones (w_h_prev,
+ * w_v_prev: device [ny*nx], the layout of rsr_update_weights), runs at most
+ * max_steps CG steps from zero on
+ *     (A + gamma E_k) dx = gamma (E_k - E_{k-1}) x_prev
+ * (eq. delta multiplied by gamma; x_prev: device [ny*nx], the previous outer
+ * step's solution for this shift) and writes, with column stride ld:
+ *     V[0]       = dx, the approximate x_prev - x_k after those steps;
+ *     V[1 + j]   = r_j / ||r_j||, j < n_kry: the CG residuals, an orthonormal
+ *                  basis of the Krylov space of the correction equation.
+ * *n_out = 1 + the Krylov vectors produced (fewer than n_kry if CG stopped
+ * earlier).  V must hold 1 + n_kry columns.  The result is meant as extra
+ * candidates for rsr_set_recycle_space.  Requires gamma > 0 and
+ * 0 <= n_kry <= max_steps: else RSR_E_ARG.  Synchronises the stream.         */
+rsr_status rsr_correction_space(rsr_ctx *ctx, int inst, const double *x_prev, const double *w_h_prev,
+                                const double *w_v_prev, double gamma, int max_steps, int n_kry, double *V,
+                                long ld, int *n_out, void *stream);
+
 /* The L-curve of a shift set (Sec. 2.1, Sec. 2.2): for each system l of m,
  *   rho[l] = ||K x_l - d||_2  and  eta[l] = ||D_k L x_l||_2 = (x_l^T E_k x_l)^{1/2}
  * with the instance's current weights.  X: device, system l at X + l*ld_x

@@ -9,7 +9,9 @@ Plain NumPy definitions of the steps around the shifted solves of Section 2.1:
     gamma_l = lambda_l^2, their curvature and the corner (the point of maximum
     curvature, Sections 2.1 and 2.2);
   * the outer stopping rule of the first experiment of Section 8: stop once
-    the selected lambda has been the same for three consecutive outer steps.
+    the selected lambda has been the same for three consecutive outer steps;
+  * the right-hand side of the correction equation of Section 5.2 (eq. delta,
+    multiplied by gamma): gamma (E_k - E_{k-1}) x^(k-1,l).
 
 Readings where the paper is silent:
   * L stacks the horizontal and the vertical forward differences that exist in
@@ -25,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import conv
+from . import apply_E, conv
 
 
 def _differences(x: np.ndarray):
@@ -102,3 +104,8 @@ def lcurve_corner(gammas, rho, eta) -> int:
 def stop_rule(history, repeats: int = 3) -> bool:
     """True once the last `repeats` selected indices are all the same."""
     return len(history) >= repeats and len(set(history[-repeats:])) == 1
+
+
+def correction_rhs(wh, wv, wh_prev, wv_prev, gamma: float, x):
+    """gamma (E_k - E_{k-1}) x with E_k from (wh, wv) and E_{k-1} from the previous weights."""
+    return gamma * (apply_E(wh, wv, x) - apply_E(wh_prev, wv_prev, x))

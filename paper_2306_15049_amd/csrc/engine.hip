@@ -146,6 +146,7 @@ struct rsr_ctx {
     DBuf d_gprev;                      // previous shift's correction in sequential solves
     DBuf d_lz, d_lzc, d_lzr;           // CG-Lanczos capture (residuals, coefficients) and its Ritz vectors
     DBuf d_aux;                        // workgroup partials of the edge-weight and L-curve reductions
+    DBuf d_corr;                       // right-hand side of the correction equation
     // staging arena for launch descriptors and coefficients: pinned host and
     // device halves bump-allocated in step, reset whenever the stream is drained,
     // so that launches whose inputs come from the host need no synchronisation
@@ -1304,7 +1305,7 @@ void rsr_destroy(rsr_ctx *c)
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
                     &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
-                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux})
+                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux, &c->d_corr})
         b->release();
     if (c->ar_host) (void)hipHostFree(c->ar_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1673,6 +1674,73 @@ int seed_from_lanczos(rsr_ctx *c, const SysHost &Y, long nlz, int seed_p, hipStr
               {Q}, s);
     }
     return set_recycle_space_impl(c, Y.inst, cand, Y.n, k + 1, 0, 0.0, seed_p, 1e10, s);
+}
+
+// Correction space of the principal-space update (Sec. 5.2, eq. delta times
+// gamma): at most max_steps CG steps on (A + gamma E_k) dx = gamma (E_k - E_{k-1}) x_prev
+// from dx = 0, recording the first n_kry residuals; V = [dx, r_j / ||r_j||].
+rsr_status rsr_correction_space(rsr_ctx *c, int ii, const double *x_prev, const double *wh_prev,
+                                const double *wv_prev, double gamma, int max_steps, int n_kry, double *V, long ld,
+                                int *n_out, void *stream)
+{
+    return guard(c, [&] {
+        Instance &I = get_inst(c, ii);
+        if (!x_prev || !wh_prev || !wv_prev || !V || !n_out) fail(RSR_E_ARG, "null argument");
+        *n_out = 0;
+        if (!(gamma > 0.0) || !std::isfinite(gamma)) fail(RSR_E_ARG, "gamma must be positive");
+        if (max_steps < 1 || n_kry < 0 || n_kry > max_steps) fail(RSR_E_ARG, "need 1 <= max_steps, 0 <= n_kry <= max_steps");
+        if (n_kry > 0 && ld < I.n) fail(RSR_E_ARG, "ld smaller than ny*nx");
+        set_device(c);
+        hipStream_t s = S(stream);
+        const long n = I.n;
+        c->d_corr.ensure(sizeof(double) * n);
+        HIPCHK(launch_weight_delta(x_prev, I.d_wh.as<double>(), I.d_wv.as<double>(), wh_prev, wv_prev, gamma, I.ny,
+                                   I.nx, c->d_corr.as<double>(), s));
+        std::vector<SysHost> sys(1);
+        SysHost &Y = sys[0];
+        Y.inst = ii;
+        Y.slot = -1;
+        Y.gamma = gamma;
+        Y.n = n;
+        Y.b = c->d_corr.as<double>();
+        Y.x = V;
+        alloc_ws(c, sys);
+        c->bnorm_cache.clear();
+        c->rhs_cache.clear();
+        if (n_kry > 0) {
+            c->d_lz.ensure(sizeof(double) * (size_t)n_kry * n);
+            c->d_lzc.ensure(sizeof(double) * (size_t)3 * n_kry);
+            HIPCHK(launch_fill(c->d_lzc.as<double>(), 0.0, 3 * (long)n_kry, s));
+            Y.lz = c->d_lz.as<double>();
+            Y.lzc = c->d_lzc.as<double>();
+            Y.nlz = n_kry;
+        }
+        c->last_cg_ms = 0.0;
+        c->last_launches = 0;
+        c->last_items = 0;
+        // plain CG from zero for at most max_steps steps (no local space)
+        Opts o{1e-15, max_steps, RSR_INIT_ZERO, 0, 0, 0, 1 << 30, gamma, gamma};
+        std::vector<SysHost *> one{&Y};
+        solve_group(c, one, o, nullptr, s);
+        int got = 0;
+        if (n_kry > 0 && Y.lz_its > 0) {
+            std::vector<double> co((size_t)3 * n_kry);
+            HIPCHK(hipMemcpyAsync(co.data(), c->d_lzc.p, sizeof(double) * co.size(), hipMemcpyDeviceToHost, s));
+            sync(c, s);
+            const double *rho = co.data() + 2 * n_kry;
+            const int m = std::min(n_kry, Y.lz_its);
+            std::vector<ComboJob> cj;
+            std::vector<std::vector<double>> qs;
+            for (int j = 0; j < m && rho[j] > 0.0; ++j, ++got) {
+                cj.push_back(ComboJob{c->d_lz.as<double>() + (size_t)j * n, n, 1, nullptr, 1, V + (size_t)(1 + j) * ld, n,
+                                      1, 0.0, nullptr, 0, n});
+                qs.push_back(std::vector<double>{1.0 / std::sqrt(rho[j])});
+            }
+            combo(c, cj, qs, s);
+        }
+        sync(c, s);
+        *n_out = 1 + got;
+    });
 }
 
 rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X,

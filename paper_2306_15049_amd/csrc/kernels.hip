@@ -267,6 +267,35 @@ hipError_t launch_edge_rule(const double *x, double *wh, double *wv, int ny, int
     return hipGetLastError();
 }
 
+// ------------------------------------------ correction right-hand side --
+// out = gamma (E_k - E_{k-1}) x with E = D^T W D: per pixel, the sum over its
+// incident differences of gamma (w_k - w_{k-1}) (x_p - x_other).
+__global__ __launch_bounds__(NT) void k_weight_delta(const double *__restrict__ x, const double *__restrict__ wh,
+                                                     const double *__restrict__ wv, const double *__restrict__ wh0,
+                                                     const double *__restrict__ wv0, double gamma, int ny, int nx,
+                                                     double *__restrict__ out)
+{
+    const long n = (long)ny * nx;
+    for (long gi = blockIdx.x * (long)NT + threadIdx.x; gi < n; gi += (long)gridDim.x * NT) {
+        const int i = gi / nx, j = gi % nx;
+        const double xc = x[gi];
+        double acc = 0.0;
+        if (j < nx - 1) acc += (wh[gi] - wh0[gi]) * (xc - x[gi + 1]);
+        if (j > 0) acc += (wh[gi - 1] - wh0[gi - 1]) * (xc - x[gi - 1]);
+        if (i < ny - 1) acc += (wv[gi] - wv0[gi]) * (xc - x[gi + nx]);
+        if (i > 0) acc += (wv[gi - nx] - wv0[gi - nx]) * (xc - x[gi - nx]);
+        out[gi] = gamma * acc;
+    }
+}
+
+hipError_t launch_weight_delta(const double *x, const double *wh, const double *wv, const double *wh0,
+                               const double *wv0, double gamma, int ny, int nx, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_weight_delta, dim3(grid_for((long)ny * nx)), dim3(NT), 0, s, x, wh, wv, wh0, wv0, gamma, ny,
+                       nx, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------ L-curve coordinates --
 // For system y (blockIdx.y): per-workgroup partial sums of (K x - d)^2 and of
 // the weighted squared differences sum_e W_e (L x)_e^2 = x^T E x.  K x is the

@@ -52,6 +52,9 @@ class RecycleParams:
     seed_lanczos: int = 0     # k = 0, sequential: CG-Lanczos steps of the first shift that seed U (0: off)
     seed_p: int = 30          # Ritz vectors of those steps kept as the seeded U
     seed_n_ritz: int = 3      # Ritz vectors in the local spaces of the shifts after the seed
+    correction: int = 5       # k >= 1: Krylov vectors of the correction equation added to U (0: off)
+    correction_steps: int = 50    # CG steps on the correction equation
+    correction_frac: float = 0.9  # the correction shift l_c = round(frac * M) (1-based)
     split_frac: float = 0.75
     beta: float = 1e-4
     cond_max: float = 1e10
@@ -160,13 +163,24 @@ class OuterLoop:
         p_dim = 0
         if self.k > 0:
             for i in range(n_inst):
+                corr = self.method != "plain" and self.rp.correction > 0
+                if corr:
+                    wold = ctx.get_weights(i)   # W_{k-1}, for the correction equation
                 if self.weight_rule == "edge":
                     ctx.weights_edge_rule(i, self.X[i][self.l_stars[i]], self.edge_p)
                 else:
                     ctx.weights_from_image(i, self.X[i][self.l_stars[i]], self.rp.beta)
                 if self.method != "plain":
-                    n_retain = max(0, self.rp.p - self.M)
-                    p_dim = ctx.set_recycle_space(i, self.X[i], n_retain=n_retain,
+                    cand, n_extra = self.X[i], 0
+                    if corr:
+                        # [dx, Krylov vectors] of eq. delta at the shift l_c join the candidates
+                        lc = min(self.M - 1, max(0, int(round(self.rp.correction_frac * self.M)) - 1))
+                        V, nv = ctx.correction_space(i, self.X[i][lc], wold[0], wold[1], float(self.cfg.gammas[lc]),
+                                                     self.rp.correction_steps, self.rp.correction)
+                        cand = torch.cat([self.X[i], V[:nv]])
+                        n_extra = nv
+                    n_retain = max(0, self.rp.p - self.M - n_extra)
+                    p_dim = ctx.set_recycle_space(i, cand, n_retain=n_retain,
                                                   gamma_retain=float(self.cfg.gammas[0]), p_max=self.rp.p,
                                                   cond_max=self.rp.cond_max)
         o = self._opts()

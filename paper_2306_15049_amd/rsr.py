@@ -26,7 +26,7 @@ EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_se
            "rsr_update_weights", "rsr_weights_from_image", "rsr_get_weights", "rsr_apply",
            "rsr_set_recycle_space", "rsr_solve_shift_set", "rsr_adjoint", "rsr_autotune", "rsr_get_tile",
            "rsr_set_tile", "rsr_get_recycle_info", "rsr_get_recycle_basis", "rsr_get_counters",
-           "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve"]
+           "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve", "rsr_correction_space"]
 
 
 class RsrError(RuntimeError):
@@ -100,6 +100,7 @@ def load():
     L.rsr_last_solve_timing.argtypes = [P, pD, pI, ctypes.POINTER(L_)]
     L.rsr_weights_edge_rule.argtypes = [P, I, P, D, P]
     L.rsr_lcurve.argtypes = [P, I, I, pD, P, L_, P, pD, pD, pD, pI, P]
+    L.rsr_correction_space.argtypes = [P, I, P, P, P, D, I, I, P, L_, pI, P]
     for name in EXPORTS:
         if name not in ("rsr_destroy", "rsr_last_error", "rsr_version"):
             getattr(L, name).restype = ctypes.c_int
@@ -198,6 +199,18 @@ class Context:
                                         rho.ctypes.data_as(pd), eta.ctypes.data_as(pd), kap.ctypes.data_as(pd),
                                         ctypes.byref(corner), _stream()))
         return rho, eta, kap, corner.value
+
+    def correction_space(self, inst: int, x_prev, wh_prev, wv_prev, gamma: float, max_steps: int = 100,
+                         n_kry: int = 10):
+        """[dx, Krylov vectors] of the correction equation (eq. delta); returns (V [1+n_kry, ny, nx], n_out)."""
+        import torch
+        ny, nx = self.shapes[inst]
+        V = torch.zeros((1 + n_kry, ny, nx), dtype=torch.float64, device="cuda")
+        nout = ctypes.c_int(0)
+        self._check(self.lib.rsr_correction_space(self.h, inst, _ptr(x_prev), _ptr(wh_prev), _ptr(wv_prev),
+                                                  float(gamma), int(max_steps), int(n_kry), _ptr(V), ny * nx,
+                                                  ctypes.byref(nout), _stream()))
+        return V, nout.value
 
     def get_weights(self, inst: int):
         import torch

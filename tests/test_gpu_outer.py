@@ -8,6 +8,9 @@
   problem, and on the 256 x 256 workload's sizes.
 * The outer loop with the L-curve choice of the shift and the edge rule: the
   residual gate at every step and the weights against the oracle's rule.
+* rsr_correction_space (eq. delta): dx after a fixed number of CG steps and the
+  normalised Krylov vectors against the oracle's CG on the oracle's right-hand
+  side; the outer loop with those vectors among the principal candidates.
 """
 import numpy as np
 import pytest
@@ -134,3 +137,62 @@ def test_outer_loop_with_lcurve_and_edge_rule(ctx, mode):
         # the oracle's corner, or a point whose curvature ties with it to rounding
         assert kap_o[rec.l_star] >= np.nanmax(kap_o) * (1 - 1e-9), (rec.l_star, kap_o)
     assert loop.stopped == outer.stop_rule(loop.l_history)
+
+
+def test_correction_space_matches_oracle_cg(ctx):
+    # eq. delta times gamma, (A + gamma E_k) dx = gamma (E_k - E_{k-1}) x_{k-1}: the
+    # library's dx after `steps` CG steps and its Krylov vectors against the
+    # oracle's plain CG on the same right-hand side (Sec. 5.2)
+    pr = synth.make_problem(23, 24, 20, 1.5, 7, 3)
+    _, b = oracle.rhs(pr)
+    ny, nx = pr.ny, pr.nx
+    wh0 = np.ones((ny, nx))
+    wv0 = np.ones((ny, nx))
+    wh0[:, -1] = 0.0
+    wv0[-1, :] = 0.0
+    wh1, wv1 = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    gamma, steps, nk = 0.2, 12, 8
+    Am = dense.dense_A(pr.psf, ny, nx)
+    x_prev = dense.cholesky_solve(Am + gamma * dense.dense_E(wh0, wv0), b).reshape(ny, nx)
+    ctx.set_operators([(ny, nx)], [pr.psf])
+    ctx.update_weights(0, to_dev(wh1), to_dev(wv1))
+    print("correction space 24x20", flush=True)
+    V, nout = ctx.correction_space(0, to_dev(x_prev), to_dev(wh0), to_dev(wv0), gamma, steps, nk)
+    assert nout == 1 + nk
+    V = to_host(V)
+    rhs = outer.correction_rhs(wh1, wv1, wh0, wv0, gamma, x_prev)
+    x_o, st, R, _ = oracle.cg(pr.psf, wh1, wv1, gamma, rhs, tol=1e-30, maxit=steps, record=nk)
+    assert st["iters"] == steps
+    assert np.linalg.norm(V[0] - x_o) <= 1e-9 * np.linalg.norm(x_o), (
+        np.linalg.norm(V[0] - x_o) / np.linalg.norm(x_o))
+    for j in range(nk):
+        rj = R[j] / np.linalg.norm(R[j])
+        assert np.linalg.norm(V[1 + j] - rj) <= 1e-8, j
+    # the Krylov vectors are orthonormal (CG residuals are mutually orthogonal)
+    K = V[1:].reshape(nk, -1)
+    np.testing.assert_allclose(K @ K.T, np.eye(nk), atol=1e-9)
+    # unchanged weights: a zero right-hand side, dx = 0 and no Krylov vectors
+    V2, n2 = ctx.correction_space(0, to_dev(x_prev), to_dev(wh1), to_dev(wv1), gamma, steps, nk)
+    assert n2 == 1 and np.abs(to_host(V2)[0]).max() == 0.0
+    with pytest.raises(rsr.RsrError):
+        ctx.correction_space(0, to_dev(x_prev), to_dev(wh0), to_dev(wv0), gamma, 4, 8)   # n_kry > max_steps
+
+
+def test_outer_loop_with_correction_space(ctx):
+    # V^(new) of eq. delta (dx and 10 Krylov vectors at l_c) among the candidates of U
+    cfg = synth.config("C1")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    rp = irn.RecycleParams(p=cfg.p, correction=6, correction_steps=30)
+    loop = irn.OuterLoop(ctx, cfg, "recycled", rp=rp, mode=rsr.SEQUENTIAL)
+    loop.b[0] = to_dev(b)
+    for k in range(3):
+        print(f"outer loop with correction space: k={k}", flush=True)
+        rec = loop.step()
+        if k > 0:
+            assert rec.p > 0
+        wh, wv = (to_host(t) for t in ctx.get_weights(0))
+        X = to_host(loop.X[0])
+        for l, g in enumerate(cfg.gammas):
+            rel = oracle.true_relres(pr.psf, wh, wv, g, b, X[l])
+            assert rel <= 1e-8, (k, l, rel)

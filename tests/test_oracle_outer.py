@@ -158,3 +158,25 @@ def test_stop_rule():
     assert outer.stop_rule([2, 4, 4, 4])
     assert not outer.stop_rule([4, 4, 5])
     assert outer.stop_rule([1, 1], repeats=2)
+
+
+def test_correction_rhs_satisfies_eq_delta():
+    # with exact solutions of the steps k-1 and k, (A + gamma E_k)(x_{k-1} - x_k)
+    # is the right-hand side gamma (E_k - E_{k-1}) x_{k-1} (Sec. 5.2)
+    from oracle import dense
+    pr = synth.make_problem(9, 14, 12, 1.2, 5, 3)
+    _, b = oracle.rhs(pr)
+    w0 = _unit(14, 12)
+    w1 = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    Am = dense.dense_A(pr.psf, 14, 12)
+    for gamma in (1e-3, 0.3):
+        x0 = dense.cholesky_solve(Am + gamma * dense.dense_E(*w0), b).ravel()
+        x1 = dense.cholesky_solve(Am + gamma * dense.dense_E(*w1), b).ravel()
+        rhs = outer.correction_rhs(w1[0], w1[1], w0[0], w0[1], gamma, x0.reshape(14, 12)).ravel()
+        lhs = (Am + gamma * dense.dense_E(*w1)) @ (x0 - x1)
+        assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs)
+    # unchanged weights give a zero right-hand side; E is linear in the weights
+    x = np.random.default_rng(1).standard_normal((14, 12))
+    assert np.abs(outer.correction_rhs(w1[0], w1[1], w1[0], w1[1], 0.5, x)).max() == 0.0
+    d = outer.correction_rhs(w1[0], w1[1], w0[0], w0[1], 0.5, x)
+    np.testing.assert_allclose(d, 0.5 * oracle.apply_E(w1[0] - w0[0], w1[1] - w0[1], x), atol=1e-13)
