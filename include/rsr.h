@@ -69,11 +69,16 @@ enum { RSR_OP_B = 0,   /* y = (A + gamma E) v */
        RSR_OP_K = 3,   /* y = K v             */
        RSR_OP_KT = 4   /* y = K^T v           */ };
 
-/* Initial guess (Sec. 4.1). */
+/* Initial guess (Sec. 4.1; the oblique variant of Sec. 7). */
 enum { RSR_INIT_ZERO = 0,      /* x0 = 0                                        */
        RSR_INIT_GIVEN = 1,     /* x0 = contents of X on entry                   */
        RSR_INIT_MR = 2,        /* x0 = U q, q minimises ||b - (AU + gamma EU) q|| (eq. orthupdate) */
-       RSR_INIT_GALERKIN = 3   /* x0 = U (U^T B U)^{-1} U^T b                   */ };
+       RSR_INIT_GALERKIN = 3,  /* x0 = U (U^T B U)^{-1} U^T b                   */
+       RSR_INIT_OBLIQUE = 4    /* x0 = U q with K^T r0 = 0 for K = (A + gamma_* E) U
+                                  (eq. obliqueupdate); gamma_* = gamma_JL for
+                                  slots < split_I, gamma_JR otherwise (the two
+                                  groups' K_L, K_R); falls back to MR when
+                                  K^T (A + gamma E) U is singular            */ };
 
 /* Solve modes. */
 enum { RSR_BATCHED = 0,        /* all systems advance together in one persistent launch */

@@ -8,7 +8,8 @@ computes, written with NumPy/SciPy primitives and no blocking or fusion:
   * the generalized-eigenvector closed form of all shifted solutions
     (Section 3.1, eq. x_gamma) and the difference formula (eq. compare);
   * the minimum-residual initial guess over Range(U) (Section 4.1,
-    eq. orthupdate), also in the paper's K-basis form (eq. establishU);
+    eq. orthupdate), also in the paper's K-basis form (eq. establishU), and
+    the oblique guess of Section 7 (eq. obliqueupdate);
   * the stabilised principal basis (Algorithm 1) and the Ritz block
     (Algorithm 2);
   * deflated CG with a local space W (the CG form of the shift-specific
@@ -127,6 +128,22 @@ def mr_guess_kbasis(Am, Em, U, b, gamma, gamma_star):
     rhs = K.T @ b.ravel() + d * (EU.T @ b.ravel())
     q = np.linalg.solve(lhs, rhs)
     return Ui @ q
+
+
+def oblique_guess(Am, Em, U, b, gamma, gamma_star):
+    """The oblique initial guess of Section 7 (eq. obliqueupdate), in the paper's form.
+
+    (A + gamma_* E) U = K R (skinny QR, K orthonormal), U_t = U R^{-1}, d = gamma - gamma_*;
+    solve (I + d K^T E U_t) q = K^T b, x0 = U_t q.  Then r0 = b - (A + gamma E) x0 is
+    orthogonal to K (Petrov-Galerkin with the test space K).  Returns (x0, r0).
+    """
+    K, R = np.linalg.qr((Am + gamma_star * Em) @ U)
+    Ut = np.linalg.solve(R.T, U.T).T        # U R^{-1}, so that (A + gamma_* E) U_t = K
+    d = gamma - gamma_star
+    lhs = np.eye(U.shape[1]) + d * (K.T @ (Em @ Ut))
+    q = np.linalg.solve(lhs, K.T @ b.ravel())
+    x0 = Ut @ q
+    return x0, b.ravel() - (Am + gamma * Em) @ x0
 
 
 def galerkin_guess(Bm, U, b):

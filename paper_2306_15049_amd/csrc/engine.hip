@@ -978,7 +978,8 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         SysHost &Y = *Yp;
         Instance &I = *c->inst[Y.inst];
         int init = o.init;
-        if ((init == RSR_INIT_MR || init == RSR_INIT_GALERKIN) && (I.p == 0 || !I.ae_valid)) init = RSR_INIT_ZERO;
+        if ((init == RSR_INIT_MR || init == RSR_INIT_GALERKIN || init == RSR_INIT_OBLIQUE) && (I.p == 0 || !I.ae_valid))
+            init = RSR_INIT_ZERO;
         if (init == RSR_INIT_ZERO) {
             // x = 0 (a combination of no columns) and r = b, in the launch shared by all systems
             cj.push_back(ComboJob{nullptr, Y.n, 0, nullptr, 0, Y.x, Y.n, 1, 0.0, nullptr, 0, Y.n});
@@ -1008,13 +1009,15 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     for (auto *Yp : sy) {
         SysHost &Y = *Yp;
         Instance &I = *c->inst[Y.inst];
-        if (!((o.init == RSR_INIT_MR || o.init == RSR_INIT_GALERKIN) && I.p > 0 && I.ae_valid)) continue;
+        if (!((o.init == RSR_INIT_MR || o.init == RSR_INIT_GALERKIN || o.init == RSR_INIT_OBLIQUE) && I.p > 0 &&
+              I.ae_valid))
+            continue;
         prin.push_back(&Y);
         const auto key = std::make_tuple((const double *)Y.b, Y.inst, o.init);
         if (c->rhs_cache.count(key) || queued.count(key)) continue;   // once per right-hand side
         queued.insert(key);
         fresh.push_back(&Y);
-        if (o.init == RSR_INIT_MR)
+        if (o.init == RSR_INIT_MR || o.init == RSR_INIT_OBLIQUE)
             gj.push_back(GramJob{I.d_AE.as<double>(), I.n, 2 * I.p, Y.b, Y.n, 1, Y.n, nullptr, 0});
         else
             gj.push_back(GramJob{I.d_U.as<double>(), I.n, I.p, Y.b, Y.n, 1, Y.n, nullptr, 0});
@@ -1045,22 +1048,37 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
             const int p = I.p;
             const double g = Y.gamma;
             std::vector<double> H((size_t)p * p), f(p), q(p), P;
-            if (o.init == RSR_INIT_MR) {
-                // (AU + g EU)^T (AU + g EU) q = (AU + g EU)^T b
+            bool solved = false;
+            if (o.init == RSR_INIT_OBLIQUE) {
+                // K = AU + gs EU with the group's reference shift gs; the oblique
+                // condition K^T r0 = 0 gives K^T (AU + g EU) q = K^T b (eq. obliqueupdate)
+                const double gs = Y.slot < o.split_I ? o.gJL : o.gJR;
                 for (int i = 0; i < p; ++i)
                     for (int j = 0; j < p; ++j)
-                        H[(size_t)i * p + j] = I.Gaa[(size_t)i * p + j] + g * (I.Gae[(size_t)i * p + j] + I.Gae[(size_t)j * p + i]) +
-                                               g * g * I.Gee[(size_t)i * p + j];
-                for (int i = 0; i < p; ++i) f[i] = rhs[k][i] + g * rhs[k][p + i];
-            } else {
-                for (size_t t = 0; t < H.size(); ++t) H[t] = I.Ahat[t] + g * I.Ehat[t];
-                for (int i = 0; i < p; ++i) f[i] = rhs[k][i];
+                        H[(size_t)i * p + j] = I.Gaa[(size_t)i * p + j] + g * I.Gae[(size_t)i * p + j] +
+                                               gs * I.Gae[(size_t)j * p + i] + gs * g * I.Gee[(size_t)i * p + j];
+                for (int i = 0; i < p; ++i) f[i] = rhs[k][i] + gs * rhs[k][p + i];
+                solved = lu_solve(p, H.data(), f.data(), q.data());
             }
-            // Cholesky of the scaled p x p system; eigen pseudo-inverse when it is
-            // numerically singular (rank guard)
-            if (!spd_solve(p, H.data(), f.data(), q.data())) {
-                spd_pinv(p, H.data(), 1e-15, P);
-                matvec(p, p, P.data(), f.data(), q.data());
+            if (!solved) {
+                if (o.init == RSR_INIT_MR || o.init == RSR_INIT_OBLIQUE) {
+                    // (AU + g EU)^T (AU + g EU) q = (AU + g EU)^T b
+                    for (int i = 0; i < p; ++i)
+                        for (int j = 0; j < p; ++j)
+                            H[(size_t)i * p + j] = I.Gaa[(size_t)i * p + j] +
+                                                   g * (I.Gae[(size_t)i * p + j] + I.Gae[(size_t)j * p + i]) +
+                                                   g * g * I.Gee[(size_t)i * p + j];
+                    for (int i = 0; i < p; ++i) f[i] = rhs[k][i] + g * rhs[k][p + i];
+                } else {
+                    for (size_t t = 0; t < H.size(); ++t) H[t] = I.Ahat[t] + g * I.Ehat[t];
+                    for (int i = 0; i < p; ++i) f[i] = rhs[k][i];
+                }
+                // Cholesky of the scaled p x p system; eigen pseudo-inverse when it is
+                // numerically singular (rank guard)
+                if (!spd_solve(p, H.data(), f.data(), q.data())) {
+                    spd_pinv(p, H.data(), 1e-15, P);
+                    matvec(p, p, P.data(), f.data(), q.data());
+                }
             }
             // x = U q ; r = b - [AU EU] [q; g q]
             InitGrp *G = nullptr;
@@ -1752,7 +1770,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
         const int m = d->n_sys;
         if (m <= 0 || !d->inst || !d->gammas) fail(RSR_E_ARG, "n_sys must be positive with inst and gammas");
         if (!(d->tol > 0.0)) fail(RSR_E_ARG, "tol must be positive");
-        if (d->init < 0 || d->init > 3) fail(RSR_E_ARG, "unknown init");
+        if (d->init < 0 || d->init > 4) fail(RSR_E_ARG, "unknown init");
         if (d->n_ritz < 0 || d->n_ritz > QMAX) fail(RSR_E_ARG, "n_ritz out of range");
         if (d->seed_lanczos < 0 || d->seed_p < 0 || d->seed_n_ritz < 0 || d->seed_n_ritz > QMAX)
             fail(RSR_E_ARG, "seed sizes out of range");

@@ -279,6 +279,40 @@ inline bool chol_qr_factor(int n, const double *G, std::vector<double> &T)
     return true;
 }
 
+// Solve the general n x n system S x = f (row-major) by Gaussian elimination
+// with partial pivoting.  Returns false (x untouched) when a pivot falls below
+// rel times the largest entry of S (numerically singular).
+inline bool lu_solve(int n, const double *S, const double *f, double *x, double rel = 1e-14)
+{
+    std::vector<double> A(S, S + (size_t)n * n), b(f, f + n);
+    double amax = 0.0;
+    for (double v : A) amax = std::max(amax, std::fabs(v));
+    if (!(amax > 0.0)) return n == 0;
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(A[(size_t)i * n + k]) > std::fabs(A[(size_t)piv * n + k])) piv = i;
+        if (!(std::fabs(A[(size_t)piv * n + k]) > rel * amax)) return false;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)piv * n + j]);
+            std::swap(b[k], b[piv]);
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const double l = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+            if (l == 0.0) continue;
+            for (int j = k; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double t = b[i];
+        for (int j = i + 1; j < n; ++j) t -= A[(size_t)i * n + j] * b[j];
+        b[i] = t / A[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) x[i] = b[i];
+    return true;
+}
+
 inline void matvec(int n, int m, const double *M, const double *x, double *y)  // y = M x, M n x m
 {
     for (int i = 0; i < n; ++i) {

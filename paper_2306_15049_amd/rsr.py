@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "librsr.so")
 
 OP_B, OP_A, OP_E, OP_K, OP_KT = 0, 1, 2, 3, 4
-INIT_ZERO, INIT_GIVEN, INIT_MR, INIT_GALERKIN = 0, 1, 2, 3
+INIT_ZERO, INIT_GIVEN, INIT_MR, INIT_GALERKIN, INIT_OBLIQUE = 0, 1, 2, 3, 4
 BATCHED, SEQUENTIAL = 0, 1
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_STATE", -3: "E_NONFINITE", -4: "E_NOT_SPD",
           -5: "E_RANK", -6: "E_NOMEM", -7: "E_HIP", -8: "E_TIMEOUT"}

@@ -4,7 +4,8 @@
   sigma_1 / sigma_i threshold, range inside the candidates; the small blocks
   U^T A U and U^T E U against the oracle's loop operators.
 * Initial guess of Section 4.1 (eq. orthupdate): the minimum-residual point of
-  Range(U) against the dense least-squares solution.
+  Range(U) against the dense least-squares solution; the oblique guess of
+  Section 7 (eq. obliqueupdate) against the oracle and its residual identity.
 * The full recycled outer loop (weights -> principal space -> local spaces ->
   deflated CG) on the 32 x 32 workload, sequential and batched: residual gate
   at 1e-8 and solution gate at 1e-12 against dense Cholesky.
@@ -88,6 +89,41 @@ def test_mr_initial_guess_matches_least_squares(ctx, gamma):
     x0 = to_host(X)[0].ravel()
     assert np.linalg.norm(x0 - x0_ref) <= 1e-7 * np.linalg.norm(x0_ref)
     assert abs(st[0]["relres_init"] - np.linalg.norm(r0_ref) / np.linalg.norm(b)) <= 1e-7
+
+
+@pytest.mark.parametrize("gamma,gstar", [(1e-3, 0.1), (0.1, 0.1), (3.0, 0.5)])
+def test_oblique_initial_guess_matches_oracle(ctx, gamma, gstar):
+    # Sec. 7 (eq. obliqueupdate): two systems in two groups, each with its own
+    # reference shift (K_L from gamma_JL, K_R from gamma_JR)
+    n = 20
+    pr, b, wh, wv = _setup(ctx, n=n)
+    Am, Em = dense.dense_A(pr.psf, n, n), dense.dense_E(wh, wv)
+    xs = dense.cholesky_solve(Am + gamma * Em, b).ravel()
+    rng = np.random.default_rng(7)
+    Ur = np.stack([(xs + 1e-3 * rng.standard_normal(n * n)).reshape(n, n)] +
+                  [rng.standard_normal((n, n)) for _ in range(4)])
+    p = ctx.set_recycle_space(0, to_dev(Ur), p_max=5)
+    U = to_host(ctx.recycle_basis(0)).reshape(p, -1).T
+    refs = [gstar, 2.0 * gstar]
+    X = to_dev(np.zeros((2, n, n)))
+    o = rsr.SolveOptions(tol=1e6, init=rsr.INIT_OBLIQUE, split_I=1, gamma_JL=refs[0], gamma_JR=refs[1])
+    rc, st = ctx.solve([gamma, gamma], to_dev(b), X, slots=[0, 1], opts=o)
+    for l in range(2):
+        assert st[l]["iters"] == 0
+        x0_ref, r0_ref = dense.oblique_guess(Am, Em, U, b, gamma, refs[l])
+        x0 = to_host(X)[l].ravel()
+        assert np.linalg.norm(x0 - x0_ref) <= 1e-7 * np.linalg.norm(x0_ref), l
+        assert abs(st[l]["relres_init"] - np.linalg.norm(r0_ref) / np.linalg.norm(b)) <= 1e-7
+        # the residual identity K^T r0 = 0 on the library's own guess
+        K = (Am + refs[l] * Em) @ U
+        r0 = b.ravel() - (Am + gamma * Em) @ x0
+        assert np.linalg.norm(K.T @ r0) <= 1e-8 * np.linalg.norm(K) * np.linalg.norm(b)
+    # a full oblique-initialised solve still meets the residual gate
+    X = to_dev(np.zeros((2, n, n)))
+    o = rsr.SolveOptions(tol=1e-8, init=rsr.INIT_OBLIQUE, split_I=1, gamma_JL=refs[0], gamma_JR=refs[1])
+    rc, st = ctx.solve([gamma, 2 * gamma], to_dev(b), X, slots=[0, 1], opts=o)
+    for l, g in enumerate([gamma, 2 * gamma]):
+        assert oracle.true_relres(pr.psf, wh, wv, g, b, to_host(X)[l]) <= 1e-8
 
 
 def test_galerkin_initial_guess_matches_dense(ctx):

@@ -272,6 +272,28 @@ def test_mr_guess_kbasis_equals_least_squares():
             assert np.linalg.norm(b.ravel() - Bm @ xo) > np.linalg.norm(r0)
 
 
+def test_oblique_guess_residual_identity_and_special_cases():
+    # Sec. 7: K^T r0 = 0 for K = (A + gamma_* E) U (the defining Petrov-Galerkin
+    # condition); at gamma = gamma_* the oblique and orthogonal projections
+    # coincide; the orthogonal (minimum-residual) guess is never worse
+    Am, Em, U, b = _dense_setup()
+    for gs in (1e-3, 0.1):
+        K = (Am + gs * Em) @ U
+        for gamma in (1e-4, 1e-2, 0.1, 2.0):
+            x0, r0 = dense.oblique_guess(Am, Em, U, b, gamma, gs)
+            assert np.linalg.norm(K.T @ r0) <= 1e-9 * np.linalg.norm(K) * np.linalg.norm(b)
+            xm, rm = dense.mr_guess(Am + gamma * Em, U, b)
+            assert np.linalg.norm(rm) <= np.linalg.norm(r0) * (1 + 1e-12)
+            if gamma == gs:
+                assert np.linalg.norm(x0 - xm) <= 1e-8 * np.linalg.norm(xm)
+    # exact when the solution lies in Range(U)
+    gamma = 0.05
+    xs = dense.cholesky_solve(Am + gamma * Em, b).ravel()
+    U2, _ = np.linalg.qr(np.column_stack([U, xs]))
+    x0, r0 = dense.oblique_guess(Am, Em, U2, b, gamma, 0.5)
+    assert np.linalg.norm(r0) <= 1e-9 * np.linalg.norm(b)
+
+
 def test_mr_guess_exact_when_solution_in_range():
     Am, Em, U, b = _dense_setup()
     gamma = 0.05
