@@ -45,6 +45,37 @@ def gaussian_psf(sigma: float, size: int) -> np.ndarray:
     return h / h.sum()
 
 
+def gaussian_1d(half_width: int, sigma: float) -> np.ndarray:
+    """Sum-normalised sampled Gaussian of length 2 * half_width + 1."""
+    a = np.arange(-half_width, half_width + 1, dtype=np.float64)
+    g = np.exp(-(a * a) / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def kronecker_sum_psf(terms) -> np.ndarray:
+    """PSF of C = sum_i C_i^(1) (x) C_i^(2) with banded Gaussian Toeplitz factors.
+
+    ``terms`` lists ((band1, sigma1), (band2, sigma2)) per Kronecker term:
+    C^(1) acts along rows (horizontal), C^(2) along columns (vertical), the
+    band is the number of nonzero off-diagonals on each side.  Each term's
+    outer product v u^T is zero-padded to the common centred support and the
+    terms are averaged, so the PSF sums to 1 and has rank len(terms).
+    """
+    cols = [gaussian_1d(b2, s2) for (_, _), (b2, s2) in terms]
+    rows = [gaussian_1d(b1, s1) for (b1, s1), (_, _) in terms]
+    hy = max(len(v) for v in cols) // 2
+    hx = max(len(u) for u in rows) // 2
+    h = np.zeros((2 * hy + 1, 2 * hx + 1))
+    for v, u in zip(cols, rows):
+        oy, ox = hy - len(v) // 2, hx - len(u) // 2
+        h[oy:oy + len(v), ox:ox + len(u)] += np.outer(v, u) / len(terms)
+    return h
+
+
+# the blur of the deblurring example of Sec. 8: bands 8, 7, 12, 4 and sigmas 3, 5/2, 4, 2
+EXAMPLE1_TERMS = (((8, 3.0), (7, 2.5)), ((12, 4.0), (4, 2.0)))
+
+
 def psf_support(sigma: float) -> int:
     """Odd support 2*ceil(3 sigma) + 1 (reading of "6 sigma + 1")."""
     return 2 * int(math.ceil(3.0 * sigma)) + 1
@@ -105,7 +136,8 @@ class Config:
 
 
 def config(name: str, small: Optional[int] = None) -> Config:
-    """The five workloads C1..C5.  ``small`` replaces the image side (tests)."""
+    """The workloads C1..C5 and X1 (the first example's blur).  ``small`` replaces
+    the image side (tests)."""
     if name == "C1":
         n = small or 32
         pr = make_problem(1, n, n, 1.5, 7, 6)
@@ -128,6 +160,15 @@ def config(name: str, small: Optional[int] = None) -> Config:
             s = psf_support(float(sigmas[i]))
             probs.append(make_problem(4000 + i, n, n, float(sigmas[i]), s, 20))
         return Config("C4", probs, shift_grid(-5, 1, 8), 3, 20, 5, "batched")
+    if name == "X1":
+        # the first example's setting: 128 x 128, two-term Kronecker blur, 0.5% noise,
+        # lambda from 1e-4 to 10^2.5 (gamma = lambda^2), relative residual 1e-6
+        n = small or 128
+        rng = np.random.default_rng(11)
+        x = phantom(rng, n, n, 20)
+        g = rng.standard_normal((n, n))
+        pr = Problem(n, n, kronecker_sum_psf(EXAMPLE1_TERMS), 0.0, x, g, 0.005)
+        return Config("X1", [pr], shift_grid(-8, 5, 20), 5, 40, 5, "sequential", tol=1e-6)
     if name == "C5":
         n = small or 512
         pr = make_problem(5, n, n, 3.0, 15, 20)

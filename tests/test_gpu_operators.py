@@ -26,12 +26,15 @@ def _psf(kind, rng):
     if kind == "asym_full":           # rank > 1: direct 2-D path
         h = rng.uniform(0.1, 1, (5, 3))
         return h / h.sum()
+    if kind == "kron2":               # the first example's two-term Kronecker blur, 15 x 25
+        return synth.kronecker_sum_psf(synth.EXAMPLE1_TERMS)
     raise KeyError(kind)
 
 
 CASES = [((16, 16), "gauss7", (16, 16)), ((37, 45), "asym_full", (16, 16)), ((64, 80), "gauss15", (32, 32)),
          ((7, 9), "gauss15", (16, 16)), ((33, 31), "delta", (8, 32)), ((100, 70), "asym_sep", (16, 64)),
-         ((130, 129), "gauss25", (32, 16)), ((48, 40), "asym_sep", (8, 32))]
+         ((130, 129), "gauss25", (32, 16)), ((48, 40), "asym_sep", (8, 32)), ((45, 37), "kron2", (16, 16)),
+         ((128, 128), "kron2", (32, 32))]
 
 
 @pytest.mark.parametrize("shape,kind,tile", CASES)

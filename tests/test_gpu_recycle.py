@@ -312,3 +312,24 @@ def test_uneven_instances_one_launch(ctx):
             ref = dense.cholesky_solve(Am + g * Em, bs[i])
             x = Xh[i * 3 + l, : ny * nx].reshape(ny, nx)
             assert np.linalg.norm(x - ref) <= 1e-6 * np.linalg.norm(ref), (i, l)
+
+
+@pytest.mark.parametrize("mode", [rsr.SEQUENTIAL, rsr.BATCHED])
+def test_example1_kronecker_blur_outer_loop(ctx, mode):
+    # the first example's two-term Kronecker blur (15 x 25 support, direct 2-D
+    # stencil path) at its 128 x 128 size, gamma 1e-8 .. 1e5, relres 1e-6
+    cfg = synth.config("X1")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    loop = irn.OuterLoop(ctx, cfg, "recycled", mode=mode)
+    loop.b[0] = to_dev(b)
+    for k in range(3):
+        print(f"example-1 blur: outer step k={k} mode={mode}", flush=True)
+        rec = loop.step()
+        if k > 0:
+            assert rec.p > 0
+        wh, wv = (to_host(t) for t in ctx.get_weights(0))
+        X = to_host(loop.X[0])
+        for l, g in enumerate(cfg.gammas):
+            rel = oracle.true_relres(pr.psf, wh, wv, g, b, X[l])
+            assert rel <= 1e-6, (k, l, rel)

@@ -51,6 +51,29 @@ def test_psf_is_normalised_symmetric_rank_one():
     assert synth.psf_support(1.2) == 9
 
 
+def test_kronecker_sum_psf_is_the_papers_operator():
+    # C = sum_i C_i^(1) (x) C_i^(2) with banded Toeplitz factors (the first example
+    # of Sec. 8): applying it to vec(X) (column-major) equals the oracle's zero-
+    # boundary convolution with the two-term PSF; the PSF has rank 2 and sums to 1
+    import scipy.linalg
+    h = synth.kronecker_sum_psf(synth.EXAMPLE1_TERMS)
+    assert h.shape == (15, 25) and abs(h.sum() - 1.0) < 1e-14
+    s = np.linalg.svd(h, compute_uv=False)
+    assert s[1] / s[0] > 1e-3 and s[2] / s[0] < 1e-14
+    ny, nx = 23, 31
+
+    def toep(band, sigma, n):
+        g = synth.gaussian_1d(band, sigma)
+        col = np.zeros(n)
+        col[:min(n, band + 1)] = g[band:band + min(n, band + 1)]
+        return scipy.linalg.toeplitz(col)        # symmetric banded Toeplitz, zero boundary
+
+    C = sum(np.kron(toep(b1, s1, nx), toep(b2, s2, ny)) for (b1, s1), (b2, s2) in synth.EXAMPLE1_TERMS) / 2
+    x = np.random.default_rng(4).standard_normal((ny, nx))
+    y = (C @ x.ravel(order="F")).reshape((ny, nx), order="F")
+    np.testing.assert_allclose(oracle.conv(h, x), y, atol=1e-14)
+
+
 # ----------------------------------------------------------- operators K --
 def test_conv_impulse_response_golden(gold):
     g = gold["impulse"]
