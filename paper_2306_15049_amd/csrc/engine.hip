@@ -30,6 +30,7 @@
 #include <cstring>
 #include <fstream>
 #include <functional>
+#include <future>
 #include <map>
 #include <set>
 #include <tuple>
@@ -377,6 +378,38 @@ void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector
     ComboJob *dj = stage(c, jobs, s);
     HIPCHK(launch_combo(dj, jobs.data(), (int)jobs.size(), s));
 }
+
+// Runs fn(i) for i in [0, n) on up to nt host threads, the calling thread
+// included (the small dense solves of independent shifts and groups).  Each i
+// is computed the same way whichever thread takes it.
+template <class F> void parallel_for(int n, int nt, F fn)
+{
+    nt = std::max(1, std::min(nt, n));
+    if (nt == 1) {
+        for (int i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::vector<std::future<void>> fut;
+    for (int t = 1; t < nt; ++t)
+        fut.push_back(std::async(std::launch::async, [&fn, n, nt, t] {
+            for (int i = t; i < n; i += nt) fn(i);
+        }));
+    std::exception_ptr err;
+    try {
+        for (int i = 0; i < n; i += nt) fn(i);
+    } catch (...) {
+        err = std::current_exception();
+    }
+    for (auto &f : fut) {
+        try {
+            f.get();
+        } catch (...) {
+            if (!err) err = std::current_exception();
+        }
+    }
+    if (err) std::rethrow_exception(err);
+}
+constexpr int HOST_THREADS = 4;
 
 // Eigenpairs (ascending) of Ahat + gamma Ehat for the instance's current U,
 // from the cache when it holds this U version and shift.
@@ -827,6 +860,34 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     std::map<std::pair<int, int>, Grp> groups;
     std::vector<ComboJob> cj;
     std::vector<std::vector<double>> qs;
+    // the groups whose Ritz block is stale: their eigenproblems run concurrently
+    struct EigJob {
+        Instance *I;
+        double gJ;
+        std::vector<double> w, V;
+    };
+    std::vector<EigJob> ej;
+    {
+        std::set<std::pair<int, int>> seen;
+        for (auto *Y : sy) {
+            Instance &I = *c->inst[Y->inst];
+            if (o.n_ritz <= 0 || I.p == 0 || !I.ae_valid) continue;
+            const int side = Y->slot < o.split_I ? 0 : 1;
+            if (!seen.insert(std::make_pair(Y->inst, side)).second) continue;
+            const double gJ = side == 0 ? o.gJL : o.gJR;
+            const int nr = std::min(o.n_ritz, I.p);
+            const Instance::RitzBlock &rb = I.ritz[side];
+            if (rb.version != I.u_version || rb.gamma != gJ || rb.nr != nr) ej.push_back(EigJob{&I, gJ, {}, {}});
+        }
+        parallel_for((int)ej.size(), HOST_THREADS, [&](int k) {
+            EigJob &e = ej[k];
+            const int p = e.I->p;
+            std::vector<double> H((size_t)p * p);
+            for (size_t t = 0; t < H.size(); ++t) H[t] = e.I->Ahat[t] + e.gJ * e.I->Ehat[t];
+            sym_eig(p, H.data(), e.w, e.V);
+        });
+    }
+    size_t ejk = 0;
     for (auto *Y : sy) {
         Instance &I = *c->inst[Y->inst];
         if (o.n_ritz <= 0 || I.p == 0 || !I.ae_valid) continue;
@@ -839,9 +900,7 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         if (rb.version != I.u_version || rb.gamma != gJ || rb.nr != nr) {
             const int p = I.p;
             rb.buf.ensure(sizeof(double) * (size_t)3 * nr * I.n);
-            std::vector<double> H((size_t)p * p), w, V;
-            for (size_t k = 0; k < H.size(); ++k) H[k] = I.Ahat[k] + gJ * I.Ehat[k];
-            sym_eig(p, H.data(), w, V);
+            const std::vector<double> &V = ej[ejk++].V;   // same order as the collection above
             std::vector<double> Wt((size_t)p * nr);   // column-major p x nr
             for (int j = 0; j < nr; ++j)
                 for (int i = 0; i < p; ++i) Wt[(size_t)j * p + i] = V[(size_t)i * p + j];
@@ -1042,12 +1101,16 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         };
         std::vector<InitGrp> grp;
         grp.reserve(prin.size());
-        for (size_t k = 0; k < prin.size(); ++k) {
+        // one small solve per shift, on several host threads
+        std::vector<std::vector<double>> qv(prin.size());
+        parallel_for((int)prin.size(), HOST_THREADS, [&](int k) {
             SysHost &Y = *prin[k];
             Instance &I = *c->inst[Y.inst];
             const int p = I.p;
             const double g = Y.gamma;
-            std::vector<double> H((size_t)p * p), f(p), q(p), P;
+            std::vector<double> H((size_t)p * p), f(p), P;
+            std::vector<double> &q = qv[k];
+            q.assign(p, 0.0);
             bool solved = false;
             if (o.init == RSR_INIT_OBLIQUE) {
                 // K = AU + gs EU with the group's reference shift gs; the oblique
@@ -1080,6 +1143,12 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
                     matvec(p, p, P.data(), f.data(), q.data());
                 }
             }
+        });
+        for (size_t k = 0; k < prin.size(); ++k) {
+            SysHost &Y = *prin[k];
+            const int p = c->inst[Y.inst]->p;
+            const double g = Y.gamma;
+            const std::vector<double> &q = qv[k];
             // x = U q ; r = b - [AU EU] [q; g q]
             InitGrp *G = nullptr;
             for (auto &e : grp)
