@@ -196,3 +196,26 @@ def test_outer_loop_with_correction_space(ctx):
         for l, g in enumerate(cfg.gammas):
             rel = oracle.true_relres(pr.psf, wh, wv, g, b, X[l])
             assert rel <= 1e-8, (k, l, rel)
+
+
+def test_degenerate_cases(ctx):
+    # an L-curve of one or two points has no interior point (no corner, NaN
+    # curvature); a ramp whose differences all have the same size sends every
+    # weight to zero under the edge rule (every difference is the steepest)
+    pr = synth.make_problem(3, 12, 10, 1.0, 5, 3)
+    d, _ = oracle.rhs(pr)
+    ctx.set_operators([(12, 10)], [pr.psf])
+    X = np.stack([pr.x_true, 0.5 * pr.x_true])
+    for m in (1, 2):
+        rho, eta, kap, corner = ctx.lcurve([1e-3, 1e-2][:m], to_dev(X[:m]), to_dev(d))
+        assert corner == -1 and np.isnan(kap).all()
+        rho_o, eta_o = outer.lcurve_points(pr.psf, *oracle.unit_weights(12, 10), X[:m], d)
+        np.testing.assert_allclose(rho, rho_o, rtol=1e-12)
+        np.testing.assert_allclose(eta, eta_o, rtol=1e-12)
+    ii, jj = np.mgrid[0:12, 0:10]
+    ramp = (ii + jj).astype(np.float64)
+    ctx.weights_edge_rule(0, to_dev(ramp), 2.0)
+    gh, gv = (to_host(t) for t in ctx.get_weights(0))
+    assert np.abs(gh).max() == 0.0 and np.abs(gv).max() == 0.0
+    wh_o, wv_o = outer.edge_rule(ramp, *oracle.unit_weights(12, 10), 2.0)
+    assert np.abs(wh_o).max() == 0.0 and np.abs(wv_o).max() == 0.0
