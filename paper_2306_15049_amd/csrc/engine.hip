@@ -148,6 +148,7 @@ struct rsr_ctx {
     DBuf d_lz, d_lzc, d_lzr;           // CG-Lanczos capture (residuals, coefficients) and its Ritz vectors
     DBuf d_aux;                        // workgroup partials of the edge-weight and L-curve reductions
     DBuf d_corr;                       // right-hand side of the correction equation
+    DBuf d_r0sq;                       // ||r0||^2 per system of a solve call, read back at its end
     // staging arena for launch descriptors and coefficients: pinned host and
     // device halves bump-allocated in step, reset whenever the stream is drained,
     // so that launches whose inputs come from the host need no synchronisation
@@ -360,6 +361,21 @@ std::vector<std::vector<double>> gram(rsr_ctx *c, std::vector<GramJob> jobs, hip
     return out;
 }
 
+// X^T Y products written to device memory (each job's C set by the caller),
+// with no read-back: for results the host needs only at the end of a call.
+void gram_to_device(rsr_ctx *c, std::vector<GramJob> jobs, hipStream_t s)
+{
+    if (jobs.empty()) return;
+    size_t sc = 0;
+    for (auto &j : jobs) {
+        j.sc_off = (long)sc;
+        sc += gram_scratch_doubles(&j, 1);
+    }
+    c->d_gram_scratch.ensure(sizeof(double) * std::max<size_t>(1, sc));
+    GramJob *dj = stage(c, jobs, s);
+    HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), c->d_gram_scratch.as<double>(), sc, s));
+}
+
 // Y_j = beta Y_j + X_j Q_j (Q from host, column-major a x c with ldq = a).
 void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector<double>> &Qs, hipStream_t s)
 {
@@ -565,6 +581,7 @@ struct SysHost {
     double bnorm = 0.0;
     int iters = 0, restarts = 0, mvA = 0, mvE = 0, status = 0;
     double relres_init = 0.0, relres_true = 0.0;
+    double *r0sq_dev = nullptr;   // when set, ||r0||^2 lands here and relres_init is filled in later
     bool done = false;
     // CG-Lanczos capture of the first launch (principal-space seeding)
     double *lz = nullptr, *lzc = nullptr;
@@ -1193,12 +1210,25 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         copy_many(c, xc, s);
     }
     {
+        // ||r0|| only feeds the statistics: systems with a device slot defer the read-back
         std::vector<const double *> v;
         std::vector<long> n;
-        for (auto *Y : sy) { v.push_back(Y->r); n.push_back(Y->n); }
-        auto rn = norms(c, v, n, s);
-        for (size_t i = 0; i < sy.size(); ++i)
-            sy[i]->relres_init = sy[i]->bnorm > 0 ? rn[i] / sy[i]->bnorm : 0.0;
+        std::vector<SysHost *> now;
+        std::vector<GramJob> later;
+        for (auto *Y : sy) {
+            if (Y->r0sq_dev) {
+                later.push_back(GramJob{Y->r, Y->n, 1, Y->r, Y->n, 1, Y->n, Y->r0sq_dev, 0});
+            } else {
+                v.push_back(Y->r);
+                n.push_back(Y->n);
+                now.push_back(Y);
+            }
+        }
+        gram_to_device(c, later, s);
+        if (!now.empty()) {
+            auto rn = norms(c, v, n, s);
+            for (size_t i = 0; i < now.size(); ++i) now[i]->relres_init = now[i]->bnorm > 0 ? rn[i] / now[i]->bnorm : 0.0;
+        }
     }
     // local spaces and Galerkin correction
     tm.reset(new StageTimer(c, s, 3));
@@ -1392,7 +1422,7 @@ void rsr_destroy(rsr_ctx *c)
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
                     &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
-                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux, &c->d_corr})
+                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux, &c->d_corr, &c->d_r0sq})
         b->release();
     if (c->ar_host) (void)hipHostFree(c->ar_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1864,6 +1894,9 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
         alloc_ws(c, sys);
         c->bnorm_cache.clear();
         c->rhs_cache.clear();
+        c->d_r0sq.ensure(sizeof(double) * (size_t)m);
+        HIPCHK(launch_fill(c->d_r0sq.as<double>(), 0.0, m, s));
+        for (int i = 0; i < m; ++i) sys[i].r0sq_dev = c->d_r0sq.as<double>() + i;
         Opts o{d->tol, d->maxit, d->init, d->n_ritz, d->use_prev_k, d->use_prev_shift, d->split_I, d->gamma_JL,
                d->gamma_JR};
         c->last_cg_ms = 0.0;
@@ -1917,6 +1950,13 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
             }
             sync(c, s);
 
+        }
+        {
+            std::vector<double> r0sq(m);
+            HIPCHK(hipMemcpyAsync(r0sq.data(), c->d_r0sq.p, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+            sync(c, s);
+            for (int i = 0; i < m; ++i)
+                sys[i].relres_init = sys[i].bnorm > 0 ? std::sqrt(std::max(0.0, r0sq[i])) / sys[i].bnorm : 0.0;
         }
         bool all = true;
         for (int i = 0; i < m; ++i) {
