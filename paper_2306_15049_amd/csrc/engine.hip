@@ -251,11 +251,10 @@ struct StageTimer {
     }
 };
 
-// Copies v into the staging arena (pinned host -> device, asynchronous) and
-// returns its device address, valid until the next sync().
-template <class T> T *stage(rsr_ctx *c, const std::vector<T> &v, hipStream_t s)
+// Reserves nb bytes of the staging arena (pinned host half h, device half d),
+// draining the stream first when the arena is full.
+void arena_reserve(rsr_ctx *c, size_t nb, hipStream_t s, char *&h, char *&d)
 {
-    const size_t nb = sizeof(T) * v.size();
     const size_t bytes = (std::max<size_t>(nb, 1) + 255) & ~(size_t)255;
     if (c->ar_used + bytes > c->ar_cap) {
         sync(c, s);
@@ -269,13 +268,22 @@ template <class T> T *stage(rsr_ctx *c, const std::vector<T> &v, hipStream_t s)
             c->ar_cap = cap;
         }
     }
-    char *h = c->ar_host + c->ar_used;
-    char *d = c->ar_dev.as<char>() + c->ar_used;
+    h = c->ar_host + c->ar_used;
+    d = c->ar_dev.as<char>() + c->ar_used;
+    c->ar_used += bytes;
+}
+
+// Copies v into the staging arena (pinned host -> device, asynchronous) and
+// returns its device address, valid until the next sync().
+template <class T> T *stage(rsr_ctx *c, const std::vector<T> &v, hipStream_t s)
+{
+    const size_t nb = sizeof(T) * v.size();
+    char *h, *d;
+    arena_reserve(c, nb, s, h, d);
     if (nb) {
         memcpy(h, v.data(), nb);
         HIPCHK(hipMemcpyAsync(d, h, nb, hipMemcpyHostToDevice, s));
     }
-    c->ar_used += bytes;
     return (T *)d;
 }
 
@@ -382,17 +390,21 @@ void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector
     if (jobs.empty()) return;
     size_t tot = 0;
     for (auto &q : Qs) tot += q.size();
-    std::vector<double> all;
-    all.reserve(tot);
-    std::vector<size_t> off;
-    for (auto &q : Qs) {
-        off.push_back(all.size());
-        all.insert(all.end(), q.begin(), q.end());
+    // coefficients and descriptors in one upload: [Q_0 Q_1 ... | jobs]
+    const size_t nq = sizeof(double) * tot;
+    const size_t offj = (nq + 15) & ~(size_t)15;
+    const size_t nj = sizeof(ComboJob) * jobs.size();
+    char *h, *d;
+    arena_reserve(c, offj + nj, s, h, d);
+    size_t o = 0;
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        if (!Qs[k].empty()) memcpy(h + sizeof(double) * o, Qs[k].data(), sizeof(double) * Qs[k].size());
+        jobs[k].Q = (const double *)d + o;
+        o += Qs[k].size();
     }
-    double *dq = stage(c, all, s);
-    for (size_t k = 0; k < jobs.size(); ++k) jobs[k].Q = dq + off[k];
-    ComboJob *dj = stage(c, jobs, s);
-    HIPCHK(launch_combo(dj, jobs.data(), (int)jobs.size(), s));
+    memcpy(h + offj, jobs.data(), nj);
+    HIPCHK(hipMemcpyAsync(d, h, offj + nj, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_combo((const ComboJob *)(d + offj), jobs.data(), (int)jobs.size(), s));
 }
 
 // Runs fn(i) for i in [0, n) on up to nt host threads, the calling thread
