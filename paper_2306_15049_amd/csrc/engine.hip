@@ -144,7 +144,6 @@ struct rsr_ctx {
     DBuf d_tmp;                        // grouped initial guesses x0, r0 before they are copied out
     DBuf d_rcC, d_rcQ;                 // recycle-space candidates and their orthonormal basis (kept: no
                                        // allocation, and no free that drains the device, per update)
-    DBuf d_gprev;                      // previous shift's correction in sequential solves
     DBuf d_lz, d_lzc, d_lzr;           // CG-Lanczos capture (residuals, coefficients) and its Ritz vectors
     DBuf d_aux;                        // workgroup partials of the edge-weight and L-curve reductions
     DBuf d_corr;                       // right-hand side of the correction equation
@@ -1434,7 +1433,7 @@ void rsr_destroy(rsr_ctx *c)
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
                     &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
-                    &c->d_gprev, &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux, &c->d_corr, &c->d_r0sq})
+                    &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux, &c->d_corr, &c->d_r0sq})
         b->release();
     if (c->ar_host) (void)hipHostFree(c->ar_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1926,7 +1925,6 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                 store_corrections(c, grp, s);
             }
         } else {
-            DBuf &gprev = c->d_gprev;
             const double *gp = nullptr;
             // principal-space seeding from the first system's CG-Lanczos data
             const bool seed = d->seed_lanczos > 0 && c->inst[sys[0].inst]->p == 0;
@@ -1952,13 +1950,9 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
                     o.init = RSR_INIT_MR;
                     o.n_ritz = std::min(d->seed_n_ritz, QMAX);
                 }
-                if (o.use_prev_shift) {
-                    Instance &I = *c->inst[sys[i].inst];
-                    gprev.ensure(sizeof(double) * I.n);
-                    HIPCHK(hipMemcpyAsync(gprev.p, I.gslot(sys[i].slot), sizeof(double) * I.n,
-                                          hipMemcpyDeviceToDevice, s));
-                    gp = gprev.as<double>();
-                }
+                // g^(k,l-1) for the next shift: read in place from its slot, which is not
+                // written again (nor the slot pool moved) before that shift's solve ends
+                if (o.use_prev_shift) gp = c->inst[sys[i].inst]->gslot(sys[i].slot);
             }
             sync(c, s);
 
