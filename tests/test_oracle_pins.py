@@ -118,6 +118,50 @@ def test_adjoint_identities():
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
 
 
+def _explicit_conv_matrix(h, ny, nx):
+    """C with (C v)[i,j] = sum_{a,c} h[a,c] v[i+cy-a, j+cx-c] (zero outside), entry by entry."""
+    sy, sx = h.shape
+    cy, cx = sy // 2, sx // 2
+    C = np.zeros((ny * nx, ny * nx))
+    for i in range(ny):
+        for j in range(nx):
+            for a in range(sy):
+                for c in range(sx):
+                    ii, jj = i + cy - a, j + cx - c
+                    if 0 <= ii < ny and 0 <= jj < nx:
+                        C[i * nx + j, ii * nx + jj] += h[a, c]
+    return C
+
+
+@pytest.mark.parametrize("psf", ["asym_full", "asym_rank1", "kron2"])
+def test_apply_A_is_CtC_in_that_order(psf):
+    # A = C^T C (Sec. 2.1, eq. blkeqn): blur first, then its transpose.  For a PSF
+    # that is not symmetric under a half turn, C C^T differs from C^T C near the
+    # boundary (zero boundary), so the composition order is pinned here against
+    # an explicitly assembled convolution matrix, not the oracle's own loops.
+    rng = np.random.default_rng(29)
+    if psf == "asym_full":
+        h = _rand_psf(rng, 5, 7)
+    elif psf == "asym_rank1":
+        fy, fx = rng.uniform(0.1, 1.0, 5), rng.uniform(0.1, 1.0, 3)
+        h = np.outer(fy, fx)
+        h /= h.sum()
+    else:
+        h = synth.kronecker_sum_psf(synth.EXAMPLE1_TERMS)[::2, ::3].copy()
+        h[0, 0] += 0.05                      # break its half-turn symmetry
+    ny, nx = 9, 11
+    C = _explicit_conv_matrix(h, ny, nx)
+    np.testing.assert_allclose(C, dense.assemble(lambda v: oracle.conv(h, v), ny, nx), atol=1e-15)
+    CtC, CCt = C.T @ C, C @ C.T
+    gap = np.abs(CtC - CCt).max()
+    assert gap > 1e-3 * np.abs(CtC).max()   # the two orders are distinguishable
+    np.testing.assert_allclose(dense.dense_A(h, ny, nx), CtC, rtol=0, atol=1e-14 * np.abs(CtC).max())
+    v = rng.standard_normal((ny, nx))
+    y = oracle.apply_A(h, v).ravel()
+    assert np.abs(y - CtC @ v.ravel()).max() <= 1e-14 * np.abs(y).max()
+    assert np.abs(y - CCt @ v.ravel()).max() > 1e-6 * np.abs(y).max()
+
+
 # ----------------------------------------------------------- operators E --
 def test_diff_matches_numpy():
     rng = np.random.default_rng(5)
@@ -315,6 +359,37 @@ def test_oblique_guess_residual_identity_and_special_cases():
     U2, _ = np.linalg.qr(np.column_stack([U, xs]))
     x0, r0 = dense.oblique_guess(Am, Em, U2, b, gamma, 0.5)
     assert np.linalg.norm(r0) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_oblique_vs_orthogonal_residual_identity_sec71():
+    # Sec. 7.1: with K orthonormal, Y S = qr(K + d E U), Y^T K = F O P^T (SVD) and
+    # (I - Y Y^T) K P = Y_c Sig, the orthogonal (r1) and oblique (r2) residuals satisfy
+    # ||r2||^2 = ||r1||^2 + ||O^{-1} Sig Y_c^T b||^2, and O^2 + Sig^2 = I.  r1 and r2 come
+    # from the oracle's two guesses; the last term is assembled here from the
+    # CS-decomposition quantities alone.
+    Am, Em, U, b = _dense_setup()
+    bb = b.ravel()
+    for gs in (1e-3, 0.1):
+        K, R = np.linalg.qr((Am + gs * Em) @ U)
+        Ut = np.linalg.solve(R.T, U.T).T          # (A + gs E) Ut = K, K^T K = I
+        for gamma in (1e-4, 1e-2, 2.0):
+            d = gamma - gs
+            Y, _ = np.linalg.qr(K + d * (Em @ Ut))
+            F, om, Pt = np.linalg.svd(Y.T @ K)
+            Mc = (np.eye(len(bb)) - Y @ Y.T) @ K @ Pt.T          # = Y_c Sig
+            sig = np.linalg.norm(Mc, axis=0)
+            np.testing.assert_allclose(om ** 2 + sig ** 2, 1.0, atol=1e-12)
+            G = Mc.T @ Mc                                          # columns of Y_c Sig are orthogonal
+            assert np.abs(G - np.diag(np.diag(G))).max() <= 1e-12
+            extra = (Mc.T @ bb) / om                               # O^{-1} Sig Y_c^T b
+            _, r1 = dense.mr_guess(Am + gamma * Em, U, b)
+            _, r2 = dense.oblique_guess(Am, Em, U, b, gamma, gs)
+            lhs = np.linalg.norm(r2) ** 2
+            rhs = np.linalg.norm(r1) ** 2 + np.linalg.norm(extra) ** 2
+            assert abs(lhs - rhs) <= 1e-9 * lhs, (gs, gamma, lhs, rhs)
+            # the difference of the two residuals is the sum of Sec. 7.1
+            diff = Y @ (F @ ((sig / om) * ((Mc / np.where(sig > 0, sig, 1.0)).T @ bb)))
+            assert np.linalg.norm((r1 - r2) - diff) <= 1e-9 * max(np.linalg.norm(r1 - r2), 1e-300)
 
 
 def test_mr_guess_exact_when_solution_in_range():
