@@ -30,7 +30,8 @@ _D = ctypes.POINTER(ctypes.c_double)
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (OpenMP over shifts)."""
+    """Compile ``liboracle.so`` with gcc (portable -O2, OpenMP over shifts): the
+    library the tests load."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
@@ -39,27 +40,49 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+def _load(path: str):
+    L = ctypes.CDLL(path)
+    i, d = ctypes.c_int, ctypes.c_double
+    L.orc_conv.argtypes = [i, i, i, i, _D, _D, _D]
+    L.orc_corr.argtypes = [i, i, i, i, _D, _D, _D]
+    L.orc_diff.argtypes = [i, i, _D, _D, _D]
+    L.orc_diffT.argtypes = [i, i, _D, _D, _D]
+    L.orc_apply_E.argtypes = [i, i, _D, _D, _D, _D]
+    L.orc_apply_A.argtypes = [i, i, i, i, _D, _D, _D]
+    L.orc_apply_B.argtypes = [i, i, i, i, _D, _D, _D, d, _D, _D]
+    L.orc_weights.argtypes = [i, i, _D, d, _D, _D]
+    L.orc_cg.argtypes = [i, i, i, i, _D, _D, _D, d, _D, d, i, _D, _D, i, _D, _D]
+    L.orc_cg.restype = i
+    L.orc_cg_shifts.argtypes = [i, i, i, i, _D, _D, _D, i, _D, _D, d, i, _D, _D, i]
+    L.orc_max_threads.restype = i
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO):
             build()
-        L = ctypes.CDLL(_SO)
-        i, d = ctypes.c_int, ctypes.c_double
-        L.orc_conv.argtypes = [i, i, i, i, _D, _D, _D]
-        L.orc_corr.argtypes = [i, i, i, i, _D, _D, _D]
-        L.orc_diff.argtypes = [i, i, _D, _D, _D]
-        L.orc_diffT.argtypes = [i, i, _D, _D, _D]
-        L.orc_apply_E.argtypes = [i, i, _D, _D, _D, _D]
-        L.orc_apply_A.argtypes = [i, i, i, i, _D, _D, _D]
-        L.orc_apply_B.argtypes = [i, i, i, i, _D, _D, _D, d, _D, _D]
-        L.orc_weights.argtypes = [i, i, _D, d, _D, _D]
-        L.orc_cg.argtypes = [i, i, i, i, _D, _D, _D, d, _D, d, i, _D, _D, i, _D, _D]
-        L.orc_cg.restype = i
-        L.orc_cg_shifts.argtypes = [i, i, i, i, _D, _D, _D, i, _D, _D, d, i, _D, _D, i]
-        L.orc_max_threads.restype = i
-        _lib = L
+        _lib = _load(_SO)
     return _lib
+
+
+_native = None
+
+
+def native_lib():
+    """The same source built with ``-O3 -march=native`` for the host it runs on
+    (compiled into a temporary directory on first use): the build the CPU
+    baseline times."""
+    global _native
+    if _native is None:
+        import tempfile
+        d = tempfile.mkdtemp(prefix="oracle_native_")
+        so = os.path.join(d, "liboracle_native.so")
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                               "-o", so, _SRC, "-lm"])
+        _native = _load(so)
+    return _native
 
 
 def _p(a: np.ndarray):
@@ -164,8 +187,8 @@ def cg(h, wh, wv, gamma, b, tol=1e-8, maxit=None, record=0):
     return x, stats
 
 
-def cg_shifts(h, wh, wv, gammas, b, tol=1e-8, maxit=None, nthreads=1):
-    """Plain CG for every shift; X is [M, ny, nx]."""
+def cg_shifts(h, wh, wv, gammas, b, tol=1e-8, maxit=None, nthreads=1, L=None):
+    """Plain CG for every shift; X is [M, ny, nx].  L: the loaded library (default lib())."""
     h, wh, wv, b = _f64(h), _f64(wh), _f64(wv), _f64(b)
     g = _f64(gammas)
     ny, nx = b.shape
@@ -173,7 +196,7 @@ def cg_shifts(h, wh, wv, gammas, b, tol=1e-8, maxit=None, nthreads=1):
     maxit = int(maxit if maxit is not None else 10 * ny * nx)
     X = np.empty((m, ny, nx))
     st = np.zeros((m, 4))
-    lib().orc_cg_shifts(ny, nx, h.shape[0], h.shape[1], _p(h), _p(wh), _p(wv), m, _p(g),
+    (L or lib()).orc_cg_shifts(ny, nx, h.shape[0], h.shape[1], _p(h), _p(wh), _p(wv), m, _p(g),
                         _p(b), float(tol), maxit, _p(X), _p(st), int(nthreads))
     stats = [dict(iters=int(s[0]), matvecs=int(s[1]), relres=float(s[2]), converged=bool(s[3]))
              for s in st]

@@ -9,12 +9,28 @@ symmetric, so one recycled solve B_l lambda_l = dL/dx_l per shift gives
   dL/db       = sum_l lambda_l.
 There is no backpropagation through CG iterations.  Every numeric step runs
 in the HIP library (rsr_solve_shift_set, rsr_adjoint); torch supplies memory.
+
+With recycling options (a principal space set for the current weights, the
+minimum-residual guess, Ritz vectors, previous corrections) both the forward
+and the adjoint solves are recycled: the adjoint systems share the forward's
+principal space and Ritz blocks (same matrices B_l), and their local spaces
+take the forward correction of the same shift.  The weights are passed to the
+library only when they differ from its current ones, since new weights
+invalidate the principal space's products A U, E U.
 """
 from __future__ import annotations
 
 import torch
 
 from . import rsr
+
+
+def _set_weights(context: rsr.Context, inst: int, w_h: torch.Tensor, w_v: torch.Tensor):
+    """Upload W unless the library already holds it (entries that weigh no difference are ignored)."""
+    cur_h, cur_v = context.get_weights(inst)
+    if torch.equal(cur_h[:, :-1], w_h[:, :-1]) and torch.equal(cur_v[:-1, :], w_v[:-1, :]):
+        return
+    context.update_weights(inst, w_h.detach().contiguous(), w_v.detach().contiguous())
 
 
 class RecycledShiftSolve(torch.autograd.Function):
@@ -25,7 +41,7 @@ class RecycledShiftSolve(torch.autograd.Function):
                 b: torch.Tensor, inst: int = 0, opts: rsr.SolveOptions = None):
         opts = opts or rsr.SolveOptions(tol=1e-12)
         g = [float(v) for v in gammas.detach().cpu().tolist()]
-        context.update_weights(inst, w_h.detach().contiguous(), w_v.detach().contiguous())
+        _set_weights(context, inst, w_h.detach(), w_v.detach())
         ny, nx = context.shapes[inst]
         X = torch.zeros((len(g), ny, nx), dtype=torch.float64, device=b.device)
         rc, st = context.solve(g, b.detach().contiguous(), X, inst=[inst] * len(g), opts=opts)
@@ -40,7 +56,7 @@ class RecycledShiftSolve(torch.autograd.Function):
     def backward(fctx, gX: torch.Tensor):
         X, w_h, w_v = fctx.saved_tensors
         context = fctx.context
-        context.update_weights(fctx.inst, w_h.detach().contiguous(), w_v.detach().contiguous())
+        _set_weights(context, fctx.inst, w_h.detach(), w_v.detach())
         Lam = torch.zeros_like(X)
         rc, dg, dwh, dwv, db, st = context.adjoint(fctx.g, X, gX.contiguous(), Lam, inst=fctx.inst,
                                                   opts=fctx.opts)

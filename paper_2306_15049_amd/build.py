@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -16,7 +17,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-mcode-object-version=5",
     # packed FP32 instructions are kept out of every kernel (wrong results seen on
     # some forms); the host pass warns that it does not know the feature.
@@ -25,17 +25,37 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into ``librsr.so`` (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = SO + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-o", tmp] + srcs
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
-    if verbose and err:
-        print(err, file=sys.stderr)
+    return res.returncode, err
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source (one object each, in parallel) and link ``librsr.so``
+    (always recompiles)."""
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    objs, cmds = [], []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        cmds.append([HIPCC] + FLAGS + inc + ["-c", "-o", obj, os.path.join(CSRC, src)])
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        results = list(ex.map(_run, cmds))
+    msgs = []
+    for (rc, err), cmd in zip(results, cmds):
+        if rc != 0:
+            raise RuntimeError("hipcc failed:\n" + err)
+        if err:
+            msgs.append(err)
+    tmp = SO + ".tmp"
+    rc, err = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    if rc != 0:
+        raise RuntimeError("hipcc link failed:\n" + err)
+    for o in objs:
+        os.remove(o)
+    if verbose and msgs:
+        print("\n".join(msgs), file=sys.stderr)
     os.replace(tmp, SO)
     return SO
 

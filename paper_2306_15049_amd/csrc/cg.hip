@@ -333,7 +333,7 @@ constexpr int NBE = 2;   // interior pixels per thread whose local-basis loads a
 // ask for it (a separate instantiation, so launches without it carry no trace).  Chunk partial layout: p.w, r.r, r.w, w.w, Z^T r[QT],
 // Z^T w[QT] in a slot of NVP values.
 // At most 256 registers per lane keeps two waves per SIMD.
-template <int QT, bool LZ>
+template <int QT, bool LZ, bool TWO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_cg(CGArgs A)
 {
     constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
@@ -648,7 +648,67 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         stamp(it, 1);
 
-        // ---- the iteration's one phase under N
+        if constexpr (TWO) {
+            // ---- two-pass iterations, first pass: r_j = r_{j-1} - alpha w_{j-1} and
+            // ph_j = r_j + beta ph_{j-1} on the own cells of every item of this
+            // workgroup (elementwise, several cells per thread in flight); the
+            // stencil pass after the barrier then reads ph_j alone on its window.
+            // The tiles are those of the stencil pass, so the own cells written here
+            // are read back by the same workgroup; the halo cells come from others.
+            const int T = N.pre[mn];
+            const int chunk = chunk_of_block(blockIdx.x, s_g);
+            const int lo = chunk * ipbn;
+            const int hi = lo + ipbn < T ? lo + ipbn : T;
+            int a = lo < hi ? find_pos(N.pre, mn, lo) : 0;
+            const int pj = it & 1, pk = (it + 1) & 1;
+            for (int item = lo; item < hi; ++item) {
+                while (item >= N.pre[a + 1]) ++a;
+                const int s = uni(N.act[a]);
+                const SysDev &Y = A.sys[s];
+                const InstDev &I = A.inst[Y.inst];
+                const double alpha = s_alpha[s], beta = s_beta[s];
+                const int t = uni(item - N.pre[a]);
+                const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
+                const gdbl *__restrict__ rsrc = gp(it > 0 ? Y.rb[pk] : Y.rb[0]);
+                gdbl *__restrict__ rdst = gp(Y.rb[pj]);
+                const gdbl *__restrict__ wsrc = gp(Y.wb[pk]);
+                const gdbl *__restrict__ psrc = gp(Y.pb[pk]);
+                gdbl *__restrict__ pdst = gp(Y.pb[pj]);
+                const int ne = I.ty * I.tx;
+                constexpr int NA = 4;
+                for (int base = 0; base < ne; base += NT * NA) {
+                    int gi[NA];
+                    bool ok[NA];
+#pragma unroll
+                    for (int u = 0; u < NA; ++u) {
+                        const int k = base + u * NT + threadIdx.x;
+                        const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
+                        ok[u] = k < ne && gy < I.ny && gx < I.nx;
+                        gi[u] = ok[u] ? gy * I.nx + gx : 0;
+                    }
+                    double rv[NA], wv[NA], pv[NA];
+#pragma unroll
+                    for (int u = 0; u < NA; ++u) {
+                        rv[u] = rsrc[gi[u]];
+                        wv[u] = it > 0 ? wsrc[gi[u]] : 0.0;
+                        pv[u] = it > 0 ? psrc[gi[u]] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < NA; ++u) {
+                        const double rj = fma(-alpha, wv[u], rv[u]);
+                        const double ph = fma(beta, pv[u], rj);
+                        if (ok[u]) {
+                            if (it > 0) rdst[gi[u]] = rj;
+                            if (LZ && it < Y.nlz) gp(Y.lz)[it * Y.ldw + gi[u]] = rj;   // Lanczos capture of r_j
+                            pdst[gi[u]] = ph;
+                        }
+                    }
+                }
+            }
+            if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+        }
+
+        // ---- the iteration's stencil phase under N (its only phase in fused mode)
         {
             const int T = N.pre[mn];
             const int chunk = chunk_of_block(blockIdx.x, s_g);
@@ -752,6 +812,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 const int gx = x0 - g.hx + lj;
                 const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
                 const bool colown = lj >= g.hx && lj < g.hx + I.tx;
+                if constexpr (TWO) {
+                    // ph_j on the window as the first pass left it (coherent loads: the halo
+                    // cells are other workgroups' own cells), r_j of the own cells
+                    const gdbl *__restrict__ phs = gp(Y.pb[pj]);
+                    const gdbl *__restrict__ rjs = gp(Y.rb[pj]);
+                    for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
+                        int gi[NBW];
+                        bool ok[NBW], own[NBW];
+#pragma unroll
+                        for (int u = 0; u < NBW; ++u) {
+                            const int li = li0 + u * wm.rs;
+                            const int gy = y0 - g.hy + li;
+                            ok[u] = colok && li < g.H0 && gy >= 0 && gy < I.ny;
+                            own[u] = colown && li >= g.hy && li < g.hy + I.ty;
+                            gi[u] = ok[u] ? gy * I.nx + gx : 0;
+                        }
+                        double pv[NBW], rv[NBW];
+#pragma unroll
+                        for (int u = 0; u < NBW; ++u) pv[u] = cld(phs + gi[u]);
+#pragma unroll
+                        for (int u = 0; u < NBW; ++u) rv[u] = (ok[u] && own[u]) ? rjs[gi[u]] : 0.0;
+#pragma unroll
+                        for (int u = 0; u < NBW; ++u) {
+                            const int li = li0 + u * wm.rs;
+                            const double ph = ok[u] ? pv[u] : 0.0;
+                            double *d = (lj < g.W0 && li < g.H0) ? tile + li * g.P0 + lj : tile + g.offT + threadIdx.x;
+                            *d = ph;
+                            if (ok[u] && own[u]) {
+                                const int ii = (li - g.hy) * g.PE + (lj - g.hx);
+                                pbuf[ii] = ph;
+                                rbuf[ii] = rv[u];
+                            }
+                        }
+                    }
+                } else
                 for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
                     int gi[NBW];
                     bool ok[NBW], own[NBW];
@@ -888,15 +983,24 @@ size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys)
 }
 
 // Compiled widths of the local space; a launch uses the smallest one >= its widest q.
-// The capturing variant exists for q = 0 (a first solve) and the widest space.
-static const void *cg_kernel(int qt, bool lz)
+// The capturing variant exists for q = 0 (a first solve) and the widest space, in
+// the fused form only (captures are single systems, where fused iterations win).
+static const void *cg_kernel(int qt, bool lz, bool two)
 {
-    if (lz) return qt == 0 ? (const void *)k_cg<0, true> : (const void *)k_cg<QMAX, true>;
+    if (lz) return qt == 0 ? (const void *)k_cg<0, true, false> : (const void *)k_cg<QMAX, true, false>;
+    if (two) {
+        switch (qt) {
+        case 0: return (const void *)k_cg<0, false, true>;
+        case 3: return (const void *)k_cg<3, false, true>;
+        case 5: return (const void *)k_cg<5, false, true>;
+        default: return (const void *)k_cg<QMAX, false, true>;
+        }
+    }
     switch (qt) {
-    case 0: return (const void *)k_cg<0, false>;
-    case 3: return (const void *)k_cg<3, false>;
-    case 5: return (const void *)k_cg<5, false>;
-    default: return (const void *)k_cg<QMAX, false>;
+    case 0: return (const void *)k_cg<0, false, false>;
+    case 3: return (const void *)k_cg<3, false, false>;
+    case 5: return (const void *)k_cg<5, false, false>;
+    default: return (const void *)k_cg<QMAX, false, false>;
     }
 }
 
@@ -905,17 +1009,17 @@ int cg_width(int qmax)
     return qmax <= 0 ? 0 : qmax <= 3 ? 3 : qmax <= 5 ? 5 : QMAX;
 }
 
-int cg_max_blocks_per_cu(size_t lds, int qt, bool lz)
+int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, bool two)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cg_kernel(qt, lz), NT, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cg_kernel(qt, lz, two), NT, lds) != hipSuccess) return 0;
     return nb;
 }
 
 hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s)
 {
     void *args[] = {(void *)&a};
-    return hipLaunchCooperativeKernel(cg_kernel(qt, lz), dim3(G), dim3(NT), args, (unsigned)lds, s);
+    return hipLaunchCooperativeKernel(cg_kernel(qt, lz, a.two_pass != 0), dim3(G), dim3(NT), args, (unsigned)lds, s);
 }
 
 }  // namespace rsr

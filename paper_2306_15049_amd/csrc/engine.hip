@@ -142,18 +142,24 @@ struct rsr_ctx {
     DBuf d_ws;                         // per-system vectors of a solve
     DBuf d_dbg;                        // optional phase timestamps
     DBuf d_tmp;                        // grouped initial guesses x0, r0 before they are copied out
-    DBuf d_rcC, d_rcQ;                 // recycle-space candidates and their orthonormal basis (kept: no
+    DBuf d_rcC, d_rcQ, d_rcR, d_rcT;   // recycle-space candidates, their orthonormal basis, the projected
+                                       // residual block and a staging block (kept: no
                                        // allocation, and no free that drains the device, per update)
     DBuf d_lz, d_lzc, d_lzr;           // CG-Lanczos capture (residuals, coefficients) and its Ritz vectors
     DBuf d_aux;                        // workgroup partials of the edge-weight and L-curve reductions
     DBuf d_corr;                       // right-hand side of the correction equation
     DBuf d_r0sq;                       // ||r0||^2 per system of a solve call, read back at its end
+    DBuf d_grad;                       // gradient partials, shifts and scratch weight planes of rsr_adjoint
     // staging arena for launch descriptors and coefficients: pinned host and
     // device halves bump-allocated in step, reset whenever the stream is drained,
     // so that launches whose inputs come from the host need no synchronisation
     DBuf ar_dev;
     char *ar_host = nullptr;
     size_t ar_cap = 0, ar_used = 0;
+    // pinned host buffer that every device-to-host read-back lands in (no copy
+    // into pageable memory is left to the runtime's staging)
+    char *rb_host = nullptr;
+    size_t rb_cap = 0;
     // per-call caches of right-hand-side quantities shared by the shifts of one
     // rsr_solve_shift_set (the same b for every shift): ||b|| and U^T b or
     // [AU EU]^T b, keyed by (b, instance, init); cleared at the start of each call
@@ -165,6 +171,8 @@ struct rsr_ctx {
     // counters and timing
     long mv_A = 0, mv_E = 0;
     int cg_gmax = 1024;                // cap on persistent-kernel workgroups (autotuned)
+    double bar_timeout_s = 30.0;       // bound on one grid-barrier wait (RSR_BARRIER_TIMEOUT_US)
+    int cg_mode = 0;                   // persistent-CG iteration form: 0 by launch size, 1 fused, 2 two-pass
     double last_cg_ms = 0.0;
     int last_launches = 0;
     long last_items = 0;
@@ -286,6 +294,39 @@ template <class T> T *stage(rsr_ctx *c, const std::vector<T> &v, hipStream_t s)
     return (T *)d;
 }
 
+// Device-to-host read-backs: the listed copies land in the pinned read-back
+// buffer, the stream is drained, and the bytes are copied out to dst.
+struct ReadBack {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+void read_back(rsr_ctx *c, const std::vector<ReadBack> &v, hipStream_t s)
+{
+    size_t tot = 0;
+    for (const auto &r : v) tot += (r.bytes + 15) & ~(size_t)15;
+    if (tot > c->rb_cap) {
+        sync(c, s);
+        if (c->rb_host) (void)hipHostFree(c->rb_host);
+        c->rb_host = nullptr;
+        c->rb_cap = 0;
+        const size_t cap = std::max<size_t>(tot, (size_t)1 << 16);
+        HIPCHK(hipHostMalloc((void **)&c->rb_host, cap, hipHostMallocDefault));
+        c->rb_cap = cap;
+    }
+    size_t o = 0;
+    for (const auto &r : v) {
+        if (r.bytes) HIPCHK(hipMemcpyAsync(c->rb_host + o, r.src, r.bytes, hipMemcpyDeviceToHost, s));
+        o += (r.bytes + 15) & ~(size_t)15;
+    }
+    sync(c, s);
+    o = 0;
+    for (const auto &r : v) {
+        if (r.bytes) memcpy(r.dst, c->rb_host + o, r.bytes);
+        o += (r.bytes + 15) & ~(size_t)15;
+    }
+}
+
 int max_tile_lds(rsr_ctx *c)
 {
     int m = 2048;
@@ -358,8 +399,7 @@ std::vector<std::vector<double>> gram(rsr_ctx *c, std::vector<GramJob> jobs, hip
     GramJob *dj = stage(c, jobs, s);
     HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), c->d_gram_scratch.as<double>(), sc, s));
     std::vector<double> h(coff);
-    HIPCHK(hipMemcpyAsync(h.data(), c->d_small.p, sizeof(double) * coff, hipMemcpyDeviceToHost, s));
-    sync(c, s);
+    read_back(c, {ReadBack{h.data(), c->d_small.p, sizeof(double) * coff}}, s);
     o = 0;
     for (size_t k = 0; k < jobs.size(); ++k) {
         out[k].assign(h.begin() + o, h.begin() + o + (size_t)jobs[k].a * jobs[k].c);
@@ -484,7 +524,10 @@ std::vector<double> norms(rsr_ctx *c, const std::vector<const double *> &v, cons
     for (size_t i = 0; i < v.size(); ++i) jobs.push_back(GramJob{v[i], n[i], 1, v[i], n[i], 1, n[i], nullptr, 0});
     auto r = gram(c, jobs, s);
     std::vector<double> out(v.size());
-    for (size_t i = 0; i < v.size(); ++i) out[i] = std::sqrt(std::max(0.0, r[i][0]));
+    for (size_t i = 0; i < v.size(); ++i) {
+        const double t = r[i][0];
+        out[i] = std::isnan(t) ? t : std::sqrt(std::max(0.0, t));   // a NaN must not read as a zero norm
+    }
     return out;
 }
 
@@ -580,6 +623,8 @@ void default_tile(Instance &I)
 struct SysHost {
     int inst;
     int slot;
+    int shift = 0;             // shift index l of the system (its group: l < split_I is the left group)
+    int fwd_slot = -1;         // adjoint systems: the slot of the forward solve of the same shift
     double gamma;
     long n;
     const double *b;
@@ -660,7 +705,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     int *out_status = out_iters + m;
     double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
     double *out_alpha = out_rho + m;
-    HIPCHK(hipMemsetAsync(c->d_out.p, 0, sizeof(int) * 2 * m, s));
+    HIPCHK(launch_fill(c->d_out.as<double>(), 0.0, (long)(c->d_out.bytes / sizeof(double)), s));
 
     const int msys = (m + 7) & ~7;
     const int tl = cg_tile_lds(max_tile_lds(c), msys);
@@ -673,7 +718,21 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         lz = lz || Y->nlz > 0;
     }
     const int qt = lz && qmax > 0 ? QMAX : cg_width(qmax);
-    int bpc = cg_max_blocks_per_cu(lds, qt, lz);
+    // Fused iterations (one phase, r and ph recomputed on the halo from three
+    // step j-1 vectors) need one grid barrier per iteration; two-pass iterations
+    // (an elementwise pass, a barrier, a stencil pass that reads ph alone) need two
+    // but read a third of the halo.  Small launches are bound by the barrier
+    // latency, large ones by the halo traffic.  Launches that record CG-Lanczos
+    // data are fused.
+    int two_pass = 0;
+    {
+        long px = 0;
+        for (auto *Y : sy) px += Y->n;
+        int mode = c->cg_mode;
+        if (const char *e = getenv("RSR_CG_MODE")) mode = atoi(e);   // override for tuning sweeps
+        two_pass = lz ? 0 : mode == 2 ? 1 : mode == 1 ? 0 : (px >= (2L << 20) ? 1 : 0);
+    }
+    int bpc = cg_max_blocks_per_cu(lds, qt, lz, two_pass != 0);
     if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
     int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
     if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
@@ -698,8 +757,9 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.out_rho = out_rho;
     a.out_alpha = out_alpha;
     a.maxit = o.maxit;
+    a.two_pass = two_pass;
     a.G = G;
-    a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * 30.0);   // 30 s
+    a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * c->bar_timeout_s);
     a.tile_lds = tl;
     a.taps_lds = taps_lds;
     a.msys = msys;
@@ -711,7 +771,13 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         a.stamps = (unsigned long long *)c->d_dbg.p;
     }
     HIPCHK(hipEventRecord(c->ev0, s));
-    HIPCHK(launch_cg(a, qt, lz, G, lds, s));
+    {
+        const hipError_t e = launch_cg(a, qt, lz, G, lds, s);
+        if (e != hipSuccess)
+            fail(e == hipErrorOutOfMemory ? RSR_E_NOMEM : RSR_E_HIP,
+                 std::string("persistent CG launch ") + std::to_string(c->last_launches + 1) + " of the call (" +
+                     std::to_string(m) + " systems, " + std::to_string(G) + " workgroups): " + hipGetErrorString(e));
+    }
     HIPCHK(hipEventRecord(c->ev1, s));
     // host work that does not depend on this launch, done while it runs
     for (auto *Y : sy) {
@@ -726,10 +792,8 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     std::vector<int> hi(2 * m + 8);
     std::vector<double> hr(2 * m);   // final r.r, then the pending step alpha
     int abort_h = 0;
-    HIPCHK(hipMemcpyAsync(hi.data(), out_iters, sizeof(int) * 2 * m, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hr.data(), out_rho, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&abort_h, a.abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    sync(c, s);
+    read_back(c, {ReadBack{hi.data(), out_iters, sizeof(int) * 2 * m}, ReadBack{hr.data(), out_rho, sizeof(double) * 2 * m},
+                  ReadBack{&abort_h, a.abort_flag, sizeof(int)}}, s);
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     if (dbg) {
@@ -900,7 +964,7 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         for (auto *Y : sy) {
             Instance &I = *c->inst[Y->inst];
             if (o.n_ritz <= 0 || I.p == 0 || !I.ae_valid) continue;
-            const int side = Y->slot < o.split_I ? 0 : 1;
+            const int side = Y->shift < o.split_I ? 0 : 1;
             if (!seen.insert(std::make_pair(Y->inst, side)).second) continue;
             const double gJ = side == 0 ? o.gJL : o.gJR;
             const int nr = std::min(o.n_ritz, I.p);
@@ -919,7 +983,7 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     for (auto *Y : sy) {
         Instance &I = *c->inst[Y->inst];
         if (o.n_ritz <= 0 || I.p == 0 || !I.ae_valid) continue;
-        const int side = Y->slot < o.split_I ? 0 : 1;
+        const int side = Y->shift < o.split_I ? 0 : 1;
         auto key = std::make_pair(Y->inst, side);
         if (groups.count(key)) continue;
         const double gJ = side == 0 ? o.gJL : o.gJR;
@@ -956,7 +1020,7 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         SysHost &Y = *Yp;
         Instance &I = *c->inst[Y.inst];
         int q = 0;
-        const int side = Y.slot < o.split_I ? 0 : 1;
+        const int side = Y.shift < o.split_I ? 0 : 1;
         auto it = groups.find(std::make_pair(Y.inst, side));
         if (it != groups.end()) {
             Grp &g = it->second;
@@ -980,6 +1044,10 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         std::vector<const double *> gcols;
         if (o.use_prev_k) {
             if (double *gv = I.gslot(Y.slot)) gcols.push_back(gv);
+            // an adjoint system also takes the forward solve's correction of its
+            // shift: the same matrix, and the directions its CG had to resolve
+            if (Y.fwd_slot >= 0)
+                if (double *gv = I.gslot(Y.fwd_slot)) gcols.push_back(gv);
         }
         if (o.use_prev_shift && g_prev_shift) gcols.push_back(g_prev_shift);
         for (const double *gv : gcols) {
@@ -1053,7 +1121,10 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
             auto bn = norms(c, v, n, s);
             for (size_t i = 0; i < need.size(); ++i) c->bnorm_cache[{need[i]->b, need[i]->inst}] = bn[i];
         }
-        for (auto *Y : sy) Y->bnorm = c->bnorm_cache[{Y->b, Y->inst}];
+        for (auto *Y : sy) {
+            Y->bnorm = c->bnorm_cache[{Y->b, Y->inst}];
+            if (!std::isfinite(Y->bnorm)) fail(RSR_E_NONFINITE, "non-finite right-hand side");
+        }
     }
     // initial guess
     tm.reset(new StageTimer(c, s, 1));
@@ -1143,7 +1214,7 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
             if (o.init == RSR_INIT_OBLIQUE) {
                 // K = AU + gs EU with the group's reference shift gs; the oblique
                 // condition K^T r0 = 0 gives K^T (AU + g EU) q = K^T b (eq. obliqueupdate)
-                const double gs = Y.slot < o.split_I ? o.gJL : o.gJR;
+                const double gs = Y.shift < o.split_I ? o.gJL : o.gJR;
                 for (int i = 0; i < p; ++i)
                     for (int j = 0; j < p; ++j)
                         H[(size_t)i * p + j] = I.Gaa[(size_t)i * p + j] + g * I.Gae[(size_t)i * p + j] +
@@ -1396,6 +1467,10 @@ rsr_status rsr_create(rsr_ctx **out, int dev)
     rsr_ctx *c = new rsr_ctx();
     c->dev = dev;
     c->hprof = getenv("RSR_HOST_PROF") != nullptr;
+    if (const char *t = getenv("RSR_BARRIER_TIMEOUT_US")) {   // bound on a grid-barrier wait (default 30 s)
+        const double us = atof(t);
+        if (us >= 0.0 && us < 3.6e9) c->bar_timeout_s = us * 1e-6;
+    }
     rsr_status st = guard(c, [&] {
         set_device(c);
         hipDeviceProp_t prop;
@@ -1432,10 +1507,11 @@ void rsr_destroy(rsr_ctx *c)
         I.gpool.release();
     }
     for (DBuf *b : {&c->d_inst, &c->d_jobs, &c->d_gram_scratch, &c->d_small, &c->d_sys, &c->d_partA, &c->d_partB,
-                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ,
-                    &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux, &c->d_corr, &c->d_r0sq})
+                    &c->d_ctl, &c->d_out, &c->d_ws, &c->d_tmp, &c->d_dbg, &c->ar_dev, &c->d_rcC, &c->d_rcQ, &c->d_rcR, &c->d_rcT,
+                    &c->d_lz, &c->d_lzc, &c->d_lzr, &c->d_aux, &c->d_corr, &c->d_r0sq, &c->d_grad})
         b->release();
     if (c->ar_host) (void)hipHostFree(c->ar_host);
+    if (c->rb_host) (void)hipHostFree(c->rb_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -1581,8 +1657,7 @@ rsr_status rsr_lcurve(rsr_ctx *c, int ii, int m, const double *gammas, const dou
         c->d_aux.ensure(sizeof(double) * 2 * (size_t)m * nb);
         HIPCHK(launch_lcurve(c->d_inst.as<InstDev>(), ii, I.n, m, X, m > 1 ? ld_x : I.n, d, c->d_aux.as<double>(), s));
         std::vector<double> h((size_t)2 * m * nb);
-        HIPCHK(hipMemcpyAsync(h.data(), c->d_aux.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-        sync(c, s);
+        read_back(c, {ReadBack{h.data(), c->d_aux.p, sizeof(double) * h.size()}}, s);
         for (int i = 0; i < m; ++i) {
             double sr = 0.0, se = 0.0;
             for (int k = 0; k < nb; ++k) {
@@ -1677,50 +1752,108 @@ int set_recycle_space_impl(rsr_ctx *c, int ii, const double *U_raw, long ld, int
         for (int j = 0; j < ncols; ++j) uc.push_back(CopyJob{U_raw + (size_t)j * ld, C + (size_t)(nr + j) * n, n});
         copy_many(c, uc, s);
     }
-    // Algorithm 1 through the Gram matrix: C^T C = V diag(sigma^2) V^T,
-    // keep sigma_1 / sigma_i < cond_max (and above the FP64 resolution of
-    // the Gram route), Q = C V_k diag(1/sigma_k); a second pass restores
-    // orthonormality to rounding level.
-    DBuf &Qb = c->d_rcQ;
-    Qb.ensure(sizeof(double) * std::max((size_t)m, pcap + ncols) * n);
-    double *Q = Qb.as<double>();
-    int keep = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        const double *X = pass == 0 ? C : Q;
-        const int mm = pass == 0 ? m : keep;
-        auto Gm = gram(c, {GramJob{X, n, mm, X, n, mm, n, nullptr, 0}}, s)[0];
-        std::vector<double> Tc;
-        if (pass == 1 && chol_qr_factor(mm, Gm.data(), Tc)) {
-            // Q^T Q is close to I: Cholesky QR restores orthonormality (same span)
-            I.d_U.ensure(sizeof(double) * std::max((size_t)keep, pcap) * n);
-            combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {Tc}, s);
-            break;
-        }
-        std::vector<double> w, V;
-        sym_eig(mm, Gm.data(), w, V);
+    // Algorithm 1 (Sec. 5.1): the left singular vectors of C with
+    // sigma_1 / sigma_i < cond_max, at most p_max of them (largest first).  The
+    // skinny SVD is taken as C = Q R followed by an SVD of the small R on the
+    // host: with R = Ur diag(sigma) Vr^T, C = (Q Ur) diag(sigma) Vr^T.  Q is
+    // built in levels.  Each level takes the eigenvectors of the Gram matrix of
+    // the current residual block Z (Z = C at the first level) whose eigenvalues
+    // lie within 1e12 of the level's largest, scales them to orthonormal
+    // columns, orthogonalises those against the earlier levels and by Cholesky
+    // QR, appends them to Q, and replaces Z by C projected twice onto the
+    // complement of Range(Q).  A level resolves singular values down to about
+    // 1e-6 of its own largest, so two levels reach 1e-12 sigma_1; the loop ends
+    // once Z holds nothing above a tenth of sigma_1 / cond_max.  R = Q^T C is
+    // then accurate to rounding of sigma_1, and its one-sided Jacobi SVD applies
+    // the threshold.
+    DBuf &Qb = c->d_rcQ, &Zb = c->d_rcR, &Tb = c->d_rcT;
+    const size_t ccap = std::max((size_t)m, pcap + ncols) * n;
+    Qb.ensure(sizeof(double) * ccap);
+    Zb.ensure(sizeof(double) * ccap);
+    Tb.ensure(sizeof(double) * ccap);
+    double *Q = Qb.as<double>(), *Zr = Zb.as<double>(), *Tm = Tb.as<double>();
+    // C_X^T C_Y (row-major a x b) and Y = beta Y (or Y0) + X Qc (Qc column-major a x b)
+    auto gram1 = [&](const double *X, int a, const double *Y, int b) {
+        return gram(c, {GramJob{X, n, a, Y, n, b, n, nullptr, 0}}, s)[0];
+    };
+    auto comb1 = [&](const double *X, int a, const std::vector<double> &Qc, double *Y, int b, double beta,
+                     const double *Y0) {
+        combo(c, {ComboJob{X, n, a, nullptr, a, Y, n, b, beta, Y0, n, n}}, {Qc}, s);
+    };
+    int r = 0;
+    double lam1 = 0.0;
+    const double *Z = C;
+    for (int level = 0; level < 4 && r < m; ++level) {
+        std::vector<double> Gm = gram1(Z, m, Z, m), w, V;
+        for (int i = 0; i < m; ++i)
+            for (int j = i + 1; j < m; ++j) Gm[(size_t)j * m + i] = Gm[(size_t)i * m + j];
+        sym_eig(m, Gm.data(), w, V);
         const double lmax = w.empty() ? 0.0 : w.back();
-        if (!(lmax > 0.0) || !std::isfinite(lmax)) fail(RSR_E_RANK, "recycle candidates are zero or non-finite");
+        if (level == 0) {
+            if (!std::isfinite(lmax)) fail(RSR_E_NONFINITE, "non-finite recycle candidates");
+            if (!(lmax > 0.0)) fail(RSR_E_RANK, "recycle candidates are all zero");
+            lam1 = lmax;
+        } else if (!(lmax > 1e-2 * lam1 / (cond_max * cond_max)) || !(lmax > 1e-32 * lam1)) {
+            break;   // nothing left above the threshold
+        }
         std::vector<int> idx;
-        for (int k = mm - 1; k >= 0; --k) {
-            const double lam = w[k];
-            const bool ok = pass == 0 ? (lam > lmax / (cond_max * cond_max) && lam > lmax * 1e-14) : lam > 0.0;
-            if (ok) idx.push_back(k);
-        }
-        if (pass == 0 && (int)idx.size() > p_max) idx.resize(p_max);
-        keep = (int)idx.size();
-        if (keep == 0) fail(RSR_E_RANK, "recycle space empty after stabilisation");
-        std::vector<double> T((size_t)mm * keep);   // column-major mm x keep
-        for (int j = 0; j < keep; ++j) {
+        for (int k = m - 1; k >= 0 && r + (int)idx.size() < m; --k)
+            if (w[k] > 1e-12 * lmax && w[k] > 1e-32 * lam1) idx.push_back(k);
+        const int kk = (int)idx.size();
+        if (kk == 0) break;
+        std::vector<double> T((size_t)m * kk);   // column-major m x kk
+        for (int j = 0; j < kk; ++j) {
             const double sc = 1.0 / std::sqrt(w[idx[j]]);
-            for (int i = 0; i < mm; ++i) T[(size_t)j * mm + i] = V[(size_t)i * mm + idx[j]] * sc;
+            for (int i = 0; i < m; ++i) T[(size_t)j * m + i] = V[(size_t)i * m + idx[j]] * sc;
         }
-        if (pass == 0) {
-            combo(c, {ComboJob{C, n, mm, nullptr, mm, Q, n, keep, 0.0, nullptr, 0, n}}, {T}, s);
-        } else {
-            I.d_U.ensure(sizeof(double) * std::max((size_t)keep, pcap) * n);
-            combo(c, {ComboJob{Q, n, mm, nullptr, mm, I.d_U.as<double>(), n, keep, 0.0, nullptr, 0, n}}, {T}, s);
+        comb1(Z, m, T, Tm, kk, 0.0, nullptr);
+        if (r > 0) {   // Tm -= Q (Q^T Tm)
+            const std::vector<double> Sq = gram1(Q, r, Tm, kk);
+            std::vector<double> Sc((size_t)r * kk);
+            for (int i = 0; i < r; ++i)
+                for (int j = 0; j < kk; ++j) Sc[(size_t)j * r + i] = -Sq[(size_t)i * kk + j];
+            comb1(Q, r, Sc, Tm, kk, 1.0, nullptr);
         }
+        // Cholesky QR of the nearly orthonormal block (same span); the Gram
+        // route again should the factorisation be refused
+        std::vector<double> G2 = gram1(Tm, kk, Tm, kk), T2;
+        int kq = kk;
+        if (!chol_qr_factor(kk, G2.data(), T2)) {
+            std::vector<double> w2, V2;
+            sym_eig(kk, G2.data(), w2, V2);
+            std::vector<int> id2;
+            for (int k = kk - 1; k >= 0; --k)
+                if (w2[k] > 1e-8 * w2.back()) id2.push_back(k);
+            kq = (int)id2.size();
+            T2.assign((size_t)kk * kq, 0.0);
+            for (int j = 0; j < kq; ++j)
+                for (int i = 0; i < kk; ++i) T2[(size_t)j * kk + i] = V2[(size_t)i * kk + id2[j]] / std::sqrt(w2[id2[j]]);
+        }
+        if (kq == 0) break;
+        comb1(Tm, kk, T2, Q + (size_t)r * n, kq, 0.0, nullptr);
+        r += kq;
+        // Z = C - Q (Q^T C), then once more against Q
+        for (int pass = 0; pass < 2; ++pass) {
+            const double *X = pass == 0 ? C : Zr;
+            const std::vector<double> Sq = gram1(Q, r, X, m);
+            std::vector<double> Sc((size_t)r * m);
+            for (int i = 0; i < r; ++i)
+                for (int j = 0; j < m; ++j) Sc[(size_t)j * r + i] = -Sq[(size_t)i * m + j];
+            if (pass == 0) comb1(Q, r, Sc, Zr, m, 0.0, C);
+            else comb1(Q, r, Sc, Zr, m, 1.0, nullptr);
+        }
+        Z = Zr;
     }
+    // R = Q^T C, its SVD on the host, and U = Q Ur(:, kept)
+    const std::vector<double> Rm = gram1(Q, r, C, m);
+    std::vector<double> sig, Ur;
+    left_svd_jacobi(r, m, Rm.data(), sig, Ur);
+    int keep = 0;
+    while (keep < r && keep < p_max && sig[keep] > 0.0 && sig[0] / sig[keep] < cond_max) ++keep;
+    if (keep == 0) fail(RSR_E_RANK, "recycle space empty after stabilisation");
+    I.d_U.ensure(sizeof(double) * std::max((size_t)keep, pcap) * n);
+    comb1(Q, r, std::vector<double>(Ur.begin(), Ur.begin() + (size_t)r * keep), I.d_U.as<double>(), keep, 0.0,
+          nullptr);
     const int p = keep;
     I.p = p;
     // A U and E U (p applications each), then the small blocks
@@ -1777,8 +1910,7 @@ int seed_from_lanczos(rsr_ctx *c, const SysHost &Y, long nlz, int seed_p, hipStr
     const int m = (int)std::min<long>(nlz, (long)Y.lz_its - 1);   // steps with alpha and beta recorded
     if (m < 2 || seed_p <= 0) return 0;
     std::vector<double> co((size_t)3 * nlz);
-    HIPCHK(hipMemcpyAsync(co.data(), c->d_lzc.p, sizeof(double) * co.size(), hipMemcpyDeviceToHost, s));
-    sync(c, s);
+    read_back(c, {ReadBack{co.data(), c->d_lzc.p, sizeof(double) * co.size()}}, s);
     const double *al = co.data(), *be = co.data() + nlz, *rho = co.data() + 2 * nlz;
     std::vector<double> T((size_t)m * m, 0.0);
     for (int j = 0; j < m; ++j) {
@@ -1853,8 +1985,7 @@ rsr_status rsr_correction_space(rsr_ctx *c, int ii, const double *x_prev, const 
         int got = 0;
         if (n_kry > 0 && Y.lz_its > 0) {
             std::vector<double> co((size_t)3 * n_kry);
-            HIPCHK(hipMemcpyAsync(co.data(), c->d_lzc.p, sizeof(double) * co.size(), hipMemcpyDeviceToHost, s));
-            sync(c, s);
+            read_back(c, {ReadBack{co.data(), c->d_lzc.p, sizeof(double) * co.size()}}, s);
             const double *rho = co.data() + 2 * n_kry;
             const int m = std::min(n_kry, Y.lz_its);
             std::vector<ComboJob> cj;
@@ -1871,118 +2002,136 @@ rsr_status rsr_correction_space(rsr_ctx *c, int ii, const double *x_prev, const 
     });
 }
 
+}  // extern "C"
+
+namespace {
+// The solve of a shift set.  slot_off > 0 marks the adjoint solves: system i
+// keeps its correction in slot slot[i] + slot_off, so the forward corrections
+// in slot[i] survive, and its local space may take the forward correction of
+// its shift as well.  Returns true when every system reached tol.
+bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, rsr_shift_stats *stats,
+               hipStream_t s, int slot_off)
+{
+    if (!d || !b || !X) fail(RSR_E_ARG, "null descriptor, b or X");
+    if (c->inst.empty()) fail(RSR_E_STATE, "operators not set");
+    const int m = d->n_sys;
+    if (m <= 0 || !d->inst || !d->gammas) fail(RSR_E_ARG, "n_sys must be positive with inst and gammas");
+    if (!(d->tol > 0.0)) fail(RSR_E_ARG, "tol must be positive");
+    if (d->init < 0 || d->init > 4) fail(RSR_E_ARG, "unknown init");
+    if (d->n_ritz < 0 || d->n_ritz > QMAX) fail(RSR_E_ARG, "n_ritz out of range");
+    if (d->seed_lanczos < 0 || d->seed_p < 0 || d->seed_n_ritz < 0 || d->seed_n_ritz > QMAX)
+        fail(RSR_E_ARG, "seed sizes out of range");
+    if (d->seed_lanczos > 0 && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "seeding needs sequential mode");
+    if (d->mode != RSR_BATCHED && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "unknown mode");
+    std::vector<SysHost> sys(m);
+    for (int i = 0; i < m; ++i) {
+        Instance &I = get_inst(c, d->inst[i]);
+        if (!std::isfinite(d->gammas[i])) fail(RSR_E_ARG, "gamma must be finite");
+        if (m > 1 && d->ld_x < I.n) fail(RSR_E_ARG, "ld_x smaller than ny*nx");
+        if (d->ld_b != 0 && d->ld_b < I.n) fail(RSR_E_ARG, "ld_b smaller than ny*nx");
+        SysHost &Y = sys[i];
+        Y.inst = d->inst[i];
+        Y.shift = d->slot ? d->slot[i] : i;
+        if (Y.shift < 0 || Y.shift >= (1 << 20)) fail(RSR_E_ARG, "slots must lie in [0, 2^20)");
+        Y.slot = Y.shift + slot_off;
+        Y.fwd_slot = slot_off > 0 ? Y.shift : -1;
+        Y.gamma = d->gammas[i];
+        Y.n = I.n;
+        Y.b = b + (size_t)i * d->ld_b;
+        Y.x = X + (size_t)i * d->ld_x;
+    }
+    set_device(c);
+    alloc_ws(c, sys);
+    c->bnorm_cache.clear();
+    c->rhs_cache.clear();
+    c->d_r0sq.ensure(sizeof(double) * (size_t)m);
+    HIPCHK(launch_fill(c->d_r0sq.as<double>(), 0.0, m, s));
+    for (int i = 0; i < m; ++i) sys[i].r0sq_dev = c->d_r0sq.as<double>() + i;
+    Opts o{d->tol, d->maxit, d->init, d->n_ritz, d->use_prev_k, d->use_prev_shift, d->split_I, d->gamma_JL,
+           d->gamma_JR};
+    c->last_cg_ms = 0.0;
+    c->last_launches = 0;
+    c->last_items = 0;
+    long maxn = 0;
+    for (auto &Y : sys) maxn = std::max(maxn, Y.n);
+    if (o.maxit <= 0) o.maxit = (int)std::min<long>(10 * maxn, 1 << 30);
+    if (d->mode == RSR_BATCHED) {
+        for (int i0 = 0; i0 < m; i0 += MAXSYS) {
+            std::vector<SysHost *> grp;
+            for (int i = i0; i < std::min(m, i0 + MAXSYS); ++i) grp.push_back(&sys[i]);
+            solve_group(c, grp, o, nullptr, s);
+            StageTimer tsc(c, s, 7);
+            store_corrections(c, grp, s);
+        }
+    } else {
+        const double *gp = nullptr;
+        // principal-space seeding from the first system's CG-Lanczos data
+        const bool seed = d->seed_lanczos > 0 && c->inst[sys[0].inst]->p == 0;
+        if (seed) {
+            const long nlz = d->seed_lanczos;
+            c->d_lz.ensure(sizeof(double) * (size_t)nlz * sys[0].n);
+            c->d_lzc.ensure(sizeof(double) * (size_t)3 * nlz);
+            HIPCHK(launch_fill(c->d_lzc.as<double>(), 0.0, 3 * nlz, s));
+            sys[0].lz = c->d_lz.as<double>();
+            sys[0].lzc = c->d_lzc.as<double>();
+            sys[0].nlz = nlz;
+        }
+        for (int i = 0; i < m; ++i) {
+            std::vector<SysHost *> one{&sys[i]};
+            if (i > 0 && sys[i].inst != sys[i - 1].inst) gp = nullptr;
+            solve_group(c, one, o, o.use_prev_shift ? gp : nullptr, s);
+            {
+                StageTimer tsc(c, s, 7);
+                store_corrections(c, one, s);
+            }
+            if (seed && i == 0 && seed_from_lanczos(c, sys[0], d->seed_lanczos, d->seed_p, s) > 0) {
+                // the remaining systems start from the seeded principal space
+                o.init = RSR_INIT_MR;
+                o.n_ritz = std::min(d->seed_n_ritz, QMAX);
+            }
+            // g^(k,l-1) for the next shift: read in place from its slot, which is not
+            // written again (nor the slot pool moved) before that shift's solve ends
+            if (o.use_prev_shift) gp = c->inst[sys[i].inst]->gslot(sys[i].slot);
+        }
+        sync(c, s);
+
+    }
+    {
+        std::vector<double> r0sq(m);
+        read_back(c, {ReadBack{r0sq.data(), c->d_r0sq.p, sizeof(double) * m}}, s);
+        for (int i = 0; i < m; ++i)
+            sys[i].relres_init = sys[i].bnorm > 0 ? std::sqrt(std::max(0.0, r0sq[i])) / sys[i].bnorm : 0.0;
+    }
+    bool all = true;
+    for (int i = 0; i < m; ++i) {
+        SysHost &Y = sys[i];
+        const bool conv = Y.relres_true <= d->tol;
+        all = all && conv;
+        if (stats) {
+            rsr_shift_stats &t = stats[i];
+            t.iters = Y.iters;
+            t.matvec_A = Y.mvA;
+            t.matvec_E = Y.mvE;
+            t.converged = conv ? 1 : 0;
+            t.restarts = Y.restarts;
+            t.local_dim = Y.q;
+            t.relres_init = Y.relres_init;
+            t.relres_true = Y.relres_true;
+        }
+    }
+    sync(c, s);
+    return all;
+}
+}  // namespace
+
+extern "C" {
+
 rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X,
                                rsr_shift_stats *stats, void *stream)
 {
     return guard(c, [&] {
-        if (!d || !b || !X) fail(RSR_E_ARG, "null descriptor, b or X");
-        if (c->inst.empty()) fail(RSR_E_STATE, "operators not set");
-        const int m = d->n_sys;
-        if (m <= 0 || !d->inst || !d->gammas) fail(RSR_E_ARG, "n_sys must be positive with inst and gammas");
-        if (!(d->tol > 0.0)) fail(RSR_E_ARG, "tol must be positive");
-        if (d->init < 0 || d->init > 4) fail(RSR_E_ARG, "unknown init");
-        if (d->n_ritz < 0 || d->n_ritz > QMAX) fail(RSR_E_ARG, "n_ritz out of range");
-        if (d->seed_lanczos < 0 || d->seed_p < 0 || d->seed_n_ritz < 0 || d->seed_n_ritz > QMAX)
-            fail(RSR_E_ARG, "seed sizes out of range");
-        if (d->seed_lanczos > 0 && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "seeding needs sequential mode");
-        if (d->mode != RSR_BATCHED && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "unknown mode");
-        std::vector<SysHost> sys(m);
-        for (int i = 0; i < m; ++i) {
-            Instance &I = get_inst(c, d->inst[i]);
-            if (!(d->gammas[i] >= 0.0) || !std::isfinite(d->gammas[i])) fail(RSR_E_ARG, "gamma must be >= 0");
-            if (m > 1 && d->ld_x < I.n) fail(RSR_E_ARG, "ld_x smaller than ny*nx");
-            if (d->ld_b != 0 && d->ld_b < I.n) fail(RSR_E_ARG, "ld_b smaller than ny*nx");
-            SysHost &Y = sys[i];
-            Y.inst = d->inst[i];
-            Y.slot = d->slot ? d->slot[i] : i;
-            Y.gamma = d->gammas[i];
-            Y.n = I.n;
-            Y.b = b + (size_t)i * d->ld_b;
-            Y.x = X + (size_t)i * d->ld_x;
-        }
-        set_device(c);
-        hipStream_t s = S(stream);
-        alloc_ws(c, sys);
-        c->bnorm_cache.clear();
-        c->rhs_cache.clear();
-        c->d_r0sq.ensure(sizeof(double) * (size_t)m);
-        HIPCHK(launch_fill(c->d_r0sq.as<double>(), 0.0, m, s));
-        for (int i = 0; i < m; ++i) sys[i].r0sq_dev = c->d_r0sq.as<double>() + i;
-        Opts o{d->tol, d->maxit, d->init, d->n_ritz, d->use_prev_k, d->use_prev_shift, d->split_I, d->gamma_JL,
-               d->gamma_JR};
-        c->last_cg_ms = 0.0;
-        c->last_launches = 0;
-        c->last_items = 0;
-        long maxn = 0;
-        for (auto &Y : sys) maxn = std::max(maxn, Y.n);
-        if (o.maxit <= 0) o.maxit = (int)std::min<long>(10 * maxn, 1 << 30);
-        if (d->mode == RSR_BATCHED) {
-            for (int i0 = 0; i0 < m; i0 += MAXSYS) {
-                std::vector<SysHost *> grp;
-                for (int i = i0; i < std::min(m, i0 + MAXSYS); ++i) grp.push_back(&sys[i]);
-                solve_group(c, grp, o, nullptr, s);
-                StageTimer tsc(c, s, 7);
-                store_corrections(c, grp, s);
-            }
-        } else {
-            const double *gp = nullptr;
-            // principal-space seeding from the first system's CG-Lanczos data
-            const bool seed = d->seed_lanczos > 0 && c->inst[sys[0].inst]->p == 0;
-            if (seed) {
-                const long nlz = d->seed_lanczos;
-                c->d_lz.ensure(sizeof(double) * (size_t)nlz * sys[0].n);
-                c->d_lzc.ensure(sizeof(double) * (size_t)3 * nlz);
-                HIPCHK(launch_fill(c->d_lzc.as<double>(), 0.0, 3 * nlz, s));
-                sys[0].lz = c->d_lz.as<double>();
-                sys[0].lzc = c->d_lzc.as<double>();
-                sys[0].nlz = nlz;
-            }
-            for (int i = 0; i < m; ++i) {
-                std::vector<SysHost *> one{&sys[i]};
-                if (i > 0 && sys[i].inst != sys[i - 1].inst) gp = nullptr;
-                solve_group(c, one, o, o.use_prev_shift ? gp : nullptr, s);
-                {
-                    StageTimer tsc(c, s, 7);
-                    store_corrections(c, one, s);
-                }
-                if (seed && i == 0 && seed_from_lanczos(c, sys[0], d->seed_lanczos, d->seed_p, s) > 0) {
-                    // the remaining systems start from the seeded principal space
-                    o.init = RSR_INIT_MR;
-                    o.n_ritz = std::min(d->seed_n_ritz, QMAX);
-                }
-                // g^(k,l-1) for the next shift: read in place from its slot, which is not
-                // written again (nor the slot pool moved) before that shift's solve ends
-                if (o.use_prev_shift) gp = c->inst[sys[i].inst]->gslot(sys[i].slot);
-            }
-            sync(c, s);
-
-        }
-        {
-            std::vector<double> r0sq(m);
-            HIPCHK(hipMemcpyAsync(r0sq.data(), c->d_r0sq.p, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-            sync(c, s);
-            for (int i = 0; i < m; ++i)
-                sys[i].relres_init = sys[i].bnorm > 0 ? std::sqrt(std::max(0.0, r0sq[i])) / sys[i].bnorm : 0.0;
-        }
-        bool all = true;
-        for (int i = 0; i < m; ++i) {
-            SysHost &Y = sys[i];
-            const bool conv = Y.relres_true <= d->tol;
-            all = all && conv;
-            if (stats) {
-                rsr_shift_stats &t = stats[i];
-                t.iters = Y.iters;
-                t.matvec_A = Y.mvA;
-                t.matvec_E = Y.mvE;
-                t.converged = conv ? 1 : 0;
-                t.restarts = Y.restarts;
-                t.local_dim = Y.q;
-                t.relres_init = Y.relres_init;
-                t.relres_true = Y.relres_true;
-            }
-        }
-        sync(c, s);
-        if (!all) throw Err{RSR_NOT_CONVERGED, "some systems did not reach tol"};
+        if (!solve_set(c, d, b, X, stats, S(stream), 0))
+            throw Err{RSR_NOT_CONVERGED, "some systems did not reach tol"};
     });
 }
 
@@ -1990,57 +2139,50 @@ rsr_status rsr_adjoint(rsr_ctx *c, const rsr_solve_desc *d, const double *X, con
                        double *dgamma_host, double *dw_h, double *dw_v, double *db, rsr_shift_stats *stats,
                        void *stream)
 {
-    if (!c) return RSR_E_ARG;
-    if (!d || !X || !Gbar || !Lambda) {
-        c->err = "null argument";
-        return RSR_E_ARG;
-    }
-    // B_l lambda_l = Gbar_l with the same recycled solver (B_l symmetric); the
-    // adjoint slots are offset so the forward corrections are kept.
-    rsr_solve_desc ad = *d;
-    std::vector<int> slots(d->n_sys);
-    for (int i = 0; i < d->n_sys; ++i) slots[i] = (d->slot ? d->slot[i] : i) + (1 << 20);
-    ad.slot = slots.data();
-    ad.ld_b = d->ld_x;
-    if (ad.init == RSR_INIT_GIVEN) ad.init = RSR_INIT_ZERO;
-    rsr_status st = rsr_solve_shift_set(c, &ad, Gbar, Lambda, stats, stream);
-    if (st < 0) return st;
-    rsr_status st2 = guard(c, [&] {
+    bool all = true;
+    rsr_status st = guard(c, [&] {
+        if (!d || !X || !Gbar || !Lambda) fail(RSR_E_ARG, "null argument");
+        if (d->n_sys <= 0 || !d->inst || !d->gammas) fail(RSR_E_ARG, "n_sys must be positive with inst and gammas");
         const int m = d->n_sys;
         const int ii = d->inst[0];
         for (int i = 1; i < m; ++i)
             if (d->inst[i] != ii) fail(RSR_E_ARG, "adjoint expects one instance");
         Instance &I = get_inst(c, ii);
+        if (m > 1 && d->ld_x < I.n) fail(RSR_E_ARG, "ld_x smaller than ny*nx");
+        // B_l lambda_l = Gbar_l with the same recycled solver (B_l symmetric); the
+        // adjoint systems keep their corrections in slots of their own
+        rsr_solve_desc ad = *d;
+        ad.ld_b = d->ld_x;
+        if (ad.init == RSR_INIT_GIVEN) ad.init = RSR_INIT_ZERO;
+        ad.seed_lanczos = 0;
         hipStream_t s = S(stream);
-        set_device(c);
+        all = solve_set(c, &ad, Gbar, Lambda, stats, s, 1 << 20);
+        // gradients: one pass over X and Lambda, partial sums of dL/dgamma per chunk
         const int nch = 512;
-        DBuf dg, gam;
-        dg.ensure(sizeof(double) * (size_t)nch * m);
-        gam.ensure(sizeof(double) * m);
-        HIPCHK(hipMemcpyAsync(gam.p, d->gammas, sizeof(double) * m, hipMemcpyHostToDevice, s));
-        DBuf tmpw;
+        const long n = I.n;
+        c->d_grad.ensure(sizeof(double) * ((size_t)nch * m + ((dw_h && dw_v) ? 0 : 2 * (size_t)n)));
+        double *dg = c->d_grad.as<double>();
         double *wh = dw_h, *wv = dw_v;
         if (!wh || !wv) {
-            tmpw.ensure(sizeof(double) * 2 * I.n);
-            wh = tmpw.as<double>();
-            wv = wh + I.n;
+            wh = dg + (size_t)nch * m;
+            wv = wh + n;
         }
-        HIPCHK(launch_grad(X, Lambda, d->ld_x, gam.as<double>(), m, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny,
-                           I.nx, wh, wv, db, dg.as<double>(), nch, s));
+        const double *gam = stage(c, std::vector<double>(d->gammas, d->gammas + m), s);
+        HIPCHK(launch_grad(X, Lambda, d->ld_x, gam, m, I.d_wh.as<double>(), I.d_wv.as<double>(), I.ny, I.nx, wh, wv,
+                           db, dg, nch, s));
         std::vector<double> h((size_t)nch * m);
-        HIPCHK(hipMemcpyAsync(h.data(), dg.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-        sync(c, s);
+        read_back(c, {ReadBack{h.data(), dg, sizeof(double) * h.size()}}, s);
         if (dgamma_host)
             for (int l = 0; l < m; ++l) {
                 double sm = 0.0;
                 for (int k = 0; k < nch; ++k) sm += h[(size_t)k * m + l];
                 dgamma_host[l] = sm;
             }
-        dg.release();
-        gam.release();
-        tmpw.release();
     });
-    if (st2 != RSR_OK) return st2;
+    if (st == RSR_OK && !all) {
+        c->err = "some adjoint systems did not reach tol";
+        return RSR_NOT_CONVERGED;
+    }
     return st;
 }
 

@@ -313,6 +313,72 @@ inline bool lu_solve(int n, const double *S, const double *f, double *x, double 
     return true;
 }
 
+// Singular values and left singular vectors of a small dense r x m matrix R
+// (row-major) by one-sided Jacobi rotations (Hestenes' method) applied to the
+// columns of A = R^T, which are the rows of R.  Rotating pairs of columns of A
+// until all are mutually orthogonal gives A J = [u_1 s_1 ... u_r s_r] with J
+// orthogonal, hence R = J diag(s) [u_1 ... u_r]^T: the columns of the
+// accumulated J are R's left singular vectors.  Each rotation is exact to
+// rounding, so the singular values carry an absolute error of a few ulps of
+// the largest one (no squaring of the condition number as in an eigen
+// decomposition of R R^T).  Outputs s descending and Ul column-major r x r
+// (column k belongs to s[k]).
+inline void left_svd_jacobi(int r, int m, const double *R, std::vector<double> &s, std::vector<double> &Ul)
+{
+    std::vector<double> A(R, R + (size_t)r * m);   // column j of A = row j of R (contiguous)
+    std::vector<double> J((size_t)r * r, 0.0);     // column-major
+    for (int j = 0; j < r; ++j) J[(size_t)j * r + j] = 1.0;
+    const double tol = 4e-16;
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        bool rotated = false;
+        for (int p = 0; p + 1 < r; ++p)
+            for (int q = p + 1; q < r; ++q) {
+                double *ap = A.data() + (size_t)p * m, *aq = A.data() + (size_t)q * m;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = 0; i < m; ++i) {
+                    al += ap[i] * ap[i];
+                    be += aq[i] * aq[i];
+                    ga += ap[i] * aq[i];
+                }
+                if (!(al > 0.0) || !(be > 0.0) || !(std::fabs(ga) > tol * std::sqrt(al * be))) continue;
+                rotated = true;
+                // the rotation that zeroes the pair's inner product: t = tan(theta) is the
+                // smaller root of t^2 + 2 zeta t - 1 = 0
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+                for (int i = 0; i < m; ++i) {
+                    const double u = ap[i], v = aq[i];
+                    ap[i] = cs * u - sn * v;
+                    aq[i] = sn * u + cs * v;
+                }
+                double *jp = J.data() + (size_t)p * r, *jq = J.data() + (size_t)q * r;
+                for (int i = 0; i < r; ++i) {
+                    const double u = jp[i], v = jq[i];
+                    jp[i] = cs * u - sn * v;
+                    jq[i] = sn * u + cs * v;
+                }
+            }
+        if (!rotated) break;
+    }
+    std::vector<std::pair<double, int>> sv(r);
+    for (int j = 0; j < r; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < m; ++i) t += A[(size_t)j * m + i] * A[(size_t)j * m + i];
+        sv[j] = {std::sqrt(t), j};
+    }
+    std::stable_sort(sv.begin(), sv.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+        return a.first > b.first;
+    });
+    s.resize(r);
+    Ul.assign((size_t)r * r, 0.0);
+    for (int k = 0; k < r; ++k) {
+        s[k] = sv[k].first;
+        std::copy(J.begin() + (size_t)sv[k].second * r, J.begin() + (size_t)(sv[k].second + 1) * r,
+                  Ul.begin() + (size_t)k * r);
+    }
+}
+
 inline void matvec(int n, int m, const double *M, const double *x, double *y)  // y = M x, M n x m
 {
     for (int i = 0; i < n; ++i) {

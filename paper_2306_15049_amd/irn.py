@@ -10,8 +10,9 @@ One outer step k (Algorithm 5, per-k solve phase) on each instance:
      of Ritz vectors and previous corrections (Algorithms 2-4), deflated CG.
 At k = 0 there is no principal space (the first-step spike of Section 8.2).
 
-The "plain" variant solves every shift from x0 = 0 with plain CG, one shift at
-a time -- the naive baseline of Section 8 with CG in place of MINRES.
+The "plain" variant solves every shift from x0 = 0 with plain CG -- the naive
+baseline of Section 8 with CG in place of MINRES; "warm" is plain CG started
+from the previous outer step's solution of the same shift.
 
 l* is fixed to the middle shift (ceil(M/2), 1-based) so that the plain and
 recycled runs see identical weight sequences.
@@ -42,6 +43,7 @@ class StepRecord:
     cg_items: int = 0
     cg_launches: int = 0
     l_star: int = -1          # shift index whose solution drives the next weights
+    local_dim: List[int] = field(default_factory=list)   # local-space width used by each system
 
 
 @dataclass
@@ -85,6 +87,8 @@ class OuterLoop:
         next weights at the L-curve corner after every step; otherwise the middle shift.
         The loop reports `stopped` once that choice has repeated stop_repeats times."""
         import torch
+        if method not in ("recycled", "plain", "warm"):
+            raise ValueError("method must be 'recycled', 'plain' or 'warm'")
         if weight_rule not in ("irn", "edge"):
             raise ValueError("weight_rule must be 'irn' or 'edge'")
         self.ctx = ctx
@@ -140,6 +144,9 @@ class OuterLoop:
         g = self.cfg.gammas
         if self.method == "plain":
             return rsr.SolveOptions(tol=self.tol, mode=self.mode, init=rsr.INIT_ZERO)
+        if self.method == "warm":
+            return rsr.SolveOptions(tol=self.tol, mode=self.mode,
+                                    init=rsr.INIT_GIVEN if self.k > 0 else rsr.INIT_ZERO)
         split = int(math.ceil(self.rp.split_frac * M))
         jl = max(1, min(split, M)) - 1            # J_L = split (1-based)
         jr = max(split, M - 2)                    # J_R = M - 1 (1-based)
@@ -163,14 +170,15 @@ class OuterLoop:
         p_dim = 0
         if self.k > 0:
             for i in range(n_inst):
-                corr = self.method != "plain" and self.rp.correction > 0
+                recycled = self.method == "recycled"
+                corr = recycled and self.rp.correction > 0
                 if corr:
                     wold = ctx.get_weights(i)   # W_{k-1}, for the correction equation
                 if self.weight_rule == "edge":
                     ctx.weights_edge_rule(i, self.X[i][self.l_stars[i]], self.edge_p)
                 else:
                     ctx.weights_from_image(i, self.X[i][self.l_stars[i]], self.rp.beta)
-                if self.method != "plain":
+                if recycled:
                     cand, n_extra = self.X[i], 0
                     if corr:
                         # [dx, Krylov vectors] of eq. delta at the shift l_c join the candidates
@@ -184,13 +192,13 @@ class OuterLoop:
                                                   gamma_retain=float(self.cfg.gammas[0]), p_max=self.rp.p,
                                                   cond_max=self.rp.cond_max)
         o = self._opts()
-        iters, rel, rel0 = [], [], []
+        iters, rel, rel0, qd = [], [], [], []
         if n_inst == 1:
             rc, st = ctx.solve(self.cfg.gammas, self.b[0], self.X[0], opts=o)
             stats = [st]
         else:
             stats = self._solve_instances(o)
-        if self.k == 0 and self.method != "plain" and n_inst == 1:
+        if self.k == 0 and self.method == "recycled" and n_inst == 1:
             p_dim = ctx.recycle_info(0)[0]   # a principal space seeded during the solve
         cg_ms, launches, items = ctx.last_timing()
         if self.lcurve:
@@ -206,8 +214,9 @@ class OuterLoop:
             iters += [s["iters"] for s in st]
             rel += [s["relres_true"] for s in st]
             rel0 += [s["relres_init"] for s in st]
+            qd += [s["local_dim"] for s in st]
         rec = StepRecord(self.k, wall, a1 - a0, e1 - e0, iters, rel, rel0, p_dim, cg_ms, items, launches,
-                         self.l_stars[0])
+                         self.l_stars[0], qd)
         self.k += 1
         return rec
 

@@ -6,8 +6,10 @@ library is missing -- there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -138,6 +140,17 @@ class SolveOptions:
     seed_n_ritz: int = 0       # Ritz vectors in the local spaces of the systems after the seed
 
 
+_open_contexts: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_contexts():
+    """Destroy contexts still open at interpreter exit, while the HIP runtime is
+    still up (a destructor run later, during module teardown, would not be)."""
+    for c in list(_open_contexts):
+        c.close()
+
+
 class Context:
     """One library context on one device (wraps rsr_ctx)."""
 
@@ -147,6 +160,7 @@ class Context:
         self._check(self.lib.rsr_create(ctypes.byref(h), int(device)), None)
         self.h = h
         self.shapes: List[tuple] = []
+        _open_contexts.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -293,7 +307,7 @@ class Context:
         o = opts or SolveOptions()
         m = len(gammas)
         d, keep = self._desc([inst] * m, gammas, slots, o, X[0].numel(), X[0].numel())
-        ny, nx = self.shapes[inst]
+        ny, nx = X.shape[-2], X.shape[-1]
         dg = np.zeros(m)
         dwh = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
         dwv = torch.empty_like(dwh)

@@ -1,0 +1,138 @@
+"""GPU parity of the recycled outer loop on every workload, at full size.
+
+* 256 x 256, all 20 shifts batched (recycled, five outer steps): residual gate
+  of every shift at every step with the oracle's operator.
+* 1024 x 1024, 32 shifts batched (recycled, three outer steps): residual gate
+  on shifts 1, 16 and 32 (1-based) at every step, and every system's own
+  recomputed residual.
+* 1024 x 1024 with a delta PSF and unit weights, recycled: the second solve
+  (principal space from the first, minimum-residual guess, Ritz vectors and
+  previous corrections, a new right-hand side) against the closed form
+  IDCT(DCT(b) / (1 + gamma lambda)), so x is pinned at full size.
+* 64 uneven instances x 8 shifts in one launch (recycled, three outer steps):
+  residual gate on 4 sampled instances x shifts 1, 4, 8.
+* The autotuner: a solve after rsr_autotune meets the same gates as before it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_2306_15049_amd import irn, rsr, synth
+from conftest import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _gate(pr, wh, wv, gammas, b, X, shifts, tol, tag):
+    for l in shifts:
+        rel = oracle.true_relres(pr.psf, wh, wv, gammas[l], b, X[l])
+        assert rel <= tol, (tag, l, rel)
+
+
+def test_c2_batched_recycled_all_shifts(ctx):
+    cfg = synth.config("C2")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    loop = irn.OuterLoop(ctx, cfg, "recycled", mode=rsr.BATCHED)
+    loop.b[0] = to_dev(b)
+    for k in range(cfg.outer_steps):
+        print(f"C2 batched recycled step {k}", flush=True)
+        rec = loop.step()
+        assert max(rec.relres) <= cfg.tol
+        if k > 0:
+            assert rec.p > 0 and max(rec.relres_init) < 1.0
+        wh, wv = (to_host(t) for t in ctx.get_weights(0))
+        _gate(pr, wh, wv, cfg.gammas, b, to_host(loop.X[0]), range(len(cfg.gammas)), cfg.tol, k)
+
+
+def test_c3_recycled_batched_steps(ctx):
+    cfg = synth.config("C3")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    loop = irn.OuterLoop(ctx, cfg, "recycled")
+    loop.b[0] = to_dev(b)
+    plain_k0 = None
+    for k in range(3):
+        print(f"C3 recycled batched step {k}", flush=True)
+        rec = loop.step()
+        assert max(rec.relres) <= cfg.tol, k
+        if k == 0:
+            plain_k0 = sum(rec.iters)
+        else:
+            assert rec.p > 32 and max(rec.relres_init) < 1.0
+        wh, wv = (to_host(t) for t in ctx.get_weights(0))
+        _gate(pr, wh, wv, cfg.gammas, b, to_host(loop.X[0]), (0, 15, 31), cfg.tol, k)
+    assert plain_k0 > 0
+
+
+def test_delta_psf_recycled_solve_closed_form(ctx):
+    n = 1024
+    rng = np.random.default_rng(12)
+    ctx.set_operators([(n, n)], [np.ones((1, 1))])
+    gammas = [1e-2, 0.3, 10.0]
+    M = len(gammas)
+    b1 = rng.standard_normal((n, n))
+    X = to_dev(np.zeros((M, n, n)))
+    print("delta PSF 1024^2: plain first solve", flush=True)
+    rc, st = ctx.solve(gammas, to_dev(b1), X, opts=rsr.SolveOptions(tol=1e-10))
+    assert rc == 0
+    p = ctx.set_recycle_space(0, X.clone(), p_max=8)
+    assert p == M
+    # a new right-hand side close to the first one: the recycled machinery must
+    # still land on the exact solution of the new system
+    b2 = b1 + 0.1 * rng.standard_normal((n, n))
+    opts = rsr.SolveOptions(tol=1e-12, init=rsr.INIT_MR, n_ritz=2, use_prev_k=True, split_I=2,
+                            gamma_JL=gammas[1], gamma_JR=gammas[2])
+    print("delta PSF 1024^2: recycled second solve", flush=True)
+    rc, st = ctx.solve(gammas, to_dev(b2), X, opts=opts)
+    assert rc == 0
+    assert all(s["local_dim"] >= 2 for s in st) and all(s["relres_init"] < 1.0 for s in st)
+    Xh = to_host(X)
+    for l, g in enumerate(gammas):
+        ref = dense.neumann_dct_solve(b2, g)
+        assert np.linalg.norm(Xh[l] - ref) <= 1e-9 * np.linalg.norm(ref), l
+
+
+def test_c4_uneven_instances_recycled_steps(ctx):
+    cfg = synth.config("C4")
+    loop = irn.OuterLoop(ctx, cfg, "recycled")
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(len(cfg.problems), size=4, replace=False).tolist())
+    rhs = {i: oracle.rhs(cfg.problems[i])[1] for i in sample}
+    for i in sample:
+        loop.b[i] = to_dev(rhs[i])
+    if hasattr(loop, "_Bp"):
+        del loop._Bp
+    for k in range(cfg.outer_steps):
+        print(f"C4 recycled step {k}", flush=True)
+        rec = loop.step()
+        assert max(rec.relres) <= cfg.tol, k
+        for i in sample:
+            pr = cfg.problems[i]
+            wh, wv = (to_host(t) for t in ctx.get_weights(i))
+            _gate(pr, wh, wv, cfg.gammas, rhs[i], to_host(loop.X[i]), (0, 3, 7), cfg.tol, (k, i))
+
+
+def test_autotuned_solve_meets_the_gates(ctx):
+    cfg = synth.config("C2")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    ctx.set_operators([(256, 256)], [pr.psf])
+    wh, wv = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    gammas = [cfg.gammas[2], cfg.gammas[12], cfg.gammas[19]]
+    opts = rsr.SolveOptions(tol=1e-12)
+    X0 = to_dev(np.zeros((3, 256, 256)))
+    rc, st0 = ctx.solve(gammas, to_dev(b), X0, opts=opts)
+    assert rc == 0
+    print("autotune 256^2", flush=True)
+    tile = ctx.autotune(0, 3)
+    assert tile[0] >= 4 and tile[1] >= 4
+    X1 = to_dev(np.zeros((3, 256, 256)))
+    rc, st1 = ctx.solve(gammas, to_dev(b), X1, opts=opts)
+    assert rc == 0
+    A, B = to_host(X0), to_host(X1)
+    for l, g in enumerate(gammas):
+        assert oracle.true_relres(pr.psf, wh, wv, g, b, B[l]) <= 1e-12
+        assert np.linalg.norm(A[l] - B[l]) <= 1e-6 * np.linalg.norm(A[l])

@@ -1,0 +1,136 @@
+"""Error paths of the library, triggered from the inputs (every kernel exits
+normally; the conditions are forced from the host).
+
+* NaN in b -> RSR_E_NONFINITE before any CG launch; NaN in the weights ->
+  RSR_E_NONFINITE from the CG kernel's own check; NaN in the recycle
+  candidates -> RSR_E_NONFINITE from Algorithm 1.
+* A shift that makes B indefinite (delta PSF, unit weights, gamma = -1: the
+  high frequencies of I - L have negative eigenvalues) -> RSR_E_NOT_SPD from
+  p^T B p <= 0.
+* Duplicate candidate columns (exact rank deficiency) -> the kept dimension
+  is the rank; all-zero candidates -> RSR_E_RANK.
+* Calls out of order -> RSR_E_STATE; bad descriptors -> RSR_E_ARG.
+* The grid barrier's bounded wait: with a limit of 0 us every wait gives up
+  at once, every workgroup leaves the kernel, and the solve reports
+  RSR_E_TIMEOUT; the same context then solves normally with the default limit.
+"""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_15049_amd import rsr, synth
+from conftest import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _small(ctx, n=24):
+    pr = synth.make_problem(21, n, n, 1.5, 7, 5)
+    _, b = oracle.rhs(pr)
+    ctx.set_operators([(n, n)], [pr.psf])
+    return pr, b
+
+
+def _status(fn):
+    with pytest.raises(rsr.RsrError) as e:
+        fn()
+    return e.value.status
+
+
+def test_nonfinite_inputs(ctx):
+    n = 24
+    pr, b = _small(ctx, n)
+    X = to_dev(np.zeros((2, n, n)))
+    bad = b.copy()
+    bad[5, 7] = np.nan
+    assert _status(lambda: ctx.solve([0.1, 1.0], to_dev(bad), X)) == -3
+    wh, wv = oracle.unit_weights(n, n)
+    wh = wh.copy()
+    wh[3, 3] = np.inf
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    assert _status(lambda: ctx.solve([0.1, 1.0], to_dev(b), X)) == -3
+    wh, wv = oracle.unit_weights(n, n)
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    rc, st = ctx.solve([0.1, 1.0], to_dev(b), X)          # the context is still usable
+    assert rc == 0
+    cand = to_host(X).copy()
+    cand[1, 0, 0] = np.nan
+    assert _status(lambda: ctx.set_recycle_space(0, to_dev(cand), p_max=4)) == -3
+
+
+def test_indefinite_shift_reports_not_spd(ctx):
+    n = 32
+    ctx.set_operators([(n, n)], [np.ones((1, 1))])
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal((n, n))
+    X = to_dev(np.zeros((1, n, n)))
+    assert _status(lambda: ctx.solve([-1.0], to_dev(b), X)) == -4
+    rc, st = ctx.solve([0.5], to_dev(b), X)
+    assert rc == 0
+
+
+def test_rank_deficient_and_zero_candidates(ctx):
+    n = 20
+    pr, b = _small(ctx, n)
+    rng = np.random.default_rng(4)
+    V = rng.standard_normal((3, n, n))
+    cand = np.stack([V[0], V[1], V[0], V[2], V[1] + V[2]])
+    assert ctx.set_recycle_space(0, to_dev(cand), p_max=10) == 3
+    assert _status(lambda: ctx.set_recycle_space(0, to_dev(np.zeros((2, n, n))), p_max=4)) == -5
+
+
+def test_call_order_and_descriptor_checks(torch_cuda):
+    c = rsr.Context(0)
+    try:
+        X = to_dev(np.zeros((1, 8, 8)))
+        b = to_dev(np.ones((8, 8)))
+        assert _status(lambda: c.solve([1.0], b, X)) == -2
+        assert _status(lambda: c.set_recycle_space(0, X, p_max=2)) == -2
+        assert _status(lambda: c.adjoint([1.0], X, b.reshape(1, 8, 8).contiguous(), X)) == -2
+        c.set_operators([(8, 8)], [np.ones((1, 1))])
+        assert _status(lambda: c.solve([1.0], b, X, opts=rsr.SolveOptions(tol=0.0))) == -1
+        assert _status(lambda: c.solve([np.inf], b, X)) == -1
+        assert _status(lambda: c.solve([1.0], b, X, opts=rsr.SolveOptions(n_ritz=9))) == -1
+        assert _status(lambda: c.solve([1.0], b, X, opts=rsr.SolveOptions(init=7))) == -1
+        assert _status(lambda: c.solve([1.0], b, X, inst=[1])) == -1
+        assert _status(lambda: c.solve([1.0], b, X, slots=[-1])) == -1
+        assert _status(lambda: c.set_recycle_space(0, X, p_max=2, cond_max=0.5)) == -1
+    finally:
+        c.close()
+
+
+def test_barrier_time_limit_gives_up_and_drains():
+    # a fresh process, so the limit read at context creation applies to it alone
+    code = r"""
+import numpy as np, torch
+from paper_2306_15049_amd import rsr
+torch.cuda.set_device(0)
+n = 256
+rng = np.random.default_rng(1)
+b = torch.from_numpy(rng.standard_normal((n, n))).cuda()
+X = torch.zeros((4, n, n), dtype=torch.float64, device="cuda")
+c = rsr.Context(0)
+c.set_operators([(n, n)], [np.ones((1, 1))])
+try:
+    c.solve([0.1, 1.0, 3.0, 10.0], b, X)
+    print("NO-TIMEOUT")
+except rsr.RsrError as e:
+    print("STATUS", e.status, str(e))
+c.close()
+"""
+    env = dict(os.environ, RSR_BARRIER_TIMEOUT_US="0")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "STATUS -8" in out.stdout, out.stdout + out.stderr[-2000:]
+    # and with the default limit the same solve completes
+    env.pop("RSR_BARRIER_TIMEOUT_US")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0 and "NO-TIMEOUT" in out.stdout, out.stdout + out.stderr[-2000:]

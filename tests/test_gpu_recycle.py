@@ -34,24 +34,66 @@ def _setup(ctx, n=20, seed=31, sigma=1.5, s=7):
 
 
 def test_stabilize_threshold_and_orthonormality(ctx):
+    # Algorithm 1 with the paper's threshold: sigma_1 / sigma_i = 5e9 is kept and
+    # 5e13 dropped, as numpy's SVD decides at cond_max = 1e10
     n = 24
     pr, b, wh, wv = _setup(ctx, n=n)
     rng = np.random.default_rng(3)
     Q0, _ = np.linalg.qr(rng.standard_normal((n * n, 7)))
     W0, _ = np.linalg.qr(rng.standard_normal((7, 7)))
-    sv = np.array([5.0, 1.0, 0.3, 1e-2, 1e-4, 1e-9, 1e-13])   # 1e-9 and 1e-13 fall below the resolved range
+    sv = np.array([5.0, 1.0, 0.3, 1e-2, 1e-4, 1e-9, 1e-13])
     Ur = (Q0 @ np.diag(sv) @ W0.T).T.reshape(7, n, n)
     p = ctx.set_recycle_space(0, to_dev(Ur), p_max=10, cond_max=1e10)
-    Qref, _ = dense.stabilize(Ur.reshape(7, -1).T, 1e6)          # resolution cap of the Gram route
-    assert p == Qref.shape[1] == 5
+    Qref, _ = dense.stabilize(Ur.reshape(7, -1).T, 1e10)
+    assert p == Qref.shape[1] == 6
     U = to_host(ctx.recycle_basis(0)).reshape(p, -1).T
     np.testing.assert_allclose(U.T @ U, np.eye(p), atol=1e-12)
-    P = Q0[:, :5] @ Q0[:, :5].T
-    assert np.linalg.norm(U - P @ U) < 1e-8
+    P = Q0[:, :6] @ Q0[:, :6].T
+    assert np.linalg.norm(U - P @ U) < 5e-6          # the 1e-9 direction is resolved
+    assert np.linalg.norm(Qref - U @ (U.T @ Qref)) < 5e-6
     p2 = ctx.set_recycle_space(0, to_dev(Ur), p_max=3, cond_max=1e10)
     assert p2 == 3
+    U2 = to_host(ctx.recycle_basis(0)).reshape(p2, -1).T
+    assert np.linalg.norm(Q0[:, :3] - U2 @ (U2.T @ Q0[:, :3])) < 1e-10   # the 3 largest
     p3 = ctx.set_recycle_space(0, to_dev(Ur), p_max=10, cond_max=10.0)   # sigma_1/sigma_i < 10
     assert p3 == 2
+
+
+@pytest.mark.parametrize("m,seed", [(12, 7), (40, 8)])
+def test_stabilize_graded_spectrum_matches_numpy_svd(ctx, m, seed):
+    # a graded spectrum from 1 down to 1e-14 (no value near the threshold): the
+    # kept dimension and the kept subspace equal numpy's truncated SVD at 1e10;
+    # a duplicated column (exact rank deficiency) changes neither
+    n = 32
+    _setup(ctx, n=n)
+    rng = np.random.default_rng(seed)
+    Q0, _ = np.linalg.qr(rng.standard_normal((n * n, m)))
+    W0, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    lr = np.linspace(0.0, 14.0, m)
+    lr[np.abs(lr - 10.0) < 0.3] = 9.6                          # keep clear of the threshold
+    sv = 10.0 ** (0.37 - lr)
+    C = Q0 @ np.diag(sv) @ W0.T
+    C = np.concatenate([C, C[:, :1]], axis=1)
+    Qref, s = dense.stabilize(C, 1e10)
+    assert np.all(np.abs(np.log10(s[0] / s[:m]) - 10.0) > 0.2)
+    p = ctx.set_recycle_space(0, to_dev(C.T.reshape(m + 1, n, n)), p_max=m + 1, cond_max=1e10)
+    assert p == Qref.shape[1]
+    U = to_host(ctx.recycle_basis(0)).reshape(p, -1).T
+    np.testing.assert_allclose(U.T @ U, np.eye(p), atol=1e-12)
+    assert np.linalg.norm(Qref - U @ (U.T @ Qref)) < 1e-5
+
+
+def test_stabilize_rejects_nonfinite_and_zero_candidates(ctx):
+    n = 16
+    _setup(ctx, n=n)
+    bad = np.ones((2, n, n))
+    bad[1, 3, 4] = np.nan
+    with pytest.raises(rsr.RsrError) as e:
+        ctx.set_recycle_space(0, to_dev(bad), p_max=4)
+    assert e.value.status == -3
+    with pytest.raises(rsr.RsrError) as e:
+        ctx.set_recycle_space(0, to_dev(np.zeros((3, n, n))), p_max=4)
+    assert e.value.status == -5
 
 
 def test_projected_blocks_match_oracle(ctx):

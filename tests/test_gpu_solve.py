@@ -110,3 +110,27 @@ def test_maxit_reports_not_converged(ctx):
     rc, st = ctx.solve([1e-4, 1e-3], to_dev(b), X, opts=rsr.SolveOptions(tol=1e-10, maxit=5))
     assert rc == 1
     assert all(s["iters"] == 5 and s["converged"] == 0 for s in st)
+
+
+@pytest.mark.parametrize("recycled", [False, True])
+def test_fused_and_two_pass_iterations_agree_bitwise(ctx, monkeypatch, recycled):
+    # the two iteration forms of the persistent kernel compute the same values in
+    # the same order (r_j, ph_j per cell; the stencil; the partial sums), so the
+    # solutions agree to the last bit; ragged tiles, several systems, local spaces
+    from paper_2306_15049_amd import irn
+    pr = synth.make_problem(9, 150, 203, 2.0, 13, 12)
+    _, b = oracle.rhs(pr)
+    cfg = synth.Config("ragged", [pr], synth.shift_grid(-4, 1, 6), 3, 12, 5, "batched")
+    out = {}
+    for mode in ("1", "2"):
+        monkeypatch.setenv("RSR_CG_MODE", mode)
+        loop = irn.OuterLoop(ctx, cfg, "recycled" if recycled else "plain")
+        loop.b[0] = to_dev(b)
+        recs = loop.run(3 if recycled else 1)
+        out[mode] = (to_host(loop.X[0]), [r.iters for r in recs])
+    assert out["1"][1] == out["2"][1]
+    assert np.array_equal(out["1"][0], out["2"][0])
+    wh, wv = (to_host(t) for t in ctx.get_weights(0))
+    X = out["2"][0]
+    for l, g in enumerate(cfg.gammas):
+        assert oracle.true_relres(pr.psf, wh, wv, g, b, X[l]) <= 1e-8

@@ -105,3 +105,53 @@ def test_cholesky_qr_factor():
             P = Q @ np.linalg.pinv(Q)
             assert np.linalg.norm(U - P @ U) < 1e-12
         assert run(np.array([[1.0, 2.0], [2.0, 1.0]])) is None
+
+
+def test_left_svd_jacobi_against_lapack():
+    # singular values to a few ulps of the largest one and left singular vectors
+    # (checked through R^T u_k = s_k v_k and orthonormality) on graded matrices
+    # whose spectra span 1 .. 1e-14, wide and tall shapes and exact zeros
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    import tempfile
+    src = os.path.join(HERE, "native", "svd_check.cpp")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "svd_check")
+        subprocess.run([gxx, "-O2", "-std=c++17", src, "-o", exe], check=True)
+
+        def run(R):
+            r, m = R.shape
+            txt = f"{r} {m}\n" + "\n".join(repr(float(v)) for v in R.ravel()) + "\n"
+            out = np.array([float(t) for t in subprocess.run([exe], input=txt, capture_output=True, text=True,
+                                                                check=True).stdout.split()])
+            return out[:r], out[r:].reshape(r, r).T        # column-major -> U[:, k]
+
+        rng = np.random.default_rng(17)
+        cases = [np.zeros((0, 0)), np.array([[2.0]]), np.zeros((3, 4))]
+        for r, m in ((6, 6), (12, 20), (30, 30), (40, 64)):
+            Q1, _ = np.linalg.qr(rng.standard_normal((r, r)))
+            Q2, _ = np.linalg.qr(rng.standard_normal((m, r)))
+            sv = 10.0 ** (-np.linspace(0, 14, r))
+            cases.append(Q1 @ np.diag(sv) @ Q2.T)
+            cases.append(rng.standard_normal((r, m)))
+        R = rng.standard_normal((5, 8))
+        R[2] = R[1]                                              # rank deficient
+        cases.append(R)
+        for R in cases:
+            r, m = R.shape
+            s, U = run(R)
+            if r == 0:
+                continue
+            ref = np.linalg.svd(R, compute_uv=False) if min(r, m) else np.zeros(0)
+            ref = np.concatenate([ref, np.zeros(r - len(ref))])
+            scale = max(ref.max(), 1e-300) if len(ref) else 1.0
+            assert np.all(np.diff(s) <= 0)
+            np.testing.assert_allclose(s, ref, rtol=0, atol=1e-14 * scale)
+            np.testing.assert_allclose(U.T @ U, np.eye(r), atol=1e-13)
+            # R = U diag(s) V^T: U^T R has orthogonal rows of norms s
+            B = U.T @ R
+            np.testing.assert_allclose(np.linalg.norm(B, axis=1), s, rtol=0, atol=1e-14 * scale)
+            G = B @ B.T
+            off = G - np.diag(np.diag(G))
+            assert np.abs(off).max() <= 1e-13 * scale ** 2
