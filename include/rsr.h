@@ -18,9 +18,11 @@
  *    "host" pointers are ordinary host memory.  The caller owns every buffer
  *    it passes; the library only borrows it for the duration of the call.
  *  - The library owns its persistent state (PSF factors, weights, recycle
- *    spaces, small Gram blocks, workspaces).  It allocates device memory only
- *    in rsr_set_operators, rsr_set_recycle_space and when a solve needs a
- *    larger workspace than any earlier call.
+ *    spaces, small Gram blocks, kept corrections).  It allocates device memory
+ *    in rsr_set_operators, rsr_set_recycle_space and rsr_workspace_size.  A
+ *    solve or adjoint given a caller workspace (ws != NULL) allocates no device
+ *    or pinned host memory; without one the library keeps grow-only scratch of
+ *    its own, and such a call allocates when it needs more than any earlier one.
  *  - stream is a hipStream_t (NULL = the default stream).  Work is enqueued on
  *    it; calls that return host results (stats, p_kept, gradients, norms)
  *    synchronise that stream before returning.
@@ -90,7 +92,9 @@ enum { RSR_BATCHED = 0,        /* all systems advance together in one persistent
 typedef struct {
     int n_sys;
     const int *inst;          /* host [n_sys]                                 */
-    const double *gammas;     /* host [n_sys], >= 0                           */
+    const double *gammas;     /* host [n_sys], finite; B = A + gamma E must be SPD
+                                 (an indefinite B is reported as RSR_E_NOT_SPD
+                                 when CG meets p^T B p <= 0)                  */
     const int *slot;          /* host [n_sys] or NULL (slot = i)              */
     double tol;               /* relative residual ||b - Bx|| / ||b||          */
     int maxit;                /* CG iterations per system (<= 0: 10 * n)       */
@@ -131,7 +135,9 @@ typedef struct {
     double relres_true;       /* final ||b - B x|| / ||b|| (recomputed)          */
 } rsr_shift_stats;
 
-/* Context lifetime. */
+/* Context lifetime.  The environment variable RSR_BARRIER_TIMEOUT_US, read here,
+ * bounds one grid-barrier wait of the persistent CG kernel (default 30 s); past
+ * it every workgroup leaves the kernel and the solve returns RSR_E_TIMEOUT.   */
 rsr_status  rsr_create(rsr_ctx **out, int hip_device);
 void        rsr_destroy(rsr_ctx *ctx);
 const char *rsr_last_error(const rsr_ctx *ctx);  /* valid until the next call on ctx */
@@ -206,20 +212,40 @@ rsr_status rsr_apply(rsr_ctx *ctx, int inst, int op, double gamma, const double 
 /* Principal recycle space (Algorithm 1 and Sec. 5.2).  U_raw: device
  * [ncols][ld] candidate columns (e.g. the previous outer step's solutions).
  * If n_retain > 0 the n_retain Ritz vectors of (A_hat + gamma_retain E_hat)
- * with the smallest Ritz values from the current space are appended first
- * (the retained invariant-subspace approximation of Sec. 5.2).  The columns
- * are orthonormalised, those with sigma_1/sigma_i >= cond_max are dropped,
- * at most p_max are kept; then A U, E U and the Gram blocks U^T A U, U^T E U,
- * (AU)^T(AU), (AU)^T(EU), (EU)^T(EU) are formed.  ncols = 0 and n_retain = 0
- * clears the space.  *p_kept (host) receives the dimension.                  */
+ * with the smallest Ritz values from the current space are prepended (the
+ * retained invariant-subspace approximation of Sec. 5.2).  U holds the left
+ * singular vectors of the candidate block C with sigma_1/sigma_i < cond_max, at
+ * most p_max of them (largest first), computed as C = Q R (Q orthonormal, built
+ * on the device) and a one-sided Jacobi SVD of the small R on the host; then
+ * A U, E U and the Gram blocks U^T A U, U^T E U, (AU)^T(AU), (AU)^T(EU),
+ * (EU)^T(EU) are formed.  ncols = 0 and n_retain = 0 clears the space.
+ * *p_kept (host) receives the dimension.  Non-finite candidates:
+ * RSR_E_NONFINITE; all-zero candidates: RSR_E_RANK.                          */
 rsr_status rsr_set_recycle_space(rsr_ctx *ctx, int inst, const double *U_raw, long ld, int ncols,
                                  int n_retain, double gamma_retain, int p_max, double cond_max,
                                  int *p_kept, void *stream);
 
+/* Workspace of rsr_solve_shift_set (adjoint = 0) or rsr_adjoint (adjoint = 1)
+ * for this descriptor on the current operators and recycle spaces: *bytes
+ * (host) receives the size.  The call also reserves the persistent storage such
+ * a solve keeps (a correction column for every slot of the descriptor, and the
+ * Ritz blocks of its groups), so it allocates device memory and drains the
+ * stream; call it once per shape of shift set, outside any graph capture.  A
+ * larger recycle space (rsr_set_recycle_space) can raise the size.           */
+rsr_status rsr_workspace_size(rsr_ctx *ctx, const rsr_solve_desc *desc, int adjoint, size_t *bytes,
+                              void *stream);
+
 /* Solve a shift set.  b, X: device.  stats_host: host [n_sys] (may be NULL).
+ * ws: device workspace of ws_bytes bytes, 256-byte aligned, owned by the caller
+ * and borrowed for the call (its contents on entry do not matter), or NULL for
+ * the library's own scratch.  With a workspace the solve allocates nothing;
+ * ws_bytes below what the call needs gives RSR_E_ARG (size it with
+ * rsr_workspace_size); corrections of slots that rsr_workspace_size did not
+ * reserve are then not kept for later calls, and CG-Lanczos seeding is refused.
  * Returns RSR_OK, RSR_NOT_CONVERGED, or an error.                           */
 rsr_status rsr_solve_shift_set(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *b,
-                               double *X, rsr_shift_stats *stats_host, void *stream);
+                               double *X, void *ws, size_t ws_bytes, rsr_shift_stats *stats_host,
+                               void *stream);
 
 /* Adjoint for L(x_1..x_M) (gradient of the exact shifted solutions by
  * implicit differentiation): given the solutions X of a shift set on one
@@ -229,10 +255,17 @@ rsr_status rsr_solve_shift_set(rsr_ctx *ctx, const rsr_solve_desc *desc, const d
  *   dw_h, dw_v     = -sum_l gamma_l (D lambda_l) .* (D x_l)  (device [ny*nx], each plane;
  *                    zero where the difference does not exist)
  *   db             = sum_l lambda_l                          (device [ny*nx], may be NULL)
- * Lambda (device, layout of X) receives the adjoint solutions.             */
+ * Lambda (device, layout of X) receives the adjoint solutions.  The adjoint
+ * systems use the recycling options of desc (principal space, Ritz blocks) and
+ * keep corrections of their own (slots offset by 2^20); with use_prev_k their
+ * local spaces also take the forward correction of the same shift.  Groups
+ * follow the shift index (slot < split_I).  ws, ws_bytes: as for
+ * rsr_solve_shift_set (size with rsr_workspace_size, adjoint = 1).  A system
+ * set spanning several instances: RSR_E_ARG.                               */
 rsr_status rsr_adjoint(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *X,
                        const double *Gbar, double *Lambda, double *dgamma_host, double *dw_h,
-                       double *dw_v, double *db, rsr_shift_stats *stats_host, void *stream);
+                       double *dw_v, double *db, void *ws, size_t ws_bytes,
+                       rsr_shift_stats *stats_host, void *stream);
 
 /* Autotune the persistent CG kernel for one instance: for every candidate
  * tile shape and workgroup cap, time a bounded solve (40 iterations) of n_vec
@@ -256,6 +289,10 @@ rsr_status rsr_get_recycle_basis(rsr_ctx *ctx, int inst, double *U_out, long ld,
 /* Cumulative applications of A and of E made by the context (all calls,
  * including A U, E U and true-residual checks).                              */
 rsr_status rsr_get_counters(const rsr_ctx *ctx, long *matvec_A, long *matvec_E);
+
+/* Device and pinned host allocations the library has made so far, over all
+ * contexts of the process (for checks that a call allocated nothing).        */
+long long rsr_allocation_count(void);
 
 /* Timing of the most recent solve: milliseconds spent in the persistent CG
  * kernel(s), measured with HIP events on the solve stream, and the number of

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -58,6 +59,10 @@ struct Err {
 
 void fail(rsr_status st, const std::string &m) { throw Err{st, m}; }
 
+// Device and pinned allocations made by the library (all contexts), for checks
+// that a call allocated nothing.
+std::atomic<long long> g_alloc_calls{0};
+
 // Grow-only device buffer.
 struct DBuf {
     void *p = nullptr;
@@ -69,6 +74,7 @@ struct DBuf {
         p = nullptr;
         bytes = 0;
         size_t nb = std::max(b, (size_t)256);
+        g_alloc_calls.fetch_add(1);
         HIPCHK(hipMalloc(&p, nb));
         bytes = nb;
     }
@@ -160,6 +166,14 @@ struct rsr_ctx {
     // into pageable memory is left to the runtime's staging)
     char *rb_host = nullptr;
     size_t rb_cap = 0;
+    // caller workspace of the current call (null base: the library's own grow-only
+    // buffers).  Device scratch is carved from it with a stack discipline (see
+    // WsMark); host data bound for the device is kept until the stream is drained,
+    // and read-backs go to ordinary host memory, so a call on a workspace
+    // allocates no device or pinned memory.
+    char *wsa_base = nullptr;
+    size_t wsa_cap = 0, wsa_used = 0, wsa_peak = 0;
+    std::vector<std::vector<char>> wsa_hold;
     // per-call caches of right-hand-side quantities shared by the shifts of one
     // rsr_solve_shift_set (the same b for every shift): ||b|| and U^T b or
     // [AU EU]^T b, keyed by (b, instance, init); cleared at the start of each call
@@ -233,7 +247,35 @@ void sync(rsr_ctx *c, hipStream_t s)
 {
     HIPCHK(hipStreamSynchronize(s));
     c->ar_used = 0;
+    c->wsa_hold.clear();
 }
+
+// Device scratch of a call: from the caller's workspace when the call has one,
+// else from the library-owned buffer `own` (grown as needed).
+void *dscratch(rsr_ctx *c, DBuf &own, size_t bytes)
+{
+    if (!c->wsa_base) {
+        own.ensure(bytes);
+        return own.p;
+    }
+    const size_t off = (c->wsa_used + 255) & ~(size_t)255;
+    if (off + bytes > c->wsa_cap)
+        fail(RSR_E_ARG, "workspace of " + std::to_string(c->wsa_cap) + " bytes is too small (this call needs more than " +
+                            std::to_string(off + bytes) + "); size it with rsr_workspace_size");
+    c->wsa_used = off + bytes;
+    c->wsa_peak = std::max(c->wsa_peak, c->wsa_used);
+    return c->wsa_base + off;
+}
+
+// Scratch taken from the caller's workspace inside a scope is handed back when
+// the scope ends.  Work already enqueued that reads it runs before any later
+// work that reuses it (one stream), so only the host side is released early.
+struct WsMark {
+    rsr_ctx *c;
+    size_t used;
+    explicit WsMark(rsr_ctx *c_) : c(c_), used(c_->wsa_used) {}
+    ~WsMark() { c->wsa_used = used; }
+};
 
 // Wall time of a solve stage, accumulated when stage timing is on (the stream
 // is drained at both ends so that the device work of the stage is included).
@@ -263,6 +305,14 @@ struct StageTimer {
 void arena_reserve(rsr_ctx *c, size_t nb, hipStream_t s, char *&h, char *&d)
 {
     const size_t bytes = (std::max<size_t>(nb, 1) + 255) & ~(size_t)255;
+    if (c->wsa_base) {
+        // host half: ordinary memory kept until the stream is drained; device half
+        // from the workspace
+        c->wsa_hold.emplace_back(bytes);
+        h = c->wsa_hold.back().data();
+        d = (char *)dscratch(c, c->ar_dev, bytes);
+        return;
+    }
     if (c->ar_used + bytes > c->ar_cap) {
         sync(c, s);
         if (bytes > c->ar_cap) {
@@ -270,6 +320,7 @@ void arena_reserve(rsr_ctx *c, size_t nb, hipStream_t s, char *&h, char *&d)
             if (c->ar_host) (void)hipHostFree(c->ar_host);
             c->ar_host = nullptr;
             c->ar_cap = 0;
+            g_alloc_calls.fetch_add(1);
             HIPCHK(hipHostMalloc((void **)&c->ar_host, cap, hipHostMallocDefault));
             c->ar_dev.ensure(cap);
             c->ar_cap = cap;
@@ -303,6 +354,12 @@ struct ReadBack {
 };
 void read_back(rsr_ctx *c, const std::vector<ReadBack> &v, hipStream_t s)
 {
+    if (c->wsa_base) {   // no pinned buffer is allocated for a call on a workspace
+        for (const auto &r : v)
+            if (r.bytes) HIPCHK(hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToHost, s));
+        sync(c, s);
+        return;
+    }
     size_t tot = 0;
     for (const auto &r : v) tot += (r.bytes + 15) & ~(size_t)15;
     if (tot > c->rb_cap) {
@@ -311,6 +368,7 @@ void read_back(rsr_ctx *c, const std::vector<ReadBack> &v, hipStream_t s)
         c->rb_host = nullptr;
         c->rb_cap = 0;
         const size_t cap = std::max<size_t>(tot, (size_t)1 << 16);
+        g_alloc_calls.fetch_add(1);
         HIPCHK(hipHostMalloc((void **)&c->rb_host, cap, hipHostMallocDefault));
         c->rb_cap = cap;
     }
@@ -365,6 +423,7 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
 
 void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
 {
+    WsMark mark(c);
     // group by instance (one launch per instance)
     std::map<int, std::vector<ApplyJob>> by;
     for (auto &j : jobs) by[j.inst].push_back(j);
@@ -385,21 +444,22 @@ std::vector<std::vector<double>> gram(rsr_ctx *c, std::vector<GramJob> jobs, hip
 {
     std::vector<std::vector<double>> out(jobs.size());
     if (jobs.empty()) return out;
+    WsMark mark(c);
     size_t coff = 0;
     for (auto &j : jobs) coff += (size_t)j.a * j.c;
-    c->d_small.ensure(sizeof(double) * std::max<size_t>(1, coff));
+    double *small = (double *)dscratch(c, c->d_small, sizeof(double) * std::max<size_t>(1, coff));
     size_t o = 0, sc = 0;
     for (auto &j : jobs) {
-        j.C = c->d_small.as<double>() + o;
+        j.C = small + o;
         o += (size_t)j.a * j.c;
         j.sc_off = (long)sc;
         sc += gram_scratch_doubles(&j, 1);
     }
-    c->d_gram_scratch.ensure(sizeof(double) * std::max<size_t>(1, sc));
+    double *gsc = (double *)dscratch(c, c->d_gram_scratch, sizeof(double) * std::max<size_t>(1, sc));
     GramJob *dj = stage(c, jobs, s);
-    HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), c->d_gram_scratch.as<double>(), sc, s));
+    HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), gsc, sc, s));
     std::vector<double> h(coff);
-    read_back(c, {ReadBack{h.data(), c->d_small.p, sizeof(double) * coff}}, s);
+    read_back(c, {ReadBack{h.data(), small, sizeof(double) * coff}}, s);
     o = 0;
     for (size_t k = 0; k < jobs.size(); ++k) {
         out[k].assign(h.begin() + o, h.begin() + o + (size_t)jobs[k].a * jobs[k].c);
@@ -413,20 +473,22 @@ std::vector<std::vector<double>> gram(rsr_ctx *c, std::vector<GramJob> jobs, hip
 void gram_to_device(rsr_ctx *c, std::vector<GramJob> jobs, hipStream_t s)
 {
     if (jobs.empty()) return;
+    WsMark mark(c);
     size_t sc = 0;
     for (auto &j : jobs) {
         j.sc_off = (long)sc;
         sc += gram_scratch_doubles(&j, 1);
     }
-    c->d_gram_scratch.ensure(sizeof(double) * std::max<size_t>(1, sc));
+    double *gsc = (double *)dscratch(c, c->d_gram_scratch, sizeof(double) * std::max<size_t>(1, sc));
     GramJob *dj = stage(c, jobs, s);
-    HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), c->d_gram_scratch.as<double>(), sc, s));
+    HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), gsc, sc, s));
 }
 
 // Y_j = beta Y_j + X_j Q_j (Q from host, column-major a x c with ldq = a).
 void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector<double>> &Qs, hipStream_t s)
 {
     if (jobs.empty()) return;
+    WsMark mark(c);
     size_t tot = 0;
     for (auto &q : Qs) tot += q.size();
     // coefficients and descriptors in one upload: [Q_0 Q_1 ... | jobs]
@@ -695,17 +757,19 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         d.lzc = Y.lzc;
         d.nlz = Y.nlz;
     }
-    SysDev *dsys = upload(c, c->d_sys, hd, s);
-    c->d_partA.ensure(sizeof(double) * tiles * NVP);
-    c->d_partB.ensure(sizeof(double) * tiles * NVP);
-    c->d_ctl.ensure(BAR_BYTES);
-    c->d_out.ensure((sizeof(int) * 2 + 2 * sizeof(double)) * m + 64);
-    HIPCHK(launch_fill(c->d_ctl.as<double>(), 0.0, BAR_BYTES / sizeof(double), s));
-    int *out_iters = (int *)c->d_out.p;
+    WsMark mark(c);
+    SysDev *dsys = stage(c, hd, s);
+    double *partA = (double *)dscratch(c, c->d_partA, sizeof(double) * tiles * NVP);
+    double *partB = (double *)dscratch(c, c->d_partB, sizeof(double) * tiles * NVP);
+    char *ctl = (char *)dscratch(c, c->d_ctl, BAR_BYTES);
+    const size_t out_bytes = (sizeof(int) * 2 + 2 * sizeof(double)) * m + 64;
+    char *outb = (char *)dscratch(c, c->d_out, out_bytes);
+    HIPCHK(launch_fill((double *)ctl, 0.0, BAR_BYTES / sizeof(double), s));
+    int *out_iters = (int *)outb;
     int *out_status = out_iters + m;
     double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
     double *out_alpha = out_rho + m;
-    HIPCHK(launch_fill(c->d_out.as<double>(), 0.0, (long)(c->d_out.bytes / sizeof(double)), s));
+    HIPCHK(launch_fill((double *)outb, 0.0, (long)(out_bytes / sizeof(double)), s));
 
     const int msys = (m + 7) & ~7;
     const int tl = cg_tile_lds(max_tile_lds(c), msys);
@@ -747,11 +811,11 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.nsys = m;
     a.sys = dsys;
     a.inst = c->d_inst.as<InstDev>();
-    a.part[0] = c->d_partA.as<double>();
-    a.part[1] = c->d_partB.as<double>();
+    a.part[0] = partA;
+    a.part[1] = partB;
     a.pstride = (int)tiles;
-    a.bar = (unsigned long long *)c->d_ctl.p;
-    a.abort_flag = (int *)((char *)c->d_ctl.p + 256);
+    a.bar = (unsigned long long *)ctl;
+    a.abort_flag = (int *)(ctl + 256);
     a.out_iters = out_iters;
     a.out_status = out_status;
     a.out_rho = out_rho;
@@ -764,7 +828,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.taps_lds = taps_lds;
     a.msys = msys;
     a.stamps = nullptr;
-    const bool dbg = getenv("RSR_CG_STAMPS") != nullptr;   // phase timing of workgroup 0 (diagnostics)
+    const bool dbg = getenv("RSR_CG_STAMPS") != nullptr && !c->wsa_base;   // phase timing of workgroup 0 (diagnostics)
     if (dbg) {
         c->d_dbg.ensure(sizeof(unsigned long long) * DBG_WORDS);
         HIPCHK(launch_fill((double *)c->d_dbg.p, 0.0, (long)DBG_WORDS, s));
@@ -991,6 +1055,8 @@ void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         Instance::RitzBlock &rb = I.ritz[side];
         if (rb.version != I.u_version || rb.gamma != gJ || rb.nr != nr) {
             const int p = I.p;
+            if (c->wsa_base && rb.buf.bytes < sizeof(double) * (size_t)3 * nr * I.n)
+                fail(RSR_E_STATE, "Ritz block storage not reserved for this call: call rsr_workspace_size with its descriptor first");
             rb.buf.ensure(sizeof(double) * (size_t)3 * nr * I.n);
             const std::vector<double> &V = ej[ejk++].V;   // same order as the collection above
             std::vector<double> Wt((size_t)p * nr);   // column-major p x nr
@@ -1263,8 +1329,8 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         }
         size_t tot = 0;
         for (auto &e : grp) tot += 2 * e.sys.size() * (size_t)c->inst[e.inst]->n;
-        c->d_tmp.ensure(sizeof(double) * tot);
-        double *T = c->d_tmp.as<double>();
+        WsMark mark(c);
+        double *T = (double *)dscratch(c, c->d_tmp, sizeof(double) * tot);
         std::vector<CopyJob> out;
         for (auto &e : grp) {
             Instance &I = *c->inst[e.inst];
@@ -1385,6 +1451,7 @@ void store_corrections(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
         Instance &I = *c->inst[Y->inst];
         if (I.gcol.count(Y->slot)) continue;
         const int col = (int)I.gcol.size();
+        if (c->wsa_base && col >= I.gpool_cols) continue;   // not reserved: not kept (no allocation)
         I.gcol[Y->slot] = col;
         if (col < I.gpool_cols) continue;
         const int cap = std::max({col + 1, 2 * I.gpool_cols, 8});
@@ -1400,6 +1467,7 @@ void store_corrections(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
     }
     for (auto *Y : sy) {
         Instance &I = *c->inst[Y->inst];
+        if (!I.gslot(Y->slot)) continue;
         // g = x - xinit
         cj.push_back(ComboJob{Y->xinit, Y->n, 1, nullptr, 1, I.gslot(Y->slot), Y->n, 1, 0.0, Y->x, Y->n, Y->n});
         qs.push_back(std::vector<double>{-1.0});
@@ -1412,8 +1480,7 @@ void alloc_ws(rsr_ctx *c, std::vector<SysHost> &sys)
     // per system: r r1 w1 p0 p1 w xinit rt pa + W, Z (QMAX each)
     size_t tot = 0;
     for (auto &Y : sys) tot += (size_t)Y.n * (9 + 2 * QMAX) + 2 * QMAX + 64;
-    c->d_ws.ensure(sizeof(double) * tot);
-    double *p = c->d_ws.as<double>();
+    double *p = (double *)dscratch(c, c->d_ws, sizeof(double) * tot);
     for (auto &Y : sys) {
         const long n = Y.n;
         Y.r = p; p += n;
@@ -2022,6 +2089,7 @@ bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, 
     if (d->seed_lanczos < 0 || d->seed_p < 0 || d->seed_n_ritz < 0 || d->seed_n_ritz > QMAX)
         fail(RSR_E_ARG, "seed sizes out of range");
     if (d->seed_lanczos > 0 && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "seeding needs sequential mode");
+    if (d->seed_lanczos > 0 && c->wsa_base) fail(RSR_E_ARG, "seeding keeps library-owned memory: not with a caller workspace");
     if (d->mode != RSR_BATCHED && d->mode != RSR_SEQUENTIAL) fail(RSR_E_ARG, "unknown mode");
     std::vector<SysHost> sys(m);
     for (int i = 0; i < m; ++i) {
@@ -2044,9 +2112,9 @@ bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, 
     alloc_ws(c, sys);
     c->bnorm_cache.clear();
     c->rhs_cache.clear();
-    c->d_r0sq.ensure(sizeof(double) * (size_t)m);
-    HIPCHK(launch_fill(c->d_r0sq.as<double>(), 0.0, m, s));
-    for (int i = 0; i < m; ++i) sys[i].r0sq_dev = c->d_r0sq.as<double>() + i;
+    double *r0sq_dev = (double *)dscratch(c, c->d_r0sq, sizeof(double) * (size_t)m);
+    HIPCHK(launch_fill(r0sq_dev, 0.0, m, s));
+    for (int i = 0; i < m; ++i) sys[i].r0sq_dev = r0sq_dev + i;
     Opts o{d->tol, d->maxit, d->init, d->n_ritz, d->use_prev_k, d->use_prev_shift, d->split_I, d->gamma_JL,
            d->gamma_JR};
     c->last_cg_ms = 0.0;
@@ -2098,7 +2166,7 @@ bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, 
     }
     {
         std::vector<double> r0sq(m);
-        read_back(c, {ReadBack{r0sq.data(), c->d_r0sq.p, sizeof(double) * m}}, s);
+        read_back(c, {ReadBack{r0sq.data(), r0sq_dev, sizeof(double) * m}}, s);
         for (int i = 0; i < m; ++i)
             sys[i].relres_init = sys[i].bnorm > 0 ? std::sqrt(std::max(0.0, r0sq[i])) / sys[i].bnorm : 0.0;
     }
@@ -2122,26 +2190,153 @@ bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, 
     sync(c, s);
     return all;
 }
+// Bytes of caller workspace a solve (or, with adjoint set, an adjoint) of the
+// described shift set uses: the per-system vectors and initial residual norms
+// for the whole call, plus the largest of the transient needs (one persistent-CG
+// launch with its partials, barrier block and outputs; the grouped initial
+// guesses; the largest product batch), with room for the staged descriptors and
+// the 256-byte alignment of every piece.
+size_t solve_ws_bytes(rsr_ctx *c, const rsr_solve_desc *d, bool adjoint)
+{
+    auto al = [](size_t b) { return (b + 511) & ~(size_t)255; };
+    const int m = d->n_sys;
+    size_t per_sys = 0, sum_n = 0, max_tiles = 0, max_n = 0;
+    int max_p = 0;
+    std::vector<long> tiles(m);
+    for (int i = 0; i < m; ++i) {
+        Instance &I = get_inst(c, d->inst[i]);
+        const InstDev &D = c->h_inst[d->inst[i]];
+        per_sys += al(sizeof(double) * ((size_t)I.n * (9 + 2 * QMAX) + 2 * QMAX + 64));
+        sum_n += (size_t)I.n;
+        max_n = std::max(max_n, (size_t)I.n);
+        tiles[i] = (long)D.nty * D.ntx;
+        max_p = std::max(max_p, I.p);
+    }
+    // the largest launch: up to MAXSYS systems in batched mode, one in sequential
+    const int ml = d->mode == RSR_BATCHED ? std::min(m, MAXSYS) : 1;
+    if (d->mode == RSR_BATCHED) {
+        for (int i0 = 0; i0 < m; i0 += MAXSYS) {
+            size_t t = 0;
+            for (int i = i0; i < std::min(m, i0 + MAXSYS); ++i) t += (size_t)tiles[i];
+            max_tiles = std::max(max_tiles, t);
+        }
+    } else {
+        for (int i = 0; i < m; ++i) max_tiles = std::max(max_tiles, (size_t)tiles[i]);
+    }
+    const size_t launch = al(sizeof(SysDev) * ml) + 2 * al(sizeof(double) * max_tiles * NVP) + al(BAR_BYTES) +
+                          al((sizeof(int) * 2 + 2 * sizeof(double)) * ml + 64) +
+                          al((sizeof(ComboJob) + sizeof(double)) * ml + 16);
+    const size_t guesses = al(sizeof(double) * 2 * (d->mode == RSR_BATCHED ? sum_n : max_n)) +
+                           al((sizeof(ComboJob) + sizeof(double)) * (2 + 2 * (size_t)m) +
+                              sizeof(double) * 3 * (size_t)max_p * m + 16);
+    // products: W^T Z and W^T W of every system, [AU EU]^T b and norms
+    std::vector<GramJob> gj;
+    for (int i = 0; i < m; ++i) {
+        const long n = c->inst[d->inst[i]]->n;
+        gj.push_back(GramJob{nullptr, n, QMAX, nullptr, n, QMAX, n, nullptr, 0});
+        gj.push_back(GramJob{nullptr, n, QMAX, nullptr, n, QMAX, n, nullptr, 0});
+        gj.push_back(GramJob{nullptr, n, 2 * std::max(max_p, 1), nullptr, n, 1, n, nullptr, 0});
+    }
+    const size_t grams = al(sizeof(double) * gram_scratch_doubles(gj.data(), (int)gj.size())) +
+                         al(sizeof(double) * (2 * QMAX * QMAX + 2 * (size_t)std::max(max_p, 1)) * m) +
+                         al(sizeof(GramJob) * gj.size());
+    size_t need = per_sys + al(sizeof(double) * m) + std::max({launch, guesses, grams}) + 65536 + 4096 * (size_t)m;
+    if (adjoint) need += al(sizeof(double) * (512 * (size_t)m + 2 * max_n));
+    return need;
+}
+
+// Persistent storage a workspace call may not allocate: a correction column for
+// every slot of the descriptor (and the adjoint slots) and the Ritz blocks of its
+// groups.
+void reserve_persistent(rsr_ctx *c, const rsr_solve_desc *d, bool adjoint, hipStream_t s)
+{
+    std::map<int, std::set<int>> need;
+    for (int i = 0; i < d->n_sys; ++i) {
+        const int sl = d->slot ? d->slot[i] : i;
+        if (sl < 0 || sl >= (1 << 20)) fail(RSR_E_ARG, "slots must lie in [0, 2^20)");
+        need[d->inst[i]].insert(sl);
+        if (adjoint) need[d->inst[i]].insert(sl + (1 << 20));
+    }
+    for (auto &kv : need) {
+        Instance &I = get_inst(c, kv.first);
+        int add = 0;
+        for (int sl : kv.second) add += I.gcol.count(sl) ? 0 : 1;
+        const int want = (int)I.gcol.size() + add;
+        if (want > I.gpool_cols) {
+            DBuf nb;
+            nb.ensure(sizeof(double) * (size_t)want * I.n);
+            if (I.gpool_cols > 0)
+                HIPCHK(hipMemcpyAsync(nb.p, I.gpool.p, sizeof(double) * (size_t)I.gpool_cols * I.n,
+                                      hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+            std::swap(nb.p, I.gpool.p);
+            std::swap(nb.bytes, I.gpool.bytes);
+            nb.release();
+            I.gpool_cols = want;
+        }
+        if (d->n_ritz > 0)
+            for (auto &rb : I.ritz) rb.buf.ensure(sizeof(double) * (size_t)3 * std::min(d->n_ritz, QMAX) * I.n);
+    }
+}
+
+// The caller's workspace for the duration of one call.
+struct WsScope {
+    rsr_ctx *c;
+    hipStream_t s;
+    WsScope(rsr_ctx *c_, void *ws, size_t bytes, hipStream_t s_) : c(c_), s(s_)
+    {
+        c->wsa_base = (char *)ws;
+        c->wsa_cap = ws ? bytes : 0;
+        c->wsa_used = 0;
+        c->wsa_peak = 0;
+    }
+    ~WsScope()
+    {
+        // an error may leave copies from held host data in flight
+        if (!c->wsa_hold.empty()) (void)hipStreamSynchronize(s);
+        c->wsa_hold.clear();
+        c->wsa_base = nullptr;
+        c->wsa_cap = 0;
+        c->wsa_used = 0;
+    }
+};
 }  // namespace
 
 extern "C" {
 
-rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X,
-                               rsr_shift_stats *stats, void *stream)
+rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, void *ws,
+                               size_t ws_bytes, rsr_shift_stats *stats, void *stream)
 {
     return guard(c, [&] {
+        if (ws && ((uintptr_t)ws & 255)) fail(RSR_E_ARG, "workspace must be 256-byte aligned");
+        WsScope scope(c, ws, ws_bytes, S(stream));
         if (!solve_set(c, d, b, X, stats, S(stream), 0))
             throw Err{RSR_NOT_CONVERGED, "some systems did not reach tol"};
     });
 }
 
+rsr_status rsr_workspace_size(rsr_ctx *c, const rsr_solve_desc *d, int adjoint, size_t *bytes, void *stream)
+{
+    return guard(c, [&] {
+        if (!d || !bytes) fail(RSR_E_ARG, "null descriptor or output");
+        if (c->inst.empty()) fail(RSR_E_STATE, "operators not set");
+        if (d->n_sys <= 0 || !d->inst) fail(RSR_E_ARG, "n_sys must be positive with inst");
+        if (d->n_ritz < 0 || d->n_ritz > QMAX) fail(RSR_E_ARG, "n_ritz out of range");
+        set_device(c);
+        *bytes = solve_ws_bytes(c, d, adjoint != 0);
+        reserve_persistent(c, d, adjoint != 0, S(stream));
+    });
+}
+
 rsr_status rsr_adjoint(rsr_ctx *c, const rsr_solve_desc *d, const double *X, const double *Gbar, double *Lambda,
-                       double *dgamma_host, double *dw_h, double *dw_v, double *db, rsr_shift_stats *stats,
-                       void *stream)
+                       double *dgamma_host, double *dw_h, double *dw_v, double *db, void *ws, size_t ws_bytes,
+                       rsr_shift_stats *stats, void *stream)
 {
     bool all = true;
     rsr_status st = guard(c, [&] {
         if (!d || !X || !Gbar || !Lambda) fail(RSR_E_ARG, "null argument");
+        if (ws && ((uintptr_t)ws & 255)) fail(RSR_E_ARG, "workspace must be 256-byte aligned");
+        WsScope scope(c, ws, ws_bytes, S(stream));
         if (d->n_sys <= 0 || !d->inst || !d->gammas) fail(RSR_E_ARG, "n_sys must be positive with inst and gammas");
         const int m = d->n_sys;
         const int ii = d->inst[0];
@@ -2160,8 +2355,7 @@ rsr_status rsr_adjoint(rsr_ctx *c, const rsr_solve_desc *d, const double *X, con
         // gradients: one pass over X and Lambda, partial sums of dL/dgamma per chunk
         const int nch = 512;
         const long n = I.n;
-        c->d_grad.ensure(sizeof(double) * ((size_t)nch * m + ((dw_h && dw_v) ? 0 : 2 * (size_t)n)));
-        double *dg = c->d_grad.as<double>();
+        double *dg = (double *)dscratch(c, c->d_grad, sizeof(double) * ((size_t)nch * m + ((dw_h && dw_v) ? 0 : 2 * (size_t)n)));
         double *wh = dw_h, *wv = dw_v;
         if (!wh || !wv) {
             wh = dg + (size_t)nch * m;
@@ -2336,6 +2530,8 @@ rsr_status rsr_last_solve_timing(const rsr_ctx *c, double *ms, int *launches, lo
     if (items) *items = c->last_items;
     return RSR_OK;
 }
+
+long long rsr_allocation_count(void) { return g_alloc_calls.load(); }
 
 rsr_status rsr_get_counters(const rsr_ctx *c, long *matvec_A, long *matvec_E)
 {

@@ -81,11 +81,13 @@ class OuterLoop:
     def __init__(self, ctx: rsr.Context, cfg: synth.Config, method: str, rp: Optional[RecycleParams] = None,
                  tol: Optional[float] = None, tiles: Optional[Dict[int, tuple]] = None,
                  mode: Optional[int] = None, weight_rule: str = "irn", edge_p: float = 2.0,
-                 lcurve: bool = False, stop_repeats: int = 3):
+                 lcurve: bool = False, stop_repeats: int = 3, workspace: bool = False):
         """weight_rule: "irn" (W = ((D x)^2 + beta)^(-1/2)) or "edge" (the cumulative edge
         rule of Sec. 2.1 with exponent edge_p).  lcurve: choose the shift that drives the
         next weights at the L-curve corner after every step; otherwise the middle shift.
-        The loop reports `stopped` once that choice has repeated stop_repeats times."""
+        The loop reports `stopped` once that choice has repeated stop_repeats times.
+        workspace: solve on a caller workspace (sized and reserved with
+        rsr_workspace_size before each solve), so the solves allocate nothing."""
         import torch
         if method not in ("recycled", "plain", "warm"):
             raise ValueError("method must be 'recycled', 'plain' or 'warm'")
@@ -116,6 +118,18 @@ class OuterLoop:
         self.stop_repeats = stop_repeats
         self.l_stars = [int(math.ceil(self.M / 2)) - 1] * len(cfg.problems)
         self.l_history: List[tuple] = []
+        self.workspace = workspace
+        self._ws = None
+
+    def _workspace(self, gammas, inst, slots, o):
+        """A caller workspace large enough for this solve (grown when needed)."""
+        import torch
+        if not self.workspace:
+            return None
+        nb = self.ctx.workspace_size(gammas, inst=inst, slots=slots, opts=o)
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        return self._ws
 
     @property
     def l_star(self) -> int:
@@ -194,7 +208,8 @@ class OuterLoop:
         o = self._opts()
         iters, rel, rel0, qd = [], [], [], []
         if n_inst == 1:
-            rc, st = ctx.solve(self.cfg.gammas, self.b[0], self.X[0], opts=o)
+            ws = self._workspace(self.cfg.gammas, None, None, o)
+            rc, st = ctx.solve(self.cfg.gammas, self.b[0], self.X[0], opts=o, ws=ws)
             stats = [st]
         else:
             stats = self._solve_instances(o)
@@ -239,7 +254,8 @@ class OuterLoop:
         for i in range(n_inst):
             n = self.X[i][0].numel()
             self._Xp[i * M:(i + 1) * M, :n] = self.X[i].reshape(M, -1)
-        rc, st = self.ctx.solve(gam, self._Bp, self._Xp, inst=inst, slots=slots, opts=o, shared_b=False)
+        ws = self._workspace(gam, inst, slots, o)
+        rc, st = self.ctx.solve(gam, self._Bp, self._Xp, inst=inst, slots=slots, opts=o, shared_b=False, ws=ws)
         for i in range(n_inst):
             n = self.X[i][0].numel()
             self.X[i].copy_(self._Xp[i * M:(i + 1) * M, :n].reshape(self.X[i].shape))

@@ -28,7 +28,8 @@ EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_se
            "rsr_update_weights", "rsr_weights_from_image", "rsr_get_weights", "rsr_apply",
            "rsr_set_recycle_space", "rsr_solve_shift_set", "rsr_adjoint", "rsr_autotune", "rsr_get_tile",
            "rsr_set_tile", "rsr_get_recycle_info", "rsr_get_recycle_basis", "rsr_get_counters",
-           "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve", "rsr_correction_space"]
+           "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve", "rsr_correction_space",
+           "rsr_workspace_size", "rsr_allocation_count"]
 
 
 class RsrError(RuntimeError):
@@ -84,6 +85,7 @@ def load():
     L.rsr_destroy.restype = None
     L.rsr_last_error.argtypes = [P]
     L.rsr_last_error.restype = ctypes.c_char_p
+    L.rsr_version.argtypes = []
     L.rsr_version.restype = ctypes.c_char_p
     L.rsr_set_operators.argtypes = [P, I, ctypes.POINTER(Instance), P]
     L.rsr_update_weights.argtypes = [P, I, P, P, P]
@@ -91,8 +93,12 @@ def load():
     L.rsr_get_weights.argtypes = [P, I, P, P, P]
     L.rsr_apply.argtypes = [P, I, I, D, P, P, I, L_, P]
     L.rsr_set_recycle_space.argtypes = [P, I, P, L_, I, I, D, I, D, pI, P]
-    L.rsr_solve_shift_set.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(ShiftStats), P]
-    L.rsr_adjoint.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, P, pD, P, P, P, ctypes.POINTER(ShiftStats), P]
+    S_ = ctypes.c_size_t
+    L.rsr_solve_shift_set.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, P, S_, ctypes.POINTER(ShiftStats), P]
+    L.rsr_adjoint.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, P, pD, P, P, P, P, S_, ctypes.POINTER(ShiftStats),
+                              P]
+    L.rsr_workspace_size.argtypes = [P, ctypes.POINTER(SolveDesc), I, ctypes.POINTER(S_), P]
+    L.rsr_allocation_count.argtypes = []
     L.rsr_autotune.argtypes = [P, I, I, ctypes.c_char_p]
     L.rsr_get_tile.argtypes = [P, I, pI, pI]
     L.rsr_set_tile.argtypes = [P, I, I, I]
@@ -104,8 +110,9 @@ def load():
     L.rsr_lcurve.argtypes = [P, I, I, pD, P, L_, P, pD, pD, pD, pI, P]
     L.rsr_correction_space.argtypes = [P, I, P, P, P, D, I, I, P, L_, pI, P]
     for name in EXPORTS:
-        if name not in ("rsr_destroy", "rsr_last_error", "rsr_version"):
+        if name not in ("rsr_destroy", "rsr_last_error", "rsr_version", "rsr_allocation_count"):
             getattr(L, name).restype = ctypes.c_int
+    L.rsr_allocation_count.restype = ctypes.c_longlong
     _lib = L
     return L
 
@@ -116,6 +123,15 @@ def _ptr(t) -> int:
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 CUDA tensor")
     return t.data_ptr()
+
+
+def _ws(t):
+    """(pointer, bytes) of an optional caller workspace tensor."""
+    if t is None:
+        return None, 0
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("the workspace must be a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size()
 
 
 def _stream():
@@ -288,8 +304,9 @@ class Context:
         return d, (ia, ga, sa)
 
     def solve(self, gammas: Sequence[float], b, X, inst: Optional[Sequence[int]] = None, slots=None,
-              opts: Optional[SolveOptions] = None, shared_b: bool = True):
-        """Solve (A + gamma_i E) x_i = b_i; X is [m, ny, nx] (in/out).  Returns (status, stats)."""
+              opts: Optional[SolveOptions] = None, shared_b: bool = True, ws=None):
+        """Solve (A + gamma_i E) x_i = b_i; X is [m, ny, nx] (in/out).  ws: optional caller
+        workspace (a CUDA tensor, any dtype, 256-byte aligned).  Returns (status, stats)."""
         o = opts or SolveOptions()
         m = len(gammas)
         inst = list(inst) if inst is not None else [0] * m
@@ -297,11 +314,26 @@ class Context:
         ld_b = 0 if shared_b else b[0].numel()
         d, keep = self._desc(inst, gammas, slots, o, ld_b, ld_x)
         st = (ShiftStats * m)()
-        rc = self.lib.rsr_solve_shift_set(self.h, ctypes.byref(d), _ptr(b), _ptr(X), st, _stream())
+        wp, wn = _ws(ws)
+        rc = self.lib.rsr_solve_shift_set(self.h, ctypes.byref(d), _ptr(b), _ptr(X), wp, wn, st, _stream())
         self._check(rc, allow_not_converged=True)
         return rc, [s.as_dict() for s in st]
 
-    def adjoint(self, gammas, X, Gbar, Lam, inst: int = 0, slots=None, opts: Optional[SolveOptions] = None):
+    def workspace_size(self, gammas: Sequence[float], inst: Optional[Sequence[int]] = None, slots=None,
+                       opts: Optional[SolveOptions] = None, adjoint: bool = False) -> int:
+        """Bytes of caller workspace for solve (or adjoint) with these arguments; also
+        reserves the library's persistent storage for them."""
+        o = opts or SolveOptions()
+        m = len(gammas)
+        inst = list(inst) if inst is not None else [0] * m
+        d, keep = self._desc(inst, gammas, slots, o, 0, 0)
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.rsr_workspace_size(self.h, ctypes.byref(d), int(bool(adjoint)), ctypes.byref(n),
+                                                _stream()))
+        return n.value
+
+    def adjoint(self, gammas, X, Gbar, Lam, inst: int = 0, slots=None, opts: Optional[SolveOptions] = None,
+                ws=None):
         """Adjoint solves and gradients; returns (status, dgamma[np], dwh, dwv, db, stats)."""
         import torch
         o = opts or SolveOptions()
@@ -313,9 +345,10 @@ class Context:
         dwv = torch.empty_like(dwh)
         db = torch.empty_like(dwh)
         st = (ShiftStats * m)()
+        wp, wn = _ws(ws)
         rc = self.lib.rsr_adjoint(self.h, ctypes.byref(d), _ptr(X), _ptr(Gbar), _ptr(Lam),
                                   dg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(dwh), _ptr(dwv), _ptr(db),
-                                  st, _stream())
+                                  wp, wn, st, _stream())
         self._check(rc, allow_not_converged=True)
         return rc, dg, dwh, dwv, db, [s.as_dict() for s in st]
 
@@ -336,6 +369,10 @@ class Context:
         a, e = ctypes.c_long(), ctypes.c_long()
         self._check(self.lib.rsr_get_counters(self.h, ctypes.byref(a), ctypes.byref(e)))
         return a.value, e.value
+
+    def allocation_count(self) -> int:
+        """Device and pinned allocations the library has made (process-wide)."""
+        return int(self.lib.rsr_allocation_count())
 
     def last_timing(self):
         ms, n, it = ctypes.c_double(), ctypes.c_int(), ctypes.c_long()

@@ -81,3 +81,15 @@ int main(void) {
             rsr.SolveDesc.seed_n_ritz.offset, ctypes.sizeof(rsr.ShiftStats),
             rsr.ShiftStats.relres_init.offset, rsr.ShiftStats.relres_true.offset]
     assert vals == want
+
+
+def test_binding_argument_counts_match_the_header():
+    # every prototype in the header has as many parameters as the binding passes
+    from paper_2306_15049_amd import rsr
+    txt = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    protos = dict(re.findall(r"\b(rsr_[a-z_]+)\s*\(([^;{]*?)\)\s*;", txt))
+    L = rsr.load()
+    for name in rsr.EXPORTS:
+        params = protos[name].strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        assert len(getattr(L, name).argtypes) == n, (name, n)

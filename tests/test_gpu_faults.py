@@ -14,10 +14,6 @@ normally; the conditions are forced from the host).
   at once, every workgroup leaves the kernel, and the solve reports
   RSR_E_TIMEOUT; the same context then solves normally with the default limit.
 """
-import os
-import subprocess
-import sys
-
 import numpy as np
 import pytest
 
@@ -26,8 +22,6 @@ from paper_2306_15049_amd import rsr, synth
 from conftest import to_dev, to_host
 
 pytestmark = pytest.mark.gpu
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _small(ctx, n=24):
@@ -105,32 +99,26 @@ def test_call_order_and_descriptor_checks(torch_cuda):
         c.close()
 
 
-def test_barrier_time_limit_gives_up_and_drains():
-    # a fresh process, so the limit read at context creation applies to it alone
-    code = r"""
-import numpy as np, torch
-from paper_2306_15049_amd import rsr
-torch.cuda.set_device(0)
-n = 256
-rng = np.random.default_rng(1)
-b = torch.from_numpy(rng.standard_normal((n, n))).cuda()
-X = torch.zeros((4, n, n), dtype=torch.float64, device="cuda")
-c = rsr.Context(0)
-c.set_operators([(n, n)], [np.ones((1, 1))])
-try:
-    c.solve([0.1, 1.0, 3.0, 10.0], b, X)
-    print("NO-TIMEOUT")
-except rsr.RsrError as e:
-    print("STATUS", e.status, str(e))
-c.close()
-"""
-    env = dict(os.environ, RSR_BARRIER_TIMEOUT_US="0")
-    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
-                         timeout=120)
-    assert out.returncode == 0, out.stderr[-2000:]
-    assert "STATUS -8" in out.stdout, out.stdout + out.stderr[-2000:]
-    # and with the default limit the same solve completes
-    env.pop("RSR_BARRIER_TIMEOUT_US")
-    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
-                         timeout=120)
-    assert out.returncode == 0 and "NO-TIMEOUT" in out.stdout, out.stdout + out.stderr[-2000:]
+def test_barrier_time_limit_gives_up_and_drains(torch_cuda, monkeypatch):
+    # the limit is read when a context is created; a context made with a limit of
+    # 0 us gives up at its first grid barrier and every workgroup leaves the
+    # kernel; a context made afterwards with the default limit solves normally
+    n = 256
+    rng = np.random.default_rng(1)
+    b = to_dev(rng.standard_normal((n, n)))
+    X = to_dev(np.zeros((4, n, n)))
+    monkeypatch.setenv("RSR_BARRIER_TIMEOUT_US", "0")
+    c = rsr.Context(0)
+    try:
+        c.set_operators([(n, n)], [np.ones((1, 1))])
+        assert _status(lambda: c.solve([0.1, 1.0, 3.0, 10.0], b, X)) == -8
+    finally:
+        c.close()
+    monkeypatch.delenv("RSR_BARRIER_TIMEOUT_US")
+    c = rsr.Context(0)
+    try:
+        c.set_operators([(n, n)], [np.ones((1, 1))])
+        rc, st = c.solve([0.1, 1.0, 3.0, 10.0], b, X)
+        assert rc == 0
+    finally:
+        c.close()
