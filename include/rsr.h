@@ -225,6 +225,22 @@ rsr_status rsr_set_recycle_space(rsr_ctx *ctx, int inst, const double *U_raw, lo
                                  int n_retain, double gamma_retain, int p_max, double cond_max,
                                  int *p_kept, void *stream);
 
+/* rsr_solve_shift_set for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve, with its scratch in a static device array of 64 MiB that the library's
+ * code object holds on every device it runs on until the process ends, instead
+ * of a caller workspace.  It calls no allocating routine.  A shift set that
+ * needs more scratch (rsr_workspace_size's bound above 64 MiB, e.g. four
+ * 256 x 256 systems fit, sixteen 512 x 512 do not) is refused with RSR_E_ARG
+ * before any launch.  The array is shared by every call on one device and keeps
+ * the last call's contents (what must start at zero is cleared by each call):
+ * calls that overlap on one device -- two streams, two host threads, two
+ * contexts -- race and must not be issued.  Corrections of slots that
+ * rsr_workspace_size did not reserve are not kept for later calls, and
+ * CG-Lanczos seeding is refused, as with a caller workspace.                 */
+rsr_status rsr_solve_shift_set_noalloc(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *b,
+                                       double *X, rsr_shift_stats *stats_host, void *stream);
+
 /* Workspace of rsr_solve_shift_set (adjoint = 0) or rsr_adjoint (adjoint = 1)
  * for this descriptor on the current operators and recycle spaces: *bytes
  * (host) receives the size.  The call also reserves the persistent storage such

@@ -33,6 +33,7 @@
 #include <functional>
 #include <future>
 #include <map>
+#include <mutex>
 #include <set>
 #include <tuple>
 #include <memory>
@@ -58,6 +59,15 @@ struct Err {
     } while (0)
 
 void fail(rsr_status st, const std::string &m) { throw Err{st, m}; }
+
+// Scratch of rsr_solve_shift_set_noalloc: one array per device, mapped when the
+// code object loads (no allocation by the library).  In host code the name is a
+// host-side stand-in; kernels get the device address from hipGetSymbolAddress,
+// taken once per device in rsr_create and kept in g_scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
 
 // Device and pinned allocations made by the library (all contexts), for checks
 // that a call allocated nothing.
@@ -187,6 +197,7 @@ struct rsr_ctx {
     int cg_gmax = 1024;                // cap on persistent-kernel workgroups (autotuned)
     double bar_timeout_s = 30.0;       // bound on one grid-barrier wait (RSR_BARRIER_TIMEOUT_US)
     int cg_mode = 0;                   // persistent-CG iteration form: 0 by launch size, 1 fused, 2 two-pass
+    void *scratch_dev = nullptr;       // this device's address of the static no-allocation scratch
     double last_cg_ms = 0.0;
     int last_launches = 0;
     long last_items = 0;
@@ -1548,6 +1559,16 @@ rsr_status rsr_create(rsr_ctx **out, int dev)
             c->wall_khz = khz;
         HIPCHK(hipEventCreate(&c->ev0));
         HIPCHK(hipEventCreate(&c->ev1));
+        // the static scratch's address on this device, once per device
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        auto it = g_scratch_ptr.find(dev);
+        if (it == g_scratch_ptr.end()) {
+            void *ptr = nullptr;
+            HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) fail(RSR_E_HIP, "no device address for the static scratch");
+            it = g_scratch_ptr.emplace(dev, ptr).first;
+        }
+        c->scratch_dev = it->second;
     });
     if (st != RSR_OK) {
         delete c;
@@ -2310,6 +2331,26 @@ rsr_status rsr_solve_shift_set(rsr_ctx *c, const rsr_solve_desc *d, const double
     return guard(c, [&] {
         if (ws && ((uintptr_t)ws & 255)) fail(RSR_E_ARG, "workspace must be 256-byte aligned");
         WsScope scope(c, ws, ws_bytes, S(stream));
+        if (!solve_set(c, d, b, X, stats, S(stream), 0))
+            throw Err{RSR_NOT_CONVERGED, "some systems did not reach tol"};
+    });
+}
+
+rsr_status rsr_solve_shift_set_noalloc(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X,
+                                       rsr_shift_stats *stats, void *stream)
+{
+    return guard(c, [&] {
+        if (!d || !b || !X) fail(RSR_E_ARG, "null descriptor, b or X");
+        if (c->inst.empty()) fail(RSR_E_STATE, "operators not set");
+        if (d->n_sys <= 0 || !d->inst) fail(RSR_E_ARG, "n_sys must be positive with inst");
+        set_device(c);
+        if (!c->scratch_dev) fail(RSR_E_STATE, "static scratch not mapped on this device");
+        const size_t need = solve_ws_bytes(c, d, false);
+        if (need > NOALLOC_SCRATCH_BYTES)
+            fail(RSR_E_ARG, "this shift set needs up to " + std::to_string(need) + " bytes of scratch; the static "
+                            "scratch holds " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                            " (use rsr_solve_shift_set with a caller workspace)");
+        WsScope scope(c, c->scratch_dev, NOALLOC_SCRATCH_BYTES, S(stream));
         if (!solve_set(c, d, b, X, stats, S(stream), 0))
             throw Err{RSR_NOT_CONVERGED, "some systems did not reach tol"};
     });

@@ -29,7 +29,7 @@ EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_se
            "rsr_set_recycle_space", "rsr_solve_shift_set", "rsr_adjoint", "rsr_autotune", "rsr_get_tile",
            "rsr_set_tile", "rsr_get_recycle_info", "rsr_get_recycle_basis", "rsr_get_counters",
            "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve", "rsr_correction_space",
-           "rsr_workspace_size", "rsr_allocation_count"]
+           "rsr_workspace_size", "rsr_allocation_count", "rsr_solve_shift_set_noalloc"]
 
 
 class RsrError(RuntimeError):
@@ -99,6 +99,7 @@ def load():
                               P]
     L.rsr_workspace_size.argtypes = [P, ctypes.POINTER(SolveDesc), I, ctypes.POINTER(S_), P]
     L.rsr_allocation_count.argtypes = []
+    L.rsr_solve_shift_set_noalloc.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(ShiftStats), P]
     L.rsr_autotune.argtypes = [P, I, I, ctypes.c_char_p]
     L.rsr_get_tile.argtypes = [P, I, pI, pI]
     L.rsr_set_tile.argtypes = [P, I, I, I]
@@ -316,6 +317,20 @@ class Context:
         st = (ShiftStats * m)()
         wp, wn = _ws(ws)
         rc = self.lib.rsr_solve_shift_set(self.h, ctypes.byref(d), _ptr(b), _ptr(X), wp, wn, st, _stream())
+        self._check(rc, allow_not_converged=True)
+        return rc, [s.as_dict() for s in st]
+
+    def solve_noalloc(self, gammas: Sequence[float], b, X, inst: Optional[Sequence[int]] = None, slots=None,
+                      opts: Optional[SolveOptions] = None, shared_b: bool = True):
+        """solve() with the library's static scratch: no allocation (rsr_solve_shift_set_noalloc)."""
+        o = opts or SolveOptions()
+        m = len(gammas)
+        inst = list(inst) if inst is not None else [0] * m
+        ld_x = X[0].numel()
+        ld_b = 0 if shared_b else b[0].numel()
+        d, keep = self._desc(inst, gammas, slots, o, ld_b, ld_x)
+        st = (ShiftStats * m)()
+        rc = self.lib.rsr_solve_shift_set_noalloc(self.h, ctypes.byref(d), _ptr(b), _ptr(X), st, _stream())
         self._check(rc, allow_not_converged=True)
         return rc, [s.as_dict() for s in st]
 
