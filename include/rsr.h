@@ -241,18 +241,44 @@ rsr_status rsr_set_recycle_space(rsr_ctx *ctx, int inst, const double *U_raw, lo
 rsr_status rsr_solve_shift_set_noalloc(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *b,
                                        double *X, rsr_shift_stats *stats_host, void *stream);
 
-/* Workspace of rsr_solve_shift_set (adjoint = 0) or rsr_adjoint (adjoint = 1)
- * for this descriptor on the current operators and recycle spaces: *bytes
- * (host) receives the size.  The call also reserves the persistent storage such
- * a solve keeps (a correction column for every slot of the descriptor, and the
- * Ritz blocks of its groups), so it allocates device memory and drains the
+/* Workspace sizes (rsr_workspace_size's kind). */
+enum { RSR_WS_SOLVE = 0,      /* rsr_solve_shift_set                        */
+       RSR_WS_ADJOINT = 1,    /* rsr_adjoint                                */
+       RSR_WS_DEVICE = 2      /* rsr_solve_shift_set_async                  */ };
+
+/* Workspace of the call named by kind for this descriptor on the current
+ * operators and recycle spaces: *bytes (host) receives the size.  For
+ * RSR_WS_SOLVE and RSR_WS_ADJOINT the call also reserves the persistent storage
+ * such a solve keeps (a correction column for every slot of the descriptor, and
+ * the Ritz blocks of its groups), so it allocates device memory and drains the
  * stream; call it once per shape of shift set, outside any graph capture.  A
- * larger recycle space (rsr_set_recycle_space) can raise the size.           */
-rsr_status rsr_workspace_size(rsr_ctx *ctx, const rsr_solve_desc *desc, int adjoint, size_t *bytes,
+ * larger recycle space (rsr_set_recycle_space) can raise the size.
+ * RSR_WS_DEVICE reserves nothing.  Unknown kind: RSR_E_ARG.                   */
+rsr_status rsr_workspace_size(rsr_ctx *ctx, const rsr_solve_desc *desc, int kind, size_t *bytes,
                               void *stream);
 
+/* Plain CG of a shift set with every step on the device, so that the call can
+ * be recorded into a HIP graph (stream capture) and replayed: it enqueues work
+ * on stream and returns, with no host synchronisation, no read-back and no
+ * allocation.  The solve is the same persistent CG launch as in
+ * rsr_solve_shift_set; its descriptors are written on the device from the call's
+ * arguments, the tolerances tol * ||b_i|| come from norms computed on the device,
+ * and the final step, the true residual and the statistics are kernels.  There
+ * is no true-residual restart: the recursive residual decides, and the true
+ * relative residual is reported.  Limits: one instance, 1..128 systems, init
+ * RSR_INIT_ZERO or RSR_INIT_GIVEN, no local spaces and no seeding (else
+ * RSR_E_ARG).  ws: device workspace of ws_bytes >= rsr_workspace_size(...,
+ * RSR_WS_DEVICE) bytes, 256-byte aligned, which must stay allocated while a
+ * graph that recorded the call is replayed.  stats_dev: device [n_sys][4]
+ * doubles receiving {CG iterations, kernel status (1 converged, 2 maxit, -3
+ * non-finite, -4 not SPD), true relative residual, applications of B}.  The
+ * launch shape is fixed when the call is recorded.  The context's matvec
+ * counters do not include these solves.                                      */
+rsr_status rsr_solve_shift_set_async(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *b, double *X,
+                                     void *ws, size_t ws_bytes, double *stats_dev, void *stream);
+
 /* Solve a shift set.  b, X: device.  stats_host: host [n_sys] (may be NULL).
- * ws: device workspace of ws_bytes bytes, 256-byte aligned, owned by the caller
+ * ws: device workspace of ws_bytes bytes (rsr_workspace_size, RSR_WS_SOLVE), 256-byte aligned, owned by the caller
  * and borrowed for the call (its contents on entry do not matter), or NULL for
  * the library's own scratch.  With a workspace the solve allocates nothing;
  * ws_bytes below what the call needs gives RSR_E_ARG (size it with
@@ -276,7 +302,7 @@ rsr_status rsr_solve_shift_set(rsr_ctx *ctx, const rsr_solve_desc *desc, const d
  * keep corrections of their own (slots offset by 2^20); with use_prev_k their
  * local spaces also take the forward correction of the same shift.  Groups
  * follow the shift index (slot < split_I).  ws, ws_bytes: as for
- * rsr_solve_shift_set (size with rsr_workspace_size, adjoint = 1).  A system
+ * rsr_solve_shift_set (size with rsr_workspace_size, RSR_WS_ADJOINT).  A system
  * set spanning several instances: RSR_E_ARG.                               */
 rsr_status rsr_adjoint(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *X,
                        const double *Gbar, double *Lambda, double *dgamma_host, double *dw_h,

@@ -729,6 +729,43 @@ struct Opts {
     double gJL, gJR;
 };
 
+// Launch shape of the persistent CG kernel for m systems of px pixels and
+// `tiles` tiles in all, widest local space qmax.
+struct CgLaunch {
+    int qt, two_pass, G, msys, tl, taps;
+    size_t lds;
+};
+CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles)
+{
+    CgLaunch L;
+    L.msys = (m + 7) & ~7;
+    L.tl = cg_tile_lds(max_tile_lds(c), L.msys);
+    L.taps = max_taps_lds(c);
+    L.lds = cg_lds_bytes(L.tl, L.taps, L.msys);
+    L.qt = lz && qmax > 0 ? QMAX : cg_width(qmax);
+    // Fused iterations (one phase, r and ph recomputed on the halo from three
+    // step j-1 vectors) need one grid barrier per iteration; two-pass iterations
+    // (an elementwise pass, a barrier, a stencil pass that reads ph alone) need two
+    // but read a third of the halo.  Small launches are bound by the barrier
+    // latency, large ones by the halo traffic.  Launches that record CG-Lanczos
+    // data are fused.
+    int mode = c->cg_mode;
+    if (const char *e = getenv("RSR_CG_MODE")) mode = atoi(e);   // override for tuning sweeps
+    L.two_pass = lz ? 0 : mode == 2 ? 1 : mode == 1 ? 0 : (px >= (2L << 20) ? 1 : 0);
+    const int bpc = cg_max_blocks_per_cu(L.lds, L.qt, lz, L.two_pass != 0);
+    if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
+    int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
+    if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
+        const int v = atoi(cap);
+        if (v >= 8) G = std::min(G, v);
+    }
+    // no more workgroups than tiles (rounded up to the 8 XCDs)
+    G = (int)std::min<long>(G, (std::max<long>(8, tiles) + 7) & ~7L);
+    if (G >= 8) G -= G % 8;
+    L.G = G;
+    return L;
+}
+
 // Runs deflated CG from the current (x, r) of each listed system to the
 // recursive-residual tolerance.  Returns per-system kernel status.
 void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s)
@@ -782,41 +819,17 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     double *out_alpha = out_rho + m;
     HIPCHK(launch_fill((double *)outb, 0.0, (long)(out_bytes / sizeof(double)), s));
 
-    const int msys = (m + 7) & ~7;
-    const int tl = cg_tile_lds(max_tile_lds(c), msys);
-    const int taps_lds = max_taps_lds(c);
-    const size_t lds = cg_lds_bytes(tl, taps_lds, msys);
     int qmax = 0;
     bool lz = false;   // some system records CG-Lanczos data in this launch
+    long px = 0;
     for (auto *Y : sy) {
         qmax = std::max(qmax, Y->q);
         lz = lz || Y->nlz > 0;
+        px += Y->n;
     }
-    const int qt = lz && qmax > 0 ? QMAX : cg_width(qmax);
-    // Fused iterations (one phase, r and ph recomputed on the halo from three
-    // step j-1 vectors) need one grid barrier per iteration; two-pass iterations
-    // (an elementwise pass, a barrier, a stencil pass that reads ph alone) need two
-    // but read a third of the halo.  Small launches are bound by the barrier
-    // latency, large ones by the halo traffic.  Launches that record CG-Lanczos
-    // data are fused.
-    int two_pass = 0;
-    {
-        long px = 0;
-        for (auto *Y : sy) px += Y->n;
-        int mode = c->cg_mode;
-        if (const char *e = getenv("RSR_CG_MODE")) mode = atoi(e);   // override for tuning sweeps
-        two_pass = lz ? 0 : mode == 2 ? 1 : mode == 1 ? 0 : (px >= (2L << 20) ? 1 : 0);
-    }
-    int bpc = cg_max_blocks_per_cu(lds, qt, lz, two_pass != 0);
-    if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
-    int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
-    if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
-        const int v = atoi(cap);
-        if (v >= 8) G = std::min(G, v);
-    }
-    // no more workgroups than tiles (rounded up to the 8 XCDs)
-    G = (int)std::min<long>(G, (std::max<long>(8, tiles) + 7) & ~7L);
-    if (G >= 8) G -= G % 8;
+    const CgLaunch L = cg_config(c, m, qmax, lz, px, tiles);
+    const int qt = L.qt, two_pass = L.two_pass, G = L.G, msys = L.msys, tl = L.tl, taps_lds = L.taps;
+    const size_t lds = L.lds;
 
     CGArgs a;
     a.nsys = m;
@@ -2266,6 +2279,51 @@ size_t solve_ws_bytes(rsr_ctx *c, const rsr_solve_desc *d, bool adjoint)
     return need;
 }
 
+// Workspace layout of rsr_solve_shift_set_async (byte offsets); checks the
+// descriptor against what the device-only path supports.
+struct AsyncLayout {
+    size_t vec, cbuf, sys, jobs, bn2, part, ctl, out, part_a, part_b, bytes;
+    long vstride;
+    int nb;
+};
+AsyncLayout async_layout(rsr_ctx *c, const rsr_solve_desc *d)
+{
+    const int m = d->n_sys;
+    if (m <= 0 || m > ASYNC_MAXSYS || !d->inst || !d->gammas)
+        fail(RSR_E_ARG, "the device-only solve takes 1.." + std::to_string(ASYNC_MAXSYS) + " systems");
+    if (!(d->tol > 0.0)) fail(RSR_E_ARG, "tol must be positive");
+    if ((d->init != RSR_INIT_ZERO && d->init != RSR_INIT_GIVEN) || d->n_ritz != 0 || d->use_prev_k ||
+        d->use_prev_shift || d->seed_lanczos)
+        fail(RSR_E_ARG, "the device-only solve is plain CG (init ZERO or GIVEN, no local spaces, no seeding)");
+    const int ii = d->inst[0];
+    Instance &I = get_inst(c, ii);
+    for (int i = 0; i < m; ++i) {
+        if (d->inst[i] != ii) fail(RSR_E_ARG, "the device-only solve takes one instance");
+        if (!std::isfinite(d->gammas[i])) fail(RSR_E_ARG, "gamma must be finite");
+    }
+    if (m > 1 && d->ld_x < I.n) fail(RSR_E_ARG, "ld_x smaller than ny*nx");
+    if (d->ld_b != 0 && d->ld_b < I.n) fail(RSR_E_ARG, "ld_b smaller than ny*nx");
+    const InstDev &D = c->h_inst[ii];
+    const long tiles = (long)m * D.nty * D.ntx;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    AsyncLayout L;
+    L.nb = (int)std::max<long>(1, std::min<long>(64, (I.n + 4 * NT - 1) / (4 * NT)));
+    L.vstride = (long)(al(sizeof(double) * 9 * (size_t)I.n) / sizeof(double));
+    size_t o = 0;
+    L.vec = o; o += al(sizeof(double) * L.vstride * m);
+    L.cbuf = o; o += al(sizeof(double) * 2 * QMAX * m);
+    L.sys = o; o += al(sizeof(SysDev) * m);
+    L.jobs = o; o += al(sizeof(ApplyJob) * 2 * m);
+    L.bn2 = o; o += al(sizeof(double) * m);
+    L.part = o; o += al(sizeof(double) * (size_t)m * L.nb);
+    L.ctl = o; o += al(BAR_BYTES);
+    L.out = o; o += al((sizeof(int) * 2 + 2 * sizeof(double)) * m + 64);
+    L.part_a = o; o += al(sizeof(double) * tiles * NVP);
+    L.part_b = o; o += al(sizeof(double) * tiles * NVP);
+    L.bytes = o;
+    return L;
+}
+
 // Persistent storage a workspace call may not allocate: a correction column for
 // every slot of the descriptor (and the adjoint slots) and the Ritz blocks of its
 // groups.
@@ -2356,7 +2414,102 @@ rsr_status rsr_solve_shift_set_noalloc(rsr_ctx *c, const rsr_solve_desc *d, cons
     });
 }
 
-rsr_status rsr_workspace_size(rsr_ctx *c, const rsr_solve_desc *d, int adjoint, size_t *bytes, void *stream)
+rsr_status rsr_solve_shift_set_async(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, void *ws,
+                                     size_t ws_bytes, double *stats_dev, void *stream)
+{
+    return guard(c, [&] {
+        if (!d || !b || !X || !ws || !stats_dev) fail(RSR_E_ARG, "null descriptor, b, X, workspace or stats");
+        if ((uintptr_t)ws & 255) fail(RSR_E_ARG, "workspace must be 256-byte aligned");
+        if (c->inst.empty()) fail(RSR_E_STATE, "operators not set");
+        AsyncLayout Lo = async_layout(c, d);
+        if (ws_bytes < Lo.bytes)
+            fail(RSR_E_ARG, "workspace of " + std::to_string(ws_bytes) + " bytes is too small (needs " +
+                                std::to_string(Lo.bytes) + ")");
+        set_device(c);
+        hipStream_t s = S(stream);
+        const int m = d->n_sys;
+        const int ii = d->inst[0];
+        Instance &I = *c->inst[ii];
+        const InstDev &D = c->h_inst[ii];
+        char *w = (char *)ws;
+        AsyncArgs a;
+        memset(&a, 0, sizeof(a));
+        a.m = m;
+        a.init = d->init == RSR_INIT_GIVEN ? 1 : 0;
+        a.n = I.n;
+        a.inst = ii;
+        a.ntiles = D.nty * D.ntx;
+        a.nb = Lo.nb;
+        a.tol = d->tol;
+        a.b = b;
+        a.ld_b = d->ld_b;
+        a.X = X;
+        a.ld_x = d->ld_x;
+        a.vec = (double *)(w + Lo.vec);
+        a.vstride = Lo.vstride;
+        a.cbuf = (double *)(w + Lo.cbuf);
+        a.sys = (SysDev *)(w + Lo.sys);
+        a.jobs = (ApplyJob *)(w + Lo.jobs);
+        a.bn2 = (double *)(w + Lo.bn2);
+        a.part = (double *)(w + Lo.part);
+        char *ctl = w + Lo.ctl;
+        char *outb = w + Lo.out;
+        a.clear = (double *)ctl;
+        a.clear_n = (int)((Lo.part_a - Lo.ctl) / sizeof(double));   // barrier block and outputs (contiguous)
+        int *out_iters = (int *)outb;
+        int *out_status = out_iters + m;
+        double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
+        double *out_alpha = out_rho + m;
+        a.out_iters = out_iters;
+        a.out_status = out_status;
+        a.out_alpha = out_alpha;
+        for (int i = 0; i < m; ++i) a.gam[i] = d->gammas[i];
+        // x0, r0 and ||b||; descriptors and cleared control blocks; r0 = b - B x0
+        HIPCHK(launch_async_elem(a, 0, s));
+        HIPCHK(launch_async_setup(a, s));
+        const size_t alds = apply_lds_bytes(I);
+        if (a.init == 1) {
+            HIPCHK(launch_apply(c->d_inst.as<InstDev>(), D, a.jobs, m, alds, s));
+            HIPCHK(launch_async_elem(a, 1, s));
+        }
+        // the persistent CG launch
+        const long tiles = (long)m * a.ntiles;
+        const CgLaunch L = cg_config(c, m, 0, false, (long)m * I.n, tiles);
+        CGArgs g;
+        memset(&g, 0, sizeof(g));
+        g.nsys = m;
+        g.sys = a.sys;
+        g.inst = c->d_inst.as<InstDev>();
+        g.part[0] = (double *)(w + Lo.part_a);
+        g.part[1] = (double *)(w + Lo.part_b);
+        g.pstride = (int)tiles;
+        g.bar = (unsigned long long *)ctl;
+        g.abort_flag = (int *)(ctl + 256);
+        g.out_iters = out_iters;
+        g.out_status = out_status;
+        g.out_rho = out_rho;
+        g.out_alpha = out_alpha;
+        g.maxit = d->maxit > 0 ? d->maxit : (int)std::min<long>(10 * I.n, 1 << 30);
+        g.two_pass = L.two_pass;
+        g.G = L.G;
+        g.timeout_ticks = (long long)(c->wall_khz * 1000.0 * c->bar_timeout_s);
+        g.tile_lds = L.tl;
+        g.taps_lds = L.taps;
+        g.msys = L.msys;
+        g.stamps = nullptr;
+        {
+            const hipError_t e = launch_cg(g, L.qt, false, L.G, L.lds, s);
+            if (e != hipSuccess) fail(RSR_E_HIP, std::string("persistent CG launch: ") + hipGetErrorString(e));
+        }
+        // x += alpha p, rt = B x, ||b - rt||, statistics
+        HIPCHK(launch_async_elem(a, 2, s));
+        HIPCHK(launch_apply(c->d_inst.as<InstDev>(), D, a.jobs + m, m, alds, s));
+        HIPCHK(launch_async_elem(a, 3, s));
+        HIPCHK(launch_async_stats(a, stats_dev, s));
+    });
+}
+
+rsr_status rsr_workspace_size(rsr_ctx *c, const rsr_solve_desc *d, int kind, size_t *bytes, void *stream)
 {
     return guard(c, [&] {
         if (!d || !bytes) fail(RSR_E_ARG, "null descriptor or output");
@@ -2364,8 +2517,13 @@ rsr_status rsr_workspace_size(rsr_ctx *c, const rsr_solve_desc *d, int adjoint, 
         if (d->n_sys <= 0 || !d->inst) fail(RSR_E_ARG, "n_sys must be positive with inst");
         if (d->n_ritz < 0 || d->n_ritz > QMAX) fail(RSR_E_ARG, "n_ritz out of range");
         set_device(c);
-        *bytes = solve_ws_bytes(c, d, adjoint != 0);
-        reserve_persistent(c, d, adjoint != 0, S(stream));
+        if (kind < RSR_WS_SOLVE || kind > RSR_WS_DEVICE) fail(RSR_E_ARG, "unknown workspace kind");
+        if (kind == RSR_WS_DEVICE) {   // the device-only solve keeps nothing between calls
+            *bytes = async_layout(c, d).bytes;
+            return;
+        }
+        *bytes = solve_ws_bytes(c, d, kind == RSR_WS_ADJOINT);
+        reserve_persistent(c, d, kind == RSR_WS_ADJOINT, S(stream));
     });
 }
 

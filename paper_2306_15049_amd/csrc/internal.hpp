@@ -146,6 +146,37 @@ struct ComboJob {
 };
 hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jobs_host, int njobs, hipStream_t s);
 
+// Graph-capturable plain CG of a shift set on one instance (see kernels.hip).
+constexpr int ASYNC_MAXSYS = 128;
+struct AsyncArgs {
+    int m;                     // systems (<= ASYNC_MAXSYS)
+    int init;                  // 0: x0 = 0, 1: x0 given in X
+    long n;                    // pixels per system
+    int inst;                  // instance
+    int ntiles;                // tiles per system
+    int nb;                    // workgroups per system of the elementwise kernels
+    double tol;
+    const double *b;
+    long ld_b;
+    double *X;
+    long ld_x;
+    double *vec;               // per system: r, r1, w, w1, p0, p1, (unused), rt, pa (n each) at vec + i * vstride
+    long vstride;
+    double *cbuf;              // [m][2 QMAX]
+    SysDev *sys;               // [m]
+    ApplyJob *jobs;            // [2 m]: B x -> r (GIVEN start), B x -> rt (true residual)
+    double *bn2;               // [m]
+    double *part;              // [m][nb]
+    double *clear;             // barrier block and outputs, zeroed by the setup kernel
+    int clear_n;
+    const int *out_iters, *out_status;
+    const double *out_alpha;
+    double gam[ASYNC_MAXSYS];
+};
+hipError_t launch_async_elem(const AsyncArgs &a, int stage, hipStream_t s);
+hipError_t launch_async_setup(const AsyncArgs &a, hipStream_t s);
+hipError_t launch_async_stats(const AsyncArgs &a, double *stats, hipStream_t s);
+
 hipError_t launch_grad(const double *X, const double *Lam, long ld, const double *gammas_dev, int m,
                        const double *wh, const double *wv, int ny, int nx, double *dw_h, double *dw_v,
                        double *db, double *dg_partial, int nchunks, hipStream_t s);

@@ -716,3 +716,132 @@ hipError_t launch_grad(const double *X, const double *Lam, long ld, const double
 }
 
 }  // namespace rsr
+
+namespace rsr {
+
+// ------------------------------------------- graph-capturable shift-set solve --
+// Plain CG of a shift set on one instance with every step on the device: the
+// descriptors of the persistent CG launch are written by a kernel from the
+// launch arguments, the tolerances come from norms of b computed on the device,
+// and the last step x += alpha p, the true residual and the statistics are
+// kernels too, so the whole sequence records into a HIP graph and replays.
+
+// Fixed-order sum of one value per thread over the workgroup (result in thread 0).
+__device__ double block_sum_fixed(double v, double *red)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// stage 0: ZERO start (x = 0, r = b) and the partial sums of b^2;
+// stage 1: r = b - r (GIVEN start, after r = B x);
+// stage 2: x += alpha p with the step the CG kernel left (out_alpha);
+// stage 3: partial sums of (b - rt)^2, rt = B x.
+__global__ __launch_bounds__(NT) void k_async_elem(AsyncArgs a, int stage)
+{
+    __shared__ double red[NT / 64];
+    const int i = blockIdx.y;
+    const double *b = a.b + (size_t)i * a.ld_b;
+    double *x = a.X + (size_t)i * a.ld_x;
+    double *v = a.vec + (size_t)i * a.vstride;
+    double *r = v, *pa = v + 8 * a.n, *rt = v + 7 * a.n;
+    const double alpha = stage == 2 ? a.out_alpha[i] : 0.0;
+    double acc = 0.0;
+    for (long k = blockIdx.x * (long)NT + threadIdx.x; k < a.n; k += (long)gridDim.x * NT) {
+        const double bk = b[k];
+        if (stage == 0) {
+            if (a.init == 0) {
+                x[k] = 0.0;
+                r[k] = bk;
+            }
+            acc = fma(bk, bk, acc);
+        } else if (stage == 1) {
+            r[k] = bk - r[k];
+        } else if (stage == 2) {
+            x[k] = fma(alpha, pa[k], x[k]);
+        } else {
+            const double e = bk - rt[k];
+            acc = fma(e, e, acc);
+        }
+    }
+    if (stage == 0 || stage == 3) {
+        const double s = block_sum_fixed(acc, red);
+        if (threadIdx.x == 0) a.part[(size_t)i * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// One workgroup: ||b_i||^2 from the partials, the CG descriptors and the
+// operator jobs of every system, and cleared barrier and output blocks.
+__global__ __launch_bounds__(NT) void k_async_setup(AsyncArgs a)
+{
+    for (int i = threadIdx.x; i < a.m; i += NT) {
+        double s = 0.0;
+        for (int k = 0; k < a.nb; ++k) s += a.part[(size_t)i * a.nb + k];
+        a.bn2[i] = s;
+        double *v = a.vec + (size_t)i * a.vstride;
+        SysDev d;
+        memset(&d, 0, sizeof(d));
+        d.inst = a.inst;
+        d.q = 0;
+        d.ntiles = a.ntiles;
+        d.tile_base = i * a.ntiles;
+        d.gamma = a.gam[i];
+        d.tolabs = a.tol * sqrt(s);
+        d.x = a.X + (size_t)i * a.ld_x;
+        d.rb[0] = v;
+        d.rb[1] = v + a.n;
+        d.wb[0] = v + 2 * a.n;
+        d.wb[1] = v + 3 * a.n;
+        d.pb[0] = v + 4 * a.n;
+        d.pb[1] = v + 5 * a.n;
+        d.pa = v + 8 * a.n;
+        d.cbuf = a.cbuf + (size_t)i * 2 * QMAX;
+        d.ldw = a.n;
+        a.sys[i] = d;
+        // B x into r (GIVEN start) and, after the solve, B x into rt
+        a.jobs[i] = ApplyJob{a.inst, 0, 1.0, a.gam[i], d.x, a.init == 0 ? v + 7 * a.n : v};
+        a.jobs[a.m + i] = ApplyJob{a.inst, 0, 1.0, a.gam[i], d.x, v + 7 * a.n};
+    }
+    for (int k = threadIdx.x; k < a.clear_n; k += NT) a.clear[k] = 0.0;
+}
+
+// One workgroup: stats[i] = {iterations, kernel status, true relative
+// residual, applications of B}.
+__global__ __launch_bounds__(NT) void k_async_stats(AsyncArgs a, double *stats)
+{
+    for (int i = threadIdx.x; i < a.m; i += NT) {
+        double s = 0.0;
+        for (int k = 0; k < a.nb; ++k) s += a.part[(size_t)i * a.nb + k];
+        const double bn2 = a.bn2[i];
+        stats[4 * i + 0] = (double)a.out_iters[i];
+        stats[4 * i + 1] = (double)a.out_status[i];
+        stats[4 * i + 2] = bn2 > 0.0 ? sqrt(s / bn2) : 0.0;
+        stats[4 * i + 3] = (double)(a.out_iters[i] + 1 + (a.init == 0 ? 0 : 1));
+    }
+}
+
+hipError_t launch_async_elem(const AsyncArgs &a, int stage, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_async_elem, dim3(a.nb, a.m), dim3(NT), 0, s, a, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_async_setup(const AsyncArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_async_setup, dim3(1), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_async_stats(const AsyncArgs &a, double *stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_async_stats, dim3(1), dim3(NT), 0, s, a, stats);
+    return hipGetLastError();
+}
+
+}  // namespace rsr

@@ -29,7 +29,9 @@ EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_se
            "rsr_set_recycle_space", "rsr_solve_shift_set", "rsr_adjoint", "rsr_autotune", "rsr_get_tile",
            "rsr_set_tile", "rsr_get_recycle_info", "rsr_get_recycle_basis", "rsr_get_counters",
            "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve", "rsr_correction_space",
-           "rsr_workspace_size", "rsr_allocation_count", "rsr_solve_shift_set_noalloc"]
+           "rsr_workspace_size", "rsr_allocation_count", "rsr_solve_shift_set_noalloc",
+           "rsr_solve_shift_set_async"]
+WS_SOLVE, WS_ADJOINT, WS_DEVICE = 0, 1, 2
 
 
 class RsrError(RuntimeError):
@@ -100,6 +102,7 @@ def load():
     L.rsr_workspace_size.argtypes = [P, ctypes.POINTER(SolveDesc), I, ctypes.POINTER(S_), P]
     L.rsr_allocation_count.argtypes = []
     L.rsr_solve_shift_set_noalloc.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, ctypes.POINTER(ShiftStats), P]
+    L.rsr_solve_shift_set_async.argtypes = [P, ctypes.POINTER(SolveDesc), P, P, P, S_, P, P]
     L.rsr_autotune.argtypes = [P, I, I, ctypes.c_char_p]
     L.rsr_get_tile.argtypes = [P, I, pI, pI]
     L.rsr_set_tile.argtypes = [P, I, I, I]
@@ -335,17 +338,32 @@ class Context:
         return rc, [s.as_dict() for s in st]
 
     def workspace_size(self, gammas: Sequence[float], inst: Optional[Sequence[int]] = None, slots=None,
-                       opts: Optional[SolveOptions] = None, adjoint: bool = False) -> int:
-        """Bytes of caller workspace for solve (or adjoint) with these arguments; also
-        reserves the library's persistent storage for them."""
+                       opts: Optional[SolveOptions] = None, adjoint: bool = False, kind: Optional[int] = None,
+                       ld_x: int = 0, ld_b: int = 0) -> int:
+        """Bytes of caller workspace for solve (kind WS_SOLVE), adjoint (WS_ADJOINT) or
+        solve_async (WS_DEVICE) with these arguments; the first two also reserve the
+        library's persistent storage for them."""
         o = opts or SolveOptions()
         m = len(gammas)
         inst = list(inst) if inst is not None else [0] * m
-        d, keep = self._desc(inst, gammas, slots, o, 0, 0)
+        d, keep = self._desc(inst, gammas, slots, o, ld_b, ld_x)
         n = ctypes.c_size_t(0)
-        self._check(self.lib.rsr_workspace_size(self.h, ctypes.byref(d), int(bool(adjoint)), ctypes.byref(n),
-                                                _stream()))
+        k = kind if kind is not None else (WS_ADJOINT if adjoint else WS_SOLVE)
+        self._check(self.lib.rsr_workspace_size(self.h, ctypes.byref(d), int(k), ctypes.byref(n), _stream()))
         return n.value
+
+    def solve_async(self, gammas: Sequence[float], b, X, ws, stats, inst: int = 0,
+                    opts: Optional[SolveOptions] = None, shared_b: bool = True):
+        """Device-only plain CG (rsr_solve_shift_set_async): enqueues on the current stream and
+        returns; capturable into a graph.  stats: float64 CUDA tensor [m, 4]."""
+        o = opts or SolveOptions()
+        m = len(gammas)
+        ld_x = X[0].numel()
+        ld_b = 0 if shared_b else b[0].numel()
+        d, keep = self._desc([inst] * m, gammas, None, o, ld_b, ld_x)
+        wp, wn = _ws(ws)
+        self._check(self.lib.rsr_solve_shift_set_async(self.h, ctypes.byref(d), _ptr(b), _ptr(X), wp, wn,
+                                                        _ptr(stats), _stream()))
 
     def adjoint(self, gammas, X, Gbar, Lam, inst: int = 0, slots=None, opts: Optional[SolveOptions] = None,
                 ws=None):
