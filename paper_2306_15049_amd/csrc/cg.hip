@@ -103,6 +103,7 @@ __device__ __forceinline__ bool spin_until(unsigned long long *word, unsigned lo
 // at a loop top), so the arrivals a group counter has seen are tracked in LDS:
 // *s_arr is the count before this barrier, and the group's size is the
 // current grid size *s_g over the group count.  Only thread 0 touches *s_arr.
+template <bool AGENT = false>
 __device__ __forceinline__ bool grid_barrier(const BarCtl &b, unsigned long long k, long long timeout, int *s_flag,
                                              unsigned long long *s_arr, const int *s_g)
 {
@@ -127,7 +128,11 @@ __device__ __forceinline__ bool grid_barrier(const BarCtl &b, unsigned long long
         } else {
             ok = spin_until(b.rel, k, b.abort_flag, t0, timeout);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // workgroup scope: other workgroups' data is then read with coherent loads;
+        // agent scope: the CU's L1 and the XCD's L2 drop what may be stale, and
+        // plain loads see every arrival's stores
+        if constexpr (AGENT) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         *s_flag = ok ? 1 : 0;
     }
     __syncthreads();
@@ -325,7 +330,8 @@ __device__ __forceinline__ void block_accumulate(const double (&v)[NV], int cnt,
     __syncthreads();
 }
 
-constexpr int NBW = 6;   // window rows per thread whose loads are issued together
+constexpr int NBW = 6;    // window rows per thread whose loads are issued together (three fields each)
+constexpr int NBW2 = 18;  // the same for the two-pass stencil phase (ph alone): a 72-row window in one round
 constexpr int NBE = 2;   // interior pixels per thread whose local-basis loads are issued together
 
 // QT: widest local space of the launch (the loops over basis columns are
@@ -333,9 +339,21 @@ constexpr int NBE = 2;   // interior pixels per thread whose local-basis loads a
 // ask for it (a separate instantiation, so launches without it carry no trace).  Chunk partial layout: p.w, r.r, r.w, w.w, Z^T r[QT],
 // Z^T w[QT] in a slot of NVP values.
 // At most 256 registers per lane keeps two waves per SIMD.
-template <int QT, bool LZ, bool TWO>
+// FORM 0: fused iterations, other workgroups' cells read with coherent loads
+// (the L2 keeps this workgroup's own data between iterations: small launches);
+// FORM 1: fused iterations, an agent-scope acquire after every barrier and plain
+// window loads (halo cells shared by neighbouring tiles hit the L2: large
+// launches, whose data does not stay in the L2 anyway); FORM 2: two-pass
+// iterations with the same acquire and plain loads.
+template <int QT, bool LZ, int FORM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_cg(CGArgs A)
 {
+    constexpr bool TWO = FORM == 2, ACQ = FORM != 0;
+    // a window cell written by another workgroup in the previous phase
+    auto wld = [](const gdbl *p) -> double {
+        if constexpr (ACQ) return *p;
+        else return cld(p);
+    };
     constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
     extern __shared__ double smem[];
     double *tile = smem;                          // stencil buffers / reduction scratch
@@ -705,7 +723,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     }
                 }
             }
-            if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+            if (!grid_barrier<ACQ>(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
         }
 
         // ---- the iteration's stencil phase under N (its only phase in fused mode)
@@ -813,37 +831,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
                 const bool colown = lj >= g.hx && lj < g.hx + I.tx;
                 if constexpr (TWO) {
-                    // ph_j on the window as the first pass left it (coherent loads: the halo
-                    // cells are other workgroups' own cells), r_j of the own cells
+                    // ph_j on the window as the first pass left it, all rows of a thread in
+                    // flight together (r_j of the own cells is read in the epilogue)
                     const gdbl *__restrict__ phs = gp(Y.pb[pj]);
-                    const gdbl *__restrict__ rjs = gp(Y.rb[pj]);
-                    for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
-                        int gi[NBW];
-                        bool ok[NBW], own[NBW];
+                    for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW2) {
+                        int gi[NBW2];
+                        bool ok[NBW2];
 #pragma unroll
-                        for (int u = 0; u < NBW; ++u) {
+                        for (int u = 0; u < NBW2; ++u) {
                             const int li = li0 + u * wm.rs;
                             const int gy = y0 - g.hy + li;
                             ok[u] = colok && li < g.H0 && gy >= 0 && gy < I.ny;
-                            own[u] = colown && li >= g.hy && li < g.hy + I.ty;
                             gi[u] = ok[u] ? gy * I.nx + gx : 0;
                         }
-                        double pv[NBW], rv[NBW];
+                        double pv[NBW2];
 #pragma unroll
-                        for (int u = 0; u < NBW; ++u) pv[u] = cld(phs + gi[u]);
+                        for (int u = 0; u < NBW2; ++u) pv[u] = wld(phs + gi[u]);
 #pragma unroll
-                        for (int u = 0; u < NBW; ++u) rv[u] = (ok[u] && own[u]) ? rjs[gi[u]] : 0.0;
-#pragma unroll
-                        for (int u = 0; u < NBW; ++u) {
+                        for (int u = 0; u < NBW2; ++u) {
                             const int li = li0 + u * wm.rs;
                             const double ph = ok[u] ? pv[u] : 0.0;
                             double *d = (lj < g.W0 && li < g.H0) ? tile + li * g.P0 + lj : tile + g.offT + threadIdx.x;
                             *d = ph;
-                            if (ok[u] && own[u]) {
-                                const int ii = (li - g.hy) * g.PE + (lj - g.hx);
-                                pbuf[ii] = ph;
-                                rbuf[ii] = rv[u];
-                            }
+                            if (ok[u] && colown && li >= g.hy && li < g.hy + I.ty)
+                                pbuf[(li - g.hy) * g.PE + (lj - g.hx)] = ph;
                         }
                     }
                 } else
@@ -863,12 +874,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                     // together; masked lanes load element 0 and discard it
                     double rv[NBW], wv[NBW], pv[NBW];
 #pragma unroll
-                    for (int u = 0; u < NBW; ++u) rv[u] = cld(rsrc + gi[u]);
+                    for (int u = 0; u < NBW; ++u) rv[u] = wld(rsrc + gi[u]);
                     if (it > 0) {
 #pragma unroll
                         for (int u = 0; u < NBW; ++u) {
-                            wv[u] = cld(wsrc + gi[u]);
-                            pv[u] = cld(psrc + gi[u]);
+                            wv[u] = wld(wsrc + gi[u]);
+                            pv[u] = wld(psrc + gi[u]);
                         }
                     } else {
 #pragma unroll
@@ -913,7 +924,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         ok[u] = k < ne && gy < I.ny && gx < I.nx;
                         gi[u] = ok[u] ? gy * I.nx + gx : 0;
                     }
-                    double wl[NBE][QT > 0 ? QT : 1], zl[NBE][QT > 0 ? QT : 1], xo[NBE], po[NBE];
+                    double wl[NBE][QT > 0 ? QT : 1], zl[NBE][QT > 0 ? QT : 1], xo[NBE], po[NBE], ro[NBE];
 #pragma unroll
                     for (int u = 0; u < NBE; ++u) {
 #pragma unroll
@@ -923,6 +934,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         }
                         xo[u] = Yx[gi[u]];
                         po[u] = Ypa[gi[u]];
+                        if constexpr (TWO) ro[u] = gp(Y.rb[pj])[gi[u]];   // r_j of the own cell (first pass)
                     }
 #pragma unroll
                     for (int u = 0; u < NBE; ++u) {
@@ -930,7 +942,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         const int ii = ok[u] ? (k >> I.ltx) : 0, jj = ok[u] ? (k & (I.tx - 1)) : 0;
                         double p = pbuf[ii * g.PE + jj];
                         double w = ebuf[ii * g.PE + jj];
-                        const double rj = rbuf[ii * g.PE + jj];
+                        double rj;
+                        if constexpr (TWO) rj = ro[u];
+                        else rj = rbuf[ii * g.PE + jj];
 #pragma unroll
                         for (int j = 0; j < QT; ++j) {
                             p = fma(-s_c[j], wl[u][j], p);
@@ -961,7 +975,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             if (threadIdx.x == 0) s_clast = cur_sys;   // read after the barrier
         }
         stamp(it, 2);
-        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+        if (!grid_barrier<ACQ>(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
         stamp(it, 3);
         if (flip) cur ^= 1;
     }
@@ -985,22 +999,26 @@ size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys)
 // Compiled widths of the local space; a launch uses the smallest one >= its widest q.
 // The capturing variant exists for q = 0 (a first solve) and the widest space, in
 // the fused form only (captures are single systems, where fused iterations win).
-static const void *cg_kernel(int qt, bool lz, bool two)
+static const void *cg_kernel(int qt, bool lz, int form)
 {
-    if (lz) return qt == 0 ? (const void *)k_cg<0, true, false> : (const void *)k_cg<QMAX, true, false>;
-    if (two) {
-        switch (qt) {
-        case 0: return (const void *)k_cg<0, false, true>;
-        case 3: return (const void *)k_cg<3, false, true>;
-        case 5: return (const void *)k_cg<5, false, true>;
-        default: return (const void *)k_cg<QMAX, false, true>;
-        }
+    if (lz) return qt == 0 ? (const void *)k_cg<0, true, 0> : (const void *)k_cg<QMAX, true, 0>;
+#define RSR_CG_FORM(F)                                          \
+    if (form == F) {                                           \
+        switch (qt) {                                          \
+        case 0: return (const void *)k_cg<0, false, F>;        \
+        case 3: return (const void *)k_cg<3, false, F>;        \
+        case 5: return (const void *)k_cg<5, false, F>;        \
+        default: return (const void *)k_cg<QMAX, false, F>;    \
+        }                                                      \
     }
+    RSR_CG_FORM(1)
+    RSR_CG_FORM(2)
+#undef RSR_CG_FORM
     switch (qt) {
-    case 0: return (const void *)k_cg<0, false, false>;
-    case 3: return (const void *)k_cg<3, false, false>;
-    case 5: return (const void *)k_cg<5, false, false>;
-    default: return (const void *)k_cg<QMAX, false, false>;
+    case 0: return (const void *)k_cg<0, false, 0>;
+    case 3: return (const void *)k_cg<3, false, 0>;
+    case 5: return (const void *)k_cg<5, false, 0>;
+    default: return (const void *)k_cg<QMAX, false, 0>;
     }
 }
 
@@ -1009,17 +1027,17 @@ int cg_width(int qmax)
     return qmax <= 0 ? 0 : qmax <= 3 ? 3 : qmax <= 5 ? 5 : QMAX;
 }
 
-int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, bool two)
+int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cg_kernel(qt, lz, two), NT, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cg_kernel(qt, lz, form), NT, lds) != hipSuccess) return 0;
     return nb;
 }
 
 hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s)
 {
     void *args[] = {(void *)&a};
-    return hipLaunchCooperativeKernel(cg_kernel(qt, lz, a.two_pass != 0), dim3(G), dim3(NT), args, (unsigned)lds, s);
+    return hipLaunchCooperativeKernel(cg_kernel(qt, lz, a.form), dim3(G), dim3(NT), args, (unsigned)lds, s);
 }
 
 }  // namespace rsr

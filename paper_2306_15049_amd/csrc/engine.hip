@@ -101,7 +101,9 @@ struct Instance {
     int ny = 0, nx = 0, sy = 1, sx = 1;
     long n = 0;
     std::vector<double> psf;
-    int sep = 0;
+    int sep = 0;                       // 1: the banded separable stencil runs (rank-1 PSF)
+    int sep_ok = 0;                    // the PSF is rank 1 (the banded factors exist)
+    int form = -1;                     // tuned persistent-CG iteration form (-1: by launch size)
     int ssq = 0;                       // separable path: zero-padded square size
     std::vector<double> fy, fx;
     std::vector<double> band;          // banded factors of K^T K (separable path), see band_tables
@@ -196,7 +198,7 @@ struct rsr_ctx {
     long mv_A = 0, mv_E = 0;
     int cg_gmax = 1024;                // cap on persistent-kernel workgroups (autotuned)
     double bar_timeout_s = 30.0;       // bound on one grid-barrier wait (RSR_BARRIER_TIMEOUT_US)
-    int cg_mode = 0;                   // persistent-CG iteration form: 0 by launch size, 1 fused, 2 two-pass
+    int cg_mode = 0;                   // persistent-CG iteration form: 0 by launch size, else form + 1
     void *scratch_dev = nullptr;       // this device's address of the static no-allocation scratch
     double last_cg_ms = 0.0;
     int last_launches = 0;
@@ -658,6 +660,7 @@ void factor_psf(Instance &I)
             if (v > best) { best = v; am = a; cm = c2; }
         }
     I.sep = 0;
+    I.sep_ok = 0;
     if (best <= 0.0 || sx > MAXS || sy > MAXS) return;
     const double piv = I.psf[am * sx + cm];
     std::vector<double> fy(sy), fx(sx);
@@ -676,6 +679,7 @@ void factor_psf(Instance &I)
         // both directions
         const int S = std::max(sy, sx);
         I.sep = 1;
+        I.sep_ok = 1;
         I.ssq = S;
         I.fy.assign(S, 0.0);
         I.fx.assign(S, 0.0);
@@ -732,10 +736,10 @@ struct Opts {
 // Launch shape of the persistent CG kernel for m systems of px pixels and
 // `tiles` tiles in all, widest local space qmax.
 struct CgLaunch {
-    int qt, two_pass, G, msys, tl, taps;
+    int qt, form, G, msys, tl, taps;
     size_t lds;
 };
-CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles)
+CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles, int tuned_form = -1)
 {
     CgLaunch L;
     L.msys = (m + 7) & ~7;
@@ -743,16 +747,18 @@ CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles)
     L.taps = max_taps_lds(c);
     L.lds = cg_lds_bytes(L.tl, L.taps, L.msys);
     L.qt = lz && qmax > 0 ? QMAX : cg_width(qmax);
-    // Fused iterations (one phase, r and ph recomputed on the halo from three
-    // step j-1 vectors) need one grid barrier per iteration; two-pass iterations
-    // (an elementwise pass, a barrier, a stencil pass that reads ph alone) need two
-    // but read a third of the halo.  Small launches are bound by the barrier
-    // latency, large ones by the halo traffic.  Launches that record CG-Lanczos
-    // data are fused.
+    // Iteration forms.  Small launches keep their own data in the L2 from one
+    // iteration to the next and read other workgroups' cells with coherent
+    // loads (form 0).  In large launches the data streams through the L2 anyway;
+    // there an agent-scope acquire per barrier lets the halo reads of
+    // neighbouring tiles share L2 lines (form 1).  Two-pass iterations (an
+    // elementwise pass, a barrier, a stencil pass that reads ph alone, form 2)
+    // read a third of the halo for a second barrier.  Launches that record
+    // CG-Lanczos data use form 0.
     int mode = c->cg_mode;
     if (const char *e = getenv("RSR_CG_MODE")) mode = atoi(e);   // override for tuning sweeps
-    L.two_pass = lz ? 0 : mode == 2 ? 1 : mode == 1 ? 0 : (px >= (2L << 20) ? 1 : 0);
-    const int bpc = cg_max_blocks_per_cu(L.lds, L.qt, lz, L.two_pass != 0);
+    L.form = lz ? 0 : (mode >= 1 && mode <= 3) ? mode - 1 : tuned_form >= 0 ? tuned_form : (px >= (2L << 20) ? 1 : 0);
+    const int bpc = cg_max_blocks_per_cu(L.lds, L.qt, lz, L.form);
     if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
     int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
     if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
@@ -827,8 +833,14 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         lz = lz || Y->nlz > 0;
         px += Y->n;
     }
-    const CgLaunch L = cg_config(c, m, qmax, lz, px, tiles);
-    const int qt = L.qt, two_pass = L.two_pass, G = L.G, msys = L.msys, tl = L.tl, taps_lds = L.taps;
+    // the autotuned form, when every instance of the launch has the same one
+    int tuned = -2;
+    for (auto *Y : sy) {
+        const int f = c->inst[Y->inst]->form;
+        tuned = tuned == -2 ? f : (tuned == f ? f : -1);
+    }
+    const CgLaunch L = cg_config(c, m, qmax, lz, px, tiles, tuned < 0 ? -1 : tuned);
+    const int qt = L.qt, form = L.form, G = L.G, msys = L.msys, tl = L.tl, taps_lds = L.taps;
     const size_t lds = L.lds;
 
     CGArgs a;
@@ -845,7 +857,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     a.out_rho = out_rho;
     a.out_alpha = out_alpha;
     a.maxit = o.maxit;
-    a.two_pass = two_pass;
+    a.form = form;
     a.G = G;
     a.timeout_ticks = (long long)(c->wall_khz * 1000.0 * c->bar_timeout_s);
     a.tile_lds = tl;
@@ -2474,7 +2486,7 @@ rsr_status rsr_solve_shift_set_async(rsr_ctx *c, const rsr_solve_desc *d, const 
         }
         // the persistent CG launch
         const long tiles = (long)m * a.ntiles;
-        const CgLaunch L = cg_config(c, m, 0, false, (long)m * I.n, tiles);
+        const CgLaunch L = cg_config(c, m, 0, false, (long)m * I.n, tiles, I.form);
         CGArgs g;
         memset(&g, 0, sizeof(g));
         g.nsys = m;
@@ -2490,7 +2502,7 @@ rsr_status rsr_solve_shift_set_async(rsr_ctx *c, const rsr_solve_desc *d, const 
         g.out_rho = out_rho;
         g.out_alpha = out_alpha;
         g.maxit = d->maxit > 0 ? d->maxit : (int)std::min<long>(10 * I.n, 1 << 30);
-        g.two_pass = L.two_pass;
+        g.form = L.form;
         g.G = L.G;
         g.timeout_ticks = (long long)(c->wall_khz * 1000.0 * c->bar_timeout_s);
         g.tile_lds = L.tl;
@@ -2608,28 +2620,39 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
     return guard(c, [&] {
         Instance &I = get_inst(c, ii);
         if (n_vec <= 0) n_vec = 1;
+        if (n_vec > MAXSYS) fail(RSR_E_ARG, "n_vec above the systems of one launch");
         set_device(c);
         std::ostringstream key;
         key << "gfx950 " << I.ny << " " << I.nx << " " << I.sy << " " << I.sx << " " << n_vec;
+        auto apply_choice = [&](int ty, int tx, int gc, int form, int sep) {
+            I.ty = ty;
+            I.tx = tx;
+            c->cg_gmax = gc;
+            I.form = form;
+            I.sep = sep && I.sep_ok ? 1 : 0;
+            upload_inst(c);
+        };
         if (cache_path) {
             std::ifstream f(cache_path);
             std::string line;
             while (std::getline(f, line)) {
                 if (line.rfind(key.str() + " ->", 0) == 0) {
-                    int ty = 0, tx = 0, gc = 0;
-                    if (sscanf(line.c_str() + key.str().size() + 3, "%d %d %d", &ty, &tx, &gc) == 3) {
-                        I.ty = ty;
-                        I.tx = tx;
-                        c->cg_gmax = gc;
-                        upload_inst(c);
+                    int ty = 0, tx = 0, gc = 0, form = -1, sep = 1;
+                    const int got = sscanf(line.c_str() + key.str().size() + 3, "%d %d %d %d %d", &ty, &tx, &gc, &form,
+                                           &sep);
+                    if (got >= 3) {
+                        apply_choice(ty, tx, gc, got >= 4 ? form : -1, got >= 5 ? sep : 1);
                         return;
                     }
                 }
             }
         }
         // Time the hot kernel itself: a bounded persistent-CG solve of n_vec systems
-        // (40 iterations, shifts spread over 1e-3..1e-1) for every tile shape and
-        // grid cap; keep the fastest per iteration.
+        // (shifts spread over 1e-3..1e-1) per candidate, keeping the fastest per
+        // iteration, in stages: tile shape x workgroup cap (fused form); then the
+        // iteration form (fused with coherent loads, fused with an agent acquire,
+        // two-pass); then, for a rank-1 PSF of at most 9 x 9 taps, the direct 2-D
+        // stencil against the banded separable one.
         const long n = I.n;
         DBuf bx;
         bx.ensure(sizeof(double) * n * 2 * n_vec);
@@ -2648,12 +2671,30 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
             Y.bnorm = std::sqrt((double)n);
         }
         alloc_ws(c, sys);
+        const long mvA = c->mv_A, mvE = c->mv_E;
+        const int saved_mode = c->cg_mode;
+        const int iters = 24;
+        Opts o{0.0, iters, RSR_INIT_ZERO, 0, 0, 0, 0, 0.0, 0.0};
+        auto time_it = [&]() {
+            for (auto &Y : sys) {
+                HIPCHK(launch_fill(Y.x, 0.0, n, s));
+                HIPCHK(hipMemcpyAsync(Y.r, Y.b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                Y.q = 0;
+                Y.iters = 0;
+            }
+            std::vector<SysHost *> ptrs;
+            for (auto &Y : sys) ptrs.push_back(&Y);
+            c->last_cg_ms = 0.0;
+            run_cg(c, ptrs, o, s);
+            int its = 0;
+            for (auto &Y : sys) its = std::max(its, Y.iters);
+            return c->last_cg_ms / std::max(1, its);
+        };
         const int cand[][2] = {{16, 16}, {16, 32}, {32, 16}, {32, 32}, {8, 64}, {16, 64}};
         const int gcaps[] = {128, 256, 512, 1024};
         double best = 1e30;
-        int bty = I.ty, btx = I.tx, bg = c->cg_gmax;
-        const long mvA = c->mv_A, mvE = c->mv_E;
-        Opts o{0.0, 40, RSR_INIT_ZERO, 0, 0, 0, 0, 0.0, 0.0};
+        int bty = I.ty, btx = I.tx, bg = c->cg_gmax, bform = 0, bsep = I.sep;
+        c->cg_mode = 1;   // stage 1 in the fused form with coherent loads
         for (auto &cd : cand) {
             const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I), I.sep);
             const int ms8 = (n_vec + 7) & ~7;
@@ -2663,19 +2704,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
             upload_inst(c);
             for (int gc : gcaps) {
                 c->cg_gmax = gc;
-                for (auto &Y : sys) {
-                    HIPCHK(launch_fill(Y.x, 0.0, n, s));
-                    HIPCHK(hipMemcpyAsync(Y.r, Y.b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-                    Y.q = 0;
-                    Y.iters = 0;
-                }
-                std::vector<SysHost *> ptrs;
-                for (auto &Y : sys) ptrs.push_back(&Y);
-                c->last_cg_ms = 0.0;
-                run_cg(c, ptrs, o, s);
-                int its = 0;
-                for (auto &Y : sys) its = std::max(its, Y.iters);
-                const double per = c->last_cg_ms / std::max(1, its);
+                const double per = time_it();
                 if (per < best) {
                     best = per;
                     bty = cd[0];
@@ -2684,16 +2713,41 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
                 }
             }
         }
-        c->mv_A = mvA;
-        c->mv_E = mvE;
-        c->cg_gmax = bg;
         I.ty = bty;
         I.tx = btx;
+        c->cg_gmax = bg;
         upload_inst(c);
+        for (int form = 1; form <= 2; ++form) {
+            c->cg_mode = form + 1;
+            const double per = time_it();
+            if (per < best) {
+                best = per;
+                bform = form;
+            }
+        }
+        c->cg_mode = bform + 1;
+        if (I.sep_ok && I.ssq <= 9) {
+            I.sep = 0;
+            upload_inst(c);
+            const int tl = tile_lds_doubles(bty, btx, eff_sy(I), eff_sx(I), 0);
+            const int ms8 = (n_vec + 7) & ~7;
+            if (cg_lds_bytes(cg_tile_lds(tl, ms8), taps_lds_doubles(eff_sy(I), 0), ms8) <= 160 * 1024) {
+                const double per = time_it();
+                if (per < best) {
+                    best = per;
+                    bsep = 0;
+                }
+            }
+            I.sep = 1;
+        }
+        c->mv_A = mvA;
+        c->mv_E = mvE;
+        c->cg_mode = saved_mode;
+        apply_choice(bty, btx, bg, bform, bsep);
         bx.release();
         if (cache_path) {
             std::ofstream f(cache_path, std::ios::app);
-            f << key.str() << " -> " << bty << " " << btx << " " << bg << "\n";
+            f << key.str() << " -> " << bty << " " << btx << " " << bg << " " << bform << " " << bsep << "\n";
         }
     });
 }

@@ -77,9 +77,11 @@ struct CGArgs {
     double *out_rho;               // [nsys] final recursive r.r
     double *out_alpha;             // [nsys] step still to apply after the launch: x += alpha p (p in pa)
     int maxit;
-    int two_pass;                  // 1: each iteration updates r, ph elementwise, then a grid barrier,
-                                   // then the stencil pass reads ph alone on its window; 0: one fused
-                                   // phase that recomputes r, ph on the halo from r, w, ph of step j-1
+    int form;                      // iteration form: 0 fused (one phase per iteration that recomputes r,
+                                   // ph on the halo from r, w, ph of step j-1; other workgroups' cells
+                                   // read with coherent loads), 1 fused with an agent-scope acquire per
+                                   // barrier and plain loads, 2 two-pass (r, ph updated elementwise, a
+                                   // barrier, then the stencil pass reads ph alone) with that acquire
     int G;                         // workgroups in the grid
     long long timeout_ticks;       // barrier wait limit in s_memrealtime ticks (100 MHz)
     int tile_lds;                  // doubles of dynamic LDS used by the stencil buffers
@@ -100,7 +102,7 @@ constexpr int BAR_GROUPS = 8;                          // barrier groups (one pe
 constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
 int cg_width(int qmax);                           // compiled local-space width for a widest q
 hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s);
-int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, bool two);
+int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form);
 
 struct ApplyJob {              // y = cA K^T K v + cE E v   (or K / K^T alone)
     int inst;

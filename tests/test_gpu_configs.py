@@ -136,3 +136,24 @@ def test_autotuned_solve_meets_the_gates(ctx):
     for l, g in enumerate(gammas):
         assert oracle.true_relres(pr.psf, wh, wv, g, b, B[l]) <= 1e-12
         assert np.linalg.norm(A[l] - B[l]) <= 1e-6 * np.linalg.norm(A[l])
+
+
+def test_autotuned_small_psf_meets_the_gates(ctx):
+    # a 7 x 7 PSF: the autotuner also times the direct 2-D stencil against the
+    # banded separable one; whichever it keeps, the solve meets the gates
+    cfg = synth.config("C1")
+    pr = cfg.problems[0]
+    _, b = oracle.rhs(pr)
+    ctx.set_operators([(32, 32)], [pr.psf])
+    wh, wv = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    g = list(cfg.gammas)
+    ctx.autotune(0, len(g))
+    X = to_dev(np.zeros((len(g), 32, 32)))
+    rc, st = ctx.solve(g, to_dev(b), X, opts=rsr.SolveOptions(tol=1e-12))
+    assert rc == 0
+    Xh = to_host(X)
+    Am, Em = dense.dense_A(pr.psf, 32, 32), dense.dense_E(wh, wv)
+    for l, gg in enumerate(g):
+        xr = dense.cholesky_solve(Am + gg * Em, b)
+        assert np.linalg.norm(Xh[l] - xr) <= 1e-6 * np.linalg.norm(xr), l

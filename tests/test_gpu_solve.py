@@ -122,15 +122,15 @@ def test_fused_and_two_pass_iterations_agree_bitwise(ctx, monkeypatch, recycled)
     _, b = oracle.rhs(pr)
     cfg = synth.Config("ragged", [pr], synth.shift_grid(-4, 1, 6), 3, 12, 5, "batched")
     out = {}
-    for mode in ("1", "2"):
+    for mode in ("1", "2", "3"):
         monkeypatch.setenv("RSR_CG_MODE", mode)
         loop = irn.OuterLoop(ctx, cfg, "recycled" if recycled else "plain")
         loop.b[0] = to_dev(b)
         recs = loop.run(3 if recycled else 1)
         out[mode] = (to_host(loop.X[0]), [r.iters for r in recs])
-    assert out["1"][1] == out["2"][1]
-    assert np.array_equal(out["1"][0], out["2"][0])
+    assert out["1"][1] == out["2"][1] == out["3"][1]
+    assert np.array_equal(out["1"][0], out["2"][0]) and np.array_equal(out["1"][0], out["3"][0])
     wh, wv = (to_host(t) for t in ctx.get_weights(0))
-    X = out["2"][0]
+    X = out["3"][0]
     for l, g in enumerate(cfg.gammas):
         assert oracle.true_relres(pr.psf, wh, wv, g, b, X[l]) <= 1e-8
