@@ -56,8 +56,10 @@ typedef enum {
 
 /* One deblurring instance: image ny x nx and a PSF of odd size sy x sx
  * (host, row-major, centre at (sy/2, sx/2)); the PSF is copied.  A rank-1 PSF
- * is detected and applied separably (row pass then column pass); any other
- * PSF uses the direct 2-D stencil.                                           */
+ * is applied separably (K^T K as banded row and column passes); a PSF that is a
+ * sum of 2..4 separable terms (its SVD's rank, e.g. the Kronecker-sum blur of
+ * the first example in Sec. 8) as a row pass then a column pass per term for K
+ * and again for K^T; any other PSF with the direct 2-D stencil.              */
 typedef struct {
     int ny, nx;
     int sy, sx;

@@ -101,13 +101,15 @@ struct Instance {
     int ny = 0, nx = 0, sy = 1, sx = 1;
     long n = 0;
     std::vector<double> psf;
-    int sep = 0;                       // 1: the banded separable stencil runs (rank-1 PSF)
+    int sep = 0;                       // stencil path: 1 banded separable (rank 1), 2 rank-R sum, 0 direct
     int sep_ok = 0;                    // the PSF is rank 1 (the banded factors exist)
+    int rank = 0;                      // rank of the PSF when 2..RMAX (the rank-R factors exist), else 0
+    std::vector<double> rk;            // rank-R factors, per term [fy reversed][fx reversed][fy][fx]
     int form = -1;                     // tuned persistent-CG iteration form (-1: by launch size)
     int ssq = 0;                       // separable path: zero-padded square size
     std::vector<double> fy, fx;
     std::vector<double> band;          // banded factors of K^T K (separable path), see band_tables
-    DBuf d_fy, d_fx, d_psf, d_wh, d_wv, d_band;
+    DBuf d_fy, d_fx, d_psf, d_wh, d_wv, d_band, d_rk;
     int ty = 16, tx = 16;
     // principal recycle space
     int p = 0;
@@ -142,8 +144,8 @@ struct Instance {
     } eig_pre;
 };
 
-inline int eff_sy(const Instance &I) { return I.sep ? I.ssq : I.sy; }
-inline int eff_sx(const Instance &I) { return I.sep ? I.ssq : I.sx; }
+inline int eff_sy(const Instance &I) { return I.sep == 1 ? I.ssq : I.sy; }
+inline int eff_sx(const Instance &I) { return I.sep == 1 ? I.ssq : I.sx; }
 
 }  // namespace
 
@@ -234,11 +236,13 @@ void upload_inst(rsr_ctx *c)
         d.nty = (I.ny + I.ty - 1) / I.ty;
         d.ntx = (I.nx + I.tx - 1) / I.tx;
         d.sep = I.sep;
+        d.rank = I.sep == 2 ? I.rank : 0;
+        d.rsv = 0;
         d.sy = eff_sy(I);
         d.sx = eff_sx(I);
         d.fy = I.d_fy.as<double>();
         d.fx = I.d_fx.as<double>();
-        d.band = I.d_band.as<double>();
+        d.band = I.sep == 2 ? I.d_rk.as<double>() : I.d_band.as<double>();
         d.psf = I.d_psf.as<double>();
         d.wh = I.d_wh.as<double>();
         d.wv = I.d_wv.as<double>();
@@ -661,6 +665,8 @@ void factor_psf(Instance &I)
         }
     I.sep = 0;
     I.sep_ok = 0;
+    I.rank = 0;
+    I.rk.clear();
     if (best <= 0.0 || sx > MAXS || sy > MAXS) return;
     const double piv = I.psf[am * sx + cm];
     std::vector<double> fy(sy), fx(sx);
@@ -673,6 +679,41 @@ void factor_psf(Instance &I)
             const double d = I.psf[a * sx + c2] - fy[a] * fx[c2];
             err += d * d;
         }
+    if (err > 1e-28 * nrm) {
+        // a sum of R <= RMAX separable terms: h = sum_k s_k u_k v_k^T from the SVD of
+        // the PSF (the singular values past the rank vanish to rounding); each term
+        // is split as fy_k = sqrt(s_k) u_k, fx_k = sqrt(s_k) v_k
+        std::vector<double> sv, Ul;
+        left_svd_jacobi(sy, sx, I.psf.data(), sv, Ul);
+        int R = 0;
+        while (R < (int)sv.size() && sv[R] > 1e-13 * sv[0]) ++R;
+        if (R >= 2 && R <= RMAX) {
+            std::vector<double> f((size_t)R * 2 * (sy + sx));
+            double e2 = 0.0;
+            std::vector<double> rec((size_t)sy * sx, 0.0);
+            for (int k = 0; k < R; ++k) {
+                double *fyr = f.data() + (size_t)k * 2 * (sy + sx), *fxr = fyr + sy, *fyk = fxr + sx, *fxk = fyk + sy;
+                const double sq = std::sqrt(sv[k]);
+                for (int a = 0; a < sy; ++a) fyk[a] = Ul[(size_t)k * sy + a] * sq;
+                for (int c2 = 0; c2 < sx; ++c2) {   // v_k = h^T u_k / s_k
+                    double t = 0.0;
+                    for (int a = 0; a < sy; ++a) t += I.psf[a * sx + c2] * Ul[(size_t)k * sy + a];
+                    fxk[c2] = t / sq;
+                }
+                for (int a = 0; a < sy; ++a) fyr[a] = fyk[sy - 1 - a];
+                for (int c2 = 0; c2 < sx; ++c2) fxr[c2] = fxk[sx - 1 - c2];
+                for (int a = 0; a < sy; ++a)
+                    for (int c2 = 0; c2 < sx; ++c2) rec[(size_t)a * sx + c2] += fyk[a] * fxk[c2];
+            }
+            for (size_t t = 0; t < rec.size(); ++t) e2 += (rec[t] - I.psf[t]) * (rec[t] - I.psf[t]);
+            if (e2 <= 1e-28 * nrm) {
+                I.rank = R;
+                I.rk = f;
+                I.sep = 2;
+            }
+        }
+        return;
+    }
     if (err <= 1e-28 * nrm) {
         // zero-pad both factors symmetrically to one odd square size: zero taps add
         // exact zeros, so the operator is unchanged and one compiled pass width serves
@@ -1615,6 +1656,7 @@ void rsr_destroy(rsr_ctx *c)
     for (auto &p : c->inst) {
         Instance &I = *p;
         I.d_fy.release(); I.d_fx.release(); I.d_psf.release(); I.d_wh.release(); I.d_wv.release(); I.d_band.release();
+        I.d_rk.release();
         I.d_U.release(); I.d_AE.release();
         I.ritz[0].buf.release(); I.ritz[1].buf.release();
         I.gpool.release();
@@ -1651,6 +1693,7 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
         for (auto &p : c->inst) {
             p->d_fy.release(); p->d_fx.release(); p->d_psf.release(); p->d_wh.release(); p->d_wv.release();
             p->d_band.release();
+            p->d_rk.release();
             p->d_U.release(); p->d_AE.release();
             p->ritz[0].buf.release(); p->ritz[1].buf.release();
             p->gpool.release();
@@ -1666,7 +1709,11 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
             default_tile(*I);
             I->d_psf.ensure(sizeof(double) * I->psf.size());
             HIPCHK(hipMemcpy(I->d_psf.p, I->psf.data(), sizeof(double) * I->psf.size(), hipMemcpyHostToDevice));
-            if (I->sep) {
+            if (I->rank) {
+                I->d_rk.ensure(sizeof(double) * I->rk.size());
+                HIPCHK(hipMemcpy(I->d_rk.p, I->rk.data(), sizeof(double) * I->rk.size(), hipMemcpyHostToDevice));
+            }
+            if (I->sep == 1) {
                 I->d_fy.ensure(sizeof(double) * I->ssq);
                 I->d_fx.ensure(sizeof(double) * I->ssq);
                 HIPCHK(hipMemcpy(I->d_fy.p, I->fy.data(), sizeof(double) * I->ssq, hipMemcpyHostToDevice));
@@ -2629,7 +2676,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
             I.tx = tx;
             c->cg_gmax = gc;
             I.form = form;
-            I.sep = sep && I.sep_ok ? 1 : 0;
+            I.sep = (sep == 1 && I.sep_ok) ? 1 : (sep == 2 && I.rank) ? 2 : 0;
             upload_inst(c);
         };
         if (cache_path) {
@@ -2726,7 +2773,8 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
             }
         }
         c->cg_mode = bform + 1;
-        if (I.sep_ok && I.ssq <= 9) {
+        if ((I.sep_ok && I.ssq <= 9) || I.rank) {
+            const int keep = I.sep;
             I.sep = 0;
             upload_inst(c);
             const int tl = tile_lds_doubles(bty, btx, eff_sy(I), eff_sx(I), 0);
@@ -2738,7 +2786,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
                     bsep = 0;
                 }
             }
-            I.sep = 1;
+            I.sep = keep;
         }
         c->mv_A = mvA;
         c->mv_E = mvE;

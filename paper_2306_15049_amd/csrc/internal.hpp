@@ -20,6 +20,7 @@ constexpr int NVP = 4 + 2 * QMAX;   // values per chunk partial: p.w, r.r, r.w, 
 constexpr int MAXSYS = 512;    // systems per persistent launch
 constexpr int RB = 8;          // register-blocked outputs per thread in the stencil passes
 constexpr int MAXS = 31;       // largest separable PSF extent with a compiled path
+constexpr int RMAX = 4;        // largest PSF rank with the rank-R path (terms of the separable sum)
 constexpr int TAPS = 64;       // LDS slots per staged band (4r + 1 <= 61 taps)
 
 // Device view of one instance (image geometry, PSF, weights, tiling).
@@ -28,11 +29,15 @@ struct InstDev {
     int ty, tx;        // tile (outputs per workgroup item), powers of two
     int lty, ltx;      // log2 of ty, tx
     int nty, ntx;      // tiles per dimension
-    int sep;           // 1: rank-1 separable PSF, 0: direct 2-D stencil
-    int sy, sx;        // PSF extent (odd); for sep both equal the zero-padded square size
+    int sep;           // 1: rank-1 separable PSF (banded K^T K), 2: rank-R sum of separable terms,
+                       // 0: direct 2-D stencil
+    int rank;          // terms of the rank-R path (sep 2)
+    int rsv;
+    int sy, sx;        // PSF extent (odd); for sep 1 both equal the zero-padded square size
     const double *fy;  // [sy] column factor (sep)
     const double *fx;  // [sx] row factor (sep)
-    const double *band; // banded factors of K^T K and their end corrections (sep; layout in band_tables)
+    const double *band; // sep 1: banded factors of K^T K and their end corrections (layout in band_tables);
+                        // sep 2: per term [fy reversed][fx reversed][fy][fx]
     const double *psf; // [sy*sx] (direct)
     const double *wh;  // [ny*nx] weights of x[i,j+1]-x[i,j]; 0 in the last column
     const double *wv;  // [ny*nx] weights of x[i+1,j]-x[i,j]; 0 in the last row

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void k_blur(const InstDev *__restrict__ insts,
             for (int c = 0; c < I.sx; ++c) {
                 const int jj = J.op == 3 ? j + cx - c : j - cx + c;
                 if (jj < 0 || jj >= I.nx) continue;
-                const double h = I.sep ? I.fy[a] * I.fx[c] : I.psf[a * I.sx + c];
+                const double h = I.sep == 1 ? I.fy[a] * I.fx[c] : I.psf[a * I.sx + c];
                 s = fma(h, J.v[(long)ii * I.nx + jj], s);
             }
         }
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(NT) void k_lcurve(const InstDev *__restrict__ insts
             for (int c = 0; c < I.sx; ++c) {
                 const int xj = j + cx - c;
                 if (xj < 0 || xj >= I.nx) continue;
-                const double h = I.sep ? I.fy[a] * I.fx[c] : I.psf[a * I.sx + c];
+                const double h = I.sep == 1 ? I.fy[a] * I.fx[c] : I.psf[a * I.sx + c];
                 kx = fma(h, x[(long)yi * I.nx + xj], kx);
             }
         }

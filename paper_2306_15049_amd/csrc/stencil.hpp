@@ -103,7 +103,9 @@ struct Geo {
     int PE;            // pitch of the output accumulator / interior copies
     int off1, offE, offP, offR, offT, total;   // offP/offR: interior copies; offT: a slot per thread
                                                // for discarded stores
+    int offK;          // rank-R path: K v on the tile and its PSF-radius halo
 };
+
 
 __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx, int sep)
 {
@@ -128,8 +130,14 @@ __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx, int sep)
     // the line, which are never stored, so the buffers are padded instead of
     // clamping every window load.  The direct path clamps its reads.
     const int sz0 = g.H0 * g.P0 + RB;
-    const int sz1 = sep ? g.H0 * g.P2 + RB * g.P2 + RB : g.H3 * g.P1;
+    // sep 1: x-band output; sep 2 (rank R): the x-pass output of one term (read
+    // RMAX rows past its end by the strips of the y-pass) and then K v on the
+    // tile plus halo; sep 0: the conv output
+    const int sz1 = sep == 1 ? g.H0 * g.P2 + RB * g.P2 + RB
+                  : sep == 2 ? (g.H0 + RMAX) * g.P1 + RMAX + (g.H3 + RMAX) * g.P1 + RMAX
+                             : g.H3 * g.P1;
     g.off1 = (sz0 + 1) & ~1;
+    g.offK = sep == 2 ? ((g.off1 + (g.H0 + RMAX) * g.P1 + RMAX + 1) & ~1) : g.off1;
     g.offE = (g.off1 + sz1 + 1) & ~1;
     g.offP = (g.offE + ty * g.PE + 1) & ~1;
     g.offR = g.offP + ty * g.PE;
@@ -141,12 +149,21 @@ __host__ __device__ inline Geo make_geo(int ty, int tx, int sy, int sx, int sep)
 // LDS of an instance's separable-path constants, kept apart from the tile
 // buffers: the x band at 0, the y band at TAPS, then the four r x r end
 // corrections Lx, Rx, Ly, Ry (the layout of InstDev::band after its bands).
-__host__ __device__ inline int taps_doubles(int s, int sep) { return sep ? 2 * TAPS + 4 * (s / 2) * (s / 2) : 0; }
+__host__ __device__ inline int taps_doubles(int s, int sep)
+{
+    return sep == 1 ? 2 * TAPS + 4 * (s / 2) * (s / 2) : sep == 2 ? 4 * RMAX * MAXS : 0;
+}
 
 // Copy the bands and end corrections into LDS (read as broadcasts by the
 // passes and the end fixes).
 __device__ __forceinline__ void stage_taps(const InstDev &I, double *taps)
 {
+    if (I.sep == 2) {   // rank-R factors: per term [fy reversed][fx reversed][fy][fx]
+        const int nt = 2 * I.rank * (I.sy + I.sx);
+        const gdbl *src = gp(I.band);
+        for (int k = threadIdx.x; k < nt; k += NT) taps[k] = src[k];
+        return;
+    }
     if (!I.sep) return;
     const int r = I.sx / 2, nb = 4 * r + 1, nc = 4 * r * r;
     const gdbl *src = gp(I.band);
@@ -388,10 +405,82 @@ __device__ __forceinline__ void tile_A_direct(const InstDev &I, const Geo &g, do
     __syncthreads();
 }
 
+// out[l][e] (=|+=) sum_{t < nt} b[t] in[l][e + t] over nlines lines of nout
+// outputs, a runtime tap count (the rank-R path); R outputs per thread, stores
+// past a line's end to the thread's trash slot (see pass_band).
+template <int R>
+__device__ __forceinline__ void pass_line(const double *__restrict__ in, int in_e, int in_l, double *__restrict__ out,
+                                          int out_e, int out_l, int nlines, int nout, const double *__restrict__ b,
+                                          int nt, bool acc, double *__restrict__ trash)
+{
+    const int nstrip = (nout + R - 1) / R;
+    const int total = nlines * nstrip;
+    for (int it = threadIdx.x; it < total; it += NT) {
+        const int l = it % nlines;
+        const int e0 = (it / nlines) * R;
+        const double *src = in + l * in_l + e0 * in_e;
+        double a[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) a[k] = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            const double bt = b[t];
+#pragma unroll
+            for (int k = 0; k < R; ++k) a[k] = fma(bt, src[(t + k) * in_e], a[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int e = e0 + k;
+            double *d = e < nout ? out + l * out_l + e * out_e : trash + threadIdx.x;
+            if (acc) *d += a[k];
+            else *d = a[k];
+        }
+    }
+}
+
+// ebuf += cA K^T K v for a PSF of rank R = I.rank (2..RMAX): h = sum_k fy_k fx_k^T,
+// so K v = sum_k (Ty_k (x) Tx_k) v, each term a row pass then a column pass.
+// K v is formed on the tile and its PSF-radius halo (the conv of the direct
+// path, term by term), masked to the image, scaled by cA, and K^T applied to it
+// on the tile (the corr, term by term) -- 2 (sy + sx) taps per output and term
+// instead of the 2 sy sx of the direct stencil.
+__device__ __forceinline__ void tile_A_rank(const InstDev &I, const Geo &g, double *lds, const double *taps, int y0,
+                                            int x0, double cA)
+{
+    double *buf0 = lds, *xb = lds + g.off1, *kb = lds + g.offK, *ebuf = lds + g.offE, *trash = lds + g.offT;
+    const int sy = I.sy, sx = I.sx, R = I.rank, per = 2 * (sy + sx);
+    const int xrows = g.H3 + sy - 1;   // input rows of the conv column pass
+    for (int k = 0; k < R; ++k) {
+        const double *fyr = taps + k * per, *fxr = fyr + sy;
+        pass_line<4>(buf0 + g.oy * g.P0 + g.ox, 1, g.P0, xb, 1, g.P1, xrows, g.W1, fxr, sx, false, trash);
+        __syncthreads();
+        pass_line<4>(xb, g.P1, 1, kb, g.P1, 1, g.W1, g.H3, fyr, sy, k > 0, trash);
+        __syncthreads();
+    }
+    // K v exists on the image only (zero boundary), then the scale
+    for (int e = threadIdx.x; e < g.H3 * g.W1; e += NT) {
+        const int i = e / g.W1, j = e - i * g.W1;
+        const int gy = y0 - g.ry + i, gx = x0 - g.rx + j;
+        double *d = kb + i * g.P1 + j;
+        *d = (gy >= 0 && gy < I.ny && gx >= 0 && gx < I.nx) ? cA * *d : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < R; ++k) {
+        const double *fy = taps + k * per + sy + sx, *fx = fy + sy;
+        pass_line<4>(kb, 1, g.P1, xb, 1, g.P2, g.H3, I.tx, fx, sx, false, trash);
+        __syncthreads();
+        pass_line<4>(xb, g.P2, 1, ebuf, g.PE, 1, I.tx, I.ty, fy, sy, true, trash);
+        __syncthreads();
+    }
+}
+
 // ebuf += cA K^T K (staged input in buf0, which is overwritten).
 __device__ __forceinline__ void tile_A(const InstDev &I, const Geo &g, double *lds, const double *taps, int y0,
                                        int x0, double cA)
 {
+    if (I.sep == 2) {
+        tile_A_rank(I, g, lds, taps, y0, x0, cA);
+        return;
+    }
     if (!I.sep) {
         tile_A_direct(I, g, lds, y0, x0, cA);
         return;

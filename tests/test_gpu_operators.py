@@ -23,8 +23,14 @@ def _psf(kind, rng):
         v = rng.uniform(0.1, 1, 9)
         h = np.outer(u, v)
         return h / h.sum()
-    if kind == "asym_full":           # rank > 1: direct 2-D path
+    if kind == "asym_full":           # rank 3: the rank-R path (three row + column terms)
         h = rng.uniform(0.1, 1, (5, 3))
+        return h / h.sum()
+    if kind == "rank4":               # a sum of four separable terms, 7 x 9: the rank-R path
+        h = sum(np.outer(rng.uniform(-1, 1, 7), rng.uniform(-1, 1, 9)) for _ in range(4))
+        return h / np.abs(h).sum()
+    if kind == "rank9":               # full rank 9 x 11: beyond the rank-R path, direct 2-D stencil
+        h = rng.uniform(0.1, 1, (9, 11))
         return h / h.sum()
     if kind == "kron2":               # the first example's two-term Kronecker blur, 15 x 25
         return synth.kronecker_sum_psf(synth.EXAMPLE1_TERMS)
@@ -34,7 +40,8 @@ def _psf(kind, rng):
 CASES = [((16, 16), "gauss7", (16, 16)), ((37, 45), "asym_full", (16, 16)), ((64, 80), "gauss15", (32, 32)),
          ((7, 9), "gauss15", (16, 16)), ((33, 31), "delta", (8, 32)), ((100, 70), "asym_sep", (16, 64)),
          ((130, 129), "gauss25", (32, 16)), ((48, 40), "asym_sep", (8, 32)), ((45, 37), "kron2", (16, 16)),
-         ((128, 128), "kron2", (32, 32))]
+         ((128, 128), "kron2", (32, 32)), ((58, 45), "rank4", (16, 32)), ((40, 52), "rank9", (16, 16)),
+         ((97, 61), "kron2", (32, 16))]
 
 
 @pytest.mark.parametrize("shape,kind,tile", CASES)

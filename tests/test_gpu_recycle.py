@@ -358,8 +358,9 @@ def test_uneven_instances_one_launch(ctx):
 
 @pytest.mark.parametrize("mode", [rsr.SEQUENTIAL, rsr.BATCHED])
 def test_example1_kronecker_blur_outer_loop(ctx, mode):
-    # the first example's two-term Kronecker blur (15 x 25 support, direct 2-D
-    # stencil path) at its 128 x 128 size, gamma 1e-8 .. 1e5, relres 1e-6
+    # the first example's two-term Kronecker blur (15 x 25 support, the rank-R
+    # path: a row and a column pass per term) at its 128 x 128 size,
+    # gamma 1e-8 .. 1e5, relres 1e-6
     cfg = synth.config("X1")
     pr = cfg.problems[0]
     _, b = oracle.rhs(pr)

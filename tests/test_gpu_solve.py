@@ -134,3 +134,24 @@ def test_fused_and_two_pass_iterations_agree_bitwise(ctx, monkeypatch, recycled)
     X = out["3"][0]
     for l, g in enumerate(cfg.gammas):
         assert oracle.true_relres(pr.psf, wh, wv, g, b, X[l]) <= 1e-8
+
+
+def test_rank_two_psf_solve_matches_cholesky(ctx):
+    # the first example's two-term Kronecker PSF on a 24 x 20 image (rank-R path)
+    # against dense Cholesky at tight tolerance
+    h = synth.kronecker_sum_psf(synth.EXAMPLE1_TERMS)
+    rng = np.random.default_rng(17)
+    ny, nx = 24, 20
+    b = rng.standard_normal((ny, nx))
+    wh, wv = oracle.weights(rng.standard_normal((ny, nx)) * 0.3)
+    ctx.set_operators([(ny, nx)], [h])
+    ctx.update_weights(0, to_dev(wh), to_dev(wv))
+    g = [1e-3, 0.1, 10.0]
+    X = to_dev(np.zeros((3, ny, nx)))
+    rc, st = ctx.solve(g, to_dev(b), X, opts=rsr.SolveOptions(tol=1e-13))
+    assert rc == 0
+    Am, Em = dense.dense_A(h, ny, nx), dense.dense_E(wh, wv)
+    Xh = to_host(X)
+    for l, gg in enumerate(g):
+        xr = dense.cholesky_solve(Am + gg * Em, b)
+        assert np.linalg.norm(Xh[l] - xr) <= 1e-8 * np.linalg.norm(xr), l
