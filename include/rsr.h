@@ -124,6 +124,13 @@ typedef struct {
     int seed_lanczos;
     int seed_p;
     int seed_n_ritz;
+    /* Two-system seed (eq. widetildeU): seed_second > 0 names a second
+     * representative system (its index in the list, a larger shift than the
+     * first's), solved from zero right after the first with the same capture;
+     * U is then Algorithm 1 of [x_first, x_second, Ritz vectors of each
+     * Krylov space] (seed_p - 2 Ritz vectors shared between the two), and the
+     * remaining systems follow in list order.  0: the one-system seed.       */
+    int seed_second;
 } rsr_solve_desc;
 
 typedef struct {

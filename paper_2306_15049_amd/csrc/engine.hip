@@ -2056,44 +2056,72 @@ rsr_status rsr_set_recycle_space(rsr_ctx *c, int ii, const double *U_raw, long l
     });
 }
 
-// Principal space from the CG-Lanczos data of one solve (Sec. 5.2: the Ritz
-// vectors of the first system's Krylov space seed U).  With CG coefficients
-// alpha_j and beta_j = rho_{j+1}/rho_j, the residuals v_j = r_j / ||r_j|| satisfy
+// Principal space from the CG-Lanczos data of one or two solves (Sec. 5.1: the
+// representative systems' solutions and the Ritz vectors of their Krylov
+// spaces seed U, eq. widetildeU).  With CG coefficients alpha_j and
+// beta_j = rho_{j+1}/rho_j, the residuals v_j = r_j / ||r_j|| satisfy
 // B V = V T + (residual) e_m^T, with T tridiagonal:
 //   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},   T_j,j+1 = -sqrt(beta_j)/alpha_j.
-// The seed_p - 1 eigenvectors of T with the smallest Ritz values give the Ritz
-// vectors V s; with the solve's solution x in front, Algorithm 1 turns them
-// into U (with AU, EU and the blocks).
-// Returns the principal dimension (0 if fewer than two steps were recorded).
-int seed_from_lanczos(rsr_ctx *c, const SysHost &Y, long nlz, int seed_p, hipStream_t s)
+// For each captured system the k eigenvectors of T with the smallest Ritz values
+// give the Ritz vectors V s; the candidates [x_1, .., x_s, V_1, .., V_s] go
+// through Algorithm 1 (at most seed_p columns) to U (with AU, EU, the blocks).
+// Returns the principal dimension (0 if no system recorded two steps).
+int seed_from_lanczos(rsr_ctx *c, const std::vector<const SysHost *> &ys, long nlz, int seed_p, hipStream_t s)
 {
-    const int m = (int)std::min<long>(nlz, (long)Y.lz_its - 1);   // steps with alpha and beta recorded
-    if (m < 2 || seed_p <= 0) return 0;
-    std::vector<double> co((size_t)3 * nlz);
-    read_back(c, {ReadBack{co.data(), c->d_lzc.p, sizeof(double) * co.size()}}, s);
-    const double *al = co.data(), *be = co.data() + nlz, *rho = co.data() + 2 * nlz;
-    std::vector<double> T((size_t)m * m, 0.0);
-    for (int j = 0; j < m; ++j) {
-        if (!(al[j] > 0.0) || !(rho[j] > 0.0)) return 0;
-        T[(size_t)j * m + j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
-        if (j + 1 < m) T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] = -std::sqrt(be[j]) / al[j];
-    }
-    std::vector<double> w, V;
-    sym_eig(m, T.data(), w, V);
-    // candidates [x, Ritz vectors with the k smallest Ritz values]: the first
-    // solve's solution leads, as in the seeded space of Sec. 5.2
-    const int k = std::min(seed_p - 1, m);
-    c->d_lzr.ensure(sizeof(double) * (size_t)(k + 1) * Y.n);
-    double *cand = c->d_lzr.as<double>();
-    HIPCHK(hipMemcpyAsync(cand, Y.x, sizeof(double) * Y.n, hipMemcpyDeviceToDevice, s));
-    if (k > 0) {
+    const int ns = (int)ys.size();
+    if (ns == 0 || seed_p <= 0) return 0;
+    const long n = ys[0]->n;
+    // Ritz vectors per system: the seed_p - ns columns left beside the solutions, shared out
+    const int kall = std::max(0, seed_p - ns);
+    std::vector<std::vector<double>> Qs(ns);
+    std::vector<int> ms(ns, 0), ks(ns, 0);
+    int tot = ns;
+    for (int i = 0; i < ns; ++i) {
+        const SysHost &Y = *ys[i];
+        const int m = (int)std::min<long>(nlz, (long)Y.lz_its - 1);   // steps with alpha and beta recorded
+        if (m < 2) continue;
+        std::vector<double> co((size_t)3 * nlz);
+        read_back(c, {ReadBack{co.data(), Y.lzc, sizeof(double) * co.size()}}, s);
+        const double *al = co.data(), *be = co.data() + nlz, *rho = co.data() + 2 * nlz;
+        bool good = true;
+        std::vector<double> T((size_t)m * m, 0.0);
+        for (int j = 0; j < m && good; ++j) {
+            if (!(al[j] > 0.0) || !(rho[j] > 0.0)) good = false;
+            T[(size_t)j * m + j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+            if (j + 1 < m) T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] = -std::sqrt(be[j]) / al[j];
+        }
+        if (!good) continue;
+        std::vector<double> w, V;
+        sym_eig(m, T.data(), w, V);
+        const int k = std::min(kall / ns + (i < kall % ns ? 1 : 0), m);
         std::vector<double> Q((size_t)m * k);   // column-major m x k: Ritz coefficients over the raw residuals
-        for (int i = 0; i < k; ++i)
-            for (int j = 0; j < m; ++j) Q[(size_t)i * m + j] = V[(size_t)j * m + i] / std::sqrt(rho[j]);
-        combo(c, {ComboJob{c->d_lz.as<double>(), Y.n, m, nullptr, m, cand + Y.n, Y.n, k, 0.0, nullptr, 0, Y.n}},
-              {Q}, s);
+        for (int q = 0; q < k; ++q)
+            for (int j = 0; j < m; ++j) Q[(size_t)q * m + j] = V[(size_t)j * m + q] / std::sqrt(rho[j]);
+        Qs[i] = Q;
+        ms[i] = m;
+        ks[i] = k;
+        tot += k;
     }
-    return set_recycle_space_impl(c, Y.inst, cand, Y.n, k + 1, 0, 0.0, seed_p, 1e10, s);
+    bool any = false;
+    for (int i = 0; i < ns; ++i) any = any || ms[i] > 0;
+    if (!any) return 0;
+    // candidates [x_1 .. x_ns, Ritz vectors of system 1, of system 2, ...]
+    c->d_lzr.ensure(sizeof(double) * (size_t)tot * n);
+    double *cand = c->d_lzr.as<double>();
+    std::vector<CopyJob> cp;
+    for (int i = 0; i < ns; ++i) cp.push_back(CopyJob{ys[i]->x, cand + (size_t)i * n, n});
+    copy_many(c, cp, s);
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
+    size_t col = ns;
+    for (int i = 0; i < ns; ++i) {
+        if (ks[i] == 0) continue;
+        cj.push_back(ComboJob{ys[i]->lz, n, ms[i], nullptr, ms[i], cand + col * n, n, ks[i], 0.0, nullptr, 0, n});
+        qs.push_back(Qs[i]);
+        col += ks[i];
+    }
+    combo(c, cj, qs, s);
+    return set_recycle_space_impl(c, ys[0]->inst, cand, n, tot, 0, 0.0, seed_p, 1e10, s);
 }
 
 // Correction space of the principal-space update (Sec. 5.2, eq. delta times
@@ -2226,33 +2254,54 @@ bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, 
         }
     } else {
         const double *gp = nullptr;
-        // principal-space seeding from the first system's CG-Lanczos data
+        // principal-space seeding from the CG-Lanczos data of the first system and,
+        // when asked, of a second representative system solved right after it
         const bool seed = d->seed_lanczos > 0 && c->inst[sys[0].inst]->p == 0;
+        const int second = (seed && d->seed_second > 0 && d->seed_second < m &&
+                            sys[d->seed_second].inst == sys[0].inst) ? d->seed_second : -1;
+        std::vector<int> order;
+        order.push_back(0);
+        if (second > 0) order.push_back(second);
+        for (int i = 1; i < m; ++i)
+            if (i != second) order.push_back(i);
         if (seed) {
             const long nlz = d->seed_lanczos;
-            c->d_lz.ensure(sizeof(double) * (size_t)nlz * sys[0].n);
-            c->d_lzc.ensure(sizeof(double) * (size_t)3 * nlz);
-            HIPCHK(launch_fill(c->d_lzc.as<double>(), 0.0, 3 * nlz, s));
-            sys[0].lz = c->d_lz.as<double>();
-            sys[0].lzc = c->d_lzc.as<double>();
-            sys[0].nlz = nlz;
+            const int ncap = second > 0 ? 2 : 1;
+            c->d_lz.ensure(sizeof(double) * (size_t)ncap * nlz * sys[0].n);
+            c->d_lzc.ensure(sizeof(double) * (size_t)ncap * 3 * nlz);
+            HIPCHK(launch_fill(c->d_lzc.as<double>(), 0.0, ncap * 3 * nlz, s));
+            for (int t = 0; t < ncap; ++t) {
+                SysHost &Y = sys[t == 0 ? 0 : second];
+                Y.lz = c->d_lz.as<double>() + (size_t)t * nlz * Y.n;
+                Y.lzc = c->d_lzc.as<double>() + (size_t)t * 3 * nlz;
+                Y.nlz = nlz;
+            }
         }
-        for (int i = 0; i < m; ++i) {
+        std::vector<char> solved(m, 0);
+        for (int oi = 0; oi < m; ++oi) {
+            const int i = order[oi];
             std::vector<SysHost *> one{&sys[i]};
-            if (i > 0 && sys[i].inst != sys[i - 1].inst) gp = nullptr;
+            // g^(k,l-1): the correction of the previous system in list order, read in
+            // place from its slot (not written again, nor the slot pool moved, before
+            // this solve ends)
+            gp = (i > 0 && solved[i - 1] && sys[i - 1].inst == sys[i].inst) ? c->inst[sys[i].inst]->gslot(sys[i - 1].slot)
+                                                                             : nullptr;
             solve_group(c, one, o, o.use_prev_shift ? gp : nullptr, s);
+            solved[i] = 1;
             {
                 StageTimer tsc(c, s, 7);
                 store_corrections(c, one, s);
             }
-            if (seed && i == 0 && seed_from_lanczos(c, sys[0], d->seed_lanczos, d->seed_p, s) > 0) {
-                // the remaining systems start from the seeded principal space
-                o.init = RSR_INIT_MR;
-                o.n_ritz = std::min(d->seed_n_ritz, QMAX);
+            const int last_seed = second > 0 ? 1 : 0;
+            if (seed && oi == last_seed) {
+                std::vector<const SysHost *> ys{&sys[0]};
+                if (second > 0) ys.push_back(&sys[second]);
+                if (seed_from_lanczos(c, ys, d->seed_lanczos, d->seed_p, s) > 0) {
+                    // the remaining systems start from the seeded principal space
+                    o.init = RSR_INIT_MR;
+                    o.n_ritz = std::min(d->seed_n_ritz, QMAX);
+                }
             }
-            // g^(k,l-1) for the next shift: read in place from its slot, which is not
-            // written again (nor the slot pool moved) before that shift's solve ends
-            if (o.use_prev_shift) gp = c->inst[sys[i].inst]->gslot(sys[i].slot);
         }
         sync(c, s);
 

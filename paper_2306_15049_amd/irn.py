@@ -54,6 +54,7 @@ class RecycleParams:
     seed_lanczos: int = 0     # k = 0, sequential: CG-Lanczos steps of the first shift that seed U (0: off)
     seed_p: int = 30          # Ritz vectors of those steps kept as the seeded U
     seed_n_ritz: int = 3      # Ritz vectors in the local spaces of the shifts after the seed
+    seed_two: bool = False    # seed from two representative shifts (the first and the one at split_frac)
     correction: int = 5       # k >= 1: Krylov vectors of the correction equation added to U (0: off)
     correction_steps: int = 50    # CG steps on the correction equation
     correction_frac: float = 0.9  # the correction shift l_c = round(frac * M) (1-based)
@@ -172,7 +173,8 @@ class OuterLoop:
                                 gamma_JR=float(g[min(jr, M - 1)]),
                                 seed_lanczos=self.rp.seed_lanczos if seed else 0,
                                 seed_p=min(self.rp.seed_p, self.rp.p) if seed else 0,
-                                seed_n_ritz=self.rp.seed_n_ritz if seed else 0)
+                                seed_n_ritz=self.rp.seed_n_ritz if seed else 0,
+                                seed_second=(split - 1) if (seed and self.rp.seed_two and split > 1) else 0)
 
     def step(self) -> StepRecord:
         import torch

@@ -284,12 +284,53 @@ def test_lanczos_seed_spans_the_smallest_ritz_vectors(ctx):
         assert oracle.true_relres(pr.psf, wh, wv, g, b, to_host(X[l])) <= 1e-8, l
 
 
-def test_seeded_outer_loop_c1(ctx):
-    # the outer loop with a seeded k = 0: every shift still meets the residual gate
+def test_two_system_seed_spans_both_krylov_spaces(ctx):
+    # The seed of eq. widetildeU from two representative systems (the smallest
+    # shift and a larger one): Range(U) holds both solutions (within their
+    # residual bounds) and, for each system, the k smallest Ritz vectors of its
+    # Lanczos basis (the oracle's plain-CG normalised residuals, B projected
+    # directly).
+    import torch
+    n, m, k = 24, 14, 3
+    pr, b, wh, wv = _setup(ctx, n=n)
+    gam = [1e-3, 1e-2, 0.1, 1.0]
+    o = rsr.SolveOptions(tol=1e-8, mode=rsr.SEQUENTIAL, use_prev_shift=True, seed_lanczos=m, seed_p=2 + 2 * k,
+                         seed_n_ritz=2, seed_second=2)
+    X = torch.zeros((len(gam), n, n), dtype=torch.float64, device="cuda")
+    print(f"two-system seed n={n} m={m} k={k}", flush=True)
+    rc, st = ctx.solve(gam, to_dev(b), X, opts=o)
+    assert all(s["converged"] for s in st), st
+    assert st[1]["local_dim"] > 0 and st[3]["local_dim"] > 0       # seeded systems carry Ritz vectors
+    assert st[0]["relres_init"] == 1.0 and st[2]["relres_init"] == 1.0   # the representatives start from zero
+    p, Ahat, Ehat = ctx.recycle_info(0)
+    assert p == 2 + 2 * k
+    U = to_host(ctx.recycle_basis(0)).reshape(p, -1).T
+    np.testing.assert_allclose(U.T @ U, np.eye(p), atol=1e-12)
+    for l in (0, 2):
+        _, ost, R, _ = oracle.cg(pr.psf, wh, wv, gam[l], b, tol=1e-8, record=m)
+        assert ost["iters"] > m and len(R) == m
+        Rf = R.reshape(m, -1)
+        V = Rf.T / np.linalg.norm(Rf, axis=1)
+        Bm = dense.dense_B(pr.psf, wh, wv, gam[l])
+        th, S = np.linalg.eigh(V.T @ Bm @ V)
+        assert th[k] - th[k - 1] > 1e-2 * th[-1]
+        Qy, _ = np.linalg.qr(V @ S[:, :k])
+        assert np.linalg.norm(Qy - U @ (U.T @ Qy), 2) < 1e-8, l
+        xs = dense.cholesky_solve(Bm, b).ravel()
+        bound = 1e-8 * np.linalg.norm(b) / np.linalg.eigvalsh(Bm)[0]
+        assert np.linalg.norm(xs - U @ (U.T @ xs)) <= 1.01 * bound, l
+    for l, g in enumerate(gam):
+        assert oracle.true_relres(pr.psf, wh, wv, g, b, to_host(X[l])) <= 1e-8, l
+
+
+@pytest.mark.parametrize("two", [False, True])
+def test_seeded_outer_loop_c1(ctx, two):
+    # the outer loop with a seeded k = 0 (one representative system, or two):
+    # every shift still meets the residual gate
     cfg = synth.config("C1")
     pr = cfg.problems[0]
     _, b = oracle.rhs(pr)
-    rp = irn.RecycleParams(p=cfg.p, seed_lanczos=40, seed_p=10, seed_n_ritz=3)
+    rp = irn.RecycleParams(p=cfg.p, seed_lanczos=40, seed_p=10, seed_n_ritz=3, seed_two=two)
     loop = irn.OuterLoop(ctx, cfg, "recycled", rp=rp, mode=rsr.SEQUENTIAL)
     loop.b[0] = to_dev(b)
     for k in range(3):
