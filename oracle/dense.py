@@ -15,6 +15,10 @@ computes, written with NumPy/SciPy primitives and no blocking or fusion:
   * deflated CG with a local space W (the CG form of the shift-specific
     recycling of Section 4.2; deflation as in Saad, Yeung, Erhel and
     Guyomarc'h, SIAM J. Sci. Comput. 21 (2000));
+  * recycled MINRES with a local space (Sections 2.3 and 4.2: Lanczos on
+    (I - K K^T) B and the augmented least-squares problem eq. minShift, the
+    correction of eq. xFinal), with the Krylov basis kept explicitly and the
+    small problem solved by a library least-squares routine;
   * the exact gradient of L = sum_l ||x_l - x_true||^2 with respect to the
     shifts and the weights by implicit differentiation.
 """
@@ -230,3 +234,82 @@ def exact_gradients(h, wh, wv, gammas, b, x_true):
         dwv -= g * lv * xv
         X.append(x)
     return np.array(X), dg, dwh, dwv
+
+
+# ------------------------------------------------------ recycled MINRES --
+def local_recycle_basis(Bm, Ut):
+    """eq. localU: B Ut = K R with K^T K = I, and U = Ut R^{-1} (so B U = K)."""
+    K, R = np.linalg.qr(Bm @ Ut)
+    U = np.linalg.solve(R.T, Ut.T).T
+    return U, K
+
+
+def recycled_minres(Bm, b, x0, Ut=None, tol=1e-8, maxit=10000, record=False):
+    """Recycled MINRES for B x = b from x0 with local recycle space Range(Ut).
+
+    Follows Sections 2.3 and 4.2 step by step: r = b - B x0; B Ut = K R (QR),
+    U = Ut R^{-1}; Lanczos with (I - K K^T) B from v_1 = (I - K K^T) r / xi,
+    xi = ||(I - K K^T) r||, giving (I - K K^T) B V_m = V_{m+1} T_m (T_m of size
+    (m+1) x m); y minimises ||T_m y - xi e_1|| (least squares, numpy.linalg.lstsq);
+    z = K^T r - K^T B V_m y; the correction g = V_m y + U z; x = x0 + g.  The
+    iteration stops when the least-squares residual, which equals ||b - B x||,
+    falls to tol ||b||.  V_m is kept explicitly (no short recurrences) and fully
+    re-orthogonalised against K and the previous Lanczos vectors, so that the
+    reference does not depend on the finite-precision behaviour of the three-term
+    recurrence.  Returns x, the iterations m, and (record) the residual norms
+    ||b - B x_j|| of every iterate.
+    """
+    bb = b.ravel()
+    n = bb.size
+    x0 = x0.ravel()
+    r = bb - Bm @ x0
+    bn = np.linalg.norm(bb)
+    if Ut is None or Ut.shape[1] == 0:
+        U = np.zeros((n, 0))
+        K = np.zeros((n, 0))
+    else:
+        U, K = local_recycle_basis(Bm, Ut)
+    rp = r - K @ (K.T @ r)
+    xi = np.linalg.norm(rp)
+    hist = []
+
+    def assemble(m, V, T):
+        if m == 0:
+            Vy = np.zeros(n)
+        else:
+            rhs = np.zeros(m + 1)
+            rhs[0] = xi
+            y = np.linalg.lstsq(T[:m + 1, :m], rhs, rcond=None)[0]
+            Vy = V[:, :m] @ y
+        z = K.T @ r - K.T @ (Bm @ Vy)
+        return x0 + Vy + U @ z
+
+    x = assemble(0, None, None)
+    if record:
+        hist.append(np.linalg.norm(bb - Bm @ x))
+    if xi <= tol * bn or xi == 0.0:
+        return x, 0, hist
+    V = np.zeros((n, min(maxit, n) + 1))
+    T = np.zeros((min(maxit, n) + 1, min(maxit, n)))
+    V[:, 0] = rp / xi
+    m = 0
+    while m < min(maxit, n):
+        w = Bm @ V[:, m]
+        w = w - K @ (K.T @ w)
+        for _ in range(2):     # full re-orthogonalisation (classical Gram-Schmidt, twice)
+            h = V[:, :m + 1].T @ w
+            w = w - V[:, :m + 1] @ h
+            T[:m + 1, m] += h
+            w = w - K @ (K.T @ w)
+        beta = np.linalg.norm(w)
+        T[m + 1, m] = beta
+        m += 1
+        x = assemble(m, V, T)
+        res = np.linalg.norm(bb - Bm @ x)
+        if record:
+            hist.append(res)
+        if res <= tol * bn or beta <= 1e-14 * np.linalg.norm(T[:m + 1, :m]):
+            break
+        V[:, m] = w / beta
+    return x, m, hist
+

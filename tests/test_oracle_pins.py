@@ -504,3 +504,68 @@ def test_exact_gradients_against_autograd_and_finite_differences():
     fd = (L(gammas, wh + eps * vh, wv + eps * vv) - L(gammas, wh - eps * vh, wv - eps * vv)) / (2 * eps)
     an = np.sum(dwh * vh) + np.sum(dwv * vv)
     assert abs(fd - an) <= 1e-5 * abs(an)
+
+
+# ---------------------------------------------------------- recycled MINRES --
+def _spd_case(seed=8, n=14):
+    pr = synth.make_problem(seed, n, n, 1.5, 7, 5)
+    _, b = oracle.rhs(pr)
+    wh, wv = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    Bm = dense.dense_B(pr.psf, wh, wv, 0.05)
+    return Bm, b.ravel()
+
+
+def test_recycled_minres_without_local_space_is_krylov_minimal_residual():
+    # with no local space the iterate x_m minimises ||b - B x|| over x0 + K_m(B, r0):
+    # brute force over an orthonormal basis of the explicit Krylov space
+    Bm, b = _spd_case()
+    rng = np.random.default_rng(1)
+    x0 = 0.1 * rng.standard_normal(b.size)
+    r0 = b - Bm @ x0
+    for m in (1, 2, 5, 9):
+        x, it, _ = dense.recycled_minres(Bm, b, x0, None, tol=0.0, maxit=m)
+        assert it == m
+        Kr = np.stack([np.linalg.matrix_power(Bm, j) @ r0 for j in range(m)], axis=1)
+        Q, _ = np.linalg.qr(Kr)
+        c = np.linalg.lstsq(Bm @ Q, r0, rcond=None)[0]
+        xb = x0 + Q @ c
+        assert np.linalg.norm(x - xb) <= 1e-8 * np.linalg.norm(xb), m
+
+
+def test_recycled_minres_minimises_over_local_space_plus_krylov():
+    # with a local space Range(Ut) the iterate minimises ||r - B g|| over
+    # g in Range(U) + K_m((I - K K^T) B, (I - K K^T) r) (eq. minShift)
+    Bm, b = _spd_case()
+    rng = np.random.default_rng(2)
+    x0 = np.zeros(b.size)
+    Ut = rng.standard_normal((b.size, 3))
+    U, K = dense.local_recycle_basis(Bm, Ut)
+    np.testing.assert_allclose(K.T @ K, np.eye(3), atol=1e-12)
+    np.testing.assert_allclose(Bm @ U, K, atol=1e-10 * np.abs(Bm).max())
+    P = np.eye(b.size) - K @ K.T
+    v = P @ b
+    for m in (1, 3, 6):
+        x, it, _ = dense.recycled_minres(Bm, b, x0, Ut, tol=0.0, maxit=m)
+        Kr = np.stack([np.linalg.matrix_power(P @ Bm, j) @ v for j in range(m)], axis=1)
+        S, _ = np.linalg.qr(np.concatenate([U, Kr], axis=1))
+        c = np.linalg.lstsq(Bm @ S, b, rcond=None)[0]
+        xb = S @ c
+        assert np.linalg.norm(x - xb) <= 1e-7 * np.linalg.norm(xb), m
+        # the Krylov vectors are orthogonal to K, and the LS residual is the true one
+        assert np.linalg.norm(b - Bm @ x) <= np.linalg.norm(b - Bm @ xb) * (1 + 1e-8)
+
+
+def test_recycled_minres_residuals_monotone_and_exact_space():
+    Bm, b = _spd_case()
+    xs = dense.cholesky_solve(Bm, b).ravel()
+    rng = np.random.default_rng(3)
+    # monotone residual norms, convergence to the Cholesky solution
+    x, it, hist = dense.recycled_minres(Bm, b, np.zeros(b.size), rng.standard_normal((b.size, 2)), tol=1e-12,
+                                        record=True)
+    assert all(hist[j + 1] <= hist[j] * (1 + 1e-12) for j in range(len(hist) - 1))
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    # the needed correction inside the local space: no Lanczos step at all
+    x0 = rng.standard_normal(b.size)
+    Ut = np.stack([xs - x0, rng.standard_normal(b.size)], axis=1)
+    x, it, _ = dense.recycled_minres(Bm, b, x0, Ut, tol=1e-10)
+    assert it == 0 and np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
