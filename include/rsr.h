@@ -131,7 +131,23 @@ typedef struct {
      * Krylov space] (seed_p - 2 Ritz vectors shared between the two), and the
      * remaining systems follow in list order.  0: the one-system seed.       */
     int seed_second;
+    /* Krylov solver of each system after its initial guess (RSR_SOLVER_*).
+     * RSR_SOLVER_MINRES is recycled MINRES (Sec. 2.3 with the local space of
+     * Sec. 4.2): the local space Ut (the columns of W above) gives
+     * B Ut = K R with orthonormal K (eq. localU), Lanczos runs with
+     * (I - K K^T) B from (I - K K^T) r0, the short-recurrence MINRES iterate
+     * y_m minimises the projected residual (eq. minShift), and
+     * x = x0 + y_m + U K^T (r0 - B y_m) with U = Ut R^{-1} (eq. xFinal).
+     * It runs on the host-driven batched path (one launch per step for all
+     * active systems), in either mode; it does not record CG-Lanczos data
+     * (seed_lanczos > 0 with MINRES: RSR_E_ARG).  `iters` counts Lanczos steps.
+     * Other values: RSR_E_ARG.                                                */
+    int solver;
 } rsr_solve_desc;
+
+/* Krylov solver of a system (rsr_solve_desc.solver). */
+enum { RSR_SOLVER_CG = 0,      /* deflated CG (Algorithm 4), persistent launch  */
+       RSR_SOLVER_MINRES = 1   /* recycled MINRES (Sec. 2.3, Sec. 4.2)          */ };
 
 typedef struct {
     int iters;                /* CG iterations                                 */

@@ -772,6 +772,7 @@ struct Opts {
     int use_prev_shift;
     int split_I;
     double gJL, gJR;
+    int solver = RSR_SOLVER_CG;
 };
 
 // Launch shape of the persistent CG kernel for m systems of px pixels and
@@ -1074,6 +1075,291 @@ void local_correction(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
         qs.push_back(y);
         cj.push_back(ComboJob{Y.Z, Y.n, Y.q, nullptr, Y.q, Y.r, Y.n, 1, 1.0, nullptr, 0, Y.n});
         qs.push_back(ny);
+    }
+    combo(c, cj, qs, s);
+}
+
+// ------------------------------------------------------ recycled MINRES --
+// The local recycle space of Sec. 4.2 (eq. localU): B Ut = K R with K^T K = I
+// and U = Ut R^{-1}.  W holds Ut and Z = B Ut on entry; R comes from a Cholesky
+// factorisation of Z^T Z on the host (a column whose pivot falls below 1e-12 of
+// its diagonal is dropped), and K, U overwrite Z, W column by column
+// (K_j = (Z_j - sum_{i<j} K_i R_ij) / R_jj, the same for U).
+void minres_local_basis(rsr_ctx *c, std::vector<SysHost *> &sy, hipStream_t s)
+{
+    std::vector<GramJob> gj;
+    std::vector<SysHost *> act;
+    for (auto *Y : sy)
+        if (Y->q > 0) {
+            gj.push_back(GramJob{Y->Z, Y->n, Y->q, Y->Z, Y->n, Y->q, Y->n, nullptr, 0});
+            act.push_back(Y);
+        }
+    if (act.empty()) return;
+    auto G = gram(c, gj, s);
+    std::vector<std::vector<double>> Rs(act.size());
+    std::vector<std::vector<char>> keep(act.size());
+    int qmax = 0;
+    for (size_t k = 0; k < act.size(); ++k) {
+        const int q = act[k]->q;
+        qmax = std::max(qmax, q);
+        std::vector<double> &R = Rs[k];   // row-major q x q, upper triangular, G = R^T R
+        R.assign((size_t)q * q, 0.0);
+        keep[k].assign(q, 1);
+        const std::vector<double> &Gm = G[k];
+        for (int j = 0; j < q; ++j) {
+            double d = Gm[(size_t)j * q + j];
+            for (int i = 0; i < j; ++i) d -= R[(size_t)i * q + j] * R[(size_t)i * q + j];
+            if (!(d > 1e-12 * Gm[(size_t)j * q + j]) || !std::isfinite(d)) {
+                keep[k][j] = 0;   // numerically inside the span of the earlier columns
+                continue;
+            }
+            R[(size_t)j * q + j] = std::sqrt(d);
+            for (int l = j + 1; l < q; ++l) {
+                double t = Gm[(size_t)j * q + l];
+                for (int i = 0; i < j; ++i) t -= R[(size_t)i * q + j] * R[(size_t)i * q + l];
+                R[(size_t)j * q + l] = t / R[(size_t)j * q + j];
+            }
+        }
+    }
+    for (int j = 0; j < qmax; ++j) {
+        std::vector<ComboJob> cj;
+        std::vector<std::vector<double>> qs;
+        for (size_t k = 0; k < act.size(); ++k) {
+            SysHost &Y = *act[k];
+            const int q = Y.q;
+            if (j >= q) continue;
+            const std::vector<double> &R = Rs[k];
+            const long n = Y.n;
+            const double rjj = keep[k][j] ? R[(size_t)j * q + j] : 0.0;
+            const double sc = rjj > 0.0 ? 1.0 / rjj : 0.0;
+            std::vector<double> co(std::max(j, 1), 0.0);
+            for (int i = 0; i < j; ++i) co[i] = keep[k][i] ? -R[(size_t)i * q + j] * sc : 0.0;
+            // Z_j <- (Z_j - K_{<j} R_{<j,j}) / R_jj and W_j likewise (in place)
+            cj.push_back(ComboJob{Y.Z, n, j, nullptr, std::max(j, 1), Y.Z + (size_t)j * n, n, 1, sc, nullptr, 0, n});
+            qs.push_back(co);
+            cj.push_back(ComboJob{Y.W, n, j, nullptr, std::max(j, 1), Y.W + (size_t)j * n, n, 1, sc, nullptr, 0, n});
+            qs.push_back(co);
+        }
+        combo(c, cj, qs, s);
+    }
+}
+
+// Recycled MINRES (Sec. 2.3, Sec. 4.2) from the current (x, r = b - B x) of each
+// listed system with its local space (K, U in Z, W): Lanczos with
+// (I - K K^T) B from v_1 = (I - K K^T) r / xi; the tridiagonal's QR by Givens
+// rotations gives the iterate y_m of min ||T_m y - xi e_1|| by short recurrences
+// (direction vectors d_j); the residual norm |eta| of that problem is the true
+// one of the augmented problem eq. minShift, whose U-part is solved exactly at
+// the end: x = x + y_m + U K^T (r - B y_m) (eq. xFinal).  Every step is a
+// batched launch over the active systems (operator applications, products,
+// combinations); the scalar recurrences run on the host.
+void run_minres(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s)
+{
+    const int m = (int)sy.size();
+    if (m == 0) return;
+    struct St {
+        double beta, eta, g_prev, g_cur, s_prev, s_cur;
+        double *vp, *vc, *d2, *d1;   // v_{j-1}, v_j, d_{j-2}, d_{j-1}
+        bool active;
+        int its;
+    };
+    std::vector<St> st(m);
+    // buffers: v in p0/p1 (adjacent), w in w, y_m in r1, directions in pa / w1, scratch rt
+    {
+        // r_p = (I - K K^T) r, then xi
+        std::vector<GramJob> gj;
+        for (auto *Y : sy)
+            if (Y->q > 0) gj.push_back(GramJob{Y->Z, Y->n, Y->q, Y->r, Y->n, 1, Y->n, nullptr, 0});
+        auto kr = gram(c, gj, s);
+        std::vector<ComboJob> cj;
+        std::vector<std::vector<double>> qs;
+        size_t kk = 0;
+        for (auto *Y : sy) {
+            std::vector<double> co(std::max(Y->q, 1), 0.0);
+            if (Y->q > 0) {
+                for (int i = 0; i < Y->q; ++i) co[i] = -kr[kk][i];
+                ++kk;
+            }
+            cj.push_back(ComboJob{Y->Z, Y->n, Y->q, nullptr, std::max(Y->q, 1), Y->p0, Y->n, 1, 0.0, Y->r, Y->n, Y->n});
+            qs.push_back(co);
+            // y_m = 0 and both directions 0 (combinations of no columns)
+            cj.push_back(ComboJob{nullptr, Y->n, 0, nullptr, 0, Y->r1, Y->n, 1, 0.0, nullptr, 0, Y->n});
+            qs.push_back({});
+            cj.push_back(ComboJob{nullptr, Y->n, 0, nullptr, 0, Y->pa, Y->n, 1, 0.0, nullptr, 0, Y->n});
+            qs.push_back({});
+            cj.push_back(ComboJob{nullptr, Y->n, 0, nullptr, 0, Y->w1, Y->n, 1, 0.0, nullptr, 0, Y->n});
+            qs.push_back({});
+            cj.push_back(ComboJob{nullptr, Y->n, 0, nullptr, 0, Y->p1, Y->n, 1, 0.0, nullptr, 0, Y->n});
+            qs.push_back({});
+        }
+        combo(c, cj, qs, s);
+        std::vector<const double *> v;
+        std::vector<long> n;
+        for (auto *Y : sy) {
+            v.push_back(Y->p0);
+            n.push_back(Y->n);
+        }
+        auto xi = norms(c, v, n, s);
+        cj.clear();
+        qs.clear();
+        for (int i = 0; i < m; ++i) {
+            SysHost &Y = *sy[i];
+            St &t = st[i];
+            t = St{xi[i], xi[i], 1.0, 1.0, 0.0, 0.0, Y.p1, Y.p0, Y.w1, Y.pa, true, 0};
+            if (!std::isfinite(xi[i])) fail(RSR_E_NONFINITE, "non-finite residual");
+            if (!(xi[i] > o.tol * Y.bnorm)) {
+                t.active = false;   // the local space alone meets the tolerance
+                Y.status = 1;
+                continue;
+            }
+            cj.push_back(ComboJob{nullptr, Y.n, 0, nullptr, 0, Y.p0, Y.n, 1, 1.0 / xi[i], nullptr, 0, Y.n});
+            qs.push_back({});
+        }
+        combo(c, cj, qs, s);
+    }
+    for (int it = 0;; ++it) {
+        std::vector<int> act;
+        for (int i = 0; i < m; ++i)
+            if (st[i].active) act.push_back(i);
+        if (act.empty()) break;
+        // w = B v_j
+        std::vector<ApplyJob> aj;
+        for (int i : act) {
+            SysHost &Y = *sy[i];
+            aj.push_back(ApplyJob{Y.inst, 0, 1.0, Y.gamma, st[i].vc, Y.w});
+            Y.mvA++;
+            Y.mvE++;
+        }
+        apply_jobs(c, aj, s);
+        // K^T w and alpha = v_j^T w
+        std::vector<GramJob> gj;
+        for (int i : act) {
+            SysHost &Y = *sy[i];
+            gj.push_back(GramJob{st[i].vc, Y.n, 1, Y.w, Y.n, 1, Y.n, nullptr, 0});
+            if (Y.q > 0) gj.push_back(GramJob{Y.Z, Y.n, Y.q, Y.w, Y.n, 1, Y.n, nullptr, 0});
+        }
+        auto h = gram(c, gj, s);
+        std::vector<double> alpha(m, 0.0);
+        {
+            // w <- w - K c, then w <- w - alpha v_j - beta v_{j-1} (v_{j-1}, v_j are p0, p1)
+            std::vector<ComboJob> c1, c2;
+            std::vector<std::vector<double>> q1, q2;
+            size_t k = 0;
+            for (int i : act) {
+                SysHost &Y = *sy[i];
+                alpha[i] = h[k++][0];
+                if (Y.q > 0) {
+                    std::vector<double> co(Y.q);
+                    for (int j = 0; j < Y.q; ++j) co[j] = -h[k][j];
+                    ++k;
+                    c1.push_back(ComboJob{Y.Z, Y.n, Y.q, nullptr, Y.q, Y.w, Y.n, 1, 1.0, nullptr, 0, Y.n});
+                    q1.push_back(co);
+                }
+                const bool cur_is_p1 = st[i].vc == Y.p1;
+                std::vector<double> co{cur_is_p1 ? -st[i].beta : -alpha[i], cur_is_p1 ? -alpha[i] : -st[i].beta};
+                if (it == 0) co[cur_is_p1 ? 0 : 1] = 0.0;   // v_0 = 0
+                c2.push_back(ComboJob{Y.p0, Y.n, 2, nullptr, 2, Y.w, Y.n, 1, 1.0, nullptr, 0, Y.n});
+                q2.push_back(co);
+            }
+            combo(c, c1, q1, s);
+            combo(c, c2, q2, s);
+        }
+        std::vector<const double *> v;
+        std::vector<long> nn;
+        for (int i : act) {
+            v.push_back(sy[i]->w);
+            nn.push_back(sy[i]->n);
+        }
+        auto bnew = norms(c, v, nn, s);
+        // Givens on the new column of the tridiagonal; direction and iterate updates
+        std::vector<ComboJob> ca, cb, cc;
+        std::vector<std::vector<double>> qa, qb, qc;
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int i = act[a];
+            SysHost &Y = *sy[i];
+            St &t = st[i];
+            const double al = alpha[i], bn = bnew[a];
+            const double delta = t.g_cur * al - t.g_prev * t.s_cur * t.beta;
+            const double rho1 = std::hypot(delta, bn);
+            const double rho2 = t.s_cur * al + t.g_prev * t.g_cur * t.beta;
+            const double rho3 = t.s_prev * t.beta;
+            if (!std::isfinite(rho1) || !std::isfinite(al)) fail(RSR_E_NONFINITE, "non-finite value in MINRES");
+            if (!(rho1 > 0.0)) {   // exact breakdown: the current iterate solves the problem
+                t.active = false;
+                Y.status = 1;
+                continue;
+            }
+            const double gn = delta / rho1, sn = bn / rho1;
+            // d_j = (v_j - rho3 d_{j-2} - rho2 d_{j-1}) / rho1 into d_{j-2}'s buffer;
+            // v_{j+1} = w / beta_{j+1} into v_{j-1}'s buffer
+            ca.push_back(ComboJob{t.vc, Y.n, 1, nullptr, 1, t.d2, Y.n, 1, -rho3 / rho1, nullptr, 0, Y.n});
+            qa.push_back({1.0 / rho1});
+            if (bn > 0.0) {
+                ca.push_back(ComboJob{Y.w, Y.n, 1, nullptr, 1, t.vp, Y.n, 1, 0.0, nullptr, 0, Y.n});
+                qa.push_back({1.0 / bn});
+            }
+            cb.push_back(ComboJob{t.d1, Y.n, 1, nullptr, 1, t.d2, Y.n, 1, 1.0, nullptr, 0, Y.n});
+            qb.push_back({-rho2 / rho1});
+            cc.push_back(ComboJob{t.d2, Y.n, 1, nullptr, 1, Y.r1, Y.n, 1, 1.0, nullptr, 0, Y.n});
+            qc.push_back({gn * t.eta});
+            t.eta = -sn * t.eta;
+            t.its++;
+            std::swap(t.d2, t.d1);   // d_j becomes d_{j-1}
+            std::swap(t.vp, t.vc);   // v_{j+1} becomes v_j
+            t.g_prev = t.g_cur;
+            t.g_cur = gn;
+            t.s_prev = t.s_cur;
+            t.s_cur = sn;
+            t.beta = bn;
+            if (std::fabs(t.eta) <= o.tol * Y.bnorm || bn == 0.0) {
+                t.active = false;
+                Y.status = 1;
+            } else if (t.its >= o.maxit) {
+                t.active = false;
+                Y.status = 2;
+            }
+        }
+        combo(c, ca, qa, s);
+        combo(c, cb, qb, s);
+        combo(c, cc, qc, s);
+    }
+    // x += y_m + U K^T (r - B y_m)
+    std::vector<ApplyJob> aj;
+    std::vector<ComboJob> cj;
+    std::vector<std::vector<double>> qs;
+    for (int i = 0; i < m; ++i) {
+        SysHost &Y = *sy[i];
+        Y.iters += st[i].its;
+        if (Y.q > 0) {
+            aj.push_back(ApplyJob{Y.inst, 0, 1.0, Y.gamma, Y.r1, Y.rt});
+            Y.mvA++;
+            Y.mvE++;
+        }
+        cj.push_back(ComboJob{Y.r1, Y.n, 1, nullptr, 1, Y.x, Y.n, 1, 1.0, nullptr, 0, Y.n});
+        qs.push_back({1.0});
+    }
+    apply_jobs(c, aj, s);
+    combo(c, cj, qs, s);
+    cj.clear();
+    qs.clear();
+    std::vector<GramJob> gj;
+    std::vector<SysHost *> kq;
+    for (int i = 0; i < m; ++i) {
+        SysHost &Y = *sy[i];
+        if (Y.q == 0) continue;
+        cj.push_back(ComboJob{Y.rt, Y.n, 1, nullptr, 1, Y.rt, Y.n, 1, 0.0, Y.r, Y.n, Y.n});
+        qs.push_back({-1.0});
+        gj.push_back(GramJob{Y.Z, Y.n, Y.q, Y.rt, Y.n, 1, Y.n, nullptr, 0});
+        kq.push_back(&Y);
+    }
+    combo(c, cj, qs, s);
+    auto kz = gram(c, gj, s);
+    cj.clear();
+    qs.clear();
+    for (size_t k = 0; k < kq.size(); ++k) {
+        SysHost &Y = *kq[k];
+        cj.push_back(ComboJob{Y.W, Y.n, Y.q, nullptr, Y.q, Y.x, Y.n, 1, 1.0, nullptr, 0, Y.n});
+        qs.push_back(kz[k]);
     }
     combo(c, cj, qs, s);
 }
@@ -1459,7 +1745,8 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     tm.reset(new StageTimer(c, s, 3));
     build_local(c, sy, o, g_prev_shift, s);
     tm.reset(new StageTimer(c, s, 4));
-    local_correction(c, sy, s);
+    if (o.solver == RSR_SOLVER_MINRES) minres_local_basis(c, sy, s);
+    else local_correction(c, sy, s);
     tm.reset();
 
     // CG with true-residual acceptance
@@ -1477,7 +1764,8 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
     for (int attempt = 0; attempt <= 3 && !todo.empty(); ++attempt) {
         Opts oo = o;
         tm.reset(new StageTimer(c, s, 5));
-        run_cg(c, todo, oo, s);
+        if (o.solver == RSR_SOLVER_MINRES) run_minres(c, todo, oo, s);
+        else run_cg(c, todo, oo, s);
         tm.reset(new StageTimer(c, s, 6));
         // true residual rt = b - B x
         std::vector<ApplyJob> tj;
@@ -1514,7 +1802,7 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
                 again.push_back(&Y);
             }
         }
-        if (!again.empty()) local_correction(c, again, s);
+        if (!again.empty() && o.solver != RSR_SOLVER_MINRES) local_correction(c, again, s);
         todo.swap(again);
     }
 }
@@ -2237,7 +2525,9 @@ bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, 
     HIPCHK(launch_fill(r0sq_dev, 0.0, m, s));
     for (int i = 0; i < m; ++i) sys[i].r0sq_dev = r0sq_dev + i;
     Opts o{d->tol, d->maxit, d->init, d->n_ritz, d->use_prev_k, d->use_prev_shift, d->split_I, d->gamma_JL,
-           d->gamma_JR};
+           d->gamma_JR, d->solver};
+    if (d->solver != RSR_SOLVER_CG && d->solver != RSR_SOLVER_MINRES) fail(RSR_E_ARG, "unknown solver");
+    if (d->solver == RSR_SOLVER_MINRES && d->seed_lanczos > 0) fail(RSR_E_ARG, "seeding records CG-Lanczos data");
     c->last_cg_ms = 0.0;
     c->last_launches = 0;
     c->last_items = 0;
@@ -2401,7 +2691,7 @@ AsyncLayout async_layout(rsr_ctx *c, const rsr_solve_desc *d)
         fail(RSR_E_ARG, "the device-only solve takes 1.." + std::to_string(ASYNC_MAXSYS) + " systems");
     if (!(d->tol > 0.0)) fail(RSR_E_ARG, "tol must be positive");
     if ((d->init != RSR_INIT_ZERO && d->init != RSR_INIT_GIVEN) || d->n_ritz != 0 || d->use_prev_k ||
-        d->use_prev_shift || d->seed_lanczos)
+        d->use_prev_shift || d->seed_lanczos || d->solver != RSR_SOLVER_CG)
         fail(RSR_E_ARG, "the device-only solve is plain CG (init ZERO or GIVEN, no local spaces, no seeding)");
     const int ii = d->inst[0];
     Instance &I = get_inst(c, ii);

@@ -82,22 +82,29 @@ class OuterLoop:
     def __init__(self, ctx: rsr.Context, cfg: synth.Config, method: str, rp: Optional[RecycleParams] = None,
                  tol: Optional[float] = None, tiles: Optional[Dict[int, tuple]] = None,
                  mode: Optional[int] = None, weight_rule: str = "irn", edge_p: float = 2.0,
-                 lcurve: bool = False, stop_repeats: int = 3, workspace: bool = False):
+                 lcurve: bool = False, stop_repeats: int = 3, workspace: bool = False, solver: str = "cg"):
         """weight_rule: "irn" (W = ((D x)^2 + beta)^(-1/2)) or "edge" (the cumulative edge
         rule of Sec. 2.1 with exponent edge_p).  lcurve: choose the shift that drives the
         next weights at the L-curve corner after every step; otherwise the middle shift.
         The loop reports `stopped` once that choice has repeated stop_repeats times.
         workspace: solve on a caller workspace (sized and reserved with
-        rsr_workspace_size before each solve), so the solves allocate nothing."""
+        rsr_workspace_size before each solve), so the solves allocate nothing.
+        solver: "cg" (deflated CG) or "minres" (recycled MINRES, Sec. 2.3 and 4.2; the
+        paper's inner solver) for every system of every method."""
         import torch
         if method not in ("recycled", "plain", "warm"):
             raise ValueError("method must be 'recycled', 'plain' or 'warm'")
         if weight_rule not in ("irn", "edge"):
             raise ValueError("weight_rule must be 'irn' or 'edge'")
+        if solver not in ("cg", "minres"):
+            raise ValueError("solver must be 'cg' or 'minres'")
         self.ctx = ctx
         self.cfg = cfg
         self.method = method
         self.rp = rp or RecycleParams(p=cfg.p, q=cfg.q)
+        self.solver = rsr.SOLVER_MINRES if solver == "minres" else rsr.SOLVER_CG
+        if self.solver == rsr.SOLVER_MINRES and self.rp.seed_lanczos > 0:
+            raise ValueError("the principal-space seed records CG-Lanczos data: use solver='cg'")
         self.tol = cfg.tol if tol is None else tol
         self.M = len(cfg.gammas)
         self.mode = mode if mode is not None else (rsr.SEQUENTIAL if cfg.mode == "sequential" else rsr.BATCHED)
@@ -158,10 +165,10 @@ class OuterLoop:
         M = self.M
         g = self.cfg.gammas
         if self.method == "plain":
-            return rsr.SolveOptions(tol=self.tol, mode=self.mode, init=rsr.INIT_ZERO)
+            return rsr.SolveOptions(tol=self.tol, mode=self.mode, init=rsr.INIT_ZERO, solver=self.solver)
         if self.method == "warm":
             return rsr.SolveOptions(tol=self.tol, mode=self.mode,
-                                    init=rsr.INIT_GIVEN if self.k > 0 else rsr.INIT_ZERO)
+                                    init=rsr.INIT_GIVEN if self.k > 0 else rsr.INIT_ZERO, solver=self.solver)
         split = int(math.ceil(self.rp.split_frac * M))
         jl = max(1, min(split, M)) - 1            # J_L = split (1-based)
         jr = max(split, M - 2)                    # J_R = M - 1 (1-based)
@@ -174,7 +181,8 @@ class OuterLoop:
                                 seed_lanczos=self.rp.seed_lanczos if seed else 0,
                                 seed_p=min(self.rp.seed_p, self.rp.p) if seed else 0,
                                 seed_n_ritz=self.rp.seed_n_ritz if seed else 0,
-                                seed_second=(split - 1) if (seed and self.rp.seed_two and split > 1) else 0)
+                                seed_second=(split - 1) if (seed and self.rp.seed_two and split > 1) else 0,
+                                solver=self.solver)
 
     def step(self) -> StepRecord:
         import torch

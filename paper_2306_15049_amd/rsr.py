@@ -32,6 +32,7 @@ EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_se
            "rsr_workspace_size", "rsr_allocation_count", "rsr_solve_shift_set_noalloc",
            "rsr_solve_shift_set_async"]
 WS_SOLVE, WS_ADJOINT, WS_DEVICE = 0, 1, 2
+SOLVER_CG, SOLVER_MINRES = 0, 1
 
 
 class RsrError(RuntimeError):
@@ -53,7 +54,7 @@ class SolveDesc(ctypes.Structure):
                 ("use_prev_shift", ctypes.c_int), ("split_I", ctypes.c_int), ("gamma_JL", ctypes.c_double),
                 ("gamma_JR", ctypes.c_double), ("ld_b", ctypes.c_long), ("ld_x", ctypes.c_long),
                 ("seed_lanczos", ctypes.c_int), ("seed_p", ctypes.c_int), ("seed_n_ritz", ctypes.c_int),
-                ("seed_second", ctypes.c_int)]
+                ("seed_second", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 class ShiftStats(ctypes.Structure):
@@ -160,6 +161,7 @@ class SolveOptions:
     seed_p: int = 0            # Ritz vectors kept as the seeded principal space
     seed_n_ritz: int = 0       # Ritz vectors in the local spaces of the systems after the seed
     seed_second: int = 0       # index of a second representative system of the seed (0: one-system seed)
+    solver: int = 0            # SOLVER_CG (deflated CG) or SOLVER_MINRES (recycled MINRES)
 
 
 _open_contexts: "weakref.WeakSet" = weakref.WeakSet()
@@ -306,7 +308,7 @@ class Context:
         d = SolveDesc(m, ia, ga, sa, float(o.tol), int(o.maxit), int(o.mode), int(o.init), int(o.n_ritz),
                       int(bool(o.use_prev_k)), int(bool(o.use_prev_shift)), int(o.split_I), float(o.gamma_JL),
                       float(o.gamma_JR), int(ld_b), int(ld_x), int(o.seed_lanczos), int(o.seed_p),
-                      int(o.seed_n_ritz), int(o.seed_second))
+                      int(o.seed_n_ritz), int(o.seed_second), int(o.solver))
         return d, (ia, ga, sa)
 
     def solve(self, gammas: Sequence[float], b, X, inst: Optional[Sequence[int]] = None, slots=None,
