@@ -186,6 +186,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="only the recycled method and plain per-shift CG")
     ap.add_argument("--no-plain", action="store_true", help="only the recycled method (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-minres", action="store_true", help="skip the recycled-vs-plain MINRES block")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^2 and 64-instance blocks")
     ap.add_argument("--large-only", default=None, help="comma list of large workloads to run (C3, C4)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -218,9 +219,9 @@ def main():
     log = sys.stderr if args.verbose else None
     ctx = rsr.Context(0)
 
-    def run_variant(cfg, method, mode, steps, warmup, label, tiles_cache):
+    def run_variant(cfg, method, mode, steps, warmup, label, tiles_cache, solver="cg"):
         """warmup untimed steps, then `steps` timed steps as runs of the configured loop."""
-        loop = irn.OuterLoop(ctx, cfg, method, mode=mode)
+        loop = irn.OuterLoop(ctx, cfg, method, mode=mode, solver=solver)
         n_inst = len(cfg.problems)
         key = (cfg.name, mode)
         if not args.no_autotune:
@@ -281,6 +282,18 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(cfg, pl["matvecs_A_per_step"])
 
+    # the paper's own inner solver: recycled MINRES against MINRES from zero, in
+    # the unit the paper counts (matrix-vector products per outer step)
+    minres = None
+    if not args.no_minres:
+        mr = run_variant(cfg, "recycled", rsr.BATCHED, args.steps, args.warmup, "recycled MINRES", tiles_cache,
+                         solver="minres")[0]
+        mp = run_variant(cfg, "plain", rsr.BATCHED, args.steps, args.warmup, "plain MINRES", tiles_cache,
+                         solver="minres")[0]
+        minres = {"recycled_batched": mr, "plain_batched": mp,
+                  "matvec_ratio_plain_over_recycled": mp["matvecs_A_per_step"] / mr["matvecs_A_per_step"],
+                  "speedup_vs_plain_minres": mp["ms_per_step"] / mr["ms_per_step"]}
+
     large = {}
     if not args.no_large:
         names = args.large_only.split(",") if args.large_only else ["C3", "C4"]
@@ -311,6 +324,7 @@ def main():
         "matvec_ratio_plain_over_recycled": pl["matvecs_A_per_step"] / head["matvecs_A_per_step"],
         "roofline": roof,
         "cpu_baseline": cpu,
+        "minres": minres,
         "large": large,
         "paper_context": "paper reports matvec savings 'on the order of 10,000' (MINRES, tol 1e-6, MATLAB); no timings",
     }
