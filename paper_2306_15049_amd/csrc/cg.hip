@@ -346,7 +346,7 @@ constexpr int NBE = 2;   // interior pixels per thread whose local-basis loads a
 // launches, whose data does not stay in the L2 anyway); FORM 2: two-pass
 // iterations with the same acquire and plain loads.
 template <int QT, bool LZ, int FORM>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_cg(CGArgs A)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FORM == 0 && QT > 0) ? 1 : 2))) void k_cg(CGArgs A)
 {
     constexpr bool TWO = FORM == 2, ACQ = FORM != 0;
     // a window cell written by another workgroup in the previous phase

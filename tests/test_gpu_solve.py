@@ -122,6 +122,9 @@ def test_fused_and_two_pass_iterations_agree_bitwise(ctx, monkeypatch, recycled)
     _, b = oracle.rhs(pr)
     cfg = synth.Config("ragged", [pr], synth.shift_grid(-4, 1, 6), 3, 12, 5, "batched")
     out = {}
+    # one grid size for every form (the forms may differ in occupancy, and the
+    # chunking of the reductions follows the grid)
+    monkeypatch.setenv("RSR_CG_MAX_BLOCKS", "256")
     for mode in ("1", "2", "3"):
         monkeypatch.setenv("RSR_CG_MODE", mode)
         loop = irn.OuterLoop(ctx, cfg, "recycled" if recycled else "plain")
