@@ -172,6 +172,39 @@ const char *rsr_version(void);
  * E_0 = D^T D, and recycle spaces cleared).                                  */
 rsr_status rsr_set_operators(rsr_ctx *ctx, int n_inst, const rsr_instance *inst, void *stream);
 
+/* One tomography instance (Sec. 8, second example: parallel-beam CT, A = K^T K
+ * with K a discrete Radon transform scaled to unit Frobenius norm).  Pixel
+ * (i, j) of the ny x nx image (row i from the top) is the unit square centred
+ * at x = j - (nx-1)/2, y = (ny-1)/2 - i; ray (a, k) is the line
+ *     x cos(theta_a) + y sin(theta_a) = (k - (n_det-1)/2) * spacing,
+ * and K[(a, k), (i, j)] = (length of ray (a, k) inside pixel (i, j)) / ||C||_F,
+ * C being the matrix of those lengths.  Sinograms are angle-major
+ * [n_angles][n_det].  angles_host: host [n_angles], radians, copied.         */
+typedef struct {
+    int ny, nx;
+    int n_angles, n_det;
+    double spacing;
+    const double *angles_host;
+} rsr_ct_instance;
+
+/* Set tomography instances (replaces any earlier set, deblurring or
+ * tomography; weights reset to W = I; recycle spaces cleared).  K is applied
+ * ray by ray and K^T pixel by pixel with the same exact ray-pixel clipping, so
+ * K^T is the transpose of K to rounding; B v = (K^T K + gamma E) v is two
+ * launches for a batch of vectors.  On such a context:
+ *  - rsr_apply with RSR_OP_K maps images [ny*nx] to sinograms
+ *    [n_angles*n_det] and RSR_OP_KT back; with n_vec > 1, ld must be at least
+ *    the larger of the two sizes for these two (ny*nx for the others);
+ *  - rsr_solve_shift_set, rsr_adjoint and rsr_set_recycle_space work as for
+ *    deblurring instances, with CG run host-driven and batched (one launch per
+ *    step for all active systems, Algorithm 4's deflation included) instead
+ *    of the persistent kernel;
+ *  - rsr_autotune, rsr_set_tile, rsr_lcurve, rsr_correction_space,
+ *    principal-space seeding and rsr_solve_shift_set_async return RSR_E_ARG.
+ * Non-positive sizes or spacing, non-finite angles, or a geometry where no ray
+ * meets the image: RSR_E_ARG.  Synchronises the stream.                       */
+rsr_status rsr_set_ct_operators(rsr_ctx *ctx, int n_inst, const rsr_ct_instance *inst, void *stream);
+
 /* Replace W_k of one instance: device w_h, w_v [ny*nx]; w_h[i,j] weights
  * x[i,j+1]-x[i,j] (ignored in the last column), w_v[i,j] weights
  * x[i+1,j]-x[i,j] (ignored in the last row).  Invalidates the instance's

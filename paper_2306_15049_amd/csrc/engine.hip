@@ -111,6 +111,11 @@ struct Instance {
     std::vector<double> band;          // banded factors of K^T K (separable path), see band_tables
     DBuf d_fy, d_fx, d_psf, d_wh, d_wv, d_band, d_rk;
     int ty = 16, tx = 16;
+    // tomography instance (rsr_set_ct_operators): projector geometry and scale
+    bool ct = false;
+    int na = 0, nd = 0;
+    double spacing = 1.0, ct_scale = 1.0;
+    DBuf d_cs;                         // [na][2] cos, sin
     // principal recycle space
     int p = 0;
     DBuf d_U, d_AE;   // U: p columns; AE: [AU | EU], 2p columns; stride n
@@ -206,6 +211,11 @@ struct rsr_ctx {
     int last_launches = 0;
     long last_items = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // tomography instances: every instance of the context is one (rsr_set_ct_operators)
+    bool ct = false;
+    DBuf d_ctinst;                     // CtDev[n_inst]
+    std::vector<CtDev> h_ct;
+    DBuf d_ct_sino;                    // sinogram scratch of K^T K applications
 };
 
 namespace {
@@ -249,6 +259,16 @@ void upload_inst(rsr_ctx *c)
     }
     c->d_inst.ensure(sizeof(InstDev) * std::max<size_t>(1, c->h_inst.size()));
     HIPCHK(hipMemcpy(c->d_inst.p, c->h_inst.data(), sizeof(InstDev) * c->h_inst.size(), hipMemcpyHostToDevice));
+    if (c->ct) {
+        c->h_ct.resize(c->inst.size());
+        for (size_t i = 0; i < c->inst.size(); ++i) {
+            Instance &I = *c->inst[i];
+            c->h_ct[i] = CtDev{I.ny, I.nx, I.na, I.nd, I.spacing, I.ct_scale, I.d_cs.as<double>(),
+                               I.d_wh.as<double>(), I.d_wv.as<double>()};
+        }
+        c->d_ctinst.ensure(sizeof(CtDev) * c->h_ct.size());
+        HIPCHK(hipMemcpy(c->d_ctinst.p, c->h_ct.data(), sizeof(CtDev) * c->h_ct.size(), hipMemcpyHostToDevice));
+    }
 }
 
 // Upload a host array through the job buffer region starting at byte offset.
@@ -423,6 +443,41 @@ size_t apply_lds_bytes(const Instance &I)
 }
 
 // ----------------------------------------------------------- operators --
+// Projector applications of tomography instances: one forward launch (the
+// sinograms K v of the jobs that need them, into scratch or the output) and
+// one backward launch (K^T of those sinograms, plus cE E v) for the batch.
+void ct_apply_jobs(rsr_ctx *c, const std::vector<ApplyJob> &jobs, hipStream_t s)
+{
+    if (jobs.empty()) return;
+    WsMark mark(c);
+    size_t need = 0;
+    for (const auto &j : jobs) {
+        const Instance &I = *c->inst[j.inst];
+        if (j.op == 0 && j.cA != 0.0) need += (size_t)I.na * I.nd;
+    }
+    double *sino = (double *)dscratch(c, c->d_ct_sino, sizeof(double) * std::max<size_t>(1, need));
+    std::vector<CtJob> cj;
+    size_t o = 0;
+    int max_rays = 1;
+    long max_px = 1;
+    for (const auto &j : jobs) {
+        const Instance &I = *c->inst[j.inst];
+        CtJob t{j.inst, j.op, j.cA, j.cE, j.v, j.y, nullptr};
+        if (j.op == 0 && j.cA != 0.0) {
+            t.sino = sino + o;
+            o += (size_t)I.na * I.nd;
+        }
+        cj.push_back(t);
+        max_rays = std::max(max_rays, I.na * I.nd);
+        max_px = std::max(max_px, I.n);
+        if (j.op == 0 && j.cA != 0.0) c->mv_A++;
+        if (j.op == 0 && j.cE != 0.0) c->mv_E++;
+    }
+    CtJob *dj = stage(c, cj, s);
+    HIPCHK(launch_ct_fwd(c->d_ctinst.as<CtDev>(), dj, (int)cj.size(), max_rays, s));
+    HIPCHK(launch_ct_back(c->d_ctinst.as<CtDev>(), dj, (int)cj.size(), max_px, s));
+}
+
 // y_j = cA A v_j + cE E v_j for nvec vectors of one instance.
 void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ldv, double *y, long ldy,
               int nvec, hipStream_t s, DBuf *jobbuf = nullptr)
@@ -431,6 +486,10 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
     Instance &I = get_inst(c, ii);
     std::vector<ApplyJob> jobs(nvec);
     for (int j = 0; j < nvec; ++j) jobs[j] = ApplyJob{ii, 0, cA, cE, v + j * ldv, y + j * ldy};
+    if (I.ct) {
+        ct_apply_jobs(c, jobs, s);
+        return;
+    }
     ApplyJob *dj = jobbuf ? upload(c, *jobbuf, jobs, s) : stage(c, jobs, s);
     const size_t lds = apply_lds_bytes(I);
     HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, nvec, lds, s));
@@ -440,6 +499,10 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
 
 void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
 {
+    if (c->ct) {
+        ct_apply_jobs(c, jobs, s);
+        return;
+    }
     WsMark mark(c);
     // group by instance (one launch per instance)
     std::map<int, std::vector<ApplyJob>> by;
@@ -1364,6 +1427,142 @@ void run_minres(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream
     combo(c, cj, qs, s);
 }
 
+// ------------------------------------------------- host-driven deflated CG --
+// Deflated CG (Algorithm 4 in CG form) for systems whose operator has no
+// persistent kernel (tomography instances): every step is one batched launch
+// over the active systems (operator application, products, combinations) with
+// the scalars formed on the host.  From x, r with W^T r = 0 (the Galerkin
+// correction), p_0 = r_0 - W mu_0 and per step
+//   w = B p, alpha = r.r / p.w, x += alpha p, r -= alpha w,
+//   beta = r'.r' / r.r, mu = G^+ Z^T r', p = r' + beta p - W mu,
+// with mu = G^+ Z^T r (G = W^T Z, Z = B W).
+void run_cg_host(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s)
+{
+    const int m = (int)sy.size();
+    if (m == 0) return;
+    struct St {
+        double rr;
+        bool active;
+        int its;
+    };
+    std::vector<St> st(m);
+    // r.r and Z^T r of the current residuals: the columns of one product
+    auto rz = [&](const std::vector<int> &idx) {
+        std::vector<GramJob> gj;
+        for (int i : idx) {
+            SysHost &Y = *sy[i];
+            gj.push_back(GramJob{Y.r, Y.n, 1, Y.r, Y.n, 1, Y.n, nullptr, 0});
+            if (Y.q > 0) gj.push_back(GramJob{Y.Z, Y.n, Y.q, Y.r, Y.n, 1, Y.n, nullptr, 0});
+        }
+        return gram(c, gj, s);
+    };
+    // p = beta p + r, then p -= W mu
+    auto new_dir = [&](const std::vector<int> &idx, const std::vector<double> &beta,
+                       const std::vector<std::vector<double>> &zr) {
+        std::vector<ComboJob> c1, c2;
+        std::vector<std::vector<double>> q1, q2;
+        for (size_t a = 0; a < idx.size(); ++a) {
+            SysHost &Y = *sy[idx[a]];
+            c1.push_back(ComboJob{Y.r, Y.n, 1, nullptr, 1, Y.pa, Y.n, 1, beta[a], nullptr, 0, Y.n});
+            q1.push_back({1.0});
+            if (Y.q > 0) {
+                std::vector<double> mu(Y.q);
+                matvec(Y.q, Y.q, Y.Ginv.data(), zr[a].data(), mu.data());
+                for (double &v : mu) v = -v;
+                c2.push_back(ComboJob{Y.W, Y.n, Y.q, nullptr, Y.q, Y.pa, Y.n, 1, 1.0, nullptr, 0, Y.n});
+                q2.push_back(mu);
+            }
+        }
+        combo(c, c1, q1, s);
+        combo(c, c2, q2, s);
+    };
+    {
+        std::vector<int> all(m);
+        for (int i = 0; i < m; ++i) all[i] = i;
+        auto h = rz(all);
+        std::vector<int> go;
+        std::vector<double> beta;
+        std::vector<std::vector<double>> zr;
+        size_t k = 0;
+        for (int i = 0; i < m; ++i) {
+            SysHost &Y = *sy[i];
+            const double rr = h[k++][0];
+            std::vector<double> z;
+            if (Y.q > 0) z = h[k++];
+            if (!std::isfinite(rr)) fail(RSR_E_NONFINITE, "non-finite residual");
+            st[i] = St{rr, true, 0};
+            if (!(std::sqrt(rr) > o.tol * Y.bnorm)) {
+                st[i].active = false;
+                Y.status = 1;
+                continue;
+            }
+            go.push_back(i);
+            beta.push_back(0.0);
+            zr.push_back(z);
+        }
+        new_dir(go, beta, zr);
+    }
+    for (;;) {
+        std::vector<int> act;
+        for (int i = 0; i < m; ++i)
+            if (st[i].active) act.push_back(i);
+        if (act.empty()) break;
+        std::vector<ApplyJob> aj;
+        std::vector<GramJob> gj;
+        for (int i : act) {
+            SysHost &Y = *sy[i];
+            aj.push_back(ApplyJob{Y.inst, 0, 1.0, Y.gamma, Y.pa, Y.w});
+            Y.mvA++;
+            Y.mvE++;
+            gj.push_back(GramJob{Y.pa, Y.n, 1, Y.w, Y.n, 1, Y.n, nullptr, 0});
+        }
+        apply_jobs(c, aj, s);
+        auto pw = gram(c, gj, s);
+        std::vector<ComboJob> cj;
+        std::vector<std::vector<double>> qs;
+        for (size_t a = 0; a < act.size(); ++a) {
+            SysHost &Y = *sy[act[a]];
+            const double d = pw[a][0];
+            if (!std::isfinite(d)) fail(RSR_E_NONFINITE, "non-finite value in CG");
+            if (!(d > 0.0)) fail(RSR_E_NOT_SPD, "shifted matrix not SPD (p^T B p <= 0)");
+            const double alpha = st[act[a]].rr / d;
+            cj.push_back(ComboJob{Y.pa, Y.n, 1, nullptr, 1, Y.x, Y.n, 1, 1.0, nullptr, 0, Y.n});
+            qs.push_back({alpha});
+            cj.push_back(ComboJob{Y.w, Y.n, 1, nullptr, 1, Y.r, Y.n, 1, 1.0, nullptr, 0, Y.n});
+            qs.push_back({-alpha});
+        }
+        combo(c, cj, qs, s);
+        auto h = rz(act);
+        std::vector<int> go;
+        std::vector<double> beta;
+        std::vector<std::vector<double>> zr;
+        size_t k = 0;
+        for (int i : act) {
+            SysHost &Y = *sy[i];
+            St &t = st[i];
+            const double rr = h[k++][0];
+            std::vector<double> z;
+            if (Y.q > 0) z = h[k++];
+            if (!std::isfinite(rr)) fail(RSR_E_NONFINITE, "non-finite value in CG");
+            t.its++;
+            if (std::sqrt(rr) <= o.tol * Y.bnorm) {
+                t.active = false;
+                Y.status = 1;
+            } else if (t.its >= o.maxit) {
+                t.active = false;
+                Y.status = 2;
+            } else {
+                go.push_back(i);
+                beta.push_back(rr / t.rr);
+                zr.push_back(z);
+            }
+            t.rr = rr;
+        }
+        new_dir(go, beta, zr);
+    }
+    for (int i = 0; i < m; ++i) sy[i]->iters += st[i].its;
+}
+
 // Builds W, Z, G^+ for each system (Algorithms 2-4 in CG form).
 void build_local(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const double *g_prev_shift,
                  hipStream_t s)
@@ -1765,6 +1964,7 @@ void solve_group(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, const do
         Opts oo = o;
         tm.reset(new StageTimer(c, s, 5));
         if (o.solver == RSR_SOLVER_MINRES) run_minres(c, todo, oo, s);
+        else if (c->ct) run_cg_host(c, todo, oo, s);
         else run_cg(c, todo, oo, s);
         tm.reset(new StageTimer(c, s, 6));
         // true residual rt = b - B x
@@ -1985,8 +2185,10 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
             p->d_U.release(); p->d_AE.release();
             p->ritz[0].buf.release(); p->ritz[1].buf.release();
             p->gpool.release();
+            p->d_cs.release();
         }
         c->inst.clear();
+        c->ct = false;
         for (int i = 0; i < n_inst; ++i) {
             std::unique_ptr<Instance> I(new Instance());
             const rsr_instance &r = in[i];
@@ -2014,6 +2216,90 @@ rsr_status rsr_set_operators(rsr_ctx *c, int n_inst, const rsr_instance *in, voi
             HIPCHK(launch_copy_weights(nullptr, nullptr, I->d_wh.as<double>(), I->d_wv.as<double>(), I->ny, I->nx, s));
             c->inst.push_back(std::move(I));
         }
+        upload_inst(c);
+        sync(c, s);
+    });
+}
+
+rsr_status rsr_set_ct_operators(rsr_ctx *c, int n_inst, const rsr_ct_instance *in, void *stream)
+{
+    return guard(c, [&] {
+        if (n_inst <= 0 || !in) fail(RSR_E_ARG, "n_inst must be positive");
+        for (int i = 0; i < n_inst; ++i) {
+            const rsr_ct_instance &r = in[i];
+            const std::string who = "tomography instance " + std::to_string(i);
+            if (r.ny <= 0 || r.nx <= 0 || r.n_angles <= 0 || r.n_det <= 0 || !r.angles_host)
+                fail(RSR_E_ARG, who + ": sizes must be positive and the angles given");
+            if (!(r.spacing > 0.0) || !std::isfinite(r.spacing)) fail(RSR_E_ARG, who + ": spacing must be positive");
+            if ((long)r.ny * r.nx >= (1L << 31) || (long)r.n_angles * r.n_det >= (1L << 31))
+                fail(RSR_E_ARG, who + ": image or sinogram of 2^31 values or more");
+            for (int a = 0; a < r.n_angles; ++a)
+                if (!std::isfinite(r.angles_host[a])) fail(RSR_E_ARG, who + ": angles must be finite");
+        }
+        set_device(c);
+        hipStream_t s = S(stream);
+        sync(c, s);
+        for (auto &p : c->inst) {
+            p->d_fy.release(); p->d_fx.release(); p->d_psf.release(); p->d_wh.release(); p->d_wv.release();
+            p->d_band.release();
+            p->d_rk.release();
+            p->d_U.release(); p->d_AE.release();
+            p->ritz[0].buf.release(); p->ritz[1].buf.release();
+            p->gpool.release();
+            p->d_cs.release();
+        }
+        c->inst.clear();
+        c->ct = true;
+        for (int i = 0; i < n_inst; ++i) {
+            std::unique_ptr<Instance> I(new Instance());
+            const rsr_ct_instance &r = in[i];
+            I->ny = r.ny; I->nx = r.nx;
+            I->n = (long)r.ny * r.nx;
+            I->ct = true;
+            I->na = r.n_angles;
+            I->nd = r.n_det;
+            I->spacing = r.spacing;
+            // a 1 x 1 PSF keeps the stencil descriptor well formed; no stencil
+            // kernel runs on a tomography instance
+            I->psf.assign(1, 1.0);
+            I->sy = I->sx = 1;
+            default_tile(*I);
+            I->d_psf.ensure(sizeof(double));
+            HIPCHK(hipMemcpy(I->d_psf.p, I->psf.data(), sizeof(double), hipMemcpyHostToDevice));
+            std::vector<double> cs(2 * (size_t)r.n_angles);
+            for (int a = 0; a < r.n_angles; ++a) {
+                cs[2 * a] = std::cos(r.angles_host[a]);
+                cs[2 * a + 1] = std::sin(r.angles_host[a]);
+            }
+            I->d_cs.ensure(sizeof(double) * cs.size());
+            HIPCHK(hipMemcpy(I->d_cs.p, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice));
+            I->d_wh.ensure(sizeof(double) * I->n);
+            I->d_wv.ensure(sizeof(double) * I->n);
+            HIPCHK(launch_copy_weights(nullptr, nullptr, I->d_wh.as<double>(), I->d_wv.as<double>(), I->ny, I->nx, s));
+            c->inst.push_back(std::move(I));
+        }
+        upload_inst(c);
+        // ||C||_F: per-ray sums of squared intersection lengths, summed on the host in ray order
+        size_t rays = 0;
+        for (auto &p : c->inst) rays = std::max(rays, (size_t)p->na * p->nd);
+        DBuf sq;
+        sq.ensure(sizeof(double) * rays);
+        std::vector<double> h(rays);
+        for (int i = 0; i < n_inst; ++i) {
+            Instance &I = *c->inst[i];
+            std::vector<CtJob> one{CtJob{i, 5, 0.0, 0.0, nullptr, nullptr, sq.as<double>()}};
+            CtJob *dj = upload(c, c->d_jobs, one, s);
+            HIPCHK(launch_ct_fwd(c->d_ctinst.as<CtDev>(), dj, 1, I.na * I.nd, s));
+            read_back(c, {ReadBack{h.data(), sq.p, sizeof(double) * I.na * I.nd}}, s);
+            double f = 0.0;
+            for (long k = 0; k < (long)I.na * I.nd; ++k) f += h[k];
+            if (!(f > 0.0)) {
+                sq.release();
+                fail(RSR_E_ARG, "tomography instance " + std::to_string(i) + ": no ray meets the image");
+            }
+            I.ct_scale = 1.0 / std::sqrt(f);
+        }
+        sq.release();
         upload_inst(c);
         sync(c, s);
     });
@@ -2093,6 +2379,7 @@ rsr_status rsr_lcurve(rsr_ctx *c, int ii, int m, const double *gammas, const dou
 {
     return guard(c, [&] {
         Instance &I = get_inst(c, ii);
+        if (I.ct) fail(RSR_E_ARG, "the L-curve kernel is for deblurring instances");
         if (m <= 0 || !gammas || !X || !d || !rho || !eta || !corner) fail(RSR_E_ARG, "null argument or m <= 0");
         if (m > 1 && ld_x < I.n) fail(RSR_E_ARG, "ld_x smaller than ny*nx");
         for (int i = 0; i < m; ++i) {
@@ -2135,8 +2422,26 @@ rsr_status rsr_apply(rsr_ctx *c, int ii, int op, double gamma, const double *v, 
     return guard(c, [&] {
         Instance &I = get_inst(c, ii);
         if (!v || !y || n_vec <= 0) fail(RSR_E_ARG, "null vectors or n_vec <= 0");
-        if (n_vec > 1 && ld < I.n) fail(RSR_E_ARG, "ld smaller than ny*nx");
         if (!std::isfinite(gamma)) fail(RSR_E_ARG, "gamma not finite");
+        if (I.ct) {
+            // K and K^T read or write sinograms: their columns hold the larger of the two sizes
+            const long big = (op == RSR_OP_K || op == RSR_OP_KT) ? std::max(I.n, (long)I.na * I.nd) : I.n;
+            if (n_vec > 1 && ld < big) fail(RSR_E_ARG, "ld smaller than the image (or, for K and K^T, sinogram) size");
+            if (ld <= 0) ld = big;
+            if (op != RSR_OP_B && op != RSR_OP_A && op != RSR_OP_E && op != RSR_OP_K && op != RSR_OP_KT)
+                fail(RSR_E_ARG, "unknown operator");
+            set_device(c);
+            hipStream_t s = S(stream);
+            std::vector<ApplyJob> jobs(n_vec);
+            const double cA = op == RSR_OP_E ? 0.0 : 1.0;
+            const double cE = op == RSR_OP_B ? gamma : op == RSR_OP_E ? 1.0 : 0.0;
+            const int jop = op == RSR_OP_K ? 3 : op == RSR_OP_KT ? 4 : 0;
+            for (int j = 0; j < n_vec; ++j) jobs[j] = ApplyJob{ii, jop, cA, cE, v + j * ld, y + j * ld};
+            ct_apply_jobs(c, jobs, s);
+            sync(c, s);
+            return;
+        }
+        if (n_vec > 1 && ld < I.n) fail(RSR_E_ARG, "ld smaller than ny*nx");
         if (ld <= 0) ld = I.n;
         set_device(c);
         hipStream_t s = S(stream);
@@ -2423,6 +2728,7 @@ rsr_status rsr_correction_space(rsr_ctx *c, int ii, const double *x_prev, const 
         Instance &I = get_inst(c, ii);
         if (!x_prev || !wh_prev || !wv_prev || !V || !n_out) fail(RSR_E_ARG, "null argument");
         *n_out = 0;
+        if (I.ct) fail(RSR_E_ARG, "the correction space runs the persistent CG kernel (deblurring instances)");
         if (!(gamma > 0.0) || !std::isfinite(gamma)) fail(RSR_E_ARG, "gamma must be positive");
         if (max_steps < 1 || n_kry < 0 || n_kry > max_steps) fail(RSR_E_ARG, "need 1 <= max_steps, 0 <= n_kry <= max_steps");
         if (n_kry > 0 && ld < I.n) fail(RSR_E_ARG, "ld smaller than ny*nx");
@@ -2528,6 +2834,7 @@ bool solve_set(rsr_ctx *c, const rsr_solve_desc *d, const double *b, double *X, 
            d->gamma_JR, d->solver};
     if (d->solver != RSR_SOLVER_CG && d->solver != RSR_SOLVER_MINRES) fail(RSR_E_ARG, "unknown solver");
     if (d->solver == RSR_SOLVER_MINRES && d->seed_lanczos > 0) fail(RSR_E_ARG, "seeding records CG-Lanczos data");
+    if (c->ct && d->seed_lanczos > 0) fail(RSR_E_ARG, "seeding records CG-Lanczos data of the persistent kernel");
     c->last_cg_ms = 0.0;
     c->last_launches = 0;
     c->last_items = 0;
@@ -2673,6 +2980,11 @@ size_t solve_ws_bytes(rsr_ctx *c, const rsr_solve_desc *d, bool adjoint)
                          al(sizeof(double) * (2 * QMAX * QMAX + 2 * (size_t)std::max(max_p, 1)) * m) +
                          al(sizeof(GramJob) * gj.size());
     size_t need = per_sys + al(sizeof(double) * m) + std::max({launch, guesses, grams}) + 65536 + 4096 * (size_t)m;
+    if (c->ct) {   // sinograms of the K^T K applications: up to two per system at once
+        size_t rays = 0;
+        for (int i = 0; i < m; ++i) rays = std::max(rays, (size_t)c->inst[d->inst[i]]->na * c->inst[d->inst[i]]->nd);
+        need += al(sizeof(double) * rays * 2 * (size_t)m) + al(sizeof(CtJob) * 2 * (size_t)m);
+    }
     if (adjoint) need += al(sizeof(double) * (512 * (size_t)m + 2 * max_n));
     return need;
 }
@@ -2695,6 +3007,7 @@ AsyncLayout async_layout(rsr_ctx *c, const rsr_solve_desc *d)
         fail(RSR_E_ARG, "the device-only solve is plain CG (init ZERO or GIVEN, no local spaces, no seeding)");
     const int ii = d->inst[0];
     Instance &I = get_inst(c, ii);
+    if (I.ct) fail(RSR_E_ARG, "the device-only solve runs the persistent CG kernel (deblurring instances)");
     for (int i = 0; i < m; ++i) {
         if (d->inst[i] != ii) fail(RSR_E_ARG, "the device-only solve takes one instance");
         if (!std::isfinite(d->gammas[i])) fail(RSR_E_ARG, "gamma must be finite");
@@ -2989,6 +3302,7 @@ rsr_status rsr_set_tile(rsr_ctx *c, int ii, int ty, int tx)
 {
     return guard(c, [&] {
         Instance &I = get_inst(c, ii);
+        if (I.ct) fail(RSR_E_ARG, "tomography instances have no stencil tiles");
         if (ty < 4 || tx < 4 || ty > 64 || tx > 64 || (ty & (ty - 1)) || (tx & (tx - 1)))
             fail(RSR_E_ARG, "tile sides must be powers of two in [4, 64]");
         const int tl = tile_lds_doubles(ty, tx, eff_sy(I), eff_sx(I), I.sep);
@@ -3005,6 +3319,7 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
 {
     return guard(c, [&] {
         Instance &I = get_inst(c, ii);
+        if (I.ct) fail(RSR_E_ARG, "nothing to tune on a tomography instance");
         if (n_vec <= 0) n_vec = 1;
         if (n_vec > MAXSYS) fail(RSR_E_ARG, "n_vec above the systems of one launch");
         set_device(c);

@@ -188,4 +188,28 @@ hipError_t launch_grad(const double *X, const double *Lam, long ld, const double
                        const double *wh, const double *wv, int ny, int nx, double *dw_h, double *dw_v,
                        double *db, double *dg_partial, int nchunks, hipStream_t s);
 
+// Parallel-beam tomography instances (ct.hip).  Pixel (i, j) is the unit square
+// centred at x = j - (nx - 1) / 2, y = (ny - 1) / 2 - i; ray (a, k) is the line
+// x cos(theta_a) + y sin(theta_a) = (k - (nd - 1) / 2) * spacing; K = scale * C
+// with C the ray-pixel intersection lengths and scale = 1 / ||C||_F.
+struct CtDev {
+    int ny, nx;
+    int na, nd;        // angles, detector bins (sinogram [na][nd], angle-major)
+    double spacing;
+    double scale;
+    const double *cs;  // [na][2] cos, sin of the angles
+    const double *wh;  // weight planes of E (layout of InstDev)
+    const double *wv;
+};
+struct CtJob {         // op 0: y = cA K^T K v + cE E v; op 3: y = K v (sinogram); op 4: y = K^T v (v a sinogram)
+    int inst;
+    int op;
+    double cA, cE;
+    const double *v;
+    double *y;
+    double *sino;      // op 0 with cA != 0: [na*nd] scratch for K v; op 5: per-ray sums of squared lengths
+};
+hipError_t launch_ct_fwd(const CtDev *inst_dev, const CtJob *jobs_dev, int njobs, int max_rays, hipStream_t s);
+hipError_t launch_ct_back(const CtDev *inst_dev, const CtJob *jobs_dev, int njobs, long max_px, hipStream_t s);
+
 }  // namespace rsr

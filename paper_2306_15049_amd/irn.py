@@ -108,9 +108,10 @@ class OuterLoop:
         self.tol = cfg.tol if tol is None else tol
         self.M = len(cfg.gammas)
         self.mode = mode if mode is not None else (rsr.SEQUENTIAL if cfg.mode == "sequential" else rsr.BATCHED)
-        shapes = [(p.ny, p.nx) for p in cfg.problems]
-        ctx.set_operators(shapes, [p.psf for p in cfg.problems])
-        if tiles:
+        if self.ct and (lcurve or self.rp.seed_lanczos > 0):
+            raise ValueError("the L-curve choice and the seed are for deblurring instances")
+        self._set_operators()
+        if tiles and not self.ct:
             for i, t in tiles.items():
                 ctx.set_tile(i, *t)
         self.b, self.d = [], []
@@ -128,6 +129,19 @@ class OuterLoop:
         self.l_history: List[tuple] = []
         self.workspace = workspace
         self._ws = None
+
+    @property
+    def ct(self) -> bool:
+        """Tomography instances (the second example's projector) instead of blurs."""
+        return self.cfg.problems[0].ct is not None
+
+    def _set_operators(self):
+        shapes = [(p.ny, p.nx) for p in self.cfg.problems]
+        if self.ct:
+            self.ctx.set_ct_operators(shapes, [p.ct[0] for p in self.cfg.problems],
+                                      [p.ct[1] for p in self.cfg.problems])
+        else:
+            self.ctx.set_operators(shapes, [p.psf for p in self.cfg.problems])
 
     def _workspace(self, gammas, inst, slots, o):
         """A caller workspace large enough for this solve (grown when needed)."""
@@ -152,11 +166,13 @@ class OuterLoop:
     def reset(self):
         for i in range(len(self.cfg.problems)):
             self.X[i].zero_()
-        shapes = [(p.ny, p.nx) for p in self.cfg.problems]
-        tiles = [self.ctx.tile(i) for i in range(len(shapes))]
-        self.ctx.set_operators(shapes, [p.psf for p in self.cfg.problems])
-        for i, t in enumerate(tiles):
-            self.ctx.set_tile(i, *t)
+        if self.ct:
+            self._set_operators()
+        else:
+            tiles = [self.ctx.tile(i) for i in range(len(self.cfg.problems))]
+            self._set_operators()
+            for i, t in enumerate(tiles):
+                self.ctx.set_tile(i, *t)
         self.k = 0
         self.l_stars = [int(math.ceil(self.M / 2)) - 1] * len(self.cfg.problems)
         self.l_history = []
@@ -195,7 +211,8 @@ class OuterLoop:
         if self.k > 0:
             for i in range(n_inst):
                 recycled = self.method == "recycled"
-                corr = recycled and self.rp.correction > 0
+                # the correction space runs the persistent kernel: deblurring instances only
+                corr = recycled and self.rp.correction > 0 and not self.ct
                 if corr:
                     wold = ctx.get_weights(i)   # W_{k-1}, for the correction equation
                 if self.weight_rule == "edge":

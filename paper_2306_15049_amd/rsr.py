@@ -30,7 +30,7 @@ EXPORTS = ["rsr_create", "rsr_destroy", "rsr_last_error", "rsr_version", "rsr_se
            "rsr_set_tile", "rsr_get_recycle_info", "rsr_get_recycle_basis", "rsr_get_counters",
            "rsr_last_solve_timing", "rsr_weights_edge_rule", "rsr_lcurve", "rsr_correction_space",
            "rsr_workspace_size", "rsr_allocation_count", "rsr_solve_shift_set_noalloc",
-           "rsr_solve_shift_set_async"]
+           "rsr_solve_shift_set_async", "rsr_set_ct_operators"]
 WS_SOLVE, WS_ADJOINT, WS_DEVICE = 0, 1, 2
 SOLVER_CG, SOLVER_MINRES = 0, 1
 
@@ -44,6 +44,11 @@ class RsrError(RuntimeError):
 class Instance(ctypes.Structure):
     _fields_ = [("ny", ctypes.c_int), ("nx", ctypes.c_int), ("sy", ctypes.c_int), ("sx", ctypes.c_int),
                 ("psf_host", ctypes.POINTER(ctypes.c_double))]
+
+
+class CtInstance(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int), ("nx", ctypes.c_int), ("n_angles", ctypes.c_int), ("n_det", ctypes.c_int),
+                ("spacing", ctypes.c_double), ("angles_host", ctypes.POINTER(ctypes.c_double))]
 
 
 class SolveDesc(ctypes.Structure):
@@ -115,6 +120,7 @@ def load():
     L.rsr_weights_edge_rule.argtypes = [P, I, P, D, P]
     L.rsr_lcurve.argtypes = [P, I, I, pD, P, L_, P, pD, pD, pD, pI, P]
     L.rsr_correction_space.argtypes = [P, I, P, P, P, D, I, I, P, L_, pI, P]
+    L.rsr_set_ct_operators.argtypes = [P, I, ctypes.POINTER(CtInstance), P]
     for name in EXPORTS:
         if name not in ("rsr_destroy", "rsr_last_error", "rsr_version", "rsr_allocation_count"):
             getattr(L, name).restype = ctypes.c_int
@@ -215,6 +221,24 @@ class Context:
                               h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         self._check(self.lib.rsr_set_operators(self.h, n, arr, _stream()))
         self.shapes = [tuple(s) for s in shapes]
+        self.sinograms = {}
+
+    def set_ct_operators(self, shapes: Sequence[tuple], angles: Sequence[np.ndarray], n_det: Sequence[int],
+                         spacing: Sequence[float] = None):
+        """Tomography instances (rsr_set_ct_operators): image shapes, projection angles
+        (radians) and detector bins per instance."""
+        n = len(shapes)
+        arr = (CtInstance * n)()
+        keep = []
+        sp = spacing if spacing is not None else [1.0] * n
+        for i, ((ny, nx), th, nd, h) in enumerate(zip(shapes, angles, n_det, sp)):
+            th = np.ascontiguousarray(th, dtype=np.float64)
+            keep.append(th)
+            arr[i] = CtInstance(int(ny), int(nx), th.size, int(nd), float(h),
+                                th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._check(self.lib.rsr_set_ct_operators(self.h, n, arr, _stream()))
+        self.shapes = [tuple(s) for s in shapes]
+        self.sinograms = {i: (len(angles[i]), int(n_det[i])) for i in range(n)}
 
     def update_weights(self, inst: int, wh, wv):
         self._check(self.lib.rsr_update_weights(self.h, inst, _ptr(wh), _ptr(wv), _stream()))
@@ -259,10 +283,27 @@ class Context:
         return wh, wv
 
     def apply(self, inst: int, op: int, v, gamma: float = 0.0, out=None):
-        """op(v) for v of shape [ny, nx] or [k, ny, nx]."""
+        """op(v) for v of shape [ny, nx] or [k, ny, nx].  On a tomography instance OP_K
+        maps images to sinograms [n_angles, n_det] and OP_KT sinograms to images."""
         import torch
-        y = torch.empty_like(v) if out is None else out
         nvec = 1 if v.dim() == 2 else v.shape[0]
+        if inst in getattr(self, "sinograms", {}):
+            img, sino = self.shapes[inst], self.sinograms[inst]
+            if op in (OP_K, OP_KT):
+                oshape = sino if op == OP_K else img
+                ld = max(img[0] * img[1], sino[0] * sino[1])
+                vin = torch.zeros((nvec, ld), dtype=v.dtype, device=v.device)
+                vin[:, :v[0].numel() if nvec > 1 else v.numel()] = v.reshape(nvec, -1)
+                yo = torch.empty((nvec, ld), dtype=v.dtype, device=v.device)
+                self._check(self.lib.rsr_apply(self.h, inst, op, float(gamma), _ptr(vin), _ptr(yo), nvec, ld,
+                                               _stream()))
+                y = yo[:, :oshape[0] * oshape[1]].reshape((nvec,) + tuple(oshape))
+                y = y[0].contiguous() if v.dim() == 2 else y.contiguous()
+                if out is not None:
+                    out.copy_(y)
+                    return out
+                return y
+        y = torch.empty_like(v) if out is None else out
         ld = v.shape[-1] * v.shape[-2]
         self._check(self.lib.rsr_apply(self.h, inst, op, float(gamma), _ptr(v), _ptr(y), nvec, ld, _stream()))
         return y

@@ -104,8 +104,9 @@ class Problem:
     psf: np.ndarray          # (s, s), sums to 1
     sigma: float
     x_true: np.ndarray       # (ny, nx)
-    noise_dir: np.ndarray    # (ny, nx), standard normal
+    noise_dir: np.ndarray    # (ny, nx), standard normal (the sinogram's shape for tomography)
     noise_level: float       # relative noise level, e.g. 0.01
+    ct: Optional[tuple] = None   # tomography instance: (angles in radians, detector bins); psf unused
 
     @property
     def n(self) -> int:
@@ -169,6 +170,19 @@ def config(name: str, small: Optional[int] = None) -> Config:
         g = rng.standard_normal((n, n))
         pr = Problem(n, n, kronecker_sum_psf(EXAMPLE1_TERMS), 0.0, x, g, 0.005)
         return Config("X1", [pr], shift_grid(-8, 5, 20), 5, 40, 5, "sequential", tol=1e-6)
+    if name == "X2":
+        # the second example's setting: an 82 x 82 image, parallel-beam projections at
+        # 1, 2, ..., 135 degrees (unit-spaced bins covering the diagonal), 1% noise on the
+        # sinogram, lambda from 1e-4 to 1e1 (gamma = lambda^2), relative residual 1e-6
+        n = small or 82
+        rng = np.random.default_rng(12)
+        x = phantom(rng, n, n, 20)
+        angles = np.deg2rad(np.arange(1, 136, dtype=np.float64))
+        nd = int(np.ceil(np.sqrt(2.0) * n))
+        nd += (nd - n) % 2
+        g = rng.standard_normal((angles.size, nd))
+        pr = Problem(n, n, np.ones((1, 1)), 0.0, x, g, 0.01, ct=(angles, nd))
+        return Config("X2", [pr], shift_grid(-8, 2, 20), 5, 40, 5, "sequential", tol=1e-6)
     if name == "C5":
         n = small or 512
         pr = make_problem(5, n, n, 3.0, 15, 20)

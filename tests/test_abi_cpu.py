@@ -63,11 +63,12 @@ def test_ctypes_struct_layout_matches_c():
 #include <stddef.h>
 #include "rsr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsr_instance), sizeof(rsr_solve_desc),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsr_instance), sizeof(rsr_solve_desc),
          offsetof(rsr_solve_desc, tol), offsetof(rsr_solve_desc, gamma_JL), offsetof(rsr_solve_desc, ld_x),
          offsetof(rsr_solve_desc, seed_lanczos), offsetof(rsr_solve_desc, seed_n_ritz),
          offsetof(rsr_solve_desc, seed_second), offsetof(rsr_solve_desc, solver),
-         sizeof(rsr_shift_stats), offsetof(rsr_shift_stats, relres_init), offsetof(rsr_shift_stats, relres_true));
+         sizeof(rsr_shift_stats), offsetof(rsr_shift_stats, relres_init), offsetof(rsr_shift_stats, relres_true),
+         sizeof(rsr_ct_instance), offsetof(rsr_ct_instance, spacing), offsetof(rsr_ct_instance, angles_host));
   return 0;
 }
 '''
@@ -81,7 +82,8 @@ int main(void) {
             rsr.SolveDesc.gamma_JL.offset, rsr.SolveDesc.ld_x.offset, rsr.SolveDesc.seed_lanczos.offset,
             rsr.SolveDesc.seed_n_ritz.offset, rsr.SolveDesc.seed_second.offset,
             rsr.SolveDesc.solver.offset, ctypes.sizeof(rsr.ShiftStats),
-            rsr.ShiftStats.relres_init.offset, rsr.ShiftStats.relres_true.offset]
+            rsr.ShiftStats.relres_init.offset, rsr.ShiftStats.relres_true.offset, ctypes.sizeof(rsr.CtInstance),
+            rsr.CtInstance.spacing.offset, rsr.CtInstance.angles_host.offset]
     assert vals == want
 
 
