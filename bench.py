@@ -114,6 +114,8 @@ def kernel_source_hash() -> str:
 
 def desc_problems(cfg) -> str:
     pr = cfg.problems
+    if pr[0].ct is not None:
+        return f"{pr[0].ny}x{pr[0].nx} parallel-beam CT, {len(pr[0].ct[0])} angles, {pr[0].ct[1]} bins"
     if len(pr) == 1:
         s = pr[0].psf.shape[0]
         return f"{pr[0].ny}x{pr[0].nx} deblur, PSF {s}x{s} sigma={pr[0].sigma}"
@@ -228,7 +230,7 @@ def main():
         loop = irn.OuterLoop(ctx, cfg, method, mode=mode, solver=solver)
         n_inst = len(cfg.problems)
         key = (cfg.name, mode)
-        if not args.no_autotune:
+        if not args.no_autotune and cfg.problems[0].ct is None:
             if key not in tiles_cache:
                 M = len(cfg.gammas)
                 tiles_cache[key] = {i: ctx.autotune(i, 1 if mode == rsr.SEQUENTIAL else M, args.tune_cache)
@@ -280,7 +282,10 @@ def main():
     for name, v in list(variants.items()) + [("recycled_headline", head)]:
         v["speedup_vs_plain_per_shift"] = t_plain / v["ms_per_step"]
 
-    roof = roofline(cfg, head_recs, seq == rsr.BATCHED, "sequential" if seq == rsr.SEQUENTIAL else "batched")
+    if cfg.problems[0].ct is None:
+        roof = roofline(cfg, head_recs, seq == rsr.BATCHED, "sequential" if seq == rsr.SEQUENTIAL else "batched")
+    else:   # no persistent CG kernel: the projector launches of the host-driven solvers dominate
+        roof = None
 
     cpu = None
     if not args.no_cpu:
