@@ -115,7 +115,7 @@ struct Instance {
     bool ct = false;
     int na = 0, nd = 0;
     double spacing = 1.0, ct_scale = 1.0;
-    DBuf d_cs;                         // [na][2] cos, sin
+    DBuf d_cs;                         // [na][4] cos, sin, 1/(-sin), 1/cos
     // principal recycle space
     int p = 0;
     DBuf d_U, d_AE;   // U: p columns; AE: [AU | EU], 2p columns; stride n
@@ -2266,10 +2266,14 @@ rsr_status rsr_set_ct_operators(rsr_ctx *c, int n_inst, const rsr_ct_instance *i
             default_tile(*I);
             I->d_psf.ensure(sizeof(double));
             HIPCHK(hipMemcpy(I->d_psf.p, I->psf.data(), sizeof(double), hipMemcpyHostToDevice));
-            std::vector<double> cs(2 * (size_t)r.n_angles);
+            // per angle: cos, sin and the reciprocals of the ray direction (-sin, cos), 0 for a 0 component
+            std::vector<double> cs(4 * (size_t)r.n_angles);
             for (int a = 0; a < r.n_angles; ++a) {
-                cs[2 * a] = std::cos(r.angles_host[a]);
-                cs[2 * a + 1] = std::sin(r.angles_host[a]);
+                const double co = std::cos(r.angles_host[a]), si = std::sin(r.angles_host[a]);
+                cs[4 * a] = co;
+                cs[4 * a + 1] = si;
+                cs[4 * a + 2] = si != 0.0 ? 1.0 / -si : 0.0;
+                cs[4 * a + 3] = co != 0.0 ? 1.0 / co : 0.0;
             }
             I->d_cs.ensure(sizeof(double) * cs.size());
             HIPCHK(hipMemcpy(I->d_cs.p, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice));

@@ -197,7 +197,7 @@ struct CtDev {
     int na, nd;        // angles, detector bins (sinogram [na][nd], angle-major)
     double spacing;
     double scale;
-    const double *cs;  // [na][2] cos, sin of the angles
+    const double *cs;  // [na][4] cos, sin of the angles and the reciprocals 1/(-sin), 1/cos (0 for a 0)
     const double *wh;  // weight planes of E (layout of InstDev)
     const double *wv;
 };
