@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "librsr.so")
-SOURCES = ["kernels.hip", "cg.hip", "ct.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "cg.hip", "cg1.hip", "ct.hip", "engine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,336 @@
+// Persistent deflated CG of one system whose tiles fit the grid (gfx950, FP64).
+//
+// The launches of the sequential mode (one shift at a time) hold a single
+// system, and at the benchmark's 256 x 256 that is 128 tiles: one per
+// workgroup, an iteration being a chain of dependent steps (partial sums,
+// decisions, window loads, stencil, epilogue, barrier) rather than a stream of
+// bytes.  This kernel is k_cg (cg.hip) with the generality that chain does not
+// need taken out:
+//   * each workgroup owns the same tile for the whole launch, so the tile's
+//     x, p and its columns of W and Z live in registers; only r, w and ph,
+//     which the neighbours' windows read, go to memory each iteration (x and
+//     p once, at the end);
+//   * there is no work assignment, no system switch and no grid shrink: the
+//     top of an iteration reduces one system's partials, and every workgroup
+//     forms c_j itself from them.
+// Iteration j is otherwise the fused iteration of k_cg with coherent loads:
+// the same recomputation of r_j and ph_j on the window, the same stencil, the
+// same partial sums in the same slots and the same reduction order, so the
+// iterates are those of k_cg.
+#include "cgcore.hpp"
+
+namespace rsr {
+
+namespace {
+
+constexpr int NPX = 4;   // own pixels per thread: tiles of up to 4 NT pixels
+
+template <int QT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_cg1(CGArgs A)
+{
+    constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
+    constexpr int QW = QT > 0 ? QT : 1;
+    extern __shared__ double smem[];
+    double *tile = smem;                          // stencil buffers / reduction scratch
+    double *taps = smem + A.tile_lds;             // bands and end corrections of the instance
+    const BarCtl bc = bar_ctl(A);
+    __shared__ int s_flag, s_g;
+    __shared__ unsigned long long s_arr;
+    __shared__ double s_red[(NT / 64) * NVP];
+    __shared__ double s_vals[NVP];
+    __shared__ double s_acc[NVP];
+    __shared__ double s_sums[4];
+    __shared__ double s_dec[3];                   // alpha_{j-1}, beta_j, status of iteration j
+    __shared__ double s_z[QMAX];
+    __shared__ double s_c[QMAX];                  // c_j (c_{-1} = 0)
+    __shared__ SysDev s_sd;
+    __shared__ InstDev s_id;
+
+    {
+        static_assert(sizeof(SysDev) % 8 == 0 && sizeof(InstDev) % 8 == 0, "descriptor size");
+        constexpr int NSD = (int)(sizeof(SysDev) / 8), NID = (int)(sizeof(InstDev) / 8);
+        const unsigned long long *src = (const unsigned long long *)A.sys;
+        if (threadIdx.x < NSD) ((unsigned long long *)&s_sd)[threadIdx.x] = src[threadIdx.x];
+        __syncthreads();
+        const unsigned long long *isrc = (const unsigned long long *)(A.inst + s_sd.inst);
+        if (threadIdx.x < NID) ((unsigned long long *)&s_id)[threadIdx.x] = isrc[threadIdx.x];
+        if (threadIdx.x == 0) {
+            s_arr = 0;
+            s_g = A.G;
+        }
+        if (threadIdx.x < QMAX) s_c[threadIdx.x] = 0.0;
+        __syncthreads();
+        stage_taps(s_id, taps);
+        __syncthreads();
+    }
+    const SysDev &Y = s_sd;
+    const InstDev &I = s_id;
+    const int PS = A.pstride;
+    const int q = Y.q;
+    const double tol2 = Y.tolabs * Y.tolabs;      // compared with rho = ||r||^2
+    const int F = Y.ntiles;                       // chunks of the system: one tile each
+    const int chunk = chunk_of_block(blockIdx.x, A.G);
+    const bool has = chunk < F;                   // workgroups past the tiles only reduce and wait
+    const int slot = Y.tile_base + chunk;
+    const int t = has ? chunk : 0;
+    const int y0 = (t / I.ntx) * I.ty, x0 = (t % I.ntx) * I.tx;
+    const int ne = I.ty * I.tx;
+    const long ldw = Y.ldw;
+    const Geo g = make_geo(I.ty, I.tx, I.sy, I.sx, I.sep);
+
+    // own pixels k = i * NT + threadIdx.x (the order of k_cg's interior loop)
+    int gi[NPX];
+    bool ok[NPX];
+    double xr[NPX], pr[NPX], wl[NPX][QW], zl[NPX][QW];
+#pragma unroll
+    for (int i = 0; i < NPX; ++i) {
+        const int k = i * NT + threadIdx.x;
+        const int gy = y0 + (k >> I.ltx), gx = x0 + (k & (I.tx - 1));
+        ok[i] = has && k < ne && gy < I.ny && gx < I.nx;
+        gi[i] = ok[i] ? gy * I.nx + gx : 0;
+        xr[i] = ok[i] ? gp(Y.x)[gi[i]] : 0.0;
+        pr[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < QT; ++j) {
+            wl[i][j] = (j < q && ok[i]) ? gp(Y.W)[j * ldw + gi[i]] : 0.0;
+            zl[i][j] = (j < q && ok[i]) ? gp(Y.Z)[j * ldw + gi[i]] : 0.0;
+        }
+    }
+
+    // ---- initial pass: r_0.r_0 and Z^T r_0 into the slots read by iteration 0
+    {
+        if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
+        __syncthreads();
+        double v[NVT];
+#pragma unroll
+        for (int j = 0; j < NVT; ++j) v[j] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NPX; ++i) {
+            if (ok[i]) {
+                const double r = gp(Y.rb[0])[gi[i]];
+                v[1] = fma(r, r, v[1]);
+#pragma unroll
+                for (int j = 0; j < QT; ++j)
+                    if (j < q) v[4 + j] = fma(zl[i][j], r, v[4 + j]);
+            }
+        }
+        if (has) {
+            block_accumulate<NVT>(v, NVT, s_acc, s_red);
+            if (threadIdx.x < NVP) gp(A.part[1])[(int)threadIdx.x * PS + slot] = s_acc[threadIdx.x];
+        }
+    }
+    int nbar = 0;
+    if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+
+    for (int it = 0;; ++it) {
+        const double *pprev = (it & 1) ? A.part[0] : A.part[1];
+        double *pcur = (it & 1) ? A.part[1] : A.part[0];
+        // ---- the previous phase's partials: p.w, r.r, r.w, w.w and Z^T r, Z^T w
+        double accz[QT > 0 ? 2 * QT : 1];
+        const bool zok = threadIdx.x < F;
+        if constexpr (QT > 0) {
+            const int k = zok ? (int)threadIdx.x : 0;
+            const double *pz = pprev + 4 * PS + Y.tile_base + k;
+#pragma unroll
+            for (int j = 0; j < 2 * QT; ++j) accz[j] = cld(pz + j * PS);
+        }
+        double *fl = tile;   // [4][F]
+        for (int f = threadIdx.x; f < F; f += NT) {
+            const double *p = pprev + Y.tile_base + f;
+            const double v0 = cld(p), v1 = cld(p + PS), v2 = cld(p + 2 * PS), v3 = cld(p + 3 * PS);
+            fl[f] = v0;
+            fl[F + f] = v1;
+            fl[2 * F + f] = v2;
+            fl[3 * F + f] = v3;
+        }
+        __syncthreads();
+        if constexpr (QT > 0) {
+#pragma unroll
+            for (int j = 0; j < 2 * QT; ++j) accz[j] = zok ? accz[j] : 0.0;
+            block_sum<2 * QT>(accz, 2 * QT, s_vals, s_red);
+        }
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = lane; k < F; k += 64)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] += fl[u * F + k];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double sv = wave_sum(v[u]);
+                if (lane == 0) s_sums[u] = sv;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double pw = s_sums[0], rr = s_sums[1], rw = s_sums[2], ww = s_sums[3];
+            double rho, alpha = 0.0, beta = 0.0;
+            int st = 0;
+            if (it == 0) {
+                rho = rr;
+                if (!isfinite(rr)) st = -3;
+            } else {
+                // alpha_{j-1} from the exact rho_{j-1}; rho_j = ||r_{j-1} - alpha w_{j-1}||^2 expanded
+                alpha = rr / pw;
+                rho = fma(alpha, fma(alpha, ww, -2.0 * rw), rr);
+                if (rho < 0.0) rho = 0.0;
+                beta = rho / rr;
+                if (!isfinite(pw) || !isfinite(rr) || !isfinite(rho)) st = -3;
+                else if (!(pw > 0.0)) st = -4;
+            }
+            if (st == 0) {
+                if (rho <= tol2) st = 1;
+                else if (it >= A.maxit) st = 2;
+            }
+            s_dec[0] = alpha;
+            s_dec[1] = beta;
+            s_dec[2] = st;
+            if (st != 0 && blockIdx.x == 0) {
+                A.out_status[0] = st;
+                A.out_iters[0] = it;
+                A.out_rho[0] = rho;
+                A.out_alpha[0] = st > 0 ? alpha : 0.0;   // x_j = x_{j-1} + alpha p_{j-1} is applied after the launch
+            }
+        }
+        __syncthreads();
+        const double alpha = s_dec[0], beta = s_dec[1];
+        if (s_dec[2] != 0.0) {
+            // x_{j-1} and p_{j-1} of the own pixels, for the step left to the host
+#pragma unroll
+            for (int i = 0; i < NPX; ++i)
+                if (ok[i]) {
+                    gp(Y.x)[gi[i]] = xr[i];
+                    gp(Y.pa)[gi[i]] = pr[i];
+                }
+            return;
+        }
+        if constexpr (QT > 0) {
+            // mu = Ginv (Z^T r_{j-1} - alpha Z^T w_{j-1}); c_j = beta c_{j-1} + mu
+            if (threadIdx.x < q) s_z[threadIdx.x] = fma(-alpha, s_vals[QT + threadIdx.x], s_vals[threadIdx.x]);
+            __syncthreads();
+            if (threadIdx.x < q) {
+                double m = 0.0;
+                for (int j = 0; j < q; ++j) m += Y.Ginv[threadIdx.x * QMAX + j] * s_z[j];
+                s_c[threadIdx.x] = fma(beta, s_c[threadIdx.x], m);
+            }
+            __syncthreads();
+        }
+
+        if (has) {
+            const int pj = it & 1, pk = (it + 1) & 1;      // buffers of step j and of step j - 1
+            const gdbl *__restrict__ rsrc = gp(it > 0 ? Y.rb[pk] : Y.rb[0]);
+            gdbl *__restrict__ rdst = gp(Y.rb[pj]);
+            const gdbl *__restrict__ wsrc = gp(Y.wb[pk]);
+            gdbl *__restrict__ wdst = gp(Y.wb[pj]);
+            const gdbl *__restrict__ psrc = gp(Y.pb[pk]);
+            gdbl *__restrict__ pdst = gp(Y.pb[pj]);
+            double *pbuf = tile + g.offP;
+            double *rbuf = tile + g.offR;
+            if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
+            // stage ph_j = r_j + beta ph_{j-1} with r_j = r_{j-1} - alpha w_{j-1} on the
+            // window (halo recomputed from the neighbours' step j-1 vectors)
+            EWts ew;
+            tile_E_load(I, y0, x0, 0, Y.gamma, ew);   // in flight with the window loads
+            const WinMap wm = win_map(g.W0);
+            const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);     // window column of this thread
+            const int gx = x0 - g.hx + lj;
+            const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
+            const bool colown = lj >= g.hx && lj < g.hx + I.tx;
+            for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
+                int wi[NBW];
+                bool wok[NBW], own[NBW];
+#pragma unroll
+                for (int u = 0; u < NBW; ++u) {
+                    const int li = li0 + u * wm.rs;
+                    const int gy = y0 - g.hy + li;
+                    wok[u] = colok && li < g.H0 && gy >= 0 && gy < I.ny;
+                    own[u] = colown && li >= g.hy && li < g.hy + I.ty;
+                    wi[u] = wok[u] ? gy * I.nx + gx : 0;
+                }
+                // every window cell with coherent loads (halo cells were written by
+                // other workgroups), branch-free so that all loads are in flight together
+                double rv[NBW], wv[NBW], pv[NBW];
+#pragma unroll
+                for (int u = 0; u < NBW; ++u) rv[u] = cld(rsrc + wi[u]);
+                if (it > 0) {
+#pragma unroll
+                    for (int u = 0; u < NBW; ++u) {
+                        wv[u] = cld(wsrc + wi[u]);
+                        pv[u] = cld(psrc + wi[u]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < NBW; ++u) wv[u] = pv[u] = 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NBW; ++u) {
+                    const int li = li0 + u * wm.rs;
+                    const double rj = fma(-alpha, wv[u], rv[u]);
+                    const double ph = wok[u] ? fma(beta, pv[u], rj) : 0.0;
+                    double *d = (lj < g.W0 && li < g.H0) ? tile + li * g.P0 + lj : tile + g.offT + threadIdx.x;
+                    *d = ph;
+                    if (wok[u] && own[u]) {
+                        if (it > 0) rdst[wi[u]] = rj;
+                        pdst[wi[u]] = ph;
+                        const int ii = (li - g.hy) * g.PE + (lj - g.hx);
+                        pbuf[ii] = ph;
+                        rbuf[ii] = rj;
+                    }
+                }
+            }
+            __syncthreads();
+            tile_E(I, g, tile, y0, x0, Y.gamma, ew);
+            tile_A(I, g, tile, taps, y0, x0, 1.0);
+            // interior: x_j = x_{j-1} + alpha p_{j-1}; p_j = ph_j - W c_j; w_j = B ph_j - Z c_j;
+            // partials p.w, r.r, r.w, w.w, Z^T r, Z^T w
+            const double *ebuf = tile + g.offE;
+            double v[NVT];
+#pragma unroll
+            for (int j = 0; j < NVT; ++j) v[j] = 0.0;
+#pragma unroll
+            for (int i = 0; i < NPX; ++i) {
+                const int k = i * NT + threadIdx.x;
+                const int ii = ok[i] ? (k >> I.ltx) : 0, jj = ok[i] ? (k & (I.tx - 1)) : 0;
+                double p = pbuf[ii * g.PE + jj];
+                double w = ebuf[ii * g.PE + jj];
+                const double rj = rbuf[ii * g.PE + jj];
+#pragma unroll
+                for (int j = 0; j < QT; ++j) {
+                    p = fma(-s_c[j], wl[i][j], p);
+                    w = fma(-s_c[j], zl[i][j], w);
+                }
+                if (ok[i]) {
+                    if (it > 0) xr[i] = fma(alpha, pr[i], xr[i]);
+                    pr[i] = p;
+                    wdst[gi[i]] = w;
+                    v[0] = fma(p, w, v[0]);
+                    v[1] = fma(rj, rj, v[1]);
+                    v[2] = fma(rj, w, v[2]);
+                    v[3] = fma(w, w, v[3]);
+#pragma unroll
+                    for (int j = 0; j < QT; ++j) {
+                        v[4 + j] = fma(zl[i][j], rj, v[4 + j]);
+                        v[4 + QT + j] = fma(zl[i][j], w, v[4 + QT + j]);
+                    }
+                }
+            }
+            block_accumulate<NVT>(v, NVT, s_acc, s_red);
+            if (threadIdx.x < NVP) gp(pcur)[(int)threadIdx.x * PS + slot] = s_acc[threadIdx.x];
+        }
+        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+    }
+}
+
+}  // namespace
+
+const void *cg1_kernel(int qt)
+{
+    switch (qt) {
+    case 0: return (const void *)k_cg1<0>;
+    case 3: return (const void *)k_cg1<3>;
+    case 5: return (const void *)k_cg1<5>;
+    default: return (const void *)k_cg1<QMAX>;
+    }
+}
+
+}  // namespace rsr

@@ -844,7 +844,8 @@ struct CgLaunch {
     int qt, form, G, msys, tl, taps;
     size_t lds;
 };
-CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles, int tuned_form = -1)
+CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles, int tuned_form = -1, int tile_px = 0,
+                   bool allow_one = true)
 {
     CgLaunch L;
     L.msys = (m + 7) & ~7;
@@ -858,23 +859,34 @@ CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles, in
     // there an agent-scope acquire per barrier lets the halo reads of
     // neighbouring tiles share L2 lines (form 1).  Two-pass iterations (an
     // elementwise pass, a barrier, a stencil pass that reads ph alone, form 2)
-    // read a third of the halo for a second barrier.  Launches that record
-    // CG-Lanczos data use form 0.
+    // read a third of the halo for a second barrier.  A single system whose
+    // tiles each get a workgroup runs the single-system kernel (form 3: tile
+    // data in registers, no assignment).  Launches that record CG-Lanczos data
+    // use form 0.
     int mode = c->cg_mode;
     if (const char *e = getenv("RSR_CG_MODE")) mode = atoi(e);   // override for tuning sweeps
-    L.form = lz ? 0 : (mode >= 1 && mode <= 3) ? mode - 1 : tuned_form >= 0 ? tuned_form : (px >= (2L << 20) ? 1 : 0);
-    const int bpc = cg_max_blocks_per_cu(L.lds, L.qt, lz, L.form);
-    if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
-    int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
-    if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
-        const int v = atoi(cap);
-        if (v >= 8) G = std::min(G, v);
+    const bool one = allow_one && m == 1 && !lz && tiles <= NT && tile_px > 0 && tile_px <= 4 * NT;
+    const int by_size = px >= (2L << 20) ? 1 : 0;
+    L.form = lz ? 0 : (mode >= 1 && mode <= 4) ? mode - 1 : tuned_form >= 0 ? tuned_form : one ? 3 : by_size;
+    if (L.form == 3 && !one) L.form = by_size;
+    for (;;) {
+        const int bpc = cg_max_blocks_per_cu(L.lds, L.qt, lz, L.form);
+        if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
+        int G = std::min<long>((long)bpc * c->n_cu, std::min(1024, c->cg_gmax));
+        if (const char *cap = getenv("RSR_CG_MAX_BLOCKS")) {   // launch-shape override for tuning sweeps
+            const int v = atoi(cap);
+            if (v >= 8) G = std::min(G, v);
+        }
+        // no more workgroups than tiles (rounded up to the 8 XCDs)
+        G = (int)std::min<long>(G, (std::max<long>(8, tiles) + 7) & ~7L);
+        if (G >= 8) G -= G % 8;
+        L.G = G;
+        if (L.form == 3 && G < tiles) {   // a workgroup per tile does not fit this grid
+            L.form = by_size;
+            continue;
+        }
+        return L;
     }
-    // no more workgroups than tiles (rounded up to the 8 XCDs)
-    G = (int)std::min<long>(G, (std::max<long>(8, tiles) + 7) & ~7L);
-    if (G >= 8) G -= G % 8;
-    L.G = G;
-    return L;
 }
 
 // Runs deflated CG from the current (x, r) of each listed system to the
@@ -933,10 +945,12 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     int qmax = 0;
     bool lz = false;   // some system records CG-Lanczos data in this launch
     long px = 0;
+    int tile_px = 0;
     for (auto *Y : sy) {
         qmax = std::max(qmax, Y->q);
         lz = lz || Y->nlz > 0;
         px += Y->n;
+        tile_px = std::max(tile_px, c->h_inst[Y->inst].ty * c->h_inst[Y->inst].tx);
     }
     // the autotuned form, when every instance of the launch has the same one
     int tuned = -2;
@@ -944,7 +958,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         const int f = c->inst[Y->inst]->form;
         tuned = tuned == -2 ? f : (tuned == f ? f : -1);
     }
-    const CgLaunch L = cg_config(c, m, qmax, lz, px, tiles, tuned < 0 ? -1 : tuned);
+    const CgLaunch L = cg_config(c, m, qmax, lz, px, tiles, tuned < 0 ? -1 : tuned, tile_px);
     const int qt = L.qt, form = L.form, G = L.G, msys = L.msys, tl = L.tl, taps_lds = L.taps;
     const size_t lds = L.lds;
 
@@ -3189,7 +3203,7 @@ rsr_status rsr_solve_shift_set_async(rsr_ctx *c, const rsr_solve_desc *d, const 
         }
         // the persistent CG launch
         const long tiles = (long)m * a.ntiles;
-        const CgLaunch L = cg_config(c, m, 0, false, (long)m * I.n, tiles, I.form);
+        const CgLaunch L = cg_config(c, m, 0, false, (long)m * I.n, tiles, I.form, 0, false);
         CGArgs g;
         memset(&g, 0, sizeof(g));
         g.nsys = m;
@@ -3354,8 +3368,9 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         }
         // Time the hot kernel itself: a bounded persistent-CG solve of n_vec systems
         // (shifts spread over 1e-3..1e-1) per candidate, keeping the fastest per
-        // iteration, in stages: tile shape x workgroup cap (fused form); then the
-        // iteration form (fused with coherent loads, fused with an agent acquire,
+        // iteration, in stages: tile shape x workgroup cap (the single-system
+        // kernel for one system, else the fused form); then the other iteration
+        // forms (fused with coherent loads, fused with an agent acquire,
         // two-pass); then, for a rank-1 PSF of at most 9 x 9 taps, the direct 2-D
         // stencil against the banded separable one.
         const long n = I.n;
@@ -3398,8 +3413,12 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         const int cand[][2] = {{16, 16}, {16, 32}, {32, 16}, {32, 32}, {8, 64}, {16, 64}};
         const int gcaps[] = {128, 256, 512, 1024};
         double best = 1e30;
-        int bty = I.ty, btx = I.tx, bg = c->cg_gmax, bform = 0, bsep = I.sep;
-        c->cg_mode = 1;   // stage 1 in the fused form with coherent loads
+        // stage 1 in the single-system kernel for one system (where a launch
+        // does not fit it, the launch falls back by size), else the fused form
+        // with coherent loads
+        const int form1 = n_vec == 1 ? 3 : 0;
+        int bty = I.ty, btx = I.tx, bg = c->cg_gmax, bform = form1, bsep = I.sep;
+        c->cg_mode = form1 + 1;
         for (auto &cd : cand) {
             const int tl = tile_lds_doubles(cd[0], cd[1], eff_sy(I), eff_sx(I), I.sep);
             const int ms8 = (n_vec + 7) & ~7;
@@ -3422,7 +3441,8 @@ rsr_status rsr_autotune(rsr_ctx *c, int ii, int n_vec, const char *cache_path)
         I.tx = btx;
         c->cg_gmax = bg;
         upload_inst(c);
-        for (int form = 1; form <= 2; ++form) {
+        for (int form = 0; form <= 2; ++form) {
+            if (form == form1) continue;
             c->cg_mode = form + 1;
             const double per = time_it();
             if (per < best) {

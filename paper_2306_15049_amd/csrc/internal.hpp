@@ -108,6 +108,9 @@ constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
 int cg_width(int qmax);                           // compiled local-space width for a widest q
 hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s);
 int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form);
+// Form 3: the single-system kernel k_cg1 (cg1.hip), for one system whose tiles
+// (at most NT, of at most 4 NT pixels each) each get a workgroup of their own.
+const void *cg1_kernel(int qt);
 
 struct ApplyJob {              // y = cA K^T K v + cE E v   (or K / K^T alone)
     int inst;

@@ -139,6 +139,31 @@ def test_fused_and_two_pass_iterations_agree_bitwise(ctx, monkeypatch, recycled)
         assert oracle.true_relres(pr.psf, wh, wv, g, b, X[l]) <= 1e-8
 
 
+@pytest.mark.parametrize("tile,recycled", [((16, 16), False), ((32, 32), True), ((16, 32), True)])
+def test_single_system_kernel_matches_general_kernel_bitwise(ctx, monkeypatch, tile, recycled):
+    # one system per launch (sequential mode), a workgroup per tile: the
+    # single-system kernel keeps the tile's x, p, W and Z in registers but forms
+    # the general kernel's values in the same order, so the iterates agree to the
+    # last bit (ragged tiles, local spaces of up to 5 columns, 4 pixels per thread
+    # with 32 x 32 tiles)
+    from paper_2306_15049_amd import irn
+    pr = synth.make_problem(9, 150, 203, 2.0, 13, 12)
+    _, b = oracle.rhs(pr)
+    cfg = synth.Config("ragged", [pr], synth.shift_grid(-4, 1, 4), 3, 12, 5, "sequential")
+    out = {}
+    for mode in ("1", "4"):
+        monkeypatch.setenv("RSR_CG_MODE", mode)
+        loop = irn.OuterLoop(ctx, cfg, "recycled" if recycled else "plain", tiles={0: tile})
+        loop.b[0] = to_dev(b)
+        recs = loop.run(3 if recycled else 1)
+        out[mode] = (to_host(loop.X[0]), [r.iters for r in recs])
+    assert out["1"][1] == out["4"][1]
+    assert np.array_equal(out["1"][0], out["4"][0])
+    wh, wv = (to_host(t) for t in ctx.get_weights(0))
+    for l, g in enumerate(cfg.gammas):
+        assert oracle.true_relres(pr.psf, wh, wv, g, b, out["4"][0][l]) <= 1e-8
+
+
 def test_rank_two_psf_solve_matches_cholesky(ctx):
     # the first example's two-term Kronecker PSF on a 24 x 20 image (rank-R path)
     # against dense Cholesky at tight tolerance
