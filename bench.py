@@ -99,7 +99,8 @@ MEASURED_TRAFFIC = {
 }
 # the measured traffic holds for these sources: the CG kernel, and the outer
 # loop whose defaults decide how the iterations are split into launches
-KERNEL_SOURCES = ["paper_2306_15049_amd/csrc/cg.hip", "paper_2306_15049_amd/csrc/stencil.hpp",
+KERNEL_SOURCES = ["paper_2306_15049_amd/csrc/cg.hip", "paper_2306_15049_amd/csrc/cg1.hip",
+                  "paper_2306_15049_amd/csrc/cgcore.hpp", "paper_2306_15049_amd/csrc/stencil.hpp",
                   "paper_2306_15049_amd/csrc/internal.hpp", "paper_2306_15049_amd/irn.py"]
 
 
@@ -149,7 +150,7 @@ def roofline(cfg, recs, mode_batched: bool, label: str):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": MEASURED_TRAFFIC.get(key),
-            "kernel": "k_cg (persistent deflated CG, one stencil + update phase per iteration)",
+            "kernel": "k_cg / k_cg1 (persistent deflated CG, one stencil + update phase per iteration)",
             "alg_bytes_per_launch": tot_bytes / max(1, launches),
             "avg_launch_ms": tot_ms / max(1, launches),
             "launches": launches,

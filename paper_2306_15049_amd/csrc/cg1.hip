@@ -121,8 +121,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
     }
     int nbar = 0;
     if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+    // optional phase timestamps of workgroup 0 (diagnostics): [it][k], k = 0..8
+    auto stamp = [&](int it, int k) {
+        if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS)
+            A.stamps[it * DBG_SLOTS + k] = __builtin_amdgcn_s_memrealtime();
+    };
 
     for (int it = 0;; ++it) {
+        stamp(it, 0);
         const double *pprev = (it & 1) ? A.part[0] : A.part[1];
         double *pcur = (it & 1) ? A.part[1] : A.part[0];
         // ---- the previous phase's partials: p.w, r.r, r.w, w.w and Z^T r, Z^T w
@@ -144,6 +150,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             fl[3 * F + f] = v3;
         }
         __syncthreads();
+        stamp(it, 1);
         if constexpr (QT > 0) {
 #pragma unroll
             for (int j = 0; j < 2 * QT; ++j) accz[j] = zok ? accz[j] : 0.0;
@@ -193,6 +200,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             }
         }
         __syncthreads();
+        stamp(it, 2);
         const double alpha = s_dec[0], beta = s_dec[1];
         if (s_dec[2] != 0.0) {
             // x_{j-1} and p_{j-1} of the own pixels, for the step left to the host
@@ -215,6 +223,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             }
             __syncthreads();
         }
+        stamp(it, 3);
 
         if (has) {
             const int pj = it & 1, pk = (it + 1) & 1;      // buffers of step j and of step j - 1
@@ -279,8 +288,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                 }
             }
             __syncthreads();
+            stamp(it, 4);
             tile_E(I, g, tile, y0, x0, Y.gamma, ew);
             tile_A(I, g, tile, taps, y0, x0, 1.0);
+            stamp(it, 5);
             // interior: x_j = x_{j-1} + alpha p_{j-1}; p_j = ph_j - W c_j; w_j = B ph_j - Z c_j;
             // partials p.w, r.r, r.w, w.w, Z^T r, Z^T w
             const double *ebuf = tile + g.offE;
@@ -314,10 +325,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                     }
                 }
             }
+            stamp(it, 6);
             block_accumulate<NVT>(v, NVT, s_acc, s_red);
             if (threadIdx.x < NVP) gp(pcur)[(int)threadIdx.x * PS + slot] = s_acc[threadIdx.x];
         }
+        stamp(it, 7);
         if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+        stamp(it, 8);
     }
 }
 

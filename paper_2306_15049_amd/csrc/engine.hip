@@ -1015,7 +1015,26 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
                   ReadBack{&abort_h, a.abort_flag, sizeof(int)}}, s);
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    if (dbg) {
+    if (dbg && form == 3) {
+        // the single-system kernel's phases of workgroup 0: loads, sums and
+        // decisions, deflation step, window, stencil, epilogue, partials, barrier
+        std::vector<unsigned long long> st((size_t)DBG_ITERS * DBG_SLOTS);
+        HIPCHK(hipMemcpy(st.data(), c->d_dbg.p, sizeof(unsigned long long) * st.size(), hipMemcpyDeviceToHost));
+        const double tk = c->wall_khz / 1000.0;
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int n = 0;
+        for (int it = 1; it + 1 < DBG_ITERS; ++it) {
+            const unsigned long long *e = st.data() + (size_t)it * DBG_SLOTS;
+            if (!e[0] || !e[8] || !st[(size_t)(it + 1) * DBG_SLOTS]) break;
+            for (int k = 0; k < 8; ++k) acc[k] += (double)(e[k + 1] - e[k]);
+            ++n;
+        }
+        if (n > 0)
+            fprintf(stderr, "[rsr cg1 stamps] G=%d iters=%d us: loads %.2f sums+decide %.2f local %.2f window %.2f "
+                            "stencil %.2f epilogue %.2f partials %.2f barrier %.2f\n",
+                    G, n, acc[0] / n / tk, acc[1] / n / tk, acc[2] / n / tk, acc[3] / n / tk, acc[4] / n / tk,
+                    acc[5] / n / tk, acc[6] / n / tk, acc[7] / n / tk);
+    } else if (dbg) {
         std::vector<unsigned long long> st(DBG_WORDS);
         HIPCHK(hipMemcpy(st.data(), c->d_dbg.p, sizeof(unsigned long long) * st.size(), hipMemcpyDeviceToHost));
         {
