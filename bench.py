@@ -93,9 +93,9 @@ def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
 # the factors a 256 MiB device copy gives), keyed by the workload, the solve mode and
 # the hash of the kernel sources they were taken on; any other build reports null.
 MEASURED_TRAFFIC = {
-    ("C2", "sequential", "5e437f17bc53f2eb"): 1.0111e9,     # profiles/k_cg_256x256_sequential_recycled.md
-    ("C3", "batched", "5e437f17bc53f2eb"): 2.0524e12,       # profiles/k_cg_1024x1024_batched_recycled.md
-    ("C4", "batched", "5e437f17bc53f2eb"): 3.4119e12,       # profiles/k_cg_64_instances_batched_recycled.md
+    ("C2", "sequential", "d49149473c19574f"): 0.5163e9,      # profiles/k_cg1_256x256_sequential_recycled.md
+    ("C3", "batched", "d49149473c19574f"): 2.0533e12,        # profiles/k_cg_1024x1024_batched_recycled.md
+    ("C4", "batched", "d49149473c19574f"): 3.4708e12,        # profiles/k_cg_64_instances_batched_recycled.md
 }
 # the measured traffic holds for these sources: the CG kernel, and the outer
 # loop whose defaults decide how the iterations are split into launches
