@@ -370,13 +370,16 @@ rsr_status rsr_adjoint(rsr_ctx *ctx, const rsr_solve_desc *desc, const double *X
 /* Autotune the persistent CG kernel for one instance and n_vec (1..512)
  * systems advancing together: a bounded solve (24 iterations, shifts spread
  * over 1e-3..1e-1) is timed per candidate and the fastest per iteration kept,
- * in stages: tile shape (6 shapes) x workgroup cap (128..1024); the iteration
- * form (fused with coherent loads, fused with an agent-scope acquire per grid
- * barrier, two-pass); for a rank-1 PSF of at most 9 x 9 taps, the direct 2-D
- * stencil against the banded separable one.  The choice applies to later solves
- * (the form when every instance of a launch has the same one) and is cached in a
- * text file when cache_path is given (lines "gfx950 ny nx sy sx n_vec -> ty tx
- * cap form separable"; a matching line is applied without timing).            */
+ * in stages: tile shape (6 shapes) x workgroup cap (128..1024), timed in the
+ * single-system kernel when n_vec = 1 and in the fused form with coherent loads
+ * otherwise; the other iteration forms (fused with coherent loads, fused with an
+ * agent-scope acquire per grid barrier, two-pass); for a rank-1 PSF of at most
+ * 9 x 9 taps, the direct 2-D stencil against the banded separable one.  The
+ * choice applies to later solves (the form when every instance of a launch has
+ * the same one; the single-system form only for launches it fits: one system,
+ * at most 256 tiles of at most 1024 pixels) and is cached in a text file when
+ * cache_path is given (lines "gfx950 ny nx sy sx n_vec -> ty tx cap form
+ * separable", form 0..3; a matching line is applied without timing).          */
 rsr_status rsr_autotune(rsr_ctx *ctx, int inst, int n_vec, const char *cache_path);
 
 /* Current tile shape of an instance (host outputs). */
