@@ -88,26 +88,33 @@ def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
     return 8.0 * s - 4.0 + 13.0 + 14.0 + 8.0 * q
 
 
-# HBM bytes per k_cg launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on
+# HBM bytes per CG launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on
 # the recycled loop of each workload (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0:
 # the factors a 256 MiB device copy gives), keyed by the workload, the solve mode and
-# the hash of the kernel sources they were taken on; any other build reports null.
+# the hash of the sources of the kernels that mode launches; any other build reports null.
 MEASURED_TRAFFIC = {
-    ("C2", "sequential", "d49149473c19574f"): 0.5163e9,      # profiles/k_cg1_256x256_sequential_recycled.md
-    ("C3", "batched", "d49149473c19574f"): 2.0533e12,        # profiles/k_cg_1024x1024_batched_recycled.md
-    ("C4", "batched", "d49149473c19574f"): 3.4708e12,        # profiles/k_cg_64_instances_batched_recycled.md
+    ("C2", "sequential", "6bda6b5a6aa73afb"): 0.7892e9,   # profiles/k_cg1_256x256_sequential_recycled.md
+    ("C3", "batched", "035462f77a438e94"): 2.0533e12,        # profiles/k_cg_1024x1024_batched_recycled.md
+    ("C4", "batched", "035462f77a438e94"): 3.4708e12,        # profiles/k_cg_64_instances_batched_recycled.md
 }
-# the measured traffic holds for these sources: the CG kernel, and the outer
-# loop whose defaults decide how the iterations are split into launches
-KERNEL_SOURCES = ["paper_2306_15049_amd/csrc/cg.hip", "paper_2306_15049_amd/csrc/cg1.hip",
-                  "paper_2306_15049_amd/csrc/cgcore.hpp", "paper_2306_15049_amd/csrc/stencil.hpp",
-                  "paper_2306_15049_amd/csrc/internal.hpp", "paper_2306_15049_amd/irn.py"]
+# the measured traffic holds for these sources: the CG kernels a mode launches
+# (batched launches hold several systems and never run the single-system
+# kernel), and the outer loop whose defaults decide how the iterations are
+# split into launches
+_COMMON_SOURCES = ["paper_2306_15049_amd/csrc/cg.hip", "paper_2306_15049_amd/csrc/cgcore.hpp",
+                   "paper_2306_15049_amd/csrc/stencil.hpp", "paper_2306_15049_amd/csrc/internal.hpp",
+                   "paper_2306_15049_amd/irn.py"]
+KERNEL_SOURCES = {"batched": _COMMON_SOURCES,
+                  "sequential": _COMMON_SOURCES + ["paper_2306_15049_amd/csrc/cg1.hip"]}
+KERNEL_NAMES = {"batched": "k_cg (persistent deflated CG, one stencil + update phase per iteration)",
+                "sequential": "k_cg1 / k_cg (persistent deflated CG of one system / of many; "
+                              "one stencil + update phase per iteration)"}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(label: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[label]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -146,11 +153,11 @@ def roofline(cfg, recs, mode_batched: bool, label: str):
         tot_ms += r.cg_kernel_ms
         launches += r.cg_launches
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
-    key = (cfg.name, label, kernel_source_hash())
+    key = (cfg.name, label, kernel_source_hash(label))
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": MEASURED_TRAFFIC.get(key),
-            "kernel": "k_cg / k_cg1 (persistent deflated CG, one stencil + update phase per iteration)",
+            "kernel": KERNEL_NAMES[label],
             "alg_bytes_per_launch": tot_bytes / max(1, launches),
             "avg_launch_ms": tot_ms / max(1, launches),
             "launches": launches,

@@ -12,7 +12,9 @@
 //     p once, at the end);
 //   * there is no work assignment, no system switch and no grid shrink: the
 //     top of an iteration reduces one system's partials, and every workgroup
-//     forms c_j itself from them.
+//     forms c_j itself from them;
+//   * what other workgroups read (r, ph, w and the partial sums) is stored
+//     write-through, so the barrier needs no L2 write-back (wst below).
 // Iteration j is otherwise the fused iteration of k_cg with coherent loads:
 // the same recomputation of r_j and ph_j on the window, the same stencil, the
 // same partial sums in the same slots and the same reduction order, so the
@@ -22,6 +24,50 @@
 namespace rsr {
 
 namespace {
+
+// Write-through publication, the cheaper barrier for a kernel that knows the
+// few arrays its neighbours read.  An agent-scope store (sc1) is written
+// through the XCD's L2 to the device coherence point, and it counts as done
+// (vmcnt) only once it is there.  When every such store of every wave has
+// completed before the workgroup meets at the barrier, nothing written for
+// other workgroups sits dirty in the L2, so the arrival needs no release: a
+// release writes back the whole L2 on the barrier's critical path.  Stores
+// that only this workgroup reads back (its own x and p at the end) stay plain.
+__device__ __forceinline__ void wst(gdbl *p, double v)
+{
+    typedef __attribute__((address_space(1))) unsigned long long gu64;
+    __hip_atomic_store((gu64 *)p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wst(double *p, double v) { wst(gp(p), v); }
+
+// grid_barrier (cgcore.hpp) for data published with wst only: each wave waits
+// for its own stores, then the arrival is relaxed.  The rest is grid_barrier's.
+__device__ __forceinline__ bool grid_barrier_wt(const BarCtl &b, unsigned long long k, long long timeout, int *s_flag,
+                                                unsigned long long *s_arr, const int *s_g)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t0 = realtime();
+        bool ok;
+        const unsigned long long gsize = (unsigned long long)(*s_g / b.ngrp);
+        const unsigned long long old = __hip_atomic_fetch_add(b.arr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long before = *s_arr;
+        *s_arr = before + gsize;
+        if (old == before + gsize - 1) {
+            __hip_atomic_fetch_add(b.glob, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = spin_until(b.glob, k * (unsigned long long)b.ngrp, b.abort_flag, t0, timeout);
+            if (ok) __hip_atomic_store(b.rel, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = spin_until(b.rel, k, b.abort_flag, t0, timeout);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        *s_flag = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
 
 constexpr int NPX = 4;   // own pixels per thread: tiles of up to 4 NT pixels
 
@@ -116,11 +162,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
         }
         if (has) {
             block_accumulate<NVT>(v, NVT, s_acc, s_red);
-            if (threadIdx.x < NVP) gp(A.part[1])[(int)threadIdx.x * PS + slot] = s_acc[threadIdx.x];
+            if (threadIdx.x < NVP) wst(gp(A.part[1]) + (int)threadIdx.x * PS + slot, s_acc[threadIdx.x]);
         }
     }
     int nbar = 0;
-    if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+    if (!grid_barrier_wt(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
     // optional phase timestamps of workgroup 0 (diagnostics): [it][k], k = 0..8
     auto stamp = [&](int it, int k) {
         if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS)
@@ -279,8 +325,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                     double *d = (lj < g.W0 && li < g.H0) ? tile + li * g.P0 + lj : tile + g.offT + threadIdx.x;
                     *d = ph;
                     if (wok[u] && own[u]) {
-                        if (it > 0) rdst[wi[u]] = rj;
-                        pdst[wi[u]] = ph;
                         const int ii = (li - g.hy) * g.PE + (lj - g.hx);
                         pbuf[ii] = ph;
                         rbuf[ii] = rj;
@@ -313,7 +357,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                 if (ok[i]) {
                     if (it > 0) xr[i] = fma(alpha, pr[i], xr[i]);
                     pr[i] = p;
-                    wdst[gi[i]] = w;
+                    if (it > 0) wst(rdst + gi[i], rj);
+                    wst(pdst + gi[i], pbuf[ii * g.PE + jj]);
+                    wst(wdst + gi[i], w);
                     v[0] = fma(p, w, v[0]);
                     v[1] = fma(rj, rj, v[1]);
                     v[2] = fma(rj, w, v[2]);
@@ -327,10 +373,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             }
             stamp(it, 6);
             block_accumulate<NVT>(v, NVT, s_acc, s_red);
-            if (threadIdx.x < NVP) gp(pcur)[(int)threadIdx.x * PS + slot] = s_acc[threadIdx.x];
+            if (threadIdx.x < NVP) wst(gp(pcur) + (int)threadIdx.x * PS + slot, s_acc[threadIdx.x]);
         }
         stamp(it, 7);
-        if (!grid_barrier(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+        if (!grid_barrier_wt(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
         stamp(it, 8);
     }
 }
