@@ -14,7 +14,11 @@
 //     top of an iteration reduces one system's partials, and every workgroup
 //     forms c_j itself from them;
 //   * what other workgroups read (r, ph, w and the partial sums) is stored
-//     write-through, so the barrier needs no L2 write-back (wst below).
+//     write-through, so the barrier needs no L2 write-back (wst below);
+//   * the step j-1 vectors on the window are loaded at the top of the
+//     iteration, behind the partial sums, and their latency overlaps the
+//     reductions that decide alpha and beta; the weights of E stay in
+//     registers for the whole launch.
 // Iteration j is otherwise the fused iteration of k_cg with coherent loads:
 // the same recomputation of r_j and ph_j on the window, the same stencil, the
 // same partial sums in the same slots and the same reduction order, so the
@@ -70,11 +74,15 @@ __device__ __forceinline__ bool grid_barrier_wt(const BarCtl &b, unsigned long l
 }
 
 constexpr int NPX = 4;   // own pixels per thread: tiles of up to 4 NT pixels
+// window rows per thread loaded at the top of an iteration (fewer for the widest
+// local spaces, whose registers would spill)
+template <int QT> constexpr int nbp() { return QT >= 8 ? 6 : 12; }
 
 template <int QT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_cg1(CGArgs A)
 {
     constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
+    constexpr int NBP = nbp<QT>();
     constexpr int QW = QT > 0 ? QT : 1;
     extern __shared__ double smem[];
     double *tile = smem;                          // stencil buffers / reduction scratch
@@ -143,6 +151,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
         }
     }
 
+    // window cells of this thread: column lj, rows lbase + u * rs; the first NBP
+    // of them are loaded at the top of each iteration
+    const WinMap wm = win_map(g.W0);
+    const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);
+    const int lbase = (int)threadIdx.x >> wm.lw_log;
+    const int gxw = x0 - g.hx + lj;
+    const bool colok = lj < g.W0 && gxw >= 0 && gxw < I.nx;
+    const bool colown = lj >= g.hx && lj < g.hx + I.tx;
+    int wiP[NBP];
+    bool wokP[NBP], ownP[NBP];
+#pragma unroll
+    for (int u = 0; u < NBP; ++u) {
+        const int li = lbase + u * wm.rs;
+        const int gy = y0 - g.hy + li;
+        wokP[u] = has && colok && li < g.H0 && gy >= 0 && gy < I.ny;
+        ownP[u] = colown && li >= g.hy && li < g.hy + I.ty;
+        wiP[u] = wokP[u] ? gy * I.nx + gxw : 0;
+    }
+
     // ---- initial pass: r_0.r_0 and Z^T r_0 into the slots read by iteration 0
     {
         if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
@@ -173,11 +200,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             A.stamps[it * DBG_SLOTS + k] = __builtin_amdgcn_s_memrealtime();
     };
 
+    EWts ew;   // the weights do not change during the launch
+    tile_E_load(I, y0, x0, 0, Y.gamma, ew);
+
     for (int it = 0;; ++it) {
         stamp(it, 0);
+        const int pj = it & 1, pk = (it + 1) & 1;      // buffers of step j and of step j - 1
         const double *pprev = (it & 1) ? A.part[0] : A.part[1];
         double *pcur = (it & 1) ? A.part[1] : A.part[0];
         // ---- the previous phase's partials: p.w, r.r, r.w, w.w and Z^T r, Z^T w
+        // (issued first: loads complete in order, and these are needed first)
         double accz[QT > 0 ? 2 * QT : 1];
         const bool zok = threadIdx.x < F;
         if constexpr (QT > 0) {
@@ -186,8 +218,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
 #pragma unroll
             for (int j = 0; j < 2 * QT; ++j) accz[j] = cld(pz + j * PS);
         }
+        double fv[4];
+        {
+            const double *p = pprev + Y.tile_base + (zok ? (int)threadIdx.x : 0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) fv[u] = cld(p + u * PS);
+        }
+        // the step j-1 vectors on the first window rows: they do not depend on
+        // alpha and beta, so their loads overlap the reductions below (branch-free;
+        // at j = 0 the w and p loads read r_0 and are discarded)
+        const gdbl *__restrict__ rsrc = gp(it > 0 ? Y.rb[pk] : Y.rb[0]);
+        const gdbl *__restrict__ wsrc = it > 0 ? gp(Y.wb[pk]) : rsrc;
+        const gdbl *__restrict__ psrc = it > 0 ? gp(Y.pb[pk]) : rsrc;
+        double rq[NBP], wq[NBP], pq[NBP];
+#pragma unroll
+        for (int u = 0; u < NBP; ++u) {
+            rq[u] = cld(rsrc + wiP[u]);
+            wq[u] = cld(wsrc + wiP[u]);
+            pq[u] = cld(psrc + wiP[u]);
+        }
         double *fl = tile;   // [4][F]
-        for (int f = threadIdx.x; f < F; f += NT) {
+        if (zok) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) fl[u * F + threadIdx.x] = fv[u];
+        }
+        for (int f = threadIdx.x + NT; f < F; f += NT) {
             const double *p = pprev + Y.tile_base + f;
             const double v0 = cld(p), v1 = cld(p + PS), v2 = cld(p + 2 * PS), v3 = cld(p + 3 * PS);
             fl[f] = v0;
@@ -272,26 +327,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
         stamp(it, 3);
 
         if (has) {
-            const int pj = it & 1, pk = (it + 1) & 1;      // buffers of step j and of step j - 1
-            const gdbl *__restrict__ rsrc = gp(it > 0 ? Y.rb[pk] : Y.rb[0]);
             gdbl *__restrict__ rdst = gp(Y.rb[pj]);
-            const gdbl *__restrict__ wsrc = gp(Y.wb[pk]);
             gdbl *__restrict__ wdst = gp(Y.wb[pj]);
-            const gdbl *__restrict__ psrc = gp(Y.pb[pk]);
             gdbl *__restrict__ pdst = gp(Y.pb[pj]);
             double *pbuf = tile + g.offP;
             double *rbuf = tile + g.offR;
             if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
             // stage ph_j = r_j + beta ph_{j-1} with r_j = r_{j-1} - alpha w_{j-1} on the
             // window (halo recomputed from the neighbours' step j-1 vectors)
-            EWts ew;
-            tile_E_load(I, y0, x0, 0, Y.gamma, ew);   // in flight with the window loads
-            const WinMap wm = win_map(g.W0);
-            const int lj = threadIdx.x & ((1 << wm.lw_log) - 1);     // window column of this thread
-            const int gx = x0 - g.hx + lj;
-            const bool colok = lj < g.W0 && gx >= 0 && gx < I.nx;
-            const bool colown = lj >= g.hx && lj < g.hx + I.tx;
-            for (int li0 = threadIdx.x >> wm.lw_log; li0 < g.H0; li0 += wm.rs * NBW) {
+#pragma unroll
+            for (int u = 0; u < NBP; ++u) {
+                const int li = lbase + u * wm.rs;
+                const double wj = it > 0 ? wq[u] : 0.0, pj1 = it > 0 ? pq[u] : 0.0;
+                const double rj = fma(-alpha, wj, rq[u]);
+                const double ph = wokP[u] ? fma(beta, pj1, rj) : 0.0;
+                double *d = (lj < g.W0 && li < g.H0) ? tile + li * g.P0 + lj : tile + g.offT + threadIdx.x;
+                *d = ph;
+                if (wokP[u] && ownP[u]) {
+                    const int ii = (li - g.hy) * g.PE + (lj - g.hx);
+                    pbuf[ii] = ph;
+                    rbuf[ii] = rj;
+                }
+            }
+            const int gx = gxw;
+            for (int li0 = lbase + NBP * wm.rs; li0 < g.H0; li0 += wm.rs * NBW) {
                 int wi[NBW];
                 bool wok[NBW], own[NBW];
 #pragma unroll
