@@ -103,8 +103,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
     {
         static_assert(sizeof(SysDev) % 8 == 0 && sizeof(InstDev) % 8 == 0, "descriptor size");
         constexpr int NSD = (int)(sizeof(SysDev) / 8), NID = (int)(sizeof(InstDev) / 8);
-        const unsigned long long *src = (const unsigned long long *)A.sys;
-        if (threadIdx.x < NSD) ((unsigned long long *)&s_sd)[threadIdx.x] = src[threadIdx.x];
+        if (threadIdx.x < NSD)
+            ((unsigned long long *)&s_sd)[threadIdx.x] =
+                A.sys ? ((const unsigned long long *)A.sys)[threadIdx.x]
+                      : reinterpret_cast<const unsigned long long *>(&A.sys1)[threadIdx.x];
         __syncthreads();
         const unsigned long long *isrc = (const unsigned long long *)(A.inst + s_sd.inst);
         if (threadIdx.x < NID) ((unsigned long long *)&s_id)[threadIdx.x] = isrc[threadIdx.x];

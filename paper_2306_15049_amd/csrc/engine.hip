@@ -490,9 +490,10 @@ void apply_op(rsr_ctx *c, int ii, double cA, double cE, const double *v, long ld
         ct_apply_jobs(c, jobs, s);
         return;
     }
-    ApplyJob *dj = jobbuf ? upload(c, *jobbuf, jobs, s) : stage(c, jobs, s);
+    // up to KJ jobs travel in the kernel arguments
+    ApplyJob *dj = nvec <= KJ ? nullptr : jobbuf ? upload(c, *jobbuf, jobs, s) : stage(c, jobs, s);
     const size_t lds = apply_lds_bytes(I);
-    HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, nvec, lds, s));
+    HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[ii], dj, jobs.data(), nvec, lds, s));
     if (cA != 0.0) c->mv_A += nvec;
     if (cE != 0.0) c->mv_E += nvec;
 }
@@ -509,9 +510,10 @@ void apply_jobs(rsr_ctx *c, std::vector<ApplyJob> &jobs, hipStream_t s)
     for (auto &j : jobs) by[j.inst].push_back(j);
     for (auto &kv : by) {
         Instance &I = get_inst(c, kv.first);
-        ApplyJob *dj = stage(c, kv.second, s);
+        const int nj = (int)kv.second.size();
+        ApplyJob *dj = nj <= KJ ? nullptr : stage(c, kv.second, s);
         const size_t lds = apply_lds_bytes(I);
-        HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[kv.first], dj, (int)kv.second.size(), lds, s));
+        HIPCHK(launch_apply(c->d_inst.as<InstDev>(), c->h_inst[kv.first], dj, kv.second.data(), nj, lds, s));
         for (auto &j : kv.second) {
             if (j.cA != 0.0) c->mv_A++;
             if (j.cE != 0.0) c->mv_E++;
@@ -536,7 +538,7 @@ std::vector<std::vector<double>> gram(rsr_ctx *c, std::vector<GramJob> jobs, hip
         sc += gram_scratch_doubles(&j, 1);
     }
     double *gsc = (double *)dscratch(c, c->d_gram_scratch, sizeof(double) * std::max<size_t>(1, sc));
-    GramJob *dj = stage(c, jobs, s);
+    GramJob *dj = jobs.size() <= (size_t)KJ ? nullptr : stage(c, jobs, s);
     HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), gsc, sc, s));
     std::vector<double> h(coff);
     read_back(c, {ReadBack{h.data(), small, sizeof(double) * coff}}, s);
@@ -560,7 +562,7 @@ void gram_to_device(rsr_ctx *c, std::vector<GramJob> jobs, hipStream_t s)
         sc += gram_scratch_doubles(&j, 1);
     }
     double *gsc = (double *)dscratch(c, c->d_gram_scratch, sizeof(double) * std::max<size_t>(1, sc));
-    GramJob *dj = stage(c, jobs, s);
+    GramJob *dj = jobs.size() <= (size_t)KJ ? nullptr : stage(c, jobs, s);
     HIPCHK(launch_gram(dj, jobs.data(), (int)jobs.size(), gsc, sc, s));
 }
 
@@ -571,6 +573,18 @@ void combo(rsr_ctx *c, std::vector<ComboJob> jobs, const std::vector<std::vector
     WsMark mark(c);
     size_t tot = 0;
     for (auto &q : Qs) tot += q.size();
+    bool inl = jobs.size() <= (size_t)KJ && tot <= (size_t)KQ;
+    for (size_t k = 0; inl && k < jobs.size(); ++k) {
+        const size_t nq = (size_t)jobs[k].a * jobs[k].c;
+        inl = Qs[k].size() == nq && (nq == 0 || jobs[k].ldq == jobs[k].a);
+    }
+    if (inl) {
+        // descriptors and coefficients in the kernel arguments: no upload
+        std::vector<const double *> qp(jobs.size());
+        for (size_t k = 0; k < jobs.size(); ++k) qp[k] = Qs[k].data();
+        HIPCHK(launch_combo(nullptr, jobs.data(), (int)jobs.size(), s, qp.data()));
+        return;
+    }
     // coefficients and descriptors in one upload: [Q_0 Q_1 ... | jobs]
     const size_t nq = sizeof(double) * tot;
     const size_t offj = (nq + 15) & ~(size_t)15;
@@ -929,18 +943,17 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
         d.nlz = Y.nlz;
     }
     WsMark mark(c);
-    SysDev *dsys = stage(c, hd, s);
     double *partA = (double *)dscratch(c, c->d_partA, sizeof(double) * tiles * NVP);
     double *partB = (double *)dscratch(c, c->d_partB, sizeof(double) * tiles * NVP);
-    char *ctl = (char *)dscratch(c, c->d_ctl, BAR_BYTES);
+    // the barrier block and the outputs, zeroed by one fill
     const size_t out_bytes = (sizeof(int) * 2 + 2 * sizeof(double)) * m + 64;
-    char *outb = (char *)dscratch(c, c->d_out, out_bytes);
-    HIPCHK(launch_fill((double *)ctl, 0.0, BAR_BYTES / sizeof(double), s));
+    char *ctl = (char *)dscratch(c, c->d_ctl, BAR_BYTES + out_bytes);
+    char *outb = ctl + BAR_BYTES;
+    HIPCHK(launch_fill((double *)ctl, 0.0, (long)((BAR_BYTES + out_bytes) / sizeof(double)), s));
     int *out_iters = (int *)outb;
     int *out_status = out_iters + m;
     double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
     double *out_alpha = out_rho + m;
-    HIPCHK(launch_fill((double *)outb, 0.0, (long)(out_bytes / sizeof(double)), s));
 
     int qmax = 0;
     bool lz = false;   // some system records CG-Lanczos data in this launch
@@ -964,7 +977,13 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
 
     CGArgs a;
     a.nsys = m;
-    a.sys = dsys;
+    // the single-system kernel takes its descriptor in the kernel arguments
+    if (form == 3) {
+        a.sys = nullptr;
+        a.sys1 = hd[0];
+    } else {
+        a.sys = stage(c, hd, s);
+    }
     a.inst = c->d_inst.as<InstDev>();
     a.part[0] = partA;
     a.part[1] = partB;
@@ -3217,7 +3236,7 @@ rsr_status rsr_solve_shift_set_async(rsr_ctx *c, const rsr_solve_desc *d, const 
         HIPCHK(launch_async_setup(a, s));
         const size_t alds = apply_lds_bytes(I);
         if (a.init == 1) {
-            HIPCHK(launch_apply(c->d_inst.as<InstDev>(), D, a.jobs, m, alds, s));
+            HIPCHK(launch_apply(c->d_inst.as<InstDev>(), D, a.jobs, nullptr, m, alds, s));
             HIPCHK(launch_async_elem(a, 1, s));
         }
         // the persistent CG launch
@@ -3251,7 +3270,7 @@ rsr_status rsr_solve_shift_set_async(rsr_ctx *c, const rsr_solve_desc *d, const 
         }
         // x += alpha p, rt = B x, ||b - rt||, statistics
         HIPCHK(launch_async_elem(a, 2, s));
-        HIPCHK(launch_apply(c->d_inst.as<InstDev>(), D, a.jobs + m, m, alds, s));
+        HIPCHK(launch_apply(c->d_inst.as<InstDev>(), D, a.jobs + m, nullptr, m, alds, s));
         HIPCHK(launch_async_elem(a, 3, s));
         HIPCHK(launch_async_stats(a, stats_dev, s));
     });

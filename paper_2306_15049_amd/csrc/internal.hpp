@@ -93,6 +93,8 @@ struct CGArgs {
     int taps_lds;                  // doubles of dynamic LDS for an instance's bands and end corrections
     int msys;                      // capacity of the per-system LDS arrays (>= nsys)
     unsigned long long *stamps;    // optional [DBG_ITERS][8] phase timestamps of workgroup 0 (or null)
+    SysDev sys1;                   // the system of a single-system launch (form 3) when sys is null:
+                                   // no upload before the launch
 };
 constexpr int DBG_ITERS = 1024, DBG_SLOTS = 16;   // workgroup 0's stamps: [DBG_ITERS][DBG_SLOTS]
 constexpr int DBG_WG_IT0 = 100, DBG_WG_NIT = 8, DBG_WG_MAX = 1024;   // per-workgroup stamps: [DBG_WG_NIT][DBG_WG_MAX][8]
@@ -112,6 +114,42 @@ int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form);
 // (at most NT, of at most 4 NT pixels each) each get a workgroup of their own.
 const void *cg1_kernel(int qt);
 
+// The job descriptors of a launch: carried in the kernel arguments when there
+// are at most KJ of them, so the launch needs no upload of its own, else read
+// from a device array.
+constexpr int KJ = 8;
+template <class J>
+struct Jobs {
+    const J *dev;              // device array (used when n == 0)
+    int n;                     // jobs held in inl
+    J inl[KJ];
+    // the descriptor of job i, the same in every lane: read through a
+    // uniform branch and kept in scalar registers
+    __device__ J operator[](int i) const
+    {
+        static_assert(sizeof(J) % 4 == 0, "descriptor size");
+        J v;
+        if (n) v = inl[i];
+        else v = dev[i];
+        unsigned w[sizeof(J) / 4];
+        __builtin_memcpy(w, &v, sizeof(J));
+#pragma unroll
+        for (int k = 0; k < (int)(sizeof(J) / 4); ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+        __builtin_memcpy(&v, w, sizeof(J));
+        return v;
+    }
+};
+template <class J>
+Jobs<J> make_jobs(const J *dev, const J *host, int njobs)
+{
+    Jobs<J> a;
+    a.dev = dev;
+    a.n = 0;
+    if (!dev)
+        for (int i = 0; i < njobs; ++i) a.inl[a.n++] = host[i];
+    return a;
+}
+
 struct ApplyJob {              // y = cA K^T K v + cE E v   (or K / K^T alone)
     int inst;
     int op;                    // 0: cA*A + cE*E ; 3: K ; 4: K^T
@@ -119,8 +157,10 @@ struct ApplyJob {              // y = cA K^T K v + cE E v   (or K / K^T alone)
     const double *v;
     double *y;
 };
+// jobs_dev == nullptr: the njobs (at most KJ) jobs of jobs_host go in the
+// kernel arguments.
 hipError_t launch_apply(const InstDev *inst_dev, const InstDev &inst_host, const ApplyJob *jobs_dev,
-                        int njobs, size_t lds, hipStream_t s);
+                        const ApplyJob *jobs_host, int njobs, size_t lds, hipStream_t s);
 
 hipError_t launch_blur(const InstDev *inst_dev, const InstDev &inst_host, const ApplyJob *jobs_dev,
                        int njobs, hipStream_t s);
@@ -153,8 +193,20 @@ struct ComboJob {
     const double *Y0;          // optional: Y = Y0 + X Q when non-null (beta ignored)
     long ldy0;
     long n;
+    int qoff = -1;             // >= 0: Q is at this offset of the launch's inline coefficients
 };
-hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jobs_host, int njobs, hipStream_t s);
+// The coefficients of a combination launch whose jobs are inline, when they
+// fit: a launch without any upload.
+constexpr int KQ = 256;
+struct ComboArgs {
+    Jobs<ComboJob> jobs;
+    double q[KQ];
+};
+// jobs_dev == nullptr: the jobs (at most KJ) go in the kernel arguments, and so
+// do Qs (column-major a x c each, at most KQ doubles in all) when qs is given;
+// otherwise each job's Q points to device memory.
+hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jobs_host, int njobs, hipStream_t s,
+                        const double *const *qs = nullptr);
 
 // Graph-capturable plain CG of a shift set on one instance (see kernels.hip).
 constexpr int ASYNC_MAXSYS = 128;

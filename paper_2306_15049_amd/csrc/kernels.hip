@@ -35,8 +35,7 @@ int taps_lds_doubles(int s, int sep) { return taps_doubles(s, sep); }
 
 // ---------------------------------------------------------- apply kernel --
 // y = cA A v + cE E v for one tile per workgroup; blockIdx.y selects the job.
-__global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts,
-                                              const ApplyJob *__restrict__ jobs)
+__global__ __launch_bounds__(NT) void k_apply(const InstDev *__restrict__ insts, const Jobs<ApplyJob> jobs)
 {
     extern __shared__ double lds[];
     const ApplyJob J = jobs[blockIdx.y];
@@ -106,11 +105,12 @@ __global__ __launch_bounds__(NT) void k_blur(const InstDev *__restrict__ insts,
     }
 }
 
-hipError_t launch_apply(const InstDev *inst_dev, const InstDev &ih, const ApplyJob *jobs_dev, int njobs,
-                        size_t lds, hipStream_t s)
+hipError_t launch_apply(const InstDev *inst_dev, const InstDev &ih, const ApplyJob *jobs_dev,
+                        const ApplyJob *jobs_host, int njobs, size_t lds, hipStream_t s)
 {
+    if (!jobs_dev && njobs > KJ) return hipErrorInvalidValue;
     dim3 grid(ih.nty * ih.ntx, njobs);
-    hipLaunchKernelGGL(k_apply, grid, dim3(NT), lds, s, inst_dev, jobs_dev);
+    hipLaunchKernelGGL(k_apply, grid, dim3(NT), lds, s, inst_dev, make_jobs(jobs_dev, jobs_host, njobs));
     return hipGetLastError();
 }
 
@@ -384,7 +384,7 @@ __host__ __device__ inline long gram_chunks(long n, int c)
     return (n + gram_chunk_rows(n, c) - 1) / gram_chunk_rows(n, c);
 }
 
-__global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, double *__restrict__ scratch)
+__global__ __launch_bounds__(NT) void k_gram(const Jobs<GramJob> jobs, double *__restrict__ scratch)
 {
     __shared__ double xs[GR][GB + 1];
     __shared__ double ys[GR][GB + 1];
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(NT) void k_gram(const GramJob *__restrict__ jobs, d
         }
 }
 
-__global__ void k_gram_reduce(const GramJob *__restrict__ jobs, const double *__restrict__ scratch)
+__global__ void k_gram_reduce(const Jobs<GramJob> jobs, const double *__restrict__ scratch)
 {
     const GramJob J = jobs[blockIdx.y];
     const int tiles_c = (J.c + GT - 1) / GT;
@@ -480,7 +480,7 @@ __global__ void k_gram_reduce(const GramJob *__restrict__ jobs, const double *__
 // scratch layout as k_gram (output tile 0), so k_gram_reduce finishes both.
 constexpr int GSMALL = 64;
 constexpr int GSMALL_A = 8;
-__global__ __launch_bounds__(NT) void k_gram_small(const GramJob *__restrict__ jobs, double *__restrict__ scratch)
+__global__ __launch_bounds__(NT) void k_gram_small(const Jobs<GramJob> jobs, double *__restrict__ scratch)
 {
     __shared__ double red[NT / 64][GSMALL];
     const GramJob J = jobs[blockIdx.z];
@@ -546,6 +546,8 @@ size_t gram_scratch_doubles(const GramJob *jh, int njobs)
 hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, double *scratch,
                        size_t scratch_doubles, hipStream_t s)
 {
+    if (!jobs_dev && njobs > KJ) return hipErrorInvalidValue;
+    const Jobs<GramJob> ja = make_jobs(jobs_dev, jh, njobs);
     long maxchunk = 1;
     bool any_big = false, any_small = false;
     for (int i = 0; i < njobs; ++i) {
@@ -561,7 +563,7 @@ hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, do
     if (any_small) {
         long maxa8 = 1;
         for (int i = 0; i < njobs; ++i) maxa8 = std::max<long>(maxa8, (jh[i].a + GSMALL_A - 1) / GSMALL_A);
-        hipLaunchKernelGGL(k_gram_small, dim3(maxchunk, maxa8, njobs), dim3(NT), 0, s, jobs_dev, scratch);
+        hipLaunchKernelGGL(k_gram_small, dim3(maxchunk, maxa8, njobs), dim3(NT), 0, s, ja, scratch);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -569,14 +571,14 @@ hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, do
         long maxblocks = 1;
         for (int i = 0; i < njobs; ++i)
             maxblocks = std::max<long>(maxblocks, (long)((jh[i].a + GB - 1) / GB) * ((jh[i].c + GB - 1) / GB));
-        hipLaunchKernelGGL(k_gram, dim3(maxchunk, maxblocks, njobs), dim3(NT), 0, s, jobs_dev, scratch);
+        hipLaunchKernelGGL(k_gram, dim3(maxchunk, maxblocks, njobs), dim3(NT), 0, s, ja, scratch);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     long outs = 1;
     for (int i = 0; i < njobs; ++i) outs = std::max<long>(outs, (long)jh[i].a * jh[i].c);
     const int gr = (int)std::min<long>(64, (outs + NT - 1) / NT);
-    hipLaunchKernelGGL(k_gram_reduce, dim3(gr, njobs), dim3(NT), 0, s, jobs_dev, scratch);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(gr, njobs), dim3(NT), 0, s, ja, scratch);
     return hipGetLastError();
 }
 
@@ -589,10 +591,10 @@ hipError_t launch_gram(const GramJob *jobs_dev, const GramJob *jh, int njobs, do
 constexpr int CJ = 16;    // output columns per register chunk
 constexpr int CK = 8;     // X columns loaded together
 constexpr int CQ = 256;   // Q rows staged in LDS per pass
-__global__ __launch_bounds__(NT) void k_combo(const ComboJob *__restrict__ jobs)
+__global__ __launch_bounds__(NT) void k_combo(const ComboArgs ca)
 {
     __shared__ double qs[CQ * CJ];
-    const ComboJob J = jobs[blockIdx.y];
+    const ComboJob J = ca.jobs[blockIdx.y];
     const int a = J.a, c = J.c;
     const int j0 = blockIdx.z * CJ;
     if (j0 >= c) return;
@@ -617,7 +619,8 @@ __global__ __launch_bounds__(NT) void k_combo(const ComboJob *__restrict__ jobs)
                 __syncthreads();
                 for (int e = threadIdx.x; e < ka * CJ; e += NT) {
                     const int k = e / CJ, u = e % CJ;
-                    qs[e] = u < cu ? gp(J.Q)[(kb + k) + (long)(j0 + u) * J.ldq] : 0.0;
+                    const long qi = (kb + k) + (long)(j0 + u) * J.ldq;
+                    qs[e] = u >= cu ? 0.0 : J.qoff >= 0 ? ca.q[J.qoff + qi] : gp(J.Q)[qi];
                 }
                 __syncthreads();
                 staged = true;
@@ -647,8 +650,23 @@ __global__ __launch_bounds__(NT) void k_combo(const ComboJob *__restrict__ jobs)
     }
 }
 
-hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jh, int njobs, hipStream_t s)
+hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jh, int njobs, hipStream_t s,
+                        const double *const *qs)
 {
+    if (!jobs_dev && njobs > KJ) return hipErrorInvalidValue;
+    ComboArgs ca;
+    ca.jobs = make_jobs(jobs_dev, jh, njobs);
+    if (!jobs_dev && qs) {
+        int o = 0;
+        for (int i = 0; i < njobs; ++i) {
+            const int nq = jh[i].a * jh[i].c;   // column-major with ldq = a
+            if (o + nq > KQ || (nq > 0 && jh[i].ldq != jh[i].a)) return hipErrorInvalidValue;
+            if (nq == 0) continue;
+            for (int k = 0; k < nq; ++k) ca.q[o + k] = qs[i][k];
+            ca.jobs.inl[i].qoff = o;
+            o += nq;
+        }
+    }
     long nmax = 1;
     int cch = 1;
     for (int i = 0; i < njobs; ++i) {
@@ -657,7 +675,7 @@ hipError_t launch_combo(const ComboJob *jobs_dev, const ComboJob *jh, int njobs,
     }
     int gx = grid_for(nmax);
     if (gx > 2048) gx = 2048;
-    hipLaunchKernelGGL(k_combo, dim3(gx, njobs, cch), dim3(NT), 0, s, jobs_dev);
+    hipLaunchKernelGGL(k_combo, dim3(gx, njobs, cch), dim3(NT), 0, s, ca);
     return hipGetLastError();
 }
 
