@@ -14,7 +14,9 @@
 //     top of an iteration reduces one system's partials, and every workgroup
 //     forms c_j itself from them;
 //   * what other workgroups read (r, ph, w and the partial sums) is stored
-//     write-through, so the barrier needs no L2 write-back (wst below);
+//     write-through, so publishing a step needs no L2 write-back (wst below),
+//     and the steps are ordered by per-tile flags rather than a grid barrier
+//     (step_sync below);
 //   * the step j-1 vectors on the window are loaded at the top of the
 //     iteration, behind the partial sums, and their latency overlaps the
 //     reductions that decide alpha and beta; the weights of E stay in
@@ -45,32 +47,25 @@ __device__ __forceinline__ void wst(gdbl *p, double v)
 }
 __device__ __forceinline__ void wst(double *p, double v) { wst(gp(p), v); }
 
-// grid_barrier (cgcore.hpp) for data published with wst only: each wave waits
-// for its own stores, then the arrival is relaxed.  The rest is grid_barrier's.
-__device__ __forceinline__ bool grid_barrier_wt(const BarCtl &b, unsigned long long k, long long timeout, int *s_flag,
-                                                unsigned long long *s_arr, const int *s_g)
+// Step flags in place of a grid barrier.  Each workgroup publishes the end of
+// its step k by writing k into its tile's flag, once its write-through stores
+// have completed (every wave waits for its own before the workgroup meets),
+// and then waits until every tile's flag has reached k.  That is one write and
+// one poll round trip, where a counter barrier takes an arrival, a release and
+// the polls of both.  The flags start at zero and only grow, so the wait for
+// step k cannot be met by an older step.  Every wait is bounded as in
+// grid_barrier (cgcore.hpp): past the time limit the abort flag is raised, and
+// a workgroup that sees it leaves at its next wait.
+__device__ __forceinline__ bool step_sync(unsigned long long *flags, int nflags, int own, bool has,
+                                          unsigned long long k, int *abort_flag, long long timeout)
 {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned long long t0 = realtime();
-        bool ok;
-        const unsigned long long gsize = (unsigned long long)(*s_g / b.ngrp);
-        const unsigned long long old = __hip_atomic_fetch_add(b.arr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long before = *s_arr;
-        *s_arr = before + gsize;
-        if (old == before + gsize - 1) {
-            __hip_atomic_fetch_add(b.glob, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = spin_until(b.glob, k * (unsigned long long)b.ngrp, b.abort_flag, t0, timeout);
-            if (ok) __hip_atomic_store(b.rel, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            ok = spin_until(b.rel, k, b.abort_flag, t0, timeout);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        *s_flag = ok ? 1 : 0;
-    }
-    __syncthreads();
-    return *s_flag != 0;
+    if (threadIdx.x == 0 && has) __hip_atomic_store(flags + own, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool ok = true;
+    if ((int)threadIdx.x < nflags) ok = spin_until(flags + threadIdx.x, k, abort_flag, realtime(), timeout);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return __syncthreads_or(ok ? 0 : 1) == 0;
 }
 
 constexpr int NPX = 4;   // own pixels per thread: tiles of up to 4 NT pixels
@@ -87,9 +82,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
     extern __shared__ double smem[];
     double *tile = smem;                          // stencil buffers / reduction scratch
     double *taps = smem + A.tile_lds;             // bands and end corrections of the instance
-    const BarCtl bc = bar_ctl(A);
-    __shared__ int s_flag, s_g;
-    __shared__ unsigned long long s_arr;
+    // one flag per tile after the barrier block (zero at launch)
+    unsigned long long *flags = (unsigned long long *)((char *)A.bar + BAR_BYTES);
     __shared__ double s_red[(NT / 64) * NVP];
     __shared__ double s_vals[NVP];
     __shared__ double s_acc[NVP];
@@ -110,10 +104,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
         __syncthreads();
         const unsigned long long *isrc = (const unsigned long long *)(A.inst + s_sd.inst);
         if (threadIdx.x < NID) ((unsigned long long *)&s_id)[threadIdx.x] = isrc[threadIdx.x];
-        if (threadIdx.x == 0) {
-            s_arr = 0;
-            s_g = A.G;
-        }
         if (threadIdx.x < QMAX) s_c[threadIdx.x] = 0.0;
         __syncthreads();
         stage_taps(s_id, taps);
@@ -195,7 +185,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
         }
     }
     int nbar = 0;
-    if (!grid_barrier_wt(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+    if (!step_sync(flags + Y.tile_base, F, chunk, has, (unsigned long long)(++nbar), A.abort_flag, A.timeout_ticks))
+        return;
     // optional phase timestamps of workgroup 0 (diagnostics): [it][k], k = 0..8
     auto stamp = [&](int it, int k) {
         if (A.stamps && blockIdx.x == 0 && threadIdx.x == 0 && it < DBG_ITERS)
@@ -437,7 +428,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             if (threadIdx.x < NVP) wst(gp(pcur) + (int)threadIdx.x * PS + slot, s_acc[threadIdx.x]);
         }
         stamp(it, 7);
-        if (!grid_barrier_wt(bc, (unsigned long long)(++nbar), A.timeout_ticks, &s_flag, &s_arr, &s_g)) return;
+        if (!step_sync(flags + Y.tile_base, F, chunk, has, (unsigned long long)(++nbar), A.abort_flag,
+                       A.timeout_ticks))
+            return;
         stamp(it, 8);
     }
 }

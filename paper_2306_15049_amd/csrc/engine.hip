@@ -945,11 +945,12 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     WsMark mark(c);
     double *partA = (double *)dscratch(c, c->d_partA, sizeof(double) * tiles * NVP);
     double *partB = (double *)dscratch(c, c->d_partB, sizeof(double) * tiles * NVP);
-    // the barrier block and the outputs, zeroed by one fill
+    // the barrier block, the step flags and the outputs, zeroed by one fill
     const size_t out_bytes = (sizeof(int) * 2 + 2 * sizeof(double)) * m + 64;
-    char *ctl = (char *)dscratch(c, c->d_ctl, BAR_BYTES + out_bytes);
-    char *outb = ctl + BAR_BYTES;
-    HIPCHK(launch_fill((double *)ctl, 0.0, (long)((BAR_BYTES + out_bytes) / sizeof(double)), s));
+    const size_t ctl_bytes = BAR_BYTES + FLAG_BYTES + out_bytes;
+    char *ctl = (char *)dscratch(c, c->d_ctl, ctl_bytes);
+    char *outb = ctl + BAR_BYTES + FLAG_BYTES;
+    HIPCHK(launch_fill((double *)ctl, 0.0, (long)(ctl_bytes / sizeof(double)), s));
     int *out_iters = (int *)outb;
     int *out_status = out_iters + m;
     double *out_rho = (double *)(((uintptr_t)(out_status + m) + 15) & ~(uintptr_t)15);
@@ -3018,7 +3019,7 @@ size_t solve_ws_bytes(rsr_ctx *c, const rsr_solve_desc *d, bool adjoint)
     } else {
         for (int i = 0; i < m; ++i) max_tiles = std::max(max_tiles, (size_t)tiles[i]);
     }
-    const size_t launch = al(sizeof(SysDev) * ml) + 2 * al(sizeof(double) * max_tiles * NVP) + al(BAR_BYTES) +
+    const size_t launch = al(sizeof(SysDev) * ml) + 2 * al(sizeof(double) * max_tiles * NVP) + al(BAR_BYTES + FLAG_BYTES) +
                           al((sizeof(int) * 2 + 2 * sizeof(double)) * ml + 64) +
                           al((sizeof(ComboJob) + sizeof(double)) * ml + 16);
     const size_t guesses = al(sizeof(double) * 2 * (d->mode == RSR_BATCHED ? sum_n : max_n)) +

@@ -107,6 +107,8 @@ int cg_tile_lds(int tile_lds, int msys);      // tile LDS rounded up to the redu
 size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys);
 constexpr int BAR_GROUPS = 8;                          // barrier groups (one per XCD when G % 8 == 0)
 constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
+constexpr size_t FLAG_BYTES = 8 * NT;                  // step flags of the single-system kernel, after the
+                                                       // barrier block (one per tile, at most NT tiles)
 int cg_width(int qmax);                           // compiled local-space width for a widest q
 hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s);
 int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form);
