@@ -87,12 +87,14 @@ __device__ __forceinline__ int find_pos(const int *v, int n, int key)   // last 
 // reduce partials.  While T > G the grid is kept whole, since the active set
 // only shrinks and the workgroups that leave cannot come back.  The new grid
 // size is left in *s_g.
-__device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m, int *s_ipb, int *tmp, bool shrink,
+// (It takes the descriptor array, not the argument block: a reference to the
+// block would make the kernel keep a copy of it in scratch.)
+__device__ void build_assign(const SysDev *sys, Assign &S, int m, int G, int *s_m, int *s_ipb, int *tmp, bool shrink,
                              int *s_g)
 {
     for (int k = threadIdx.x; k < m; k += NT) {
-        S.pre[k] = A.sys[S.act[k]].ntiles;
-        S.tb[k] = A.sys[S.act[k]].tile_base;
+        S.pre[k] = sys[S.act[k]].ntiles;
+        S.tb[k] = sys[S.act[k]].tile_base;
     }
     __syncthreads();
     const int T = block_excl_scan(S.pre, m, tmp);
@@ -110,7 +112,7 @@ __device__ void build_assign(const CGArgs &A, Assign &S, int m, int G, int *s_m,
     }
     __syncthreads();
     const int ipb = *s_ipb;
-    for (int k = threadIdx.x; k < m; k += NT) S.foff[k] = nch_of(S.pre[k], A.sys[S.act[k]].ntiles, ipb);
+    for (int k = threadIdx.x; k < m; k += NT) S.foff[k] = nch_of(S.pre[k], sys[S.act[k]].ntiles, ipb);
     __syncthreads();
     const int F = block_excl_scan(S.foff, m, tmp);
     if (threadIdx.x == 0) S.foff[m] = F;
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FORM == 0 &
         s_tol[k] = A.sys[k].tolabs * A.sys[k].tolabs;   // compared with rho = ||r||^2
     }
     __syncthreads();
-    build_assign(A, S0, A.nsys, A.G, &s_m[0], &s_ipb[0], s_tmp, false, &s_g);
+    build_assign(A.sys, S0, A.nsys, A.G, &s_m[0], &s_ipb[0], s_tmp, false, &s_g);
 
     auto slot_of = [&](const Assign &As, int m, int ipb, int s, int chunk) {
         const int a = find_pos(As.act, m, s);
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((FORM == 0 &
             // tiles move between workgroups when the active set shrinks: drop cached copies
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int gold = s_g;
-            build_assign(A, N, mn, gold, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp, true, &s_g);
+            build_assign(A.sys, N, mn, gold, &s_m[cur ^ 1], &s_ipb[cur ^ 1], s_tmp, true, &s_g);
             // every workgroup takes the same decision; the ones past the new grid
             // have published all they wrote at the last barrier
             if ((int)blockIdx.x >= s_g) return;
@@ -818,8 +820,14 @@ int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form)
     return nb;
 }
 
-hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s)
+hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s, const SysDev *sys1)
 {
+    if (a.form == 3) {
+        if (!sys1 && !a.sys) return hipErrorInvalidValue;
+        SysDev none{};   // unused when a.sys is given
+        void *args[] = {(void *)&a, (void *)(sys1 ? sys1 : &none)};
+        return hipLaunchCooperativeKernel(cg_kernel(qt, lz, a.form), dim3(G), dim3(NT), args, (unsigned)lds, s);
+    }
     void *args[] = {(void *)&a};
     return hipLaunchCooperativeKernel(cg_kernel(qt, lz, a.form), dim3(G), dim3(NT), args, (unsigned)lds, s);
 }

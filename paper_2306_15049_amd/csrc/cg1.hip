@@ -74,7 +74,7 @@ constexpr int NPX = 4;   // own pixels per thread: tiles of up to 4 NT pixels
 template <int QT> constexpr int nbp() { return QT >= 8 ? 6 : 12; }
 
 template <int QT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_cg1(CGArgs A)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_cg1(CGArgs A, SysDev S1)
 {
     constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
     constexpr int NBP = nbp<QT>();
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
         if (threadIdx.x < NSD)
             ((unsigned long long *)&s_sd)[threadIdx.x] =
                 A.sys ? ((const unsigned long long *)A.sys)[threadIdx.x]
-                      : reinterpret_cast<const unsigned long long *>(&A.sys1)[threadIdx.x];
+                      : reinterpret_cast<const unsigned long long *>(&S1)[threadIdx.x];
         __syncthreads();
         const unsigned long long *isrc = (const unsigned long long *)(A.inst + s_sd.inst);
         if (threadIdx.x < NID) ((unsigned long long *)&s_id)[threadIdx.x] = isrc[threadIdx.x];

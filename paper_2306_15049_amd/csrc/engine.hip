@@ -979,12 +979,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     CGArgs a;
     a.nsys = m;
     // the single-system kernel takes its descriptor in the kernel arguments
-    if (form == 3) {
-        a.sys = nullptr;
-        a.sys1 = hd[0];
-    } else {
-        a.sys = stage(c, hd, s);
-    }
+    a.sys = form == 3 ? nullptr : stage(c, hd, s);
     a.inst = c->d_inst.as<InstDev>();
     a.part[0] = partA;
     a.part[1] = partB;
@@ -1011,7 +1006,7 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     }
     HIPCHK(hipEventRecord(c->ev0, s));
     {
-        const hipError_t e = launch_cg(a, qt, lz, G, lds, s);
+        const hipError_t e = launch_cg(a, qt, lz, G, lds, s, form == 3 ? &hd[0] : nullptr);
         if (e != hipSuccess)
             fail(e == hipErrorOutOfMemory ? RSR_E_NOMEM : RSR_E_HIP,
                  std::string("persistent CG launch ") + std::to_string(c->last_launches + 1) + " of the call (" +

@@ -93,8 +93,6 @@ struct CGArgs {
     int taps_lds;                  // doubles of dynamic LDS for an instance's bands and end corrections
     int msys;                      // capacity of the per-system LDS arrays (>= nsys)
     unsigned long long *stamps;    // optional [DBG_ITERS][8] phase timestamps of workgroup 0 (or null)
-    SysDev sys1;                   // the system of a single-system launch (form 3) when sys is null:
-                                   // no upload before the launch
 };
 constexpr int DBG_ITERS = 1024, DBG_SLOTS = 16;   // workgroup 0's stamps: [DBG_ITERS][DBG_SLOTS]
 constexpr int DBG_WG_IT0 = 100, DBG_WG_NIT = 8, DBG_WG_MAX = 1024;   // per-workgroup stamps: [DBG_WG_NIT][DBG_WG_MAX][8]
@@ -110,7 +108,11 @@ constexpr size_t BAR_BYTES = 256 * (2 + 2 * BAR_GROUPS);
 constexpr size_t FLAG_BYTES = 8 * NT;                  // step flags of the single-system kernel, after the
                                                        // barrier block (one per tile, at most NT tiles)
 int cg_width(int qmax);                           // compiled local-space width for a widest q
-hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s);
+// Form 3 takes its one system's descriptor as a second kernel argument (sys1,
+// with a.sys null): no upload before the launch.  It is not a field of CGArgs,
+// whose copies the general kernel keeps in scratch.
+hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStream_t s,
+                     const SysDev *sys1 = nullptr);
 int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form);
 // Form 3: the single-system kernel k_cg1 (cg1.hip), for one system whose tiles
 // (at most NT, of at most 4 NT pixels each) each get a workgroup of their own.
