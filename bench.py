@@ -94,8 +94,8 @@ def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
 # the hash of the sources of the kernels that mode launches; any other build reports null.
 MEASURED_TRAFFIC = {
     ("C2", "sequential", "dee3e6b1ac7becf5"): 0.7922e9,   # profiles/k_cg1_256x256_sequential_recycled.md
-    ("C3", "batched", "035462f77a438e94"): 2.0533e12,        # profiles/k_cg_1024x1024_batched_recycled.md
-    ("C4", "batched", "035462f77a438e94"): 3.4708e12,        # profiles/k_cg_64_instances_batched_recycled.md
+    ("C3", "batched", "5402206c0668db1d"): 2.0433e12,        # profiles/k_cg_1024x1024_batched_recycled.md
+    ("C4", "batched", "5402206c0668db1d"): 3.4616e12,        # profiles/k_cg_64_instances_batched_recycled.md
 }
 # the measured traffic holds for these sources: the CG kernels a mode launches
 # (batched launches hold several systems and never run the single-system
