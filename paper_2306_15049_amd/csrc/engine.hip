@@ -1026,8 +1026,15 @@ void run_cg(rsr_ctx *c, std::vector<SysHost *> &sy, const Opts &o, hipStream_t s
     std::vector<int> hi(2 * m + 8);
     std::vector<double> hr(2 * m);   // final r.r, then the pending step alpha
     int abort_h = 0;
-    read_back(c, {ReadBack{hi.data(), out_iters, sizeof(int) * 2 * m}, ReadBack{hr.data(), out_rho, sizeof(double) * 2 * m},
-                  ReadBack{&abort_h, a.abort_flag, sizeof(int)}}, s);
+    {
+        // one copy from the abort flag to the end of the outputs
+        const char *from = (const char *)a.abort_flag;
+        std::vector<char> hb((size_t)(ctl + ctl_bytes - from));
+        read_back(c, {ReadBack{hb.data(), from, hb.size()}}, s);
+        memcpy(&abort_h, hb.data(), sizeof(int));
+        memcpy(hi.data(), hb.data() + ((const char *)out_iters - from), sizeof(int) * 2 * m);
+        memcpy(hr.data(), hb.data() + ((const char *)out_rho - from), sizeof(double) * 2 * m);
+    }
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     if (dbg && form == 3) {
