@@ -13,6 +13,7 @@ normally; the conditions are forced from the host).
 * The grid barrier's bounded wait: with a limit of 0 us every wait gives up
   at once, every workgroup leaves the kernel, and the solve reports
   RSR_E_TIMEOUT; the same context then solves normally with the default limit.
+  The same for the single-system kernel's step-flag waits.
 """
 import numpy as np
 import pytest
@@ -119,6 +120,34 @@ def test_barrier_time_limit_gives_up_and_drains(torch_cuda, monkeypatch):
     try:
         c.set_operators([(n, n)], [np.ones((1, 1))])
         rc, st = c.solve([0.1, 1.0, 3.0, 10.0], b, X)
+        assert rc == 0
+    finally:
+        c.close()
+
+def test_step_flag_time_limit_gives_up_and_drains(torch_cuda, monkeypatch):
+    # the same for the single-system kernel (one shift at a time, form 3 forced),
+    # whose steps are ordered by per-tile flags: a limit of 0 us gives up at the
+    # first wait, every workgroup leaves, and the solve reports RSR_E_TIMEOUT
+    n = 256
+    rng = np.random.default_rng(2)
+    b = to_dev(rng.standard_normal((n, n)))
+    X = to_dev(np.zeros((2, n, n)))
+    o = rsr.SolveOptions(mode=rsr.SEQUENTIAL)
+    monkeypatch.setenv("RSR_CG_MODE", "4")
+    monkeypatch.setenv("RSR_BARRIER_TIMEOUT_US", "0")
+    c = rsr.Context(0)
+    try:
+        c.set_operators([(n, n)], [np.ones((1, 1))])
+        c.set_tile(0, 16, 32)
+        assert _status(lambda: c.solve([0.1, 1.0], b, X, opts=o)) == -8
+    finally:
+        c.close()
+    monkeypatch.delenv("RSR_BARRIER_TIMEOUT_US")
+    c = rsr.Context(0)
+    try:
+        c.set_operators([(n, n)], [np.ones((1, 1))])
+        c.set_tile(0, 16, 32)
+        rc, st = c.solve([0.1, 1.0], b, X, opts=o)
         assert rc == 0
     finally:
         c.close()
