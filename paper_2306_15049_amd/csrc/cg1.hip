@@ -68,6 +68,26 @@ __device__ __forceinline__ bool step_sync(unsigned long long *flags, int nflags,
     return __syncthreads_or(ok ? 0 : 1) == 0;
 }
 
+// A tile's partial sums into its slot: block_accumulate (cgcore.hpp) onto
+// zeroed accumulators, each value stored by the thread that forms it (no
+// second workgroup barrier; 0.0 + s keeps the rounding, and the sign of a zero,
+// of accumulating onto zero).
+template <int NV>
+__device__ __forceinline__ void block_sum_to_slot(const double (&v)[NV], double *red, gdbl *dst, int ps, int slot)
+{
+    wave_partials<NV>(v, NV, red + ((int)threadIdx.x >> 6) * NVP);
+    __syncthreads();
+    if (threadIdx.x < NVP) {
+        double val = 0.0;
+        if (threadIdx.x < NV) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w * NVP + threadIdx.x];
+            val = 0.0 + s;
+        }
+        wst(dst + (int)threadIdx.x * ps + slot, val);
+    }
+}
+
 constexpr int NPX = 4;   // own pixels per thread: tiles of up to 4 NT pixels
 // window rows per thread loaded at the top of an iteration (fewer for the widest
 // local spaces, whose registers would spill)
@@ -86,7 +106,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
     unsigned long long *flags = (unsigned long long *)((char *)A.bar + BAR_BYTES);
     __shared__ double s_red[(NT / 64) * NVP];
     __shared__ double s_vals[NVP];
-    __shared__ double s_acc[NVP];
     __shared__ double s_sums[4];
     __shared__ double s_dec[3];                   // alpha_{j-1}, beta_j, status of iteration j
     __shared__ double s_z[QMAX];
@@ -164,7 +183,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
 
     // ---- initial pass: r_0.r_0 and Z^T r_0 into the slots read by iteration 0
     {
-        if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
         __syncthreads();
         double v[NVT];
 #pragma unroll
@@ -180,8 +198,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             }
         }
         if (has) {
-            block_accumulate<NVT>(v, NVT, s_acc, s_red);
-            if (threadIdx.x < NVP) wst(gp(A.part[1]) + (int)threadIdx.x * PS + slot, s_acc[threadIdx.x]);
+            block_sum_to_slot<NVT>(v, s_red, gp(A.part[1]), PS, slot);
         }
     }
     int nbar = 0;
@@ -325,8 +342,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
             gdbl *__restrict__ pdst = gp(Y.pb[pj]);
             double *pbuf = tile + g.offP;
             double *rbuf = tile + g.offR;
-            if (threadIdx.x < NVP) s_acc[threadIdx.x] = 0.0;
-            // stage ph_j = r_j + beta ph_{j-1} with r_j = r_{j-1} - alpha w_{j-1} on the
+                // stage ph_j = r_j + beta ph_{j-1} with r_j = r_{j-1} - alpha w_{j-1} on the
             // window (halo recomputed from the neighbours' step j-1 vectors)
 #pragma unroll
             for (int u = 0; u < NBP; ++u) {
@@ -424,8 +440,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                 }
             }
             stamp(it, 6);
-            block_accumulate<NVT>(v, NVT, s_acc, s_red);
-            if (threadIdx.x < NVP) wst(gp(pcur) + (int)threadIdx.x * PS + slot, s_acc[threadIdx.x]);
+            block_sum_to_slot<NVT>(v, s_red, gp(pcur), PS, slot);
         }
         stamp(it, 7);
         if (!step_sync(flags + Y.tile_base, F, chunk, has, (unsigned long long)(++nbar), A.abort_flag,
