@@ -106,7 +106,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
     unsigned long long *flags = (unsigned long long *)((char *)A.bar + BAR_BYTES);
     __shared__ double s_red[(NT / 64) * NVP];
     __shared__ double s_vals[NVP];
-    __shared__ double s_sums[4];
     __shared__ double s_dec[3];                   // alpha_{j-1}, beta_j, status of iteration j
     __shared__ double s_z[QMAX];
     __shared__ double s_c[QMAX];                  // c_j (c_{-1} = 0)
@@ -262,10 +261,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
         }
         __syncthreads();
         stamp(it, 1);
+        // Z^T r, Z^T w as block_sum does it, whose second barrier is shared with
+        // the decisions: wave 0 forms the flat sums (a wave reduction leaves
+        // them in every lane) and decides from them without a round trip
+        // through LDS.
         if constexpr (QT > 0) {
 #pragma unroll
             for (int j = 0; j < 2 * QT; ++j) accz[j] = zok ? accz[j] : 0.0;
-            block_sum<2 * QT>(accz, 2 * QT, s_vals, s_red);
+            wave_partials<2 * QT>(accz, 2 * QT, s_red + ((int)threadIdx.x >> 6) * NVP);
+            __syncthreads();
+            if (threadIdx.x < 2 * QT) {
+                double sz = 0.0;
+                for (int w = 0; w < NT / 64; ++w) sz += s_red[w * NVP + threadIdx.x];
+                s_vals[threadIdx.x] = sz;
+            }
         }
         if (threadIdx.x < 64) {
             const int lane = threadIdx.x;
@@ -274,14 +283,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
 #pragma unroll
                 for (int u = 0; u < 4; ++u) v[u] += fl[u * F + k];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double sv = wave_sum(v[u]);
-                if (lane == 0) s_sums[u] = sv;
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const double pw = s_sums[0], rr = s_sums[1], rw = s_sums[2], ww = s_sums[3];
+            for (int u = 0; u < 4; ++u) v[u] = wave_sum(v[u]);
+            const double pw = v[0], rr = v[1], rw = v[2], ww = v[3];
             double rho, alpha = 0.0, beta = 0.0;
             int st = 0;
             if (it == 0) {
@@ -300,14 +303,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                 if (rho <= tol2) st = 1;
                 else if (it >= A.maxit) st = 2;
             }
-            s_dec[0] = alpha;
-            s_dec[1] = beta;
-            s_dec[2] = st;
-            if (st != 0 && blockIdx.x == 0) {
-                A.out_status[0] = st;
-                A.out_iters[0] = it;
-                A.out_rho[0] = rho;
-                A.out_alpha[0] = st > 0 ? alpha : 0.0;   // x_j = x_{j-1} + alpha p_{j-1} is applied after the launch
+            if (lane == 0) {
+                s_dec[0] = alpha;
+                s_dec[1] = beta;
+                s_dec[2] = st;
+                if (st != 0 && blockIdx.x == 0) {
+                    A.out_status[0] = st;
+                    A.out_iters[0] = it;
+                    A.out_rho[0] = rho;
+                    A.out_alpha[0] = st > 0 ? alpha : 0.0;   // x_j = x_{j-1} + alpha p_{j-1} is applied after the launch
+                }
             }
         }
         __syncthreads();
