@@ -786,8 +786,8 @@ size_t cg_lds_bytes(int tile_lds, int taps_lds, int msys)
 // the fused form only (captures are single systems, where fused iterations win).
 static const void *cg_kernel(int qt, bool lz, int form)
 {
+    if (form == 3) return cg1_kernel(qt, lz);
     if (lz) return qt == 0 ? (const void *)k_cg<0, true, 0> : (const void *)k_cg<QMAX, true, 0>;
-    if (form == 3) return cg1_kernel(qt);
 #define RSR_CG_FORM(F)                                          \
     if (form == F) {                                           \
         switch (qt) {                                          \

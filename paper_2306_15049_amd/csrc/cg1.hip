@@ -17,6 +17,8 @@
 //     write-through, so publishing a step needs no L2 write-back (wst below),
 //     and the steps are ordered by per-tile flags rather than a grid barrier
 //     (step_sync below);
+//   * a launch that records CG-Lanczos data (the LZ instantiations) stores r_j
+//     and the step's coefficients as k_cg does;
 //   * the step j-1 vectors on the window are loaded at the top of the
 //     iteration, behind the partial sums, and their latency overlaps the
 //     reductions that decide alpha and beta; the weights of E stay in
@@ -93,7 +95,7 @@ constexpr int NPX = 4;   // own pixels per thread: tiles of up to 4 NT pixels
 // local spaces, whose registers would spill)
 template <int QT> constexpr int nbp() { return QT >= 8 ? 6 : 12; }
 
-template <int QT>
+template <int QT, bool LZ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_cg1(CGArgs A, SysDev S1)
 {
     constexpr int NVT = 4 + 2 * QT;   // used values per partial slot
@@ -304,6 +306,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                 else if (it >= A.maxit) st = 2;
             }
             if (lane == 0) {
+                // Lanczos capture: alpha_{j-1}, beta_{j-1} and rho_j of a step j = it that runs
+                if (LZ && st == 0 && Y.nlz > 0 && chunk == 0) {
+                    if (it >= 1 && it <= Y.nlz) {
+                        gp(Y.lzc)[it - 1] = alpha;
+                        gp(Y.lzc)[Y.nlz + it - 1] = beta;
+                    }
+                    if (it < Y.nlz) gp(Y.lzc)[2 * Y.nlz + it] = rho;
+                }
                 s_dec[0] = alpha;
                 s_dec[1] = beta;
                 s_dec[2] = st;
@@ -431,6 +441,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
                     if (it > 0) xr[i] = fma(alpha, pr[i], xr[i]);
                     pr[i] = p;
                     if (it > 0) wst(rdst + gi[i], rj);
+                    if (LZ && it < Y.nlz) gp(Y.lz)[it * Y.ldw + gi[i]] = rj;   // Lanczos capture of r_j
                     wst(pdst + gi[i], pbuf[ii * g.PE + jj]);
                     wst(wdst + gi[i], w);
                     v[0] = fma(p, w, v[0]);
@@ -457,13 +468,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1))) void k_
 
 }  // namespace
 
-const void *cg1_kernel(int qt)
+const void *cg1_kernel(int qt, bool lz)
 {
+    if (lz) return qt == 0 ? (const void *)k_cg1<0, true> : (const void *)k_cg1<QMAX, true>;
     switch (qt) {
-    case 0: return (const void *)k_cg1<0>;
-    case 3: return (const void *)k_cg1<3>;
-    case 5: return (const void *)k_cg1<5>;
-    default: return (const void *)k_cg1<QMAX>;
+    case 0: return (const void *)k_cg1<0, false>;
+    case 3: return (const void *)k_cg1<3, false>;
+    case 5: return (const void *)k_cg1<5, false>;
+    default: return (const void *)k_cg1<QMAX, false>;
     }
 }
 

@@ -875,14 +875,17 @@ CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles, in
     // elementwise pass, a barrier, a stencil pass that reads ph alone, form 2)
     // read a third of the halo for a second barrier.  A single system whose
     // tiles each get a workgroup runs the single-system kernel (form 3: tile
-    // data in registers, no assignment).  Launches that record CG-Lanczos data
-    // use form 0.
+    // data in registers, no assignment).  Other launches that record CG-Lanczos
+    // data use form 0.
     int mode = c->cg_mode;
     if (const char *e = getenv("RSR_CG_MODE")) mode = atoi(e);   // override for tuning sweeps
-    const bool one = allow_one && m == 1 && !lz && tiles <= NT && tile_px > 0 && tile_px <= 4 * NT;
+    const bool one = allow_one && m == 1 && tiles <= NT && tile_px > 0 && tile_px <= 4 * NT;
     const int by_size = px >= (2L << 20) ? 1 : 0;
-    L.form = lz ? 0 : (mode >= 1 && mode <= 4) ? mode - 1 : tuned_form >= 0 ? tuned_form : one ? 3 : by_size;
-    if (L.form == 3 && !one) L.form = by_size;
+    if (lz)
+        L.form = one && mode != 1 ? 3 : 0;   // mode 1 forces form 0 (comparisons)
+    else
+        L.form = (mode >= 1 && mode <= 4) ? mode - 1 : tuned_form >= 0 ? tuned_form : one ? 3 : by_size;
+    if (L.form == 3 && !one) L.form = lz ? 0 : by_size;
     for (;;) {
         const int bpc = cg_max_blocks_per_cu(L.lds, L.qt, lz, L.form);
         if (bpc < 1) fail(RSR_E_HIP, "persistent kernel does not fit on a CU");
@@ -896,7 +899,7 @@ CgLaunch cg_config(rsr_ctx *c, int m, int qmax, bool lz, long px, long tiles, in
         if (G >= 8) G -= G % 8;
         L.G = G;
         if (L.form == 3 && G < tiles) {   // a workgroup per tile does not fit this grid
-            L.form = by_size;
+            L.form = lz ? 0 : by_size;
             continue;
         }
         return L;

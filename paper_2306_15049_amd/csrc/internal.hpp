@@ -116,7 +116,7 @@ hipError_t launch_cg(const CGArgs &a, int qt, bool lz, int G, size_t lds, hipStr
 int cg_max_blocks_per_cu(size_t lds, int qt, bool lz, int form);
 // Form 3: the single-system kernel k_cg1 (cg1.hip), for one system whose tiles
 // (at most NT, of at most 4 NT pixels each) each get a workgroup of their own.
-const void *cg1_kernel(int qt);
+const void *cg1_kernel(int qt, bool lz);   // lz: the variant that records CG-Lanczos data (qt 0 or QMAX)
 
 // The job descriptors of a launch: carried in the kernel arguments when there
 // are at most KJ of them, so the launch needs no upload of its own, else read

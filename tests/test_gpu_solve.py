@@ -164,6 +164,27 @@ def test_single_system_kernel_matches_general_kernel_bitwise(ctx, monkeypatch, t
         assert oracle.true_relres(pr.psf, wh, wv, g, b, out["4"][0][l]) <= 1e-8
 
 
+def test_single_system_kernel_records_lanczos_data_bitwise(ctx, monkeypatch):
+    # the correction equation's solve records CG-Lanczos data (r_j and the step
+    # coefficients); its one system runs the single-system kernel unless form 0
+    # is forced, and the Krylov vectors built from the record agree to the last bit
+    pr = synth.make_problem(9, 150, 203, 2.0, 13, 12)
+    ny, nx = pr.ny, pr.nx
+    wh0, wv0 = oracle.weights(pr.x_true)
+    wh1, wv1 = oracle.weights(pr.x_true + 0.05 * pr.noise_dir)
+    ctx.set_operators([(ny, nx)], [pr.psf])
+    ctx.set_tile(0, 16, 32)
+    ctx.update_weights(0, to_dev(wh1), to_dev(wv1))
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("RSR_CG_MODE", mode)
+        print(f"correction space, mode {mode}", flush=True)
+        V, nout = ctx.correction_space(0, to_dev(pr.x_true), to_dev(wh0), to_dev(wv0), 0.3, 30, 10)
+        out[mode] = (to_host(V), nout)
+    assert out["1"][1] == out["0"][1] == 11
+    assert np.array_equal(out["1"][0], out["0"][0])
+
+
 def test_rank_two_psf_solve_matches_cholesky(ctx):
     # the first example's two-term Kronecker PSF on a 24 x 20 image (rank-R path)
     # against dense Cholesky at tight tolerance
