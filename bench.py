@@ -93,9 +93,9 @@ def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
 # the factors a 256 MiB device copy gives), keyed by the workload, the solve mode and
 # the hash of the sources of the kernels that mode launches; any other build reports null.
 MEASURED_TRAFFIC = {
-    ("C2", "sequential", "0f86b9886559dde4"): 0.7964e9,   # profiles/k_cg1_256x256_sequential_recycled.md
-    ("C3", "batched", "5402206c0668db1d"): 2.0433e12,        # profiles/k_cg_1024x1024_batched_recycled.md
-    ("C4", "batched", "5402206c0668db1d"): 3.4616e12,        # profiles/k_cg_64_instances_batched_recycled.md
+    ("C2", "sequential", "95f9602f891c63dc"): 0.7964e9,   # profiles/k_cg1_256x256_sequential_recycled.md
+    ("C3", "batched", "af3dceadc2bcabfa"): 2.0434e12,        # profiles/k_cg_1024x1024_batched_recycled.md
+    ("C4", "batched", "af3dceadc2bcabfa"): 3.4616e12,        # profiles/k_cg_64_instances_batched_recycled.md
 }
 # the measured traffic holds for these sources: the CG kernels a mode launches
 # (batched launches hold several systems and never run the single-system
