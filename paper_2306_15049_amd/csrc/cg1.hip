@@ -65,7 +65,23 @@ __device__ __forceinline__ bool step_sync(unsigned long long *flags, int nflags,
     __syncthreads();
     if (threadIdx.x == 0 && has) __hip_atomic_store(flags + own, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool ok = true;
-    if ((int)threadIdx.x < nflags) ok = spin_until(flags + threadIdx.x, k, abort_flag, realtime(), timeout);
+    if ((int)threadIdx.x < nflags) {
+        // spin_until without the sleep between polls: the flags are written once per
+        // step, and a poll round trip already takes a microsecond
+        unsigned long long *word = flags + threadIdx.x;
+        const unsigned long long t0 = realtime();
+        while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = false;
+                break;
+            }
+            if ((long long)(realtime() - t0) > timeout) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+        }
+    }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     return __syncthreads_or(ok ? 0 : 1) == 0;
 }
