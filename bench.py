@@ -93,7 +93,7 @@ def cg_alg_flops_per_px_iter(s: int, q: int) -> float:
 # the factors a 256 MiB device copy gives), keyed by the workload, the solve mode and
 # the hash of the sources of the kernels that mode launches; any other build reports null.
 MEASURED_TRAFFIC = {
-    ("C2", "sequential", "95f9602f891c63dc"): 0.7964e9,   # profiles/k_cg1_256x256_sequential_recycled.md
+    ("C2", "sequential", "66bfc4247badd383"): 0.7960e9,   # profiles/k_cg1_256x256_sequential_recycled.md
     ("C3", "batched", "af3dceadc2bcabfa"): 2.0434e12,        # profiles/k_cg_1024x1024_batched_recycled.md
     ("C4", "batched", "af3dceadc2bcabfa"): 3.4616e12,        # profiles/k_cg_64_instances_batched_recycled.md
 }
